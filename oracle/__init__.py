@@ -1,0 +1,143 @@
+"""CPU oracle for the BMLP hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the HIP library and never imports it.
+
+Contents
+--------
+* ``closure_rows``, ``smp``, ``compose_rows``, ``warshall``: the C oracle
+  (``bmlp_oracle.c``): per-source breadth-first search, i.e. the plain
+  definition of the transitive closure R1+ (Eq. 1), of the selection v R1+
+  (Eq. 5) and of the linear composition P = Rs* Rb (Theorem 1), plus
+  Warshall's algorithm as an independent brute force.
+* ``algorithms``: Algorithms 1 and 2 of the paper stepped literally on dense
+  0/1 matrices (numpy), for small sizes and iteration counts.
+* ``datalog``: a pure-Python semi-naive bottom-up evaluator over sets of
+  pairs, for the paper's programs (P2, the linear composition, and the
+  stratified P3 u P4 u P5 example).
+* ``boolops``: Boolean matrix addition, multiplication, transpose and
+  negation (Section 2) on dense 0/1 arrays, and the oracle's own conversion
+  between dense 0/1 arrays and the LSB-first uint64 bit rows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bmlp_oracle.c")
+_LIB = os.path.join(_HERE, "libbmlp_oracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (OpenMP).  Returns the library path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-std=c11", "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        i64, ip, i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+        L.bmlp_oracle_closure_rows.argtypes = [i64, i64, ip, ip, ip, i64, ip, i64, i32, ip]
+        L.bmlp_oracle_smp.argtypes = [i64, i64, ip, ip, ip, i64, i64, ip, i32, i32, ip]
+        L.bmlp_oracle_compose_rows.argtypes = [i64, i64, ip, ip, i64, ip, ip, ip, i64, ip, i64, i32, ip]
+        L.bmlp_oracle_warshall.argtypes = [i64, ip, i64]
+        for f in (L.bmlp_oracle_closure_rows, L.bmlp_oracle_smp,
+                  L.bmlp_oracle_compose_rows, L.bmlp_oracle_warshall):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def words(n: int) -> int:
+    return (n + 63) // 64
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _edges(src, dst):
+    s = np.ascontiguousarray(src, dtype=np.int32)
+    d = np.ascontiguousarray(dst, dtype=np.int32)
+    assert s.shape == d.shape
+    return s, d
+
+
+last_threads = 0
+
+
+def closure_rows(n, src, dst, rows=None, ld=None, threads=0):
+    """Rows of R1+ (all rows when ``rows`` is None) as uint64 bit rows."""
+    global last_threads
+    s, d = _edges(src, dst)
+    ld = ld or max(words(n), 1)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = n if r is None else len(r)
+    out = np.zeros((nr, ld), dtype=np.uint64)
+    used = ctypes.c_int(0)
+    rc = lib().bmlp_oracle_closure_rows(n, len(s), _p(s), _p(d), _p(r), nr,
+                                        _p(out), ld, threads, ctypes.byref(used))
+    if rc:
+        raise RuntimeError("oracle closure failed: %d" % rc)
+    last_threads = used.value
+    return out
+
+
+def smp(n, src, dst, V, reflexive=False, threads=0):
+    """``V R1+`` row by row (``V R1*`` when reflexive); V is uint64 bit rows."""
+    global last_threads
+    s, d = _edges(src, dst)
+    V = np.ascontiguousarray(V, dtype=np.uint64)
+    k, ldv = V.shape
+    out = np.zeros((k, ldv), dtype=np.uint64)
+    used = ctypes.c_int(0)
+    rc = lib().bmlp_oracle_smp(n, len(s), _p(s), _p(d), _p(V), k, ldv, _p(out),
+                               1 if reflexive else 0, threads, ctypes.byref(used))
+    if rc:
+        raise RuntimeError("oracle smp failed: %d" % rc)
+    last_threads = used.value
+    return out
+
+
+def compose_rows(n, bsrc, bdst, ssrc, sdst, rows=None, ld=None, threads=0):
+    """Rows of P = Rs* Rb."""
+    global last_threads
+    bs, bd = _edges(bsrc, bdst)
+    ss, sd = _edges(ssrc, sdst)
+    ld = ld or max(words(n), 1)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = n if r is None else len(r)
+    out = np.zeros((nr, ld), dtype=np.uint64)
+    used = ctypes.c_int(0)
+    rc = lib().bmlp_oracle_compose_rows(n, len(bs), _p(bs), _p(bd), len(ss), _p(ss), _p(sd),
+                                        _p(r), nr, _p(out), ld, threads, ctypes.byref(used))
+    if rc:
+        raise RuntimeError("oracle compose failed: %d" % rc)
+    last_threads = used.value
+    return out
+
+
+def warshall(bits, n):
+    """R1+ of an n x n bit matrix by Warshall's algorithm (copy returned)."""
+    R = np.array(bits, dtype=np.uint64, copy=True, order="C")
+    rc = lib().bmlp_oracle_warshall(n, _p(R), R.shape[1])
+    if rc:
+        raise RuntimeError("oracle warshall failed: %d" % rc)
+    return R
+
+
+from . import boolops, algorithms, datalog  # noqa: E402,F401

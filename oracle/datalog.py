@@ -1,0 +1,53 @@
+"""Pure-Python semi-naive bottom-up evaluation over sets of pairs.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Tiny inputs only.
+
+These evaluate the paper's datalog programs directly from their clauses,
+without matrices, so they pin the matrix formulations from outside:
+
+* ``linear`` evaluates  p(X,Y) <- b(X,Y).  p(X,Y) <- s(X,Z), p(Z,Y).
+  (the program P2 of Section 3.3 when b = s = r1; the general linear
+  recursion of Section 3.4 otherwise).  Semi-naive: each round joins the
+  step relation only with the facts that were new in the previous round.
+* ``is_foreign`` evaluates P3 u P4 u P5 of Section 3.4 stratum by stratum:
+  hasPlace, then indirectlyPartOf, then isForeign with negation against the
+  finished lower stratum.
+"""
+from __future__ import annotations
+
+
+def linear(base, step):
+    """Least model of p <- b; p <- s, p (sets of (x, y) pairs)."""
+    base = set(base)
+    succ_inv = {}
+    for (x, z) in step:
+        succ_inv.setdefault(z, []).append(x)
+    p = set(base)
+    delta = set(base)
+    while delta:
+        new = set()
+        for (z, y) in delta:
+            for x in succ_inv.get(z, ()):
+                if (x, y) not in p:
+                    new.add((x, y))
+        p |= new
+        delta = new
+    return p
+
+
+def closure(edges):
+    """P2: r2 <- r1; r2 <- r1, r2."""
+    return linear(edges, edges)
+
+
+def is_foreign(constants, contains, adjoins, location=None):
+    """The P3 u P4 u P5 program of Section 3.4; returns the four relations."""
+    location = set(constants) if location is None else set(location)
+    has_place = linear(contains, contains)
+    # indirectlyPartOf(X,Y) <- adjoins(X,Y) | adjoins(Y,X)
+    #                        | hasPlace(Z,X), indirectlyPartOf(Z,Y)
+    base = set(adjoins) | {(y, x) for (x, y) in adjoins}
+    step = {(x, z) for (z, x) in has_place}  # s(X,Z) := hasPlace(Z,X)
+    ipo = linear(base, step)
+    foreign = {(x, y) for x in location for y in location if (x, y) not in ipo}
+    return has_place, ipo, foreign
