@@ -1,0 +1,188 @@
+/*
+ * bmlp.h -- C ABI of libbmlp: Boolean Matrix Logic Programming (Ai,
+ * "Boolean Matrix Logic Programming on the GPU", arXiv 2408.10369) on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library evaluates linear dyadic recursive datalog bottom-up by
+ * Boolean-semiring (OR, AND) matrix products:
+ *   bmlp_rms             BMLP-RMS, repeated squaring to the closure R1+
+ *                        (Section 3.3, Eqs. 2-4; Algorithm 1)
+ *   bmlp_smp             BMLP-SMP, selective products v R1+ from chosen
+ *                        source rows (Section 3.3, Eq. 5; Algorithm 2)
+ *   bmlp_compose_linear  general linear recursion p <- b; p <- s, p, i.e.
+ *                        P = Rs* Rb (Section 3.4, Theorem 1)
+ * plus the Boolean matrix operators they are built from (Section 2 and
+ * Section 4: addition, multiplication, transpose, negation) and the packing
+ * of facts into matrices (Section 3.2).
+ *
+ * ---------------------------------------------------------------- layout
+ * A relation r over constants c_0..c_{n-1} (indices from the bijection of
+ * Section 3.2) is an n x n Boolean matrix with R_ij = 1 iff r(c_i, c_j)
+ * (Definition 1).  Every matrix argument is a DEVICE pointer to row-major
+ * bit rows: row i starts at word i*ld; column j is bit (j & 63) of word
+ * (j >> 6) of that row (least significant bit first).  `ld` (words) must be
+ * >= ceil(cols/64).  Bits of columns >= cols ("padding") must be 0 on input
+ * (checked when opts->check_padding is set) and are 0 on output, including
+ * whole padding words up to ld.  A vector (a partially grounded query
+ * r(c, Y), Section 3.3) is a single row; k queries are k rows.
+ *
+ * ---------------------------------------------------------------- ownership
+ * The caller owns every buffer it passes.  The library never frees a caller
+ * pointer and keeps none after a call returns.  A handle owns its device
+ * workspace (grown on demand, freed by bmlp_destroy).
+ *
+ * ---------------------------------------------------------------- streams
+ * `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ * work of a call is ordered on that stream.  Calls that iterate to a fixpoint
+ * read a one-word flag back each iteration and therefore return with the
+ * result complete; the element-wise, packing and single-product calls are
+ * asynchronous on the stream.
+ *
+ * ---------------------------------------------------------------- errors
+ * Every call returns a bmlp_status.  No C++ exception crosses the ABI.  On
+ * error the outputs are unspecified, no other caller memory is written, and
+ * bmlp_last_error() (thread-local, valid until the next call on the same
+ * thread) describes the failure.  Device faults surface as BMLP_EDEVICE.
+ * A handle must not be used by two threads at once.
+ */
+#ifndef BMLP_H
+#define BMLP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bmlp_ctx *bmlp_handle;
+
+typedef enum {
+  BMLP_OK = 0,
+  BMLP_EINVAL = -1,  /* null pointer, negative size, ld too small, bad option, index out of range */
+  BMLP_EALIGN = -2,  /* pointer not aligned (8 bytes for bit matrices, 4 for int32 arrays) */
+  BMLP_EALIAS = -3,  /* an output overlaps an input */
+  BMLP_EPAD = -4,    /* nonzero padding bits in an input (opts->check_padding) */
+  BMLP_ENOMEM = -5,  /* workspace allocation failed or would exceed opts->workspace_limit */
+  BMLP_EDEVICE = -6, /* HIP runtime error or device fault */
+  BMLP_EITER = -7,   /* iteration cap exceeded (Appendix C, Propositions 1-2); indicates a bug */
+  BMLP_EMODEL = -8   /* dispatcher model file missing, corrupt or incompatible */
+} bmlp_status;
+
+/* Kernel families ("arms").  Every arm returns identical bits. */
+typedef enum {
+  BMLP_ARM_AUTO = -1,
+  BMLP_ARM_PRODUCT_VALU = 0,  /* bit-packed product: LDS-staged 64-bit words, wave AND/OR */
+  BMLP_ARM_PRODUCT_MFMA = 1,  /* int8 matrix-core product, int32 accumulate, > 0 threshold */
+  BMLP_ARM_SMP_DENSE = 2,     /* selection by repeated dense products (semi-naive delta . R1) */
+  BMLP_ARM_SMP_SPARSE = 3,    /* selection by sparse-frontier expansion, whole fixpoint per row in one launch */
+  BMLP_ARM_SMP_CLOSURE = 4,   /* selection as V . R1+ after BMLP-RMS (closure reuse, Section 4) */
+  BMLP_ARM_COMPOSE_RMS = 5,   /* compose: Rs+ by BMLP-RMS, then P = Rb | Rs+ . Rb */
+  BMLP_ARM_COMPOSE_SEMINAIVE = 6 /* compose: P = Rb; delta' = (Rs . delta) & ~P until empty */
+} bmlp_arm;
+
+typedef enum {
+  BMLP_DISPATCH_PLAIN = 0,   /* fixed schedule */
+  BMLP_DISPATCH_LEARNED = 1, /* learned dispatcher (falls back to plain without a model) */
+  BMLP_DISPATCH_FORCED = 2   /* use the arms given in the options */
+} bmlp_dispatch;
+
+typedef struct {
+  uint32_t size;          /* sizeof(bmlp_opts); set by bmlp_opts_init */
+  int32_t dispatch;       /* bmlp_dispatch */
+  int32_t product_arm;    /* BMLP_ARM_AUTO, _PRODUCT_VALU or _PRODUCT_MFMA */
+  int32_t smp_arm;        /* BMLP_ARM_AUTO, _SMP_DENSE, _SMP_SPARSE or _SMP_CLOSURE */
+  int32_t compose_arm;    /* BMLP_ARM_AUTO, _COMPOSE_RMS or _COMPOSE_SEMINAIVE */
+  int32_t rms_variant;    /* 0: R <- R | R.R to a fixpoint (default);
+                             1: Algorithm 1 as printed: R = I + R1, square to a fixpoint, times R1 */
+  int32_t smp_reflexive;  /* 0: V . R1+ (the paper's answer, default); 1: V . R1* = V | V . R1+ */
+  int32_t check_padding;  /* nonzero: validate input padding bits (one extra pass) */
+  int64_t workspace_limit;/* bytes of device workspace a call may hold; 0 = unlimited */
+} bmlp_opts;
+
+typedef struct {
+  int32_t iterations;      /* fixpoint rounds (squarings for RMS, rounds for SMP/compose) */
+  int32_t products;        /* Boolean matrix products launched (incl. Algorithm 1's final one) */
+  int32_t arm_trace[64];   /* arm used in each round (first 64 rounds); -1 past the end */
+  int32_t arm;             /* the arm that served the call */
+  int32_t reserved;
+  uint64_t bool_ops;       /* algorithmic Boolean operations: 2*m*k*n per dense (m x k).(k x n) product */
+  uint64_t bytes_moved;    /* algorithmic device bytes read + written */
+  double device_ms;        /* device time of the call (HIP events on the call's stream) */
+  double product_ms;       /* device time inside the product kernels alone (events around each launch) */
+  uint64_t product_bool_ops; /* algorithmic Boolean operations of those product launches */
+} bmlp_stats;
+
+/* ------------------------------------------------------------ handles */
+/* Create a handle on HIP device `device` (made current for the calls).  */
+bmlp_status bmlp_create(bmlp_handle *h, int device);
+/* Release the handle and its workspace.  NULL is accepted. */
+bmlp_status bmlp_destroy(bmlp_handle h);
+/* Thread-local description of the last failure on this thread. */
+const char *bmlp_last_error(void);
+/* Fill *o with defaults: plain dispatch, automatic arms, default variants. */
+void bmlp_opts_init(bmlp_opts *o);
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t bmlp_version(void);
+
+/* ------------------------------------------------------------ facts -> matrices (Section 3.2) */
+/* bits (rows x n, ld) := dense 0/1 bytes (rows x n, row stride ldd >= n); any nonzero byte is 1. */
+bmlp_status bmlp_pack_u8(bmlp_handle h, const uint8_t *dense, int64_t rows, int64_t n, int64_t ldd,
+                         uint64_t *bits, int64_t ld, void *stream);
+/* bits (rows x n, ld) := the m facts (row[e], col[e]) (int32 device arrays; duplicates allowed).
+   An index outside [0,rows) x [0,n) gives BMLP_EINVAL.  Synchronises the stream (error check). */
+bmlp_status bmlp_pack_coo(bmlp_handle h, const int32_t *row, const int32_t *col, int64_t m, int64_t rows,
+                          int64_t n, uint64_t *bits, int64_t ld, void *stream);
+/* dense (rows x n bytes, stride ldd) := bits; the decoding of a matrix back into facts. */
+bmlp_status bmlp_unpack_u8(bmlp_handle h, const uint64_t *bits, int64_t rows, int64_t n, int64_t ld,
+                           uint8_t *dense, int64_t ldd, void *stream);
+
+/* ------------------------------------------------------------ operators (Section 2, Section 4) */
+/* C = A + B (element-wise OR).  C may equal A or B. */
+bmlp_status bmlp_or(bmlp_handle h, const uint64_t *A, const uint64_t *B, uint64_t *C, int64_t rows, int64_t n,
+                    int64_t ld, void *stream);
+/* C = A AND B (element-wise).  C may equal A or B. */
+bmlp_status bmlp_and(bmlp_handle h, const uint64_t *A, const uint64_t *B, uint64_t *C, int64_t rows, int64_t n,
+                     int64_t ld, void *stream);
+/* C = A AND NOT B (element-wise difference).  C may equal A or B. */
+bmlp_status bmlp_andnot(bmlp_handle h, const uint64_t *A, const uint64_t *B, uint64_t *C, int64_t rows, int64_t n,
+                        int64_t ld, void *stream);
+/* C = NEG(A): every bit of the rows x n matrix flipped; padding stays 0 (Section 3.4, Fig. 3). */
+bmlp_status bmlp_not(bmlp_handle h, const uint64_t *A, uint64_t *C, int64_t rows, int64_t n, int64_t ld,
+                     void *stream);
+/* AT (cols x rows, ldat) = TRANSP(A) (rows x cols, lda): swaps a relation's arguments.
+   AT must not overlap A. */
+bmlp_status bmlp_transpose(bmlp_handle h, const uint64_t *A, int64_t rows, int64_t cols, int64_t lda,
+                           uint64_t *AT, int64_t ldat, void *stream);
+/* C = Cold + A x B over the Boolean semiring (Section 2); Cold may be NULL (then C = A x B) and may
+   equal C.  A: m x kdim (lda), B: kdim x n (ldb), C: m x n (ldc).  C must not overlap A or B.
+   opts may be NULL (defaults); opts->product_arm selects the kernel. */
+bmlp_status bmlp_product(bmlp_handle h, const uint64_t *A, int64_t lda, const uint64_t *B, int64_t ldb,
+                         const uint64_t *Cold, uint64_t *C, int64_t ldc, int64_t m, int64_t kdim, int64_t n,
+                         const bmlp_opts *opts, void *stream, bmlp_stats *stats);
+
+/* ------------------------------------------------------------ the BMLP algorithms */
+/* BMLP-RMS (Algorithm 1; Eq. 1 fixed point): Rstar = R1+ = sum_{k>=1} R1^k, i.e. Rstar_ij = 1 iff
+   a path of length >= 1 leads from i to j.  R1, Rstar: n x n, leading dimension ld.  Rstar must
+   not overlap R1.  The default variant iterates R <- R + R x R from R1 (ceil(log2 L)+1 products,
+   L the longest shortest path); variant 1 steps Algorithm 1 as printed.  Same bits either way. */
+bmlp_status bmlp_rms(bmlp_handle h, const uint64_t *R1, uint64_t *Rstar, int64_t n, int64_t ld,
+                     const bmlp_opts *opts, void *stream, bmlp_stats *stats);
+/* BMLP-SMP (Eq. 5; Algorithm 2): Vstar = V x R1+ row by row, the answers of the k partially
+   grounded queries whose constants are the set bits of each row of V (a row with several bits
+   answers the union).  V, Vstar: k x n (ldv); R1: n x n (ld).  With opts->smp_reflexive the answer
+   is V x R1* = V + V x R1+.  Vstar must not overlap V or R1. */
+bmlp_status bmlp_smp(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, const uint64_t *V,
+                     uint64_t *Vstar, int64_t k, int64_t ldv, const bmlp_opts *opts, void *stream,
+                     bmlp_stats *stats);
+/* General linear recursion over binary predicates (Theorem 1): the least model of
+       p(X,Y) <- b(X,Y).    p(X,Y) <- s(X,Z), p(Z,Y).
+   as P = Rs* x Rb, the least P with P = Rb + Rs x P.  Rbase, Rstep, P: n x n (ld).  P must not
+   overlap Rbase or Rstep.  compose_linear(R1, R1) = rms(R1). */
+bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t *Rbase, const uint64_t *Rstep, uint64_t *P,
+                                int64_t n, int64_t ld, const bmlp_opts *opts, void *stream, bmlp_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMLP_H */

@@ -1,0 +1,290 @@
+"""Python binding of libbmlp (Boolean Matrix Logic Programming on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libbmlp.so`` behind the C ABI declared in ``include/bmlp.h``.
+PyTorch supplies device memory (``torch.int64`` tensors hold the uint64 bit
+words) and the HIP stream (``torch.cuda.current_stream()``).  There is no
+fallback: if the library is missing, every call raises.
+
+Bit matrices are 2-D ``torch.int64`` CUDA tensors of shape ``(rows, ld)``,
+row-major, column j of a row at bit ``j & 63`` of word ``j >> 6``.  The number
+of columns ``n`` is passed explicitly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbmlp.so")
+
+OK, EINVAL, EALIGN, EALIAS, EPAD, ENOMEM, EDEVICE, EITER, EMODEL = 0, -1, -2, -3, -4, -5, -6, -7, -8
+STATUS_NAMES = {0: "BMLP_OK", -1: "BMLP_EINVAL", -2: "BMLP_EALIGN", -3: "BMLP_EALIAS", -4: "BMLP_EPAD",
+                -5: "BMLP_ENOMEM", -6: "BMLP_EDEVICE", -7: "BMLP_EITER", -8: "BMLP_EMODEL"}
+
+ARM_AUTO = -1
+ARM_PRODUCT_VALU, ARM_PRODUCT_MFMA = 0, 1
+ARM_SMP_DENSE, ARM_SMP_SPARSE, ARM_SMP_CLOSURE = 2, 3, 4
+ARM_COMPOSE_RMS, ARM_COMPOSE_SEMINAIVE = 5, 6
+DISPATCH_PLAIN, DISPATCH_LEARNED, DISPATCH_FORCED = 0, 1, 2
+
+EXPORTS = [
+    "bmlp_create", "bmlp_destroy", "bmlp_last_error", "bmlp_opts_init", "bmlp_version",
+    "bmlp_pack_u8", "bmlp_pack_coo", "bmlp_unpack_u8",
+    "bmlp_or", "bmlp_and", "bmlp_andnot", "bmlp_not", "bmlp_transpose", "bmlp_product",
+    "bmlp_rms", "bmlp_smp", "bmlp_compose_linear",
+]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("dispatch", ctypes.c_int32), ("product_arm", ctypes.c_int32),
+                ("smp_arm", ctypes.c_int32), ("compose_arm", ctypes.c_int32), ("rms_variant", ctypes.c_int32),
+                ("smp_reflexive", ctypes.c_int32), ("check_padding", ctypes.c_int32),
+                ("workspace_limit", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("products", ctypes.c_int32), ("arm_trace", ctypes.c_int32 * 64),
+                ("arm", ctypes.c_int32), ("reserved", ctypes.c_int32), ("bool_ops", ctypes.c_uint64),
+                ("bytes_moved", ctypes.c_uint64), ("device_ms", ctypes.c_double), ("product_ms", ctypes.c_double),
+                ("product_bool_ops", ctypes.c_uint64)]
+
+    def as_dict(self):
+        tr = [int(a) for a in self.arm_trace if a != -1]
+        return {"iterations": int(self.iterations), "products": int(self.products), "arm": int(self.arm),
+                "arm_trace": tr, "bool_ops": int(self.bool_ops), "bytes_moved": int(self.bytes_moved),
+                "device_ms": float(self.device_ms), "product_ms": float(self.product_ms),
+                "product_bool_ops": int(self.product_bool_ops)}
+
+
+class BmlpError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+_lib = None
+
+
+def lib():
+    """Load libbmlp.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2408_10369_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    P = ctypes.POINTER
+    L.bmlp_create.argtypes = [P(vp), i32]
+    L.bmlp_destroy.argtypes = [vp]
+    L.bmlp_last_error.restype = ctypes.c_char_p
+    L.bmlp_last_error.argtypes = []
+    L.bmlp_opts_init.argtypes = [P(Opts)]
+    L.bmlp_opts_init.restype = None
+    L.bmlp_version.restype = ctypes.c_int32
+    L.bmlp_pack_u8.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
+    L.bmlp_pack_coo.argtypes = [vp, vp, vp, i64, i64, i64, vp, i64, vp]
+    L.bmlp_unpack_u8.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
+    for f in (L.bmlp_or, L.bmlp_and, L.bmlp_andnot):
+        f.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp]
+    L.bmlp_not.argtypes = [vp, vp, vp, i64, i64, i64, vp]
+    L.bmlp_transpose.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
+    L.bmlp_product.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, i64, i64, i64, P(Opts), vp, P(Stats)]
+    L.bmlp_rms.argtypes = [vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
+    L.bmlp_smp.argtypes = [vp, vp, i64, i64, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
+    L.bmlp_compose_linear.argtypes = [vp, vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("bmlp_last_error", "bmlp_opts_init", "bmlp_version"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def words(n: int) -> int:
+    return (n + 63) // 64
+
+
+def make_opts(**kw) -> Opts:
+    o = Opts()
+    lib().bmlp_opts_init(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, int(v))
+    return o
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise BmlpError(rc, lib().bmlp_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _bits_shape(t, rows=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.int64 and t.dim() == 2 and t.is_cuda):
+        raise TypeError("bit matrices are 2-D torch.int64 CUDA tensors (rows, ld)")
+    if not t.is_contiguous():
+        raise ValueError("bit matrix must be contiguous")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"expected {rows} rows, got {t.shape[0]}")
+    return t.shape[0], t.shape[1]
+
+
+class Context:
+    """A libbmlp handle bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.bmlp_create(ctypes.byref(h), int(device)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bmlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -------------------------------------------------------------- allocation helpers
+    def zeros(self, rows: int, n: int, ld: int | None = None):
+        import torch
+        ld = ld if ld is not None else max(words(n), 1)
+        return torch.zeros((rows, ld), dtype=torch.int64, device=f"cuda:{self.device}")
+
+    # -------------------------------------------------------------- facts -> matrices
+    def pack_coo(self, row, col, rows: int, n: int, ld: int | None = None, out=None, stream=None):
+        import torch
+        row = row.to(device=f"cuda:{self.device}", dtype=torch.int32).contiguous()
+        col = col.to(device=f"cuda:{self.device}", dtype=torch.int32).contiguous()
+        if out is None:
+            out = self.zeros(rows, n, ld)
+        _bits_shape(out, rows)
+        _check(lib().bmlp_pack_coo(self._h, _ptr(row), _ptr(col), row.numel(), rows, n, _ptr(out),
+                                   out.shape[1], _stream(stream)))
+        return out
+
+    def pack_u8(self, dense, ld: int | None = None, out=None, stream=None):
+        rows, n = dense.shape
+        if out is None:
+            out = self.zeros(rows, n, ld)
+        _check(lib().bmlp_pack_u8(self._h, _ptr(dense), rows, n, dense.stride(0), _ptr(out), out.shape[1],
+                                  _stream(stream)))
+        return out
+
+    def unpack_u8(self, bits, n: int, stream=None):
+        import torch
+        rows, ld = _bits_shape(bits)
+        out = torch.empty((rows, n), dtype=torch.uint8, device=bits.device)
+        _check(lib().bmlp_unpack_u8(self._h, _ptr(bits), rows, n, ld, _ptr(out), n, _stream(stream)))
+        return out
+
+    # -------------------------------------------------------------- operators
+    def _ew(self, fn, A, B, n, out, stream):
+        rows, ld = _bits_shape(A)
+        if B is not None:
+            _bits_shape(B, rows)
+        if out is None:
+            out = self.zeros(rows, n, ld)
+        if B is None:
+            _check(fn(self._h, _ptr(A), _ptr(out), rows, n, ld, _stream(stream)))
+        else:
+            _check(fn(self._h, _ptr(A), _ptr(B), _ptr(out), rows, n, ld, _stream(stream)))
+        return out
+
+    def or_(self, A, B, n, out=None, stream=None):
+        return self._ew(lib().bmlp_or, A, B, n, out, stream)
+
+    def and_(self, A, B, n, out=None, stream=None):
+        return self._ew(lib().bmlp_and, A, B, n, out, stream)
+
+    def andnot(self, A, B, n, out=None, stream=None):
+        return self._ew(lib().bmlp_andnot, A, B, n, out, stream)
+
+    def not_(self, A, n, out=None, stream=None):
+        return self._ew(lib().bmlp_not, A, None, n, out, stream)
+
+    def transpose(self, A, cols: int, ldat: int | None = None, out=None, stream=None):
+        rows, lda = _bits_shape(A)
+        if out is None:
+            out = self.zeros(cols, rows, ldat)
+        _check(lib().bmlp_transpose(self._h, _ptr(A), rows, cols, lda, _ptr(out), out.shape[1], _stream(stream)))
+        return out
+
+    def product(self, A, B, kdim: int, n: int, Cold=None, out=None, opts=None, stream=None, stats=None):
+        m, lda = _bits_shape(A)
+        _, ldb = _bits_shape(B, kdim)
+        if out is None:
+            out = self.zeros(m, n)
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_product(self._h, _ptr(A), lda, _ptr(B), ldb, _ptr(Cold), _ptr(out), out.shape[1], m,
+                                  kdim, n, ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                  ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return out
+
+    # -------------------------------------------------------------- BMLP algorithms
+    def rms(self, R1, n: int, out=None, opts=None, stream=None, stats=None):
+        rows, ld = _bits_shape(R1, n)
+        if out is None:
+            out = self.zeros(n, n, ld)
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_rms(self._h, _ptr(R1), _ptr(out), n, ld, ctypes.byref(opts) if opts is not None else None,
+                              _stream(stream), ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return out
+
+    def smp(self, R1, n: int, V, out=None, opts=None, stream=None, stats=None):
+        _, ld = _bits_shape(R1, n)
+        k, ldv = _bits_shape(V)
+        if out is None:
+            out = self.zeros(k, n, ldv)
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_smp(self._h, _ptr(R1), n, ld, _ptr(V), _ptr(out), k, ldv,
+                              ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                              ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return out
+
+    def compose_linear(self, Rbase, Rstep, n: int, out=None, opts=None, stream=None, stats=None):
+        _, ld = _bits_shape(Rbase, n)
+        _bits_shape(Rstep, n)
+        if out is None:
+            out = self.zeros(n, n, ld)
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_compose_linear(self._h, _ptr(Rbase), _ptr(Rstep), _ptr(out), n, ld,
+                                         ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                         ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return out

@@ -1,0 +1,72 @@
+// Internal declarations shared by the HIP translation units of libbmlp.
+// Not part of the public C-ABI (that is include/bmlp.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+
+namespace bmlp {
+
+static inline i64 words_for(i64 n) { return (n + 63) >> 6; }
+
+// ---------------------------------------------------------------- bit kernels
+// All bit matrices: row-major, LSB-first uint64 words, leading dimension in
+// words.  `nw` = ceil(cols/64) words carry data; words in [nw, ld) are padding.
+hipError_t launch_fill_zero(u64* p, i64 nwords, hipStream_t s);
+hipError_t launch_pack_u8(const uint8_t* d, i64 rows, i64 n, i64 ldd, u64* bits, i64 ld, hipStream_t s);
+hipError_t launch_unpack_u8(const u64* bits, i64 rows, i64 n, i64 ld, uint8_t* d, i64 ldd, hipStream_t s);
+// bits must be zeroed beforehand; out-of-range pairs set *bad = 1.
+hipError_t launch_pack_coo(const int32_t* r, const int32_t* c, i64 m, i64 rows, i64 n, u64* bits, i64 ld,
+                           u32* bad, hipStream_t s);
+// elementwise: op 0 = or, 1 = and, 2 = andnot (a & ~b), 3 = not a (padding kept 0), 4 = copy a
+hipError_t launch_ewise(int op, const u64* a, i64 lda, const u64* b, i64 ldb, u64* c, i64 ldc, i64 rows,
+                        i64 n, hipStream_t s);
+// zero the padding words [nw, ld) of every row (nw = ceil(n/64))
+hipError_t launch_zero_pad(u64* a, i64 rows, i64 n, i64 ld, hipStream_t s);
+// set the diagonal bits (i, i) for i < min(rows, n)
+hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s);
+// out (cols x rows) = transpose of in (rows x cols)
+hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out, i64 ldo, hipStream_t s);
+// nonzero padding bits (columns >= n) in any row -> *bad = 1
+hipError_t launch_check_pad(const u64* a, i64 rows, i64 n, i64 ld, u32* bad, hipStream_t s);
+// per-row popcount into deg (int32), plus total into *total (u64, must be zeroed)
+hipError_t launch_row_popcount(const u64* a, i64 rows, i64 n, i64 ld, int32_t* deg, unsigned long long* total,
+                               hipStream_t s);
+// exclusive scan of deg[0..n) into rp[0..n] (int64); single-workgroup
+hipError_t launch_scan_rowptr(const int32_t* deg, i64 n, i64* rp, hipStream_t s);
+// CSR column indices of the set bits of each row (rp from launch_scan_rowptr)
+hipError_t launch_bits_to_csr(const u64* a, i64 rows, i64 n, i64 ld, const i64* rp, int32_t* ci, hipStream_t s);
+
+// ---------------------------------------------------------------- products
+// C = Cold | A.B over the Boolean semiring; D = C & ~Cold (optional);
+// *changed |= 1 when any word of C differs from Cold.
+//   A: M x K bits (lda), B: K x N bits (ldb), Cold/C/D: M x N bits.
+//   Cold may be null (treated as 0).  C may equal Cold (element-wise in place);
+//   A and B must not overlap C or D.  Words >= ceil(N/64) are not written.
+struct GemmArgs {
+  const u64* A; i64 lda;
+  const u64* B; i64 ldb;
+  const u64* Cold; i64 ldco;
+  u64* C; i64 ldc;
+  u64* D; i64 ldd;
+  i64 M, K, N;
+  u32* changed;
+};
+enum ProductKernel { PK_VALU = 0, PK_MFMA = 1 };
+hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s);
+// MFMA int8 arm: needs B transposed (BT: N x K bits, ldbt) instead of B.
+hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s);
+
+// ---------------------------------------------------------------- selection
+// Per-row fixpoint of the semi-naive selection in one launch (one workgroup
+// per query row, bitmaps in LDS): out[r] = V[r] R+ (reflexive: V[r] R*).
+// Needs CSR (rp, ci) of R and the bit rows of R (for dense frontier nodes).
+hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const u64* R, i64 ldr,
+                           i64 n, int reflexive, u64* out, i64 ldo, u32* iters_max, hipStream_t s);
+i64 smp_rows_max_n();
+
+}  // namespace bmlp

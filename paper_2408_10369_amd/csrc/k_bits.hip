@@ -1,0 +1,316 @@
+// Bit-matrix utility kernels: packing (ingest), decoding, element-wise
+// Boolean operators, transpose, padding checks and bits -> CSR.
+//
+// Layout everywhere: row-major, LSB-first uint64 words; column j of row i is
+// bit (j & 63) of word i*ld + (j >> 6).  This is the paper's row encoding of a
+// relation as facts v(i, b_i) whose code b_i has bit j set iff r(c_i, c_j)
+// (Section 3.2), with the code split into 64-bit words.
+#include "bmlp_internal.h"
+
+namespace bmlp {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(i64 work, int per_block = kBlock, int cap = 65536) {
+  i64 g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+__device__ inline u64 last_word_mask(i64 n) {
+  int r = (int)(n & 63);
+  return r == 0 ? ~0ull : ((1ull << r) - 1ull);
+}
+
+__global__ void k_fill_zero(u64* __restrict__ p, i64 nwords) {
+  for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < nwords; i += (i64)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// one wave per output word: lane l looks at byte (row, 64w + l); the wave
+// ballot is the packed word.
+__global__ void k_pack_u8(const uint8_t* __restrict__ d, i64 rows, i64 n, i64 ldd, u64* __restrict__ bits, i64 ld) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  const i64 total = rows * ld;
+  for (i64 wi = wave; wi < total; wi += nwaves) {
+    const i64 row = wi / ld, w = wi - row * ld;
+    const i64 col = w * 64 + lane;
+    int v = 0;
+    if (col < n) v = d[row * ldd + col] != 0;
+    u64 word = __ballot(v);
+    if (lane == 0) bits[wi] = word;
+  }
+}
+
+__global__ void k_unpack_u8(const u64* __restrict__ bits, i64 rows, i64 n, i64 ld, uint8_t* __restrict__ d, i64 ldd) {
+  const i64 total = rows * n;
+  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
+    const i64 row = t / n, col = t - row * n;
+    d[row * ldd + col] = (uint8_t)((bits[row * ld + (col >> 6)] >> (col & 63)) & 1ull);
+  }
+}
+
+__global__ void k_pack_coo(const int32_t* __restrict__ r, const int32_t* __restrict__ c, i64 m, i64 rows, i64 n,
+                           u64* __restrict__ bits, i64 ld, u32* __restrict__ bad) {
+  for (i64 e = blockIdx.x * (i64)blockDim.x + threadIdx.x; e < m; e += (i64)gridDim.x * blockDim.x) {
+    const int32_t i = r[e], j = c[e];
+    if (i < 0 || i >= rows || j < 0 || j >= n) {
+      atomicOr(bad, 1u);
+      continue;
+    }
+    atomicOr((unsigned long long*)&bits[(i64)i * ld + (j >> 6)], 1ull << (j & 63));
+  }
+}
+
+__global__ void k_ewise(int op, const u64* __restrict__ a, i64 lda, const u64* __restrict__ b, i64 ldb,
+                        u64* __restrict__ c, i64 ldc, i64 rows, i64 n) {
+  const i64 nw = (n + 63) >> 6;
+  const i64 total = rows * ldc;
+  const u64 lm = last_word_mask(n);
+  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
+    const i64 row = t / ldc, w = t - row * ldc;
+    u64 v = 0;
+    if (w < nw) {
+      const u64 x = a[row * lda + w];
+      switch (op) {
+        case 0: v = x | b[row * ldb + w]; break;
+        case 1: v = x & b[row * ldb + w]; break;
+        case 2: v = x & ~b[row * ldb + w]; break;
+        case 3: v = ~x; break;
+        default: v = x; break;
+      }
+      if (w == nw - 1) v &= lm;
+    }
+    c[t] = v;
+  }
+}
+
+__global__ void k_zero_pad(u64* __restrict__ a, i64 rows, i64 nw, i64 ld) {
+  const i64 pw = ld - nw;
+  const i64 total = rows * pw;
+  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
+    const i64 row = t / pw, w = nw + (t - row * pw);
+    a[row * ld + w] = 0ull;
+  }
+}
+
+__global__ void k_set_diag(u64* __restrict__ a, i64 ld, i64 cnt) {
+  for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < cnt; i += (i64)gridDim.x * blockDim.x)
+    a[i * ld + (i >> 6)] |= 1ull << (i & 63);
+}
+
+// 64x64 bit-block transpose, one wave per block: lane l holds input row
+// (64 rb + l), word cw; output row (64 cw + j) word rb is the ballot of bit j.
+__global__ void k_transpose(const u64* __restrict__ in, i64 rows, i64 cols, i64 ldi, u64* __restrict__ out, i64 ldo) {
+  const int lane = threadIdx.x & 63;
+  const i64 rblocks = (rows + 63) >> 6, cwords = (cols + 63) >> 6;
+  const i64 nblocks = rblocks * cwords;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 bi = wave; bi < nblocks; bi += nwaves) {
+    const i64 rb = bi / cwords, cw = bi - rb * cwords;
+    const i64 r = rb * 64 + lane;
+    const u64 x = (r < rows) ? in[r * ldi + cw] : 0ull;
+    u64 mine = 0;
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) {
+      const u64 bal = __ballot((int)((x >> j) & 1ull));
+      mine = (lane == j) ? bal : mine;
+    }
+    const i64 orow = cw * 64 + lane;
+    if (orow < cols) out[orow * ldo + rb] = mine;
+  }
+}
+
+__global__ void k_check_pad(const u64* __restrict__ a, i64 rows, i64 n, i64 ld, u32* __restrict__ bad) {
+  const i64 nw = (n + 63) >> 6;
+  const u64 lm = last_word_mask(n);
+  const i64 total = rows * ld;
+  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
+    const i64 w = t % ld;
+    const u64 x = a[t];
+    const bool b = (w >= nw) ? (x != 0) : (w == nw - 1 && (x & ~lm) != 0);
+    if (b) atomicOr(bad, 1u);
+  }
+}
+
+__device__ inline int wave_reduce_add(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline int wave_excl_scan(int v, int lane) {
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x - v;
+}
+
+// one wave per row
+__global__ void k_row_popcount(const u64* __restrict__ a, i64 rows, i64 n, i64 ld, int32_t* __restrict__ deg,
+                               unsigned long long* __restrict__ total) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  const i64 nw = (n + 63) >> 6;
+  for (i64 row = wave; row < rows; row += nwaves) {
+    int c = 0;
+    for (i64 w = lane; w < nw; w += 64) c += __popcll(a[row * ld + w]);
+    c = wave_reduce_add(c);
+    if (lane == 0) {
+      deg[row] = c;
+      if (total) atomicAdd(total, (unsigned long long)c);
+    }
+  }
+}
+
+// single workgroup exclusive scan: rp[0] = 0, rp[i+1] = rp[i] + deg[i]
+__global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict__ deg, i64 n, i64* __restrict__ rp) {
+  __shared__ i64 part[1024];
+  const int t = threadIdx.x;
+  const i64 chunk = (n + 1023) / 1024;
+  const i64 lo = t * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
+  i64 s = 0;
+  for (i64 i = lo; i < hi; ++i) s += deg[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    i64 v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  i64 run = part[t] - s;
+  for (i64 i = lo; i < hi; ++i) {
+    rp[i] = run;
+    run += deg[i];
+  }
+  if (t == 1023) rp[n] = part[1023];
+}
+
+// one wave per row; lanes own consecutive words
+__global__ void k_bits_to_csr(const u64* __restrict__ a, i64 rows, i64 n, i64 ld, const i64* __restrict__ rp,
+                              int32_t* __restrict__ ci) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  const i64 nw = (n + 63) >> 6;
+  for (i64 row = wave; row < rows; row += nwaves) {
+    i64 base = rp[row];
+    for (i64 w0 = 0; w0 < nw; w0 += 64) {
+      const i64 w = w0 + lane;
+      u64 x = (w < nw) ? a[row * ld + w] : 0ull;
+      const int pc = __popcll(x);
+      const int ex = wave_excl_scan(pc, lane);
+      const int tot = __shfl(ex + pc, 63, 64);
+      i64 pos = base + ex;
+      while (x) {
+        const int b = __ffsll((unsigned long long)x) - 1;
+        ci[pos++] = (int32_t)(w * 64 + b);
+        x &= x - 1;
+      }
+      base += tot;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(u64* p, i64 nwords, hipStream_t s) {
+  if (nwords <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(nwords, kBlock, 16384)), dim3(kBlock), 0, s, p, nwords);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_u8(const uint8_t* d, i64 rows, i64 n, i64 ldd, u64* bits, i64 ld, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_u8, dim3(grid_for(rows * ld * 64, kBlock, 16384)), dim3(kBlock), 0, s, d, rows, n, ldd,
+                     bits, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_u8(const u64* bits, i64 rows, i64 n, i64 ld, uint8_t* d, i64 ldd, hipStream_t s) {
+  if (rows <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack_u8, dim3(grid_for(rows * n, kBlock, 16384)), dim3(kBlock), 0, s, bits, rows, n, ld, d,
+                     ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_coo(const int32_t* r, const int32_t* c, i64 m, i64 rows, i64 n, u64* bits, i64 ld, u32* bad,
+                           hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_coo, dim3(grid_for(m, kBlock, 16384)), dim3(kBlock), 0, s, r, c, m, rows, n, bits, ld,
+                     bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_ewise(int op, const u64* a, i64 lda, const u64* b, i64 ldb, u64* c, i64 ldc, i64 rows, i64 n,
+                        hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ewise, dim3(grid_for(rows * ldc, kBlock, 16384)), dim3(kBlock), 0, s, op, a, lda, b, ldb, c,
+                     ldc, rows, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_pad(u64* a, i64 rows, i64 n, i64 ld, hipStream_t s) {
+  const i64 nw = words_for(n);
+  if (rows <= 0 || ld <= nw) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_pad, dim3(grid_for(rows * (ld - nw), kBlock, 16384)), dim3(kBlock), 0, s, a, rows, nw, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s) {
+  const i64 cnt = rows < n ? rows : n;
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_diag, dim3(grid_for(cnt)), dim3(kBlock), 0, s, a, ld, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out, i64 ldo, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const i64 nwo = words_for(rows);
+  if (ldo > nwo) {
+    hipError_t e = launch_fill_zero(out, cols * ldo, s);
+    if (e != hipSuccess) return e;
+  }
+  const i64 blocks = words_for(rows) * words_for(cols);
+  hipLaunchKernelGGL(k_transpose, dim3(grid_for(blocks * 64, kBlock, 16384)), dim3(kBlock), 0, s, in, rows, cols, ldi,
+                     out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_pad(const u64* a, i64 rows, i64 n, i64 ld, u32* bad, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_pad, dim3(grid_for(rows * ld, kBlock, 16384)), dim3(kBlock), 0, s, a, rows, n, ld, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_popcount(const u64* a, i64 rows, i64 n, i64 ld, int32_t* deg, unsigned long long* total,
+                               hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_popcount, dim3(grid_for(rows * 64, kBlock, 16384)), dim3(kBlock), 0, s, a, rows, n, ld, deg,
+                     total);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_rowptr(const int32_t* deg, i64 n, i64* rp, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_rowptr, dim3(1), dim3(1024), 0, s, deg, n, rp);
+  return hipGetLastError();
+}
+
+hipError_t launch_bits_to_csr(const u64* a, i64 rows, i64 n, i64 ld, const i64* rp, int32_t* ci, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bits_to_csr, dim3(grid_for(rows * 64, kBlock, 16384)), dim3(kBlock), 0, s, a, rows, n, ld, rp,
+                     ci);
+  return hipGetLastError();
+}
+
+}  // namespace bmlp

@@ -1,0 +1,140 @@
+// Selective matrix product (BMLP-SMP, Section 3.3 Eq. 5 and Algorithm 2),
+// sparse-frontier arm.  One workgroup owns one query row r and runs the whole
+// fixpoint for it in a single launch, with three n-bit bitmaps in LDS:
+//
+//   vis : nodes reached so far by paths of length >= 1 from the row's sources
+//   fr  : the frontier (bits new in the last round; the sources at the start)
+//   nxt : successors of the frontier in the current round
+//
+// Each round is one semi-naive step of the selection: nxt = fr . R1,
+// fr = nxt & ~vis, vis |= fr.  It stops when fr is empty, which is the
+// "v* = v'" test of Algorithm 2 (the iterates are monotone).  Starting the
+// frontier at the sources and never marking them visited up front yields
+// exactly v R1+, so no final product with R1 is needed; the reflexive mode
+// adds the sources at the end (v R1*).
+//
+// Frontier nodes of low out-degree are expanded by the thread that finds them
+// through the CSR successor list (LDS atomic ORs).  High-degree nodes are
+// queued and expanded by the whole workgroup, either through CSR or, when the
+// node's row is dense, by OR-ing its bit row of R1 word by word.
+#include "bmlp_internal.h"
+
+namespace bmlp {
+
+namespace {
+
+constexpr int kSmpThreads = 256;
+constexpr int kHubDeg = 48;       // expand cooperatively above this out-degree
+constexpr int kHubCap = 512;      // LDS queue of cooperative nodes per round
+constexpr i64 kMaxLdsWords = 6144;  // 3 bitmaps x 2048 words = 48 KiB (n <= 131072)
+
+__global__ void __launch_bounds__(kSmpThreads)
+k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp, const int32_t* __restrict__ ci,
+           const u64* __restrict__ R, i64 ldr, i64 n, int reflexive, u64* __restrict__ out, i64 ldo,
+           u32* __restrict__ iters_max) {
+  extern __shared__ u64 smem[];
+  __shared__ int32_t hubs[kHubCap];
+  __shared__ int nhubs;
+  const i64 nw = (n + 63) >> 6;
+  u64* vis = smem;
+  u64* fr = smem + nw;
+  u64* nxt = smem + 2 * nw;
+  u32* nxt32 = (u32*)nxt;
+  const int t = threadIdx.x;
+  // columns >= n never enter a bitmap, whatever the padding bits of the inputs hold
+  const u64 last_mask = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
+
+  for (i64 row = blockIdx.x; row < k; row += gridDim.x) {
+    for (i64 w = t; w < nw; w += kSmpThreads) {
+      vis[w] = 0ull;
+      fr[w] = V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
+      nxt[w] = 0ull;
+    }
+    if (t == 0) nhubs = 0;
+    __syncthreads();
+    u32 rounds = 0;
+    for (;;) {
+      ++rounds;
+      // expand the frontier
+      for (i64 w = t; w < nw; w += kSmpThreads) {
+        u64 x = fr[w];
+        while (x) {
+          const int b = __ffsll((unsigned long long)x) - 1;
+          x &= x - 1;
+          const i64 u = w * 64 + b;
+          const i64 e0 = rp[u], e1 = rp[u + 1];
+          if (e1 - e0 > kHubDeg) {
+            const int slot = atomicAdd(&nhubs, 1);
+            if (slot < kHubCap) {
+              hubs[slot] = (int32_t)u;
+              continue;
+            }
+          }
+          for (i64 e = e0; e < e1; ++e) {
+            const int32_t v = ci[e];
+            atomicOr(&nxt32[v >> 5], 1u << (v & 31));
+          }
+        }
+      }
+      __syncthreads();
+      const int nh = nhubs < kHubCap ? nhubs : kHubCap;
+      for (int h = 0; h < nh; ++h) {
+        const i64 u = hubs[h];
+        const i64 e0 = rp[u], e1 = rp[u + 1];
+        if (R && (e1 - e0) * 2 > nw) {
+          for (i64 w = t; w < nw; w += kSmpThreads) {
+            const u64 x = R[u * ldr + w];
+            if (x) {
+              atomicOr(&nxt32[2 * w], (u32)x);
+              atomicOr(&nxt32[2 * w + 1], (u32)(x >> 32));
+            }
+          }
+        } else {
+          for (i64 e = e0 + t; e < e1; e += kSmpThreads) {
+            const int32_t v = ci[e];
+            atomicOr(&nxt32[v >> 5], 1u << (v & 31));
+          }
+        }
+      }
+      __syncthreads();
+      // fr = nxt & ~vis ; vis |= fr ; nxt = 0
+      int any = 0;
+      for (i64 w = t; w < nw; w += kSmpThreads) {
+        const u64 nv = nxt[w] & ~vis[w] & (w == nw - 1 ? last_mask : ~0ull);
+        vis[w] |= nv;
+        fr[w] = nv;
+        nxt[w] = 0ull;
+        any |= (nv != 0ull);
+      }
+      if (t == 0) nhubs = 0;
+      if (!__syncthreads_or(any)) break;
+      if ((i64)rounds > n + 1) break;  // unreachable for a correct monotone iteration
+    }
+    for (i64 w = t; w < nw; w += kSmpThreads) {
+      u64 v = vis[w];
+      if (reflexive) v |= V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
+      out[row * ldo + w] = v;
+    }
+    for (i64 w = nw + t; w < ldo; w += kSmpThreads) out[row * ldo + w] = 0ull;
+    if (t == 0 && iters_max) atomicMax(iters_max, rounds);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+i64 smp_rows_max_n() { return (kMaxLdsWords / 3) * 64; }
+
+hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const u64* R, i64 ldr,
+                           i64 n, int reflexive, u64* out, i64 ldo, u32* iters_max, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  const i64 nw = words_for(n);
+  if (3 * nw > kMaxLdsWords) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(3 * nw) * sizeof(u64);
+  const unsigned grid = (unsigned)(k < 65535 ? k : 65535);
+  hipLaunchKernelGGL(k_smp_rows, dim3(grid), dim3(kSmpThreads), lds, s, V, ldv, k, rp, ci, R, ldr, n, reflexive, out,
+                     ldo, iters_max);
+  return hipGetLastError();
+}
+
+}  // namespace bmlp

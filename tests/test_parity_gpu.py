@@ -1,0 +1,349 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+bit-exact, on seeded inputs.  Sizes span several tiles and ragged tails; the
+n = 16,384 density-sweep graphs are checked on sampled rows."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle import boolops
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2408_10369_amd as B  # noqa: E402
+
+ARMS_SMP = [B.ARM_SMP_DENSE, B.ARM_SMP_SPARSE, B.ARM_SMP_CLOSURE]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def dev(bits):
+    return torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def gpu_pack(ctx, n, s, d, ld=None):
+    return ctx.pack_coo(torch.as_tensor(np.asarray(s, np.int32)), torch.as_tensor(np.asarray(d, np.int32)), n, n, ld)
+
+
+def rand_graph(rng, n, p):
+    A = (rng.random((n, n)) < p).astype(np.uint8)
+    s, d = np.nonzero(A)
+    return A, s.astype(np.int32), d.astype(np.int32)
+
+
+def forced(**kw):
+    return B.make_opts(dispatch=B.DISPATCH_FORCED, **kw)
+
+
+SIZES = [1, 2, 3, 63, 64, 65, 127, 129, 200, 513, 1000, 1100]
+
+
+# ----------------------------------------------------------------- packing and operators
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 130, 1000])
+def test_pack_coo_and_u8(ctx, n):
+    rng = np.random.default_rng(n)
+    A, s, d = rand_graph(rng, n, 0.05)
+    for ld in (max(boolops.words(n), 1), boolops.words(n) + 3):
+        want = boolops.to_bits(A, ld=ld)
+        assert np.array_equal(host(gpu_pack(ctx, n, s, d, ld)), want)
+        got = host(ctx.pack_u8(torch.from_numpy(A).cuda(), ld=ld))
+        assert np.array_equal(got, want)
+        unp = ctx.unpack_u8(dev(want), n)
+        assert np.array_equal(unp.cpu().numpy(), A)
+
+
+@pytest.mark.parametrize("n", [1, 64, 65, 200, 1000])
+def test_elementwise_and_transpose(ctx, n):
+    rng = np.random.default_rng(10 + n)
+    rows = n + 7
+    X = (rng.random((rows, n)) < 0.3).astype(np.uint8)
+    Y = (rng.random((rows, n)) < 0.3).astype(np.uint8)
+    ld = boolops.words(n) + 1
+    bx, by = dev(boolops.to_bits(X, ld)), dev(boolops.to_bits(Y, ld))
+    assert np.array_equal(host(ctx.or_(bx, by, n)), boolops.to_bits(boolops.add(X, Y), ld))
+    assert np.array_equal(host(ctx.and_(bx, by, n)), boolops.to_bits(boolops.land(X, Y), ld))
+    assert np.array_equal(host(ctx.andnot(bx, by, n)), boolops.to_bits(X & (1 - Y), ld))
+    assert np.array_equal(host(ctx.not_(bx, n)), boolops.to_bits(boolops.neg(X), ld))
+    for ldt in (boolops.words(rows), boolops.words(rows) + 2):
+        got = host(ctx.transpose(bx, n, ldat=ldt))
+        assert np.array_equal(got, boolops.to_bits(boolops.transp(X), ldt))
+
+
+@pytest.mark.parametrize("arm", [B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 70, 3), (64, 64, 64), (65, 129, 200), (130, 1000, 70),
+                                   (300, 77, 4100), (1000, 1000, 1000)])
+def test_product(ctx, arm, shape):
+    m, k, n = shape
+    rng = np.random.default_rng(m * 7 + k * 3 + n)
+    A = (rng.random((m, k)) < 0.02).astype(np.uint8)
+    Bm = (rng.random((k, n)) < 0.05).astype(np.uint8)
+    Co = (rng.random((m, n)) < 0.01).astype(np.uint8)
+    o = forced(product_arm=arm)
+    ba, bb = dev(boolops.to_bits(A)), dev(boolops.to_bits(Bm))
+    got = host(ctx.product(ba, bb, k, n, opts=o))
+    assert np.array_equal(got, boolops.to_bits(boolops.mul(A, Bm)))
+    bc = dev(boolops.to_bits(Co))
+    got = host(ctx.product(ba, bb, k, n, Cold=bc, opts=o))
+    assert np.array_equal(got, boolops.to_bits(boolops.add(Co, boolops.mul(A, Bm))))
+    # in place: C = Cold
+    ctx.product(ba, bb, k, n, Cold=bc, out=bc, opts=o)
+    assert np.array_equal(host(bc), got)
+    # dense operands
+    A2 = (rng.random((m, k)) < 0.5).astype(np.uint8)
+    B2 = (rng.random((k, n)) < 0.5).astype(np.uint8)
+    got = host(ctx.product(dev(boolops.to_bits(A2)), dev(boolops.to_bits(B2)), k, n, opts=o))
+    assert np.array_equal(got, boolops.to_bits(boolops.mul(A2, B2)))
+
+
+# ----------------------------------------------------------------- RMS
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("n", SIZES)
+def test_rms_random(ctx, n, variant):
+    rng = np.random.default_rng(1000 + n)
+    for p in (1.5 / n, 4.0 / n, 0.3):
+        A, s, d = rand_graph(rng, n, min(p, 1.0))
+        R = gpu_pack(ctx, n, s, d)
+        st = {}
+        got = host(ctx.rms(R, n, opts=B.make_opts(rms_variant=variant), stats=st))
+        want = oracle.closure_rows(n, s, d)
+        assert np.array_equal(got, want), (n, p, variant)
+        assert st["products"] >= 1 and st["iterations"] <= math.ceil(math.log2(max(n, 2))) + 2
+
+
+def test_rms_first_config(ctx):
+    n, s, d, _ = gen.c1()
+    R = gpu_pack(ctx, n, s, d)
+    for variant in (0, 1):
+        got = host(ctx.rms(R, n, opts=B.make_opts(rms_variant=variant)))
+        assert np.array_equal(got, oracle.closure_rows(n, s, d))
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 9, 17, 100, 1000, 1025])
+def test_rms_path_graph_loop_counts(ctx, n):
+    s, d = gen.path_graph(n)
+    R = gpu_pack(ctx, n, s, d)
+    st = {}
+    got = host(ctx.rms(R, n, stats=st))
+    assert np.array_equal(got, oracle.closure_rows(n, s, d))
+    assert st["products"] == math.ceil(math.log2(n - 1)) + 1
+    st1 = {}
+    ctx.rms(R, n, opts=B.make_opts(rms_variant=1), stats=st1)
+    assert st1["iterations"] == math.ceil(math.log2(n - 1)) + 1
+    assert st1["products"] == st1["iterations"] + 1
+
+
+def test_rms_special_graphs(ctx):
+    for n in (1, 64, 65, 300):
+        cs, cd = gen.cycle_graph(n)
+        got = host(ctx.rms(gpu_pack(ctx, n, cs, cd), n))
+        assert np.array_equal(got, boolops.to_bits(np.ones((n, n), np.uint8)))
+        got = host(ctx.rms(ctx.zeros(n, n), n))
+        assert not got.any()
+        i = n // 2
+        got = host(ctx.rms(gpu_pack(ctx, n, [i], [i]), n))
+        want = np.zeros((n, n), np.uint8)
+        want[i, i] = 1
+        assert np.array_equal(got, boolops.to_bits(want))
+
+
+def test_rms_padding_words_zeroed(ctx):
+    n = 100
+    rng = np.random.default_rng(3)
+    A, s, d = rand_graph(rng, n, 0.03)
+    ld = boolops.words(n) + 5
+    R = gpu_pack(ctx, n, s, d, ld)
+    out = torch.full((n, ld), -1, dtype=torch.int64, device="cuda")
+    ctx.rms(R, n, out=out)
+    assert np.array_equal(host(out), oracle.closure_rows(n, s, d, ld=ld))
+
+
+# ----------------------------------------------------------------- SMP
+@pytest.mark.parametrize("reflexive", [0, 1])
+@pytest.mark.parametrize("arm", ARMS_SMP)
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 129, 700, 2000])
+def test_smp_random(ctx, n, arm, reflexive):
+    rng = np.random.default_rng(2000 + n)
+    for p in (1.2 / n, 5.0 / n):
+        A, s, d = rand_graph(rng, n, min(p, 1.0))
+        k = int(rng.integers(1, 40))
+        V = np.zeros((k, n), np.uint8)
+        V[np.arange(k), rng.integers(0, n, k)] = 1
+        V[: k // 3] |= (rng.random((k // 3, n)) < 0.02).astype(np.uint8)  # some multi-source rows
+        Vb = boolops.to_bits(V)
+        R = gpu_pack(ctx, n, s, d)
+        st = {}
+        got = host(ctx.smp(R, n, dev(Vb), opts=forced(smp_arm=arm, smp_reflexive=reflexive), stats=st))
+        want = oracle.smp(n, s, d, Vb, reflexive=bool(reflexive))
+        assert np.array_equal(got, want), (n, p, arm, reflexive)
+        assert st["arm"] == arm
+
+
+def test_smp_first_config(ctx):
+    n, s, d, srcs = gen.c1()
+    R = gpu_pack(ctx, n, s, d)
+    r, c = gen.query_lists(srcs)
+    V = ctx.pack_coo(torch.as_tensor(r), torch.as_tensor(c), len(srcs), n)
+    want = oracle.smp(n, s, d, host(V))
+    for arm in ARMS_SMP:
+        assert np.array_equal(host(ctx.smp(R, n, V, opts=forced(smp_arm=arm))), want), arm
+
+
+def test_smp_path_rounds(ctx):
+    n = 300
+    s, d = gen.path_graph(n)
+    R = gpu_pack(ctx, n, s, d)
+    V = ctx.pack_coo(torch.tensor([0], dtype=torch.int32), torch.tensor([0], dtype=torch.int32), 1, n)
+    for arm in (B.ARM_SMP_DENSE, B.ARM_SMP_SPARSE):
+        st = {}
+        got = host(ctx.smp(R, n, V, opts=forced(smp_arm=arm), stats=st))
+        want = np.r_[0, np.ones(n - 1, np.uint8)][None, :]
+        assert np.array_equal(got, boolops.to_bits(want))
+        # Algorithm 2 from node 0 of a path runs n rounds; the semi-naive form reaches the same
+        # fixpoint in n - 1 expansions plus the empty one
+        assert st["iterations"] == n
+
+
+def test_smp_hub_node(ctx):
+    # a star with a high out-degree centre exercises the cooperative (hub) expansion and the
+    # dense-row path of the sparse kernel
+    n = 5000
+    hub_s = np.zeros(n - 1, np.int32)
+    hub_d = np.arange(1, n, dtype=np.int32)
+    chain_s = np.arange(1, 200, dtype=np.int32)
+    chain_d = chain_s + 1
+    s = np.r_[hub_s, chain_s, [4999]].astype(np.int32)
+    d = np.r_[hub_d, chain_d, [0]].astype(np.int32)
+    R = gpu_pack(ctx, n, s, d)
+    V = ctx.pack_coo(torch.tensor([0, 1, 2], dtype=torch.int32), torch.tensor([0, 7, 4999], dtype=torch.int32), 3, n)
+    want = oracle.smp(n, s, d, host(V))
+    for arm in ARMS_SMP:
+        assert np.array_equal(host(ctx.smp(R, n, V, opts=forced(smp_arm=arm))), want), arm
+
+
+# ----------------------------------------------------------------- composition
+@pytest.mark.parametrize("arm", [B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE])
+@pytest.mark.parametrize("n", [1, 3, 64, 65, 300, 1000])
+def test_compose_random(ctx, n, arm):
+    rng = np.random.default_rng(3000 + n)
+    for pb, ps in ((0.01, 1.5 / n), (0.002, 3.0 / n), (0.2, 0.01)):
+        Bm, bs, bd = rand_graph(rng, n, min(pb, 1.0))
+        S, ss, sd = rand_graph(rng, n, min(ps, 1.0))
+        got = host(ctx.compose_linear(gpu_pack(ctx, n, bs, bd), gpu_pack(ctx, n, ss, sd), n, opts=forced(compose_arm=arm)))
+        assert np.array_equal(got, oracle.compose_rows(n, bs, bd, ss, sd)), (n, pb, ps, arm)
+
+
+def test_compose_of_same_relation_is_closure(ctx):
+    n, s, d, _ = gen.c1()
+    R = gpu_pack(ctx, n, s, d)
+    for arm in (B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE):
+        got = host(ctx.compose_linear(R, R, n, opts=forced(compose_arm=arm)))
+        assert np.array_equal(got, oracle.closure_rows(n, s, d))
+
+
+def test_isforeign_pipeline(ctx, golden_dir):
+    """The paper's composition example, run entirely through the GPU operators."""
+    path = os.path.join(golden_dir, "isforeign_example.txt")
+    consts, facts = None, {"contains": [], "adjoins": [], "false": []}
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if not line:
+            continue
+        if line[0] == "constants":
+            consts = line[1:]
+        else:
+            facts[line[0]].append(line[1:])
+    idx = {c: i for i, c in enumerate(consts)}
+    n = len(consts)
+
+    def pack(pairs):
+        s = [idx[a] for a, b in pairs]
+        d = [idx[b] for a, b in pairs]
+        return gpu_pack(ctx, n, s, d)
+
+    has_place = ctx.rms(pack(facts["contains"]), n)
+    adj = pack(facts["adjoins"])
+    base = ctx.or_(adj, ctx.transpose(adj, n), n)
+    step = ctx.transpose(has_place, n)
+    for arm in (B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE):
+        ipo = ctx.compose_linear(base, step, n, opts=forced(compose_arm=arm))
+        foreign = ctx.unpack_u8(ctx.not_(ipo, n), n).cpu().numpy()
+        want = np.ones((n, n), np.uint8)
+        for a, b in facts["false"]:
+            want[idx[a], idx[b]] = 0
+        assert np.array_equal(foreign, want)
+
+
+# ----------------------------------------------------------------- full-size density sweep (sampled)
+@pytest.mark.parametrize("pi", [0, 2, 4])
+def test_density_sweep_rms_sampled_rows(ctx, pi):
+    n, s, d = gen.c2(pi)
+    R = gpu_pack(ctx, n, s, d)
+    got = host(ctx.rms(R, n))
+    rng = np.random.default_rng(77 + pi)
+    rows = np.sort(rng.choice(n, 96, replace=False))
+    assert np.array_equal(got[rows], oracle.closure_rows(n, s, d, rows=rows))
+    # R1 is contained in R1+ on every row
+    r1 = host(R)
+    assert not np.any(r1 & ~got)
+
+
+@pytest.mark.parametrize("pi", [0, 2, 4])
+def test_density_sweep_smp(ctx, pi):
+    n, s, d = gen.c2(pi)
+    R = gpu_pack(ctx, n, s, d)
+    srcs = gen.c2_sources(pi, 1)
+    r, c = gen.query_lists(srcs)
+    V = ctx.pack_coo(torch.as_tensor(r), torch.as_tensor(c), len(srcs), n)
+    want = oracle.smp(n, s, d, host(V))
+    for arm in (B.ARM_SMP_DENSE, B.ARM_SMP_SPARSE):
+        assert np.array_equal(host(ctx.smp(R, n, V, opts=forced(smp_arm=arm))), want), arm
+
+
+# ----------------------------------------------------------------- boundary behaviour
+def test_errors(ctx):
+    n = 100
+    R = ctx.zeros(n, n)
+    with pytest.raises(B.BmlpError) as e:
+        ctx.rms(R, n, out=R)
+    assert e.value.status == B.EALIAS
+    bad = torch.zeros((n, 1), dtype=torch.int64, device="cuda")
+    with pytest.raises(B.BmlpError) as e:
+        ctx.rms(bad, n, out=torch.zeros_like(bad))
+    assert e.value.status == B.EINVAL
+    P = ctx.zeros(n, n)
+    P[0, 1] = 1 << 40  # column 104 >= n: a padding bit
+    with pytest.raises(B.BmlpError) as e:
+        ctx.rms(P, n, opts=B.make_opts(check_padding=1))
+    assert e.value.status == B.EPAD
+    with pytest.raises(B.BmlpError) as e:
+        ctx.pack_coo(torch.tensor([0, 5], dtype=torch.int32), torch.tensor([1, n], dtype=torch.int32), n, n)
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.BmlpError) as e:
+        ctx.smp(R, n, ctx.zeros(2, n), opts=forced(smp_arm=B.ARM_COMPOSE_RMS))
+    assert e.value.status == B.EINVAL
+
+
+def test_empty_sizes(ctx):
+    z = torch.zeros((0, 1), dtype=torch.int64, device="cuda")
+    ctx.rms(z, 0, out=torch.zeros_like(z))
+    R = ctx.zeros(10, 10)
+    out = ctx.smp(R, 10, ctx.zeros(0, 10))
+    assert out.shape == (0, 1)
+    V = ctx.zeros(3, 10)
+    assert not host(ctx.smp(R, 10, V)).any()
