@@ -28,6 +28,23 @@ if ROOT not in sys.path:
 
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 32 * 2 / 1e12  # bool-ops/s: 64 lanes x 32 bits x (AND+OR) per CU-clock
 
+# HBM bytes per launch of the product kernel on this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) scaled by the same counters on a plain 256 MiB copy (fetch x2.000, write x1.000); the summary is
+# profiles/k_gemm_valu_er16384_density_sweep.md.  Valid only for the kernel source it was measured on.
+GEMM_TRAFFIC = {"source": "paper_2408_10369_amd/csrc/k_gemm.hip",
+                "sha256": "5ccb7508fd01657d6439160d53dea3f119adddd9bf423655e162c26ec0ba5de9",
+                "bytes_per_launch": 496.6e6}
+
+
+def measured_traffic():
+    import hashlib
+    path = os.path.join(ROOT, GEMM_TRAFFIC["source"])
+    try:
+        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return GEMM_TRAFFIC["bytes_per_launch"] if digest == GEMM_TRAFFIC["sha256"] else None
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -35,7 +52,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=256)
+    ap.add_argument("--cpu-sample-rows", type=int, default=0,
+                    help="bound the oracle's closure rows per graph (0: all rows)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 256 MiB device-to-device copy (scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus %d is not supported "
@@ -51,6 +71,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}))
+        return
     ctx = B.Context(0)
     n = 16384
     graphs = []
@@ -107,7 +136,8 @@ def main():
     achieved_tops = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12 if avg_launch_ms > 0 else 0.0
     roofline = {"bound": "alu", "kernel": "k_gemm_valu (bit-packed Boolean product, RMS squarings)",
                 "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tbool-op/s",
-                "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": None,
+                "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(),
+                "traffic_unit": "HBM bytes per launch",
                 "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": prod["launches"] // args.steps}
 
     cpu = None
@@ -129,7 +159,9 @@ def main():
 
 
 def cpu_baseline(graphs, n, sample_rows):
-    """The oracle (per-source BFS) on a bounded sample of the same workload."""
+    """The oracle (per-source BFS) on the same workload as one step: every
+    closure row of every graph and every SMP query row.  ``sample_rows`` > 0
+    bounds the closure part to that many random rows per graph instead."""
     import numpy as np
 
     import oracle
@@ -141,15 +173,22 @@ def cpu_baseline(graphs, n, sample_rows):
     for g in graphs:
         s = g["s"].cpu().numpy()
         d = g["d"].cpu().numpy()
-        rows = np.sort(rng.choice(n, sample_rows, replace=False))
+        rows = None if sample_rows <= 0 else np.sort(rng.choice(n, sample_rows, replace=False))
         t0 = time.perf_counter()
         oracle.closure_rows(n, s, d, rows=rows)
         t_total += time.perf_counter() - t0
-        rows_total += sample_rows
+        rows_total += n if rows is None else len(rows)
         threads = oracle.last_threads
+        for V in g["V"]:
+            Vh = V.cpu().numpy().view(np.uint64)
+            t0 = time.perf_counter()
+            oracle.smp(n, s, d, Vh)
+            t_total += time.perf_counter() - t0
+            rows_total += Vh.shape[0]
+    what = "all closure rows" if sample_rows <= 0 else "%d random closure rows" % sample_rows
     return {"value": round(rows_total / t_total, 1), "unit": "query rows/s", "cores": threads, "kind": "oracle",
-            "sample": "%d random closure rows (per-source BFS) of each of the %d graphs; %.2f s"
-                      % (sample_rows, len(graphs), t_total)}
+            "sample": "%s of each of the %d graphs plus every SMP query row (k=1,64,1024), per-source BFS; "
+                      "%d rows in %.2f s" % (what, len(graphs), rows_total, t_total)}
 
 
 if __name__ == "__main__":
