@@ -181,6 +181,30 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, c
 bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t *Rbase, const uint64_t *Rstep, uint64_t *P,
                                 int64_t n, int64_t ld, const bmlp_opts *opts, void *stream, bmlp_stats *stats);
 
+/* ------------------------------------------------------------ batches of graphs */
+/* One graph of a batch: its relation, where its closure goes, and its query rows. */
+typedef struct {
+  int64_t n;              /* constants (nodes) of this graph; 0 is allowed */
+  int64_t ld;             /* leading dimension of R1 (words) */
+  const uint64_t *R1;     /* n x n relation (device) */
+  uint64_t *closure;      /* out: n x n R1+ with leading dimension ldc, or NULL */
+  int64_t ldc;            /* leading dimension of closure (ignored when closure is NULL) */
+  int64_t k;              /* query rows (0 for none) */
+  int64_t ldv;            /* leading dimension of V and Vstar */
+  const uint64_t *V;      /* k x n query rows (device) */
+  uint64_t *Vstar;        /* out: k x n answers V x R1+ */
+} bmlp_graph_desc;
+
+/* BMLP-RMS and BMLP-SMP (Section 3.3, Eqs. 4-5; Algorithms 1-2) for `count` independent graphs of
+   any sizes in one hipGraph launch: for each graph the closure R1+ and the answers V x R1+ (read off
+   the closure, the reuse of intermediate results of Section 4).  `graphs` is a host array; the
+   device buffers it points to must not overlap each other across outputs and inputs.  The launch is
+   asynchronous on `stream` (the captured graph is cached on the handle and reused while the
+   descriptors stay the same); with `stats` non-NULL the call waits and fills it.  Graph outputs of
+   different descriptors must not overlap. */
+bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc *graphs, int32_t count, const bmlp_opts *opts,
+                         void *stream, bmlp_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

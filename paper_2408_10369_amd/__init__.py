@@ -32,8 +32,14 @@ EXPORTS = [
     "bmlp_create", "bmlp_destroy", "bmlp_last_error", "bmlp_opts_init", "bmlp_version",
     "bmlp_pack_u8", "bmlp_pack_coo", "bmlp_unpack_u8",
     "bmlp_or", "bmlp_and", "bmlp_andnot", "bmlp_not", "bmlp_transpose", "bmlp_product",
-    "bmlp_rms", "bmlp_smp", "bmlp_compose_linear",
+    "bmlp_rms", "bmlp_smp", "bmlp_compose_linear", "bmlp_batched",
 ]
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("R1", ctypes.c_void_p), ("closure", ctypes.c_void_p),
+                ("ldc", ctypes.c_int64), ("k", ctypes.c_int64), ("ldv", ctypes.c_int64), ("V", ctypes.c_void_p),
+                ("Vstar", ctypes.c_void_p)]
 
 
 class Opts(ctypes.Structure):
@@ -96,6 +102,7 @@ def lib():
     L.bmlp_rms.argtypes = [vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_smp.argtypes = [vp, vp, i64, i64, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_compose_linear.argtypes = [vp, vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
+    L.bmlp_batched.argtypes = [vp, P(GraphDesc), ctypes.c_int32, P(Opts), vp, P(Stats)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("bmlp_last_error", "bmlp_opts_init", "bmlp_version"):
@@ -288,3 +295,29 @@ class Context:
         if st is not None:
             stats.update(st.as_dict())
         return out
+
+    def batched(self, graphs, opts=None, stream=None, stats=None):
+        """One launch over many graphs.  ``graphs``: sequence of dicts with keys
+        ``n``, ``R1`` and optionally ``closure`` (output), ``V`` and ``Vstar``
+        (output); the outputs are filled in place."""
+        arr = (GraphDesc * max(len(graphs), 1))()
+        for i, g in enumerate(graphs):
+            n = int(g["n"])
+            _, ld = _bits_shape(g["R1"], n)
+            d = arr[i]
+            d.n, d.ld, d.R1 = n, ld, g["R1"].data_ptr()
+            clo = g.get("closure")
+            if clo is not None:
+                _, d.ldc = _bits_shape(clo, n)
+                d.closure = clo.data_ptr()
+            V = g.get("V")
+            if V is not None and V.shape[0] > 0:
+                d.k, d.ldv = _bits_shape(V)
+                _bits_shape(g["Vstar"], d.k)
+                d.V, d.Vstar = V.data_ptr(), g["Vstar"].data_ptr()
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_batched(self._h, arr, len(graphs), ctypes.byref(opts) if opts is not None else None,
+                                  _stream(stream), ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return graphs

@@ -9,8 +9,10 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/bmlp.h"
+#include "bmlp_batch.h"
 #include "bmlp_internal.h"
 
 using namespace bmlp;
@@ -41,17 +43,22 @@ void hip_check(hipError_t e, const char* what) {
 
 struct bmlp_ctx {
   int device = 0;
-  static constexpr int kSlots = 12;
+  static constexpr int kSlots = 13;
   void* slot[kSlots] = {};
   size_t slot_bytes[kSlots] = {};
   u32* d_flags = nullptr;  // device flags / counters
   u32* h_flags = nullptr;  // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evp0 = nullptr, evp1 = nullptr;
+  // batched launch: the captured kernel chain, reused while the batch is unchanged
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t bgraph = nullptr;
+  hipGraphExec_t bexec = nullptr;
+  uint64_t bkey = 0;
 };
 
 namespace {
 
-enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_MISC };
+enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH };
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -147,7 +154,9 @@ struct StatsRec {
   bmlp_stats* st;
   bmlp_ctx* c;
   hipStream_t s;
-  explicit StatsRec(bmlp_stats* st_, bmlp_ctx* c_, hipStream_t s_) : st(st_), c(c_), s(s_) {
+  const bmlp_opts* o = nullptr;  // options of the call (workspace limit)
+  explicit StatsRec(bmlp_stats* st_, bmlp_ctx* c_, hipStream_t s_, const bmlp_opts* o_ = nullptr)
+      : st(st_), c(c_), s(s_), o(o_) {
     if (!st) return;
     std::memset(st, 0, sizeof *st);
     for (int i = 0; i < 64; ++i) st->arm_trace[i] = -1;
@@ -193,12 +202,31 @@ u32 read_flag(bmlp_ctx* c, hipStream_t s, int idx = 0) {
   return c->h_flags[idx];
 }
 
+// transpose of B (K x N) into the S_BT workspace, for the MFMA arm
+const u64* transpose_b(bmlp_ctx* c, const u64* B, i64 ldb, i64 K, i64 N, const bmlp_opts& o, hipStream_t s,
+                       i64* ldbt) {
+  *ldbt = std::max<i64>(words_for(K), 1);
+  u64* bt = ws_bits(c, S_BT, N, *ldbt, o);
+  hip_check(launch_transpose(B, K, N, ldb, bt, *ldbt, s), "transpose");
+  return bt;
+}
+
+// One Boolean product C = Cold | A.B (D, changed optional) with the chosen arm.  The MFMA arm reads B
+// transposed: pass BT when the caller has it, else B is transposed into workspace first.
 void product(bmlp_ctx* c, const u64* A, i64 lda, const u64* B, i64 ldb, const u64* Cold, i64 ldco, u64* C, i64 ldc,
-             u64* D, i64 ldd, i64 M, i64 K, i64 N, u32* changed, int arm, hipStream_t s, StatsRec& sr) {
+             u64* D, i64 ldd, i64 M, i64 K, i64 N, u32* changed, int arm, hipStream_t s, StatsRec& sr,
+             const u64* BT = nullptr, i64 ldbt = 0) {
   GemmArgs g{A, lda, B, ldb, Cold, ldco, C, ldc, D, ldd, M, K, N, changed};
-  (void)arm;
-  sr.product_begin();
-  hip_check(launch_gemm_valu(g, s), "gemm_valu");
+  if (arm == BMLP_ARM_PRODUCT_MFMA) {
+    bmlp_opts dflt;
+    bmlp_opts_init(&dflt);
+    if (!BT) BT = transpose_b(c, B, ldb, K, N, sr.o ? *sr.o : dflt, s, &ldbt);
+    sr.product_begin();
+    hip_check(launch_gemm_mfma(g, BT, ldbt, s), "gemm_mfma");
+  } else {
+    sr.product_begin();
+    hip_check(launch_gemm_valu(g, s), "gemm_valu");
+  }
   sr.product(M, K, N);
 }
 
@@ -208,9 +236,12 @@ int ceil_log2(i64 x) {
   return r;
 }
 
-int product_arm(const bmlp_opts& o) {
+// Plain choice of the product kernel for an (M x K).(K x N) product: the matrix-core arm once both
+// output dimensions fill its 256 x 256 workgroup tiles (measured faster from n = 4,096 up), the
+// bit-packed VALU arm (which also splits K) for thin or small products.
+int product_arm(const bmlp_opts& o, i64 M, i64 N) {
   if (o.product_arm == BMLP_ARM_PRODUCT_VALU || o.product_arm == BMLP_ARM_PRODUCT_MFMA) return o.product_arm;
-  return BMLP_ARM_PRODUCT_VALU;
+  return (M >= 1024 && N >= 1024) ? BMLP_ARM_PRODUCT_MFMA : BMLP_ARM_PRODUCT_VALU;
 }
 
 // R1+ into `out` (n x ldo) -- the RMS fixpoint driver shared by rms, the closure arm of smp and the RMS
@@ -221,7 +252,7 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   const i64 ldi = nw;
   u64* cur = ws_bits(c, S_W0, n, ldi, o);
   u64* nxt = ws_bits(c, S_W1, n, ldi, o);
-  const int arm = product_arm(o);
+  const int arm = product_arm(o, n, n);
   hip_check(launch_ewise(4, R1, ld1, nullptr, 0, cur, ldi, n, n, s), "copy");
   if (o.rms_variant == 1) hip_check(launch_set_diag(cur, ldi, n, n, s), "set_diag");
   const int cap = ceil_log2(std::max<i64>(n, 2)) + 2;
@@ -252,23 +283,41 @@ void build_csr(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const bmlp_opts& o, hip
                int32_t** ci_out) {
   int32_t* deg = (int32_t*)ws(c, S_DEG, (size_t)n * sizeof(int32_t), o);
   i64* rp = (i64*)ws(c, S_RP, (size_t)(n + 1) * sizeof(i64), o);
-  unsigned long long* tot = (unsigned long long*)(c->d_flags + 4);
-  hip_check(hipMemsetAsync(tot, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
-  hip_check(launch_row_popcount(R, n, n, ld, deg, tot, s), "row_popcount");
+  hip_check(launch_row_popcount(R, n, n, ld, deg, nullptr, s), "row_popcount");
   hip_check(launch_scan_rowptr(deg, n, rp, s), "scan");
-  hip_check(hipMemcpyAsync(c->h_flags + 4, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "memcpy");
+  // the scan's last entry is the number of set bits
+  hip_check(hipMemcpyAsync(c->h_flags + 4, rp + n, sizeof(i64), hipMemcpyDeviceToHost, s), "memcpy");
   hip_check(hipStreamSynchronize(s), "sync");
-  unsigned long long m = 0;
+  i64 m = 0;
   std::memcpy(&m, c->h_flags + 4, sizeof m);
-  int32_t* ci = (int32_t*)ws(c, S_CI, (size_t)std::max<unsigned long long>(m, 1) * sizeof(int32_t), o);
+  int32_t* ci = (int32_t*)ws(c, S_CI, (size_t)std::max<i64>(m, 1) * sizeof(int32_t), o);
   hip_check(launch_bits_to_csr(R, n, n, ld, rp, ci, s), "bits_to_csr");
   *rp_out = rp;
   *ci_out = ci;
 }
 
-int smp_plain_arm(i64 n, i64 k) {
-  (void)k;
-  if (n <= smp_rows_max_n()) return BMLP_ARM_SMP_SPARSE;
+// number of set bits of a bit matrix (device popcount, one readback)
+i64 count_bits(bmlp_ctx* c, const u64* R, i64 rows, i64 n, i64 ld, hipStream_t s) {
+  unsigned long long* tot = (unsigned long long*)(c->d_flags + 4);
+  hip_check(hipMemsetAsync(tot, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+  hip_check(launch_popcount_total(R, rows, n, ld, tot, s), "popcount_total");
+  hip_check(hipMemcpyAsync(c->h_flags + 4, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");
+  unsigned long long m = 0;
+  std::memcpy(&m, c->h_flags + 4, sizeof m);
+  return (i64)m;
+}
+
+// Plain schedule for the selection, from a timing sweep of the three arms on
+// n = 16,384 random digraphs (mean out-degree 1.6 .. 164, k = 1 .. 1024): the
+// sparse-frontier arm wins while the mean out-degree is low (its work grows with
+// the edges it visits); the dense semi-naive arm wins on dense relations (its
+// work is independent of the degree).
+int smp_plain_arm(i64 n, i64 k, i64 m) {
+  if (n > smp_rows_max_n()) return BMLP_ARM_SMP_DENSE;
+  const double deg = n > 0 ? (double)m / (double)n : 0.0;
+  if (deg < 12.0) return BMLP_ARM_SMP_SPARSE;
+  if (deg < 40.0 && k >= 32) return BMLP_ARM_SMP_SPARSE;
   return BMLP_ARM_SMP_DENSE;
 }
 
@@ -276,7 +325,7 @@ int smp_plain_arm(i64 n, i64 k) {
 void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vstar, i64 k, i64 ldv, int reflexive,
               int arm, const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
   const i64 nw = words_for(n);
-  const int parm = product_arm(o);
+  const int parm = product_arm(o, k, n);
   if (sr.st) sr.st->arm = arm;
   if (arm == BMLP_ARM_SMP_SPARSE) {
     need(n <= smp_rows_max_n(), BMLP_EINVAL, "sparse SMP arm supports n <= %lld", (long long)smp_rows_max_n());
@@ -305,18 +354,21 @@ void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vsta
   // delta' = (delta . R1) & ~Vis ; Vis |= delta' until delta' is empty.
   u64* da = ws_bits(c, S_W3, k, nw, o);
   u64* db = ws_bits(c, S_W4, k, nw, o);
+  const u64* r1t = nullptr;
+  i64 ldr1t = 0;
+  if (parm == BMLP_ARM_PRODUCT_MFMA) r1t = transpose_b(c, R1, ld, n, n, o, s, &ldr1t);
   int it = 0;
   if (reflexive) {
     hip_check(launch_ewise(4, V, ldv, nullptr, 0, Vstar, ldv, k, n, s), "copy");
     hip_check(launch_ewise(4, V, ldv, nullptr, 0, da, nw, k, n, s), "copy");
   } else {
-    product(c, V, ldv, R1, ld, nullptr, 0, Vstar, ldv, da, nw, k, n, n, nullptr, parm, s, sr);
+    product(c, V, ldv, R1, ld, nullptr, 0, Vstar, ldv, da, nw, k, n, n, nullptr, parm, s, sr, r1t, ldr1t);
     sr.trace(it++, arm);
   }
   const i64 cap = n + 2;
   for (;;) {
     zero_flag(c, s);
-    product(c, da, nw, R1, ld, Vstar, ldv, Vstar, ldv, db, nw, k, n, n, c->d_flags, parm, s, sr);
+    product(c, da, nw, R1, ld, Vstar, ldv, Vstar, ldv, db, nw, k, n, n, c->d_flags, parm, s, sr, r1t, ldr1t);
     sr.trace(it++, arm);
     const u32 changed = read_flag(c, s);
     std::swap(da, db);
@@ -405,6 +457,9 @@ bmlp_status bmlp_destroy(bmlp_handle h) {
       if (h->ev1) (void)hipEventDestroy(h->ev1);
       if (h->evp0) (void)hipEventDestroy(h->evp0);
       if (h->evp1) (void)hipEventDestroy(h->evp1);
+      if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
+      if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
+      if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     }
     delete h;
   });
@@ -525,17 +580,17 @@ bmlp_status bmlp_product(bmlp_handle h, const uint64_t* A, int64_t lda, const ui
       check_padding(h, B, kdim, n, ldb, s, "B");
       if (Cold) check_padding(h, Cold, m, n, ldc, s, "Cold");
     }
-    StatsRec sr(stats, h, s);
+    StatsRec sr(stats, h, s, &o);
     if (m > 0 && n > 0) {
       if (kdim == 0) {
         if (Cold) hip_check(launch_ewise(4, Cold, ldc, nullptr, 0, C, ldc, m, n, s), "copy");
         else hip_check(launch_fill_zero(C, m * ldc, s), "fill_zero");
       } else {
-        product(h, A, lda, B, ldb, Cold, ldc, C, ldc, nullptr, 0, m, kdim, n, nullptr, product_arm(o), s, sr);
+        product(h, A, lda, B, ldb, Cold, ldc, C, ldc, nullptr, 0, m, kdim, n, nullptr, product_arm(o, m, n), s, sr);
       }
     }
     if (m > 0) hip_check(launch_zero_pad(C, m, n, ldc, s), "zero_pad");
-    if (stats) stats->arm = product_arm(o);
+    if (stats) stats->arm = product_arm(o, m, n);
     sr.finish();
   });
 }
@@ -552,8 +607,8 @@ bmlp_status bmlp_rms(bmlp_handle h, const uint64_t* R1, uint64_t* Rstar, int64_t
     DeviceGuard dg(h->device);
     hipStream_t s = (hipStream_t)stream;
     if (o.check_padding) check_padding(h, R1, n, n, ld, s, "R1");
-    StatsRec sr(stats, h, s);
-    if (stats) stats->arm = product_arm(o);
+    StatsRec sr(stats, h, s, &o);
+    if (stats) stats->arm = product_arm(o, n, n);
     if (n > 0) rms_core(h, R1, ld, Rstar, ld, n, o, s, sr);
     sr.finish();
   });
@@ -570,17 +625,19 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, c
     const Range rv = range_of(Vstar, k, ldv);
     need(!overlap(rv, range_of(V, k, ldv)), BMLP_EALIAS, "Vstar overlaps V");
     need(!overlap(rv, range_of(R1, n, ld)), BMLP_EALIAS, "Vstar overlaps R1");
+    const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
     int arm = o.smp_arm;
-    if (o.dispatch != BMLP_DISPATCH_FORCED || arm == BMLP_ARM_AUTO) arm = smp_plain_arm(n, k);
-    need(arm == BMLP_ARM_SMP_DENSE || arm == BMLP_ARM_SMP_SPARSE || arm == BMLP_ARM_SMP_CLOSURE, BMLP_EINVAL,
-         "smp_arm %d is not a selection arm", arm);
+    if (forced)
+      need(arm == BMLP_ARM_SMP_DENSE || arm == BMLP_ARM_SMP_SPARSE || arm == BMLP_ARM_SMP_CLOSURE, BMLP_EINVAL,
+           "smp_arm %d is not a selection arm", arm);
     DeviceGuard dg(h->device);
     hipStream_t s = (hipStream_t)stream;
+    if (!forced) arm = (n > 0 && k > 0) ? smp_plain_arm(n, k, count_bits(h, R1, n, n, ld, s)) : BMLP_ARM_SMP_SPARSE;
     if (o.check_padding) {
       check_padding(h, R1, n, n, ld, s, "R1");
       check_padding(h, V, k, n, ldv, s, "V");
     }
-    StatsRec sr(stats, h, s);
+    StatsRec sr(stats, h, s, &o);
     if (k > 0) {
       if (n == 0) hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
       else smp_core(h, R1, ld, n, V, Vstar, k, ldv, o.smp_reflexive ? 1 : 0, arm, o, s, sr);
@@ -611,10 +668,10 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
       check_padding(h, Rbase, n, n, ld, s, "Rbase");
       check_padding(h, Rstep, n, n, ld, s, "Rstep");
     }
-    StatsRec sr(stats, h, s);
+    StatsRec sr(stats, h, s, &o);
     if (n > 0) {
       const i64 nw = words_for(n);
-      const int parm = product_arm(o);
+      const int parm = product_arm(o, n, n);
       if (arm == BMLP_ARM_COMPOSE_RMS) {
         // Rs+ by RMS, then P = Rb | Rs+ . Rb
         u64* sp = ws_bits(h, S_W2, n, nw, o);
@@ -631,13 +688,145 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
         u64* pt = ws_bits(h, S_T2, n, nw, o);
         hip_check(launch_transpose(Rbase, n, n, ld, rbt, nw, s), "transpose");
         hip_check(launch_transpose(Rstep, n, n, ld, rst, nw, s), "transpose");
-        const int sarm = smp_plain_arm(n, n);
+        const int sarm = smp_plain_arm(n, n, count_bits(h, rst, n, n, nw, s));
         smp_core(h, rst, nw, n, rbt, pt, n, nw, 1, sarm, o, s, sr);
         hip_check(launch_transpose(pt, n, n, nw, P, ld, s), "transpose");
       }
     }
     if (stats) stats->arm = arm;
     sr.finish();
+  });
+}
+
+bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t count, const bmlp_opts* opts,
+                         void* stream, bmlp_stats* stats) {
+  return guarded([&] {
+    need_handle(h);
+    const bmlp_opts o = opts_or_default(opts);
+    need(count >= 0, BMLP_EINVAL, "count < 0");
+    if (count == 0) return;
+    need(graphs != nullptr, BMLP_EINVAL, "graphs: null pointer");
+    for (int32_t i = 0; i < count; ++i) {
+      const bmlp_graph_desc& d = graphs[i];
+      need(d.n >= 0 && d.k >= 0, BMLP_EINVAL, "graph %d: negative size", i);
+      check_bits_arg(d.R1, "R1", d.n, d.n, d.ld);
+      if (d.closure) {
+        check_bits_arg(d.closure, "closure", d.n, d.n, d.ldc);
+        need(!overlap(range_of(d.closure, d.n, d.ldc), range_of(d.R1, d.n, d.ld)), BMLP_EALIAS,
+             "graph %d: closure overlaps R1", i);
+      }
+      if (d.k > 0) {
+        check_bits_arg(d.V, "V", d.k, d.n, d.ldv);
+        check_bits_arg(d.Vstar, "Vstar", d.k, d.n, d.ldv);
+        const Range rv = range_of(d.Vstar, d.k, d.ldv);
+        need(!overlap(rv, range_of(d.V, d.k, d.ldv)) && !overlap(rv, range_of(d.R1, d.n, d.ld)), BMLP_EALIAS,
+             "graph %d: Vstar overlaps an input", i);
+      }
+    }
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+
+    // biggest graphs first: their tiles are claimed first in every round (longest-processing-time order)
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return graphs[a].n > graphs[b].n; });
+    BatchPlan plan{0, 0, 0, 0};
+    size_t buf_words = 0;
+    for (int i = 0; i < count; ++i) {
+      const bmlp_graph_desc& d = graphs[i];
+      plan.rounds = std::max(plan.rounds, ceil_log2(std::max<int64_t>(d.n, 2)) + 2);
+      buf_words += (size_t)(2 * d.n * words_for(d.n));
+    }
+    const size_t table_bytes = ((size_t)count * sizeof(BatchGraph) + 255) & ~(size_t)255;
+    const size_t nflags = (size_t)count * plan.rounds + 2 * (size_t)plan.rounds + 1;
+    const size_t flag_bytes = (nflags * sizeof(u32) + 255) & ~(size_t)255;
+    char* base = (char*)ws(h, S_BATCH, table_bytes + flag_bytes + buf_words * sizeof(u64), o);
+    BatchGraph* d_table = (BatchGraph*)base;
+    u32* d_flags = (u32*)(base + table_bytes);
+    u64* bufs = (u64*)(base + table_bytes + flag_bytes);
+
+    std::vector<BatchGraph> tab(count);
+    size_t off = 0;
+    for (int j = 0; j < count; ++j) {
+      const bmlp_graph_desc& d = graphs[order[j]];
+      BatchGraph& G = tab[j];
+      G.n = d.n;
+      G.nw = words_for(d.n);
+      G.R1 = d.R1;
+      G.ld = d.ld;
+      G.closure = d.closure;
+      G.ldc = d.closure ? d.ldc : 0;
+      G.V = d.V;
+      G.k = d.k;
+      G.ldv = d.ldv;
+      G.Vstar = d.Vstar;
+      G.buf0 = bufs + off;
+      G.buf1 = bufs + off + (size_t)(d.n * G.nw);
+      off += (size_t)(2 * d.n * G.nw);
+      G.row_begin = plan.total_rows;
+      G.tile_begin = plan.total_tiles;
+      G.rtiles = batch_rtiles(d.n);
+      G.smp_tile_begin = plan.total_select_tiles;
+      plan.total_rows += std::max<int64_t>(d.n, d.k);
+      plan.total_tiles += batch_tiles(d.n);
+      plan.total_select_tiles += d.k > 0 ? batch_select_tiles(d.k, d.n) : 0;
+    }
+    // the captured chain is reused while the batch (and its workspace) is unchanged
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t nb) {
+      const unsigned char* b = (const unsigned char*)p;
+      for (size_t i = 0; i < nb; ++i) key = (key ^ b[i]) * 1099511628211ull;
+    };
+    mix(graphs, sizeof(bmlp_graph_desc) * (size_t)count);
+    mix(&base, sizeof base);
+    if (!h->bexec || key != h->bkey) {
+      if (h->bexec) {
+        hip_check(hipGraphExecDestroy(h->bexec), "hipGraphExecDestroy");
+        h->bexec = nullptr;
+      }
+      if (h->bgraph) {
+        hip_check(hipGraphDestroy(h->bgraph), "hipGraphDestroy");
+        h->bgraph = nullptr;
+      }
+      hip_check(hipMemcpyAsync(d_table, tab.data(), sizeof(BatchGraph) * (size_t)count, hipMemcpyHostToDevice, s),
+                "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      if (!h->capture_stream)
+        hip_check(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+      hip_check(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      const hipError_t le = launch_batch_chain(d_table, count, plan, d_flags, h->capture_stream);
+      hipGraph_t graph = nullptr;
+      const hipError_t ce = hipStreamEndCapture(h->capture_stream, &graph);
+      hip_check(le, "batch chain");
+      hip_check(ce, "hipStreamEndCapture");
+      h->bgraph = graph;
+      hip_check(hipGraphInstantiate(&h->bexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+      h->bkey = key;
+    }
+    StatsRec sr(stats, h, s, &o);
+    hip_check(hipGraphLaunch(h->bexec, s), "hipGraphLaunch");
+    if (stats) {
+      sr.finish();
+      std::vector<u32> fl(nflags);
+      hip_check(hipMemcpyAsync(fl.data(), d_flags, nflags * sizeof(u32), hipMemcpyDeviceToHost, s), "memcpy");
+      hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      int max_rounds = 0;
+      for (int j = 0; j < count; ++j) {
+        int r = 0;
+        while (r < plan.rounds && fl[(size_t)j * plan.rounds + r]) ++r;
+        need(r < plan.rounds, BMLP_EITER, "batched RMS exceeded %d rounds (graph of n=%lld)", plan.rounds,
+             (long long)tab[j].n);
+        const int prods = r + 1;  // the rounds that changed plus the one that found the fixpoint
+        max_rounds = std::max(max_rounds, prods);
+        const uint64_t nn = (uint64_t)tab[j].n;
+        stats->products += prods + (tab[j].k > 0 ? 1 : 0);
+        stats->bool_ops += (uint64_t)prods * 2u * nn * nn * nn + 2u * (uint64_t)tab[j].k * nn * nn;
+      }
+      stats->iterations = max_rounds;
+      stats->arm = BMLP_ARM_SMP_CLOSURE;
+      stats->product_bool_ops = stats->bool_ops;
+      stats->product_ms = stats->device_ms;
+    }
   });
 }
 

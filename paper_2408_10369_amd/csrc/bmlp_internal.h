@@ -36,6 +36,8 @@ hipError_t launch_check_pad(const u64* a, i64 rows, i64 n, i64 ld, u32* bad, hip
 // per-row popcount into deg (int32), plus total into *total (u64, must be zeroed)
 hipError_t launch_row_popcount(const u64* a, i64 rows, i64 n, i64 ld, int32_t* deg, unsigned long long* total,
                                hipStream_t s);
+// number of set bits of the matrix added into *total (must be zeroed)
+hipError_t launch_popcount_total(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* total, hipStream_t s);
 // exclusive scan of deg[0..n) into rp[0..n] (int64); single-workgroup
 hipError_t launch_scan_rowptr(const int32_t* deg, i64 n, i64* rp, hipStream_t s);
 // CSR column indices of the set bits of each row (rp from launch_scan_rowptr)

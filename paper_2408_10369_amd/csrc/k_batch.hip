@@ -1,0 +1,207 @@
+// Batched BMLP over many graphs of uneven sizes in one hipGraph launch.
+//
+// For every graph g of the batch: the closure R1+ by repeated squaring
+// R <- R | R.R (Section 3.3, Eq. 4 / Algorithm 1 in its R | R.R form) and the
+// answers V R1+ of its query rows (Eq. 5) read off the finished closure (the
+// reuse of intermediate results the paper describes in Section 4).
+//
+// The launch is a fixed chain of kernels captured once into a hipGraph:
+//   setup        copy every R1 into the graph's ping-pong workspace, clear flags
+//   round r      (r = 0 .. rounds-1) one squaring for every graph still active:
+//                a persistent grid claims (graph, tile) items from an atomic
+//                counter, biggest graphs first; a graph whose previous round
+//                changed nothing is skipped on the device
+//   select       Vstar = V . R1+ for every graph (tiles of query rows)
+//   copy         the closure of every graph into its output buffer
+// Round r reads buffer r & 1 and writes buffer (r + 1) & 1 of the graph, so
+// the result is independent of the order in which tiles run.  Kernel
+// boundaries make each round's writes visible to the next round on every XCD.
+#include "bmlp_batch.h"
+#include "valu_tile.h"
+
+namespace bmlp {
+
+namespace {
+
+constexpr int kRPW = 16;                 // rows per wave -> 64-row tiles
+constexpr int kTileRows = 4 * kRPW;
+constexpr int kTileWords = 64;           // one lane per word
+
+__device__ __forceinline__ int find_graph(const BatchGraph* __restrict__ gs, int count, i64 t, bool smp) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const i64 b = smp ? gs[mid].smp_tile_begin : gs[mid].tile_begin;
+    if (b <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// round at which graph g stopped changing (its last product), or -1 if it
+// never did within the rounds run
+__device__ __forceinline__ int final_round(const u32* __restrict__ changed, int g, int rounds) {
+  for (int r = 0; r < rounds; ++r)
+    if (!changed[(i64)g * rounds + r]) return r;
+  return -1;
+}
+
+__global__ void k_batch_setup(BatchGraph* __restrict__ gs, int count, i64 total_rows, u32* __restrict__ flags,
+                              i64 nflags) {
+  const i64 tid = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  const i64 nth = (i64)gridDim.x * blockDim.x;
+  for (i64 i = tid; i < nflags; i += nth) flags[i] = 0u;
+  // one thread per (graph row, word): rows are numbered across graphs by row_begin
+  for (i64 rr = tid / 64; rr < total_rows; rr += nth / 64) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (gs[mid].row_begin <= rr) lo = mid; else hi = mid - 1;
+    }
+    const BatchGraph& G = gs[lo];
+    const i64 row = rr - G.row_begin;
+    if (row >= G.n) continue;
+    for (i64 w = tid & 63; w < G.nw; w += 64) {
+      u64 x = G.R1[row * G.ld + w];
+      if (w == G.nw - 1 && (G.n & 63)) x &= (1ull << (G.n & 63)) - 1ull;
+      G.buf0[row * G.nw + w] = x;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int round, int rounds,
+              u32* __restrict__ changed, u32* __restrict__ counters, u32* __restrict__ any_active) {
+  __shared__ u64 Bs[64][kTileWords];
+  __shared__ i64 item;
+  if (round > 0 && any_active[round - 1] == 0u) return;  // every graph has converged
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (;;) {
+    if (threadIdx.x == 0) item = (i64)atomicAdd(&counters[round], 1u);
+    __syncthreads();
+    const i64 t = item;
+    __syncthreads();
+    if (t >= total_tiles) break;
+    const int g = find_graph(gs, count, t, false);
+    if (round > 0 && !changed[(i64)g * rounds + round - 1]) continue;
+    const BatchGraph& G = gs[g];
+    const i64 local = t - G.tile_begin;
+    const i64 rt = local % G.rtiles, ct = local / G.rtiles;
+    const u64* cur = (round & 1) ? G.buf1 : G.buf0;
+    u64* nxt = (round & 1) ? G.buf0 : G.buf1;
+    const i64 row0 = rt * kTileRows + (i64)wave * kRPW;
+    const i64 w0 = ct * kTileWords;
+    u32 acc[kRPW][1][2];
+#pragma unroll
+    for (int r = 0; r < kRPW; ++r) acc[r][0][0] = acc[r][0][1] = 0u;
+    valu_tile_accumulate<kRPW, 1>(cur, G.nw, cur, G.nw, G.n, G.n, G.nw, row0, w0, 0, G.nw, Bs, acc);
+    const int ch = valu_tile_store<kRPW, 1>(acc, cur, G.nw, nxt, G.nw, nullptr, 0, G.n, G.nw, row0, w0);
+    if (__ballot(ch) && lane == 0) {
+      atomicOr(&changed[(i64)g * rounds + round], 1u);
+      atomicOr(&any_active[round], 1u);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_batch_select(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int rounds,
+               const u32* __restrict__ changed, u32* __restrict__ counter) {
+  __shared__ u64 Bs[64][kTileWords];
+  __shared__ i64 item;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (;;) {
+    if (threadIdx.x == 0) item = (i64)atomicAdd(counter, 1u);
+    __syncthreads();
+    const i64 t = item;
+    __syncthreads();
+    if (t >= total_tiles) break;
+    const int g = find_graph(gs, count, t, true);
+    const BatchGraph& G = gs[g];
+    const int fr = final_round(changed, g, rounds);
+    const u64* clo = ((fr + 1) & 1) ? G.buf1 : G.buf0;  // buffer written by the last round
+    const i64 local = t - G.smp_tile_begin;
+    const i64 vrt = (G.k + kTileRows - 1) / kTileRows;
+    const i64 rt = local % vrt, ct = local / vrt;
+    const i64 row0 = rt * kTileRows + (i64)wave * kRPW;
+    const i64 w0 = ct * kTileWords;
+    u32 acc[kRPW][1][2];
+#pragma unroll
+    for (int r = 0; r < kRPW; ++r) acc[r][0][0] = acc[r][0][1] = 0u;
+    valu_tile_accumulate<kRPW, 1>(G.V, G.ldv, clo, G.nw, G.k, G.n, G.nw, row0, w0, 0, G.nw, Bs, acc);
+    (void)valu_tile_store<kRPW, 1>(acc, nullptr, 0, G.Vstar, G.ldv, nullptr, 0, G.k, G.nw, row0, w0);
+  }
+}
+
+// closure rows into the outputs (with the caller's leading dimension, padding words zeroed) and the
+// padding words of the answer rows
+__global__ void k_batch_copy(const BatchGraph* __restrict__ gs, int count, i64 total_rows, int rounds,
+                             const u32* __restrict__ changed) {
+  const i64 tid = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  const i64 nth = (i64)gridDim.x * blockDim.x;
+  for (i64 rr = tid / 64; rr < total_rows; rr += nth / 64) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (gs[mid].row_begin <= rr) lo = mid; else hi = mid - 1;
+    }
+    const BatchGraph& G = gs[lo];
+    const i64 row = rr - G.row_begin;
+    if (G.closure && row < G.n) {
+      const int fr = final_round(changed, lo, rounds);
+      const u64* clo = ((fr + 1) & 1) ? G.buf1 : G.buf0;
+      for (i64 w = tid & 63; w < G.ldc; w += 64) G.closure[row * G.ldc + w] = (w < G.nw) ? clo[row * G.nw + w] : 0ull;
+    }
+    if (row < G.k)
+      for (i64 w = G.nw + (tid & 63); w < G.ldv; w += 64) G.Vstar[row * G.ldv + w] = 0ull;
+  }
+}
+
+int grid_cap(i64 work, int cap) {
+  if (work < 1) return 1;
+  return (int)(work < cap ? work : cap);
+}
+
+}  // namespace
+
+i64 batch_tiles(i64 n) {
+  const i64 nw = words_for(n);
+  return ((n + kTileRows - 1) / kTileRows) * ((nw + kTileWords - 1) / kTileWords);
+}
+
+i64 batch_rtiles(i64 n) { return (n + kTileRows - 1) / kTileRows; }
+
+i64 batch_select_tiles(i64 k, i64 n) {
+  const i64 nw = words_for(n);
+  return ((k + kTileRows - 1) / kTileRows) * ((nw + kTileWords - 1) / kTileWords);
+}
+
+hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& p, u32* flags, hipStream_t s) {
+  // flags layout: changed[count * rounds] | any_active[rounds] | counters[rounds + 1]
+  u32* changed = flags;
+  u32* any_active = flags + (i64)count * p.rounds;
+  u32* counters = any_active + p.rounds;
+  const i64 nflags = (i64)count * p.rounds + 2 * (i64)p.rounds + 1;
+  hipLaunchKernelGGL(k_batch_setup, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
+                     count, p.total_rows, flags, nflags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int pgrid = grid_cap(p.total_tiles, 1024);
+  for (int r = 0; r < p.rounds; ++r) {
+    hipLaunchKernelGGL(k_batch_round, dim3(pgrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count, p.total_tiles,
+                       r, p.rounds, changed, counters, any_active);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (p.total_select_tiles > 0) {
+    hipLaunchKernelGGL(k_batch_select, dim3(grid_cap(p.total_select_tiles, 1024)), dim3(256), 0, s,
+                       (const BatchGraph*)d_graphs, count, p.total_select_tiles, p.rounds, (const u32*)changed,
+                       counters + p.rounds);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_batch_copy, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s,
+                     (const BatchGraph*)d_graphs, count, p.total_rows, p.rounds, (const u32*)changed);
+  return hipGetLastError();
+}
+
+}  // namespace bmlp

@@ -172,6 +172,23 @@ __global__ void k_row_popcount(const u64* __restrict__ a, i64 rows, i64 n, i64 l
   }
 }
 
+// total number of set bits: block reduction, one atomic per block
+__global__ void k_popcount_total(const u64* __restrict__ a, i64 rows, i64 nw, i64 ld,
+                                 unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long part[4];
+  unsigned long long c = 0;
+  const i64 all = rows * nw;
+  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < all; t += (i64)gridDim.x * blockDim.x) {
+    const i64 row = t / nw, w = t - row * nw;
+    c += (unsigned long long)__popcll(a[row * ld + w]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(total, part[0] + part[1] + part[2] + part[3]);
+}
+
 // single workgroup exclusive scan: rp[0] = 0, rp[i+1] = rp[i] + deg[i]
 __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict__ deg, i64 n, i64* __restrict__ rp) {
   __shared__ i64 part[1024];
@@ -298,6 +315,13 @@ hipError_t launch_row_popcount(const u64* a, i64 rows, i64 n, i64 ld, int32_t* d
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_popcount, dim3(grid_for(rows * 64, kBlock, 16384)), dim3(kBlock), 0, s, a, rows, n, ld, deg,
                      total);
+  return hipGetLastError();
+}
+
+hipError_t launch_popcount_total(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* total, hipStream_t s) {
+  if (rows <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_popcount_total, dim3(grid_for(rows * words_for(n), kBlock, 2048)), dim3(kBlock), 0, s, a, rows,
+                     words_for(n), ld, total);
   return hipGetLastError();
 }
 

@@ -11,27 +11,24 @@
 // of each of the wave's rows is wave-uniform, so the AND mask for (i, k) is a
 // scalar value and every lane does one v_and_or per 32 bit-MACs.  Chunks in
 // which no row of the tile has a set A bit are skipped entirely (sparse A).
+//
+// Split-K.  When the output has too few tiles to fill the chip, the k range
+// is split over several workgroups and partial results are merged with 64-bit
+// atomic ORs.  OR is idempotent and commutative, so the merge is exact.  C is
+// first made equal to Cold; a bit is new exactly when the atomic that sets it
+// returns an old word without it, which gives D and the changed flag exactly.
 #include "bmlp_internal.h"
+#include "valu_tile.h"
 
 namespace bmlp {
 
 namespace {
 
-// all-ones when bit `b` of the wave-uniform word x is set, else zero
-__device__ __forceinline__ u32 bit_mask(u32 x, int b) { return (u32)(((int)(x << (31 - b))) >> 31); }
-
-// acc | (b & m) as one v_and_or_b32 (m is a scalar operand)
-__device__ __forceinline__ u32 and_or(u32 b, u32 m, u32 acc) {
-  u32 r;
-  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "s"(m), "v"(acc));
-  return r;
-}
-
 template <int RPW, int WPL>
 __global__ void __launch_bounds__(256)
 k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 ldb, const u64* __restrict__ Cold,
             i64 ldco, u64* __restrict__ C, i64 ldc, u64* __restrict__ D, i64 ldd, i64 M, i64 K, i64 N,
-            u32* __restrict__ changed) {
+            u32* __restrict__ changed, int ksplit, int chunks_per_split) {
   constexpr int TW = 64 * WPL;
   constexpr int TR = 4 * RPW;
   __shared__ u64 Bs[64][TW];
@@ -39,8 +36,13 @@ k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 l
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const i64 nw = (N + 63) >> 6;
   const i64 ctiles = (nw + TW - 1) / TW;
+  const i64 rtiles = (M + TR - 1) / TR;
+  // block order: row tiles fastest, then column tiles, then k splits, so that
+  // concurrently running workgroups share the B chunks they stage
   const i64 tile = blockIdx.x;
-  const i64 ct = tile % ctiles, rt = tile / ctiles;
+  const i64 rt = tile % rtiles;
+  const i64 ct = (tile / rtiles) % ctiles;
+  const i64 ks = tile / (rtiles * ctiles);
   const i64 row0 = rt * TR + (i64)wave * RPW;
   const i64 w0 = ct * TW;
 
@@ -51,61 +53,31 @@ k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 l
     for (int wl = 0; wl < WPL; ++wl) acc[r][wl][0] = acc[r][wl][1] = 0u;
 
   const i64 kwords = (K + 63) >> 6;
-  for (i64 kw = 0; kw < kwords; ++kw) {
-    u32 alo[RPW], ahi[RPW];
-    u32 any = 0;
+  const i64 kw_begin = ks * chunks_per_split;
+  const i64 kw_end = (kw_begin + chunks_per_split < kwords) ? kw_begin + chunks_per_split : kwords;
+  valu_tile_accumulate<RPW, WPL>(A, lda, B, ldb, M, K, nw, row0, w0, kw_begin, kw_end, Bs, acc);
+
+  int ch = 0;
+  if (ksplit == 1) {
+    ch = valu_tile_store<RPW, WPL>(acc, Cold, ldco, C, ldc, D, ldd, M, nw, row0, w0);
+  } else {
+    // C already holds Cold and D is zero (the launcher sees to both)
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
       const i64 row = row0 + r;
-      const u64 a = (row < M) ? A[row * lda + kw] : 0ull;
-      alo[r] = (u32)a;
-      ahi[r] = (u32)(a >> 32);
-      any |= alo[r] | ahi[r];
-    }
-    if (!__syncthreads_or(any != 0)) continue;
-    for (int idx = threadIdx.x; idx < 64 * TW; idx += 256) {
-      const int t = idx / TW, c = idx - (idx / TW) * TW;
-      const i64 k = kw * 64 + t, w = w0 + c;
-      Bs[t][c] = (k < K && w < nw) ? B[k * ldb + w] : 0ull;
-    }
-    __syncthreads();
-    if (any) {
+      if (row >= M) break;
 #pragma unroll
-      for (int kk = 0; kk < 64; ++kk) {
-        u32 blo[WPL], bhi[WPL];
-#pragma unroll
-        for (int wl = 0; wl < WPL; ++wl) {
-          const u64 b = Bs[kk][lane + 64 * wl];
-          blo[wl] = (u32)b;
-          bhi[wl] = (u32)(b >> 32);
-        }
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          const u32 m = bit_mask(kk < 32 ? alo[r] : ahi[r], kk & 31);
-#pragma unroll
-          for (int wl = 0; wl < WPL; ++wl) {
-            acc[r][wl][0] = and_or(blo[wl], m, acc[r][wl][0]);
-            acc[r][wl][1] = and_or(bhi[wl], m, acc[r][wl][1]);
+      for (int wl = 0; wl < WPL; ++wl) {
+        const i64 w = w0 + lane + 64 * wl;
+        const u64 v = ((u64)acc[r][wl][1] << 32) | (u64)acc[r][wl][0];
+        if (w < nw && v) {
+          const u64 old = atomicOr((unsigned long long*)&C[row * ldc + w], (unsigned long long)v);
+          const u64 nb = v & ~old;
+          if (nb) {
+            if (D) atomicOr((unsigned long long*)&D[row * ldd + w], (unsigned long long)nb);
+            ch = 1;
           }
         }
-      }
-    }
-  }
-
-  int ch = 0;
-#pragma unroll
-  for (int r = 0; r < RPW; ++r) {
-    const i64 row = row0 + r;
-    if (row >= M) break;
-#pragma unroll
-    for (int wl = 0; wl < WPL; ++wl) {
-      const i64 w = w0 + lane + 64 * wl;
-      if (w < nw) {
-        const u64 old = Cold ? Cold[row * ldco + w] : 0ull;
-        const u64 v = (((u64)acc[r][wl][1] << 32) | (u64)acc[r][wl][0]) | old;
-        C[row * ldc + w] = v;
-        if (D) D[row * ldd + w] = v & ~old;
-        ch |= (v != old);
       }
     }
   }
@@ -115,32 +87,220 @@ k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 l
   }
 }
 
-}  // namespace
-
-hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+template <int RPW>
+hipError_t launch_rpw(const GemmArgs& g, hipStream_t s, i64 target_blocks) {
+  constexpr int WPL = 1;
   const i64 nw = words_for(g.N);
-  constexpr int RPW = 16;
-  if (nw >= 64) {
-    constexpr int WPL = 1;
-    const i64 ctiles = (nw + 64 * WPL - 1) / (64 * WPL);
-    const i64 rtiles = (g.M + 4 * RPW - 1) / (4 * RPW);
-    hipLaunchKernelGGL((k_gemm_valu<RPW, WPL>), dim3((unsigned)(ctiles * rtiles)), dim3(256), 0, s, g.A, g.lda, g.B,
-                       g.ldb, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed);
-  } else {
-    constexpr int WPL = 1;
-    const i64 ctiles = 1;
-    const i64 rtiles = (g.M + 4 * RPW - 1) / (4 * RPW);
-    hipLaunchKernelGGL((k_gemm_valu<RPW, WPL>), dim3((unsigned)(ctiles * rtiles)), dim3(256), 0, s, g.A, g.lda, g.B,
-                       g.ldb, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed);
+  const i64 ctiles = (nw + 64 * WPL - 1) / (64 * WPL);
+  const i64 rtiles = (g.M + 4 * RPW - 1) / (4 * RPW);
+  const i64 kwords = words_for(g.K);
+  const i64 tiles = ctiles * rtiles;
+  i64 ksplit = 1;
+  if (tiles < target_blocks && kwords > 1) {
+    ksplit = (target_blocks + tiles - 1) / tiles;
+    if (ksplit > kwords) ksplit = kwords;
   }
+  i64 cps = (kwords + ksplit - 1) / ksplit;
+  if (cps < 1) cps = 1;
+  ksplit = (kwords + cps - 1) / cps;
+  if (ksplit < 1) ksplit = 1;
+  if (ksplit > 1) {
+    // C := Cold (unless C is Cold), D := 0
+    if (g.Cold && g.Cold != g.C) {
+      hipError_t e = launch_ewise(4, g.Cold, g.ldco, nullptr, 0, g.C, g.ldc, g.M, g.N, s);
+      if (e != hipSuccess) return e;
+    } else if (!g.Cold) {
+      hipError_t e = launch_ewise(4, g.C, g.ldc, nullptr, 0, g.C, g.ldc, g.M, 0, s);  // zero C rows
+      if (e != hipSuccess) return e;
+    }
+    if (g.D) {
+      hipError_t e = launch_ewise(4, g.D, g.ldd, nullptr, 0, g.D, g.ldd, g.M, 0, s);  // zero D rows
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm_valu<RPW, WPL>), dim3((unsigned)(tiles * ksplit)), dim3(256), 0, s, g.A, g.lda, g.B,
+                     g.ldb, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed, (int)ksplit, (int)cps);
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// MFMA arm: int8 matrix cores, int32 accumulation, "> 0" threshold.
+//
+// A 0/1 count of witnesses k is at most K < 2^31, so the int32 sum is exact and
+// "sum > 0" is exactly the OR of ANDs.  The operands stay bit-packed in memory;
+// each lane expands the bits it feeds to one v_mfma_i32_16x16x64_i8 into 16
+// bytes of 0/1: dword (h, j) = (half h of the 64-bit word >> j) & 0x01010101
+// holds bits j, j+8, j+16, j+24 of that half.  Lane group g = lane / 16 takes
+// j in {g, g+4} of both halves, so the four groups cover all 64 bits.  A and B
+// use the same bit -> (lane group, byte) map, and a sum over k does not depend
+// on the order of its terms, so the product is exact whatever k order the
+// instruction assigns to (group, byte) -- it only has to be the same for both
+// operands.  B is consumed transposed (B^T rows = columns of B), so that a
+// column's 64 k-bits are one word, like a row of A.
+//
+// Tile: a workgroup of 4 waves owns 256 x 256 outputs, wave (wr, wc) owns a
+// 128 x 128 block = 8 x 8 MFMA blocks of 16 x 16.  Per chunk of kMChunk words
+// of k the workgroup stages 256 rows of A and 256 rows of B^T (bits) in LDS,
+// double-buffered: the next chunk is loaded into registers while the current
+// one is consumed, so one barrier per chunk suffices.
+// A 16 x 16 int32 block sits in lane l as rows 4*(l/16)+v, column l%16
+// (v = 0..3), so a ballot of "acc[v] > 0" holds, in bits 16g..16g+15, the 16
+// output bits of row 4g+v.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMT = 256;     // workgroup tile (rows and columns)
+constexpr int kMChunk = 8;   // words of k per LDS stage
+constexpr int kMPad = 9;     // padded LDS row stride in words (no bank conflicts)
+
+__device__ __forceinline__ v4i_t expand_frag(u64 w, int g) {
+  const u32 lo = (u32)w, hi = (u32)(w >> 32);
+  v4i_t f;
+  f.x = (int)((lo >> g) & 0x01010101u);
+  f.y = (int)((lo >> (g + 4)) & 0x01010101u);
+  f.z = (int)((hi >> g) & 0x01010101u);
+  f.w = (int)((hi >> (g + 4)) & 0x01010101u);
+  return f;
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 ldbt, const u64* __restrict__ Cold,
+            i64 ldco, u64* __restrict__ C, i64 ldc, u64* __restrict__ D, i64 ldd, i64 M, i64 K, i64 N,
+            u32* __restrict__ changed) {
+  // two LDS stages: while one is consumed, the next chunk is already in registers
+  __shared__ u64 As[2][kMT * kMPad];
+  __shared__ u64 Bs[2][kMT * kMPad];
+  __shared__ u64 bal[4][32];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g = lane >> 4, l16 = lane & 15;
+  const i64 ctiles = (N + kMT - 1) / kMT;
+  const i64 tr = blockIdx.x / ctiles, tc = blockIdx.x % ctiles;
+  const i64 row0 = tr * kMT, col0 = tc * kMT;
+  const i64 kwords = (K + 63) >> 6;
+
+  v4i_t acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = v4i_t{0, 0, 0, 0};
+
+  // this thread stages row t of the A tile and row t of the B^T tile
+  const i64 ra = row0 + t, rb = col0 + t;
+  const u64* pa = A + (ra < M ? ra : 0) * lda;
+  const u64* pb = BT + (rb < N ? rb : 0) * ldbt;
+  const bool va = ra < M, vb = rb < N;
+  u64 sa[kMChunk], sb[kMChunk];
+#pragma unroll
+  for (int q = 0; q < kMChunk; ++q) {
+    sa[q] = (va && q < kwords) ? pa[q] : 0ull;
+    sb[q] = (vb && q < kwords) ? pb[q] : 0ull;
+  }
+  int buf = 0;
+  for (i64 kc = 0; kc < kwords; kc += kMChunk, buf ^= 1) {
+#pragma unroll
+    for (int q = 0; q < kMChunk; ++q) {
+      As[buf][t * kMPad + q] = sa[q];
+      Bs[buf][t * kMPad + q] = sb[q];
+    }
+    __syncthreads();
+    const i64 kn = kc + kMChunk;
+    if (kn < kwords) {
+#pragma unroll
+      for (int q = 0; q < kMChunk; ++q) {
+        sa[q] = (va && kn + q < kwords) ? pa[kn + q] : 0ull;
+        sb[q] = (vb && kn + q < kwords) ? pb[kn + q] : 0ull;
+      }
+    }
+    const u64* as = &As[buf][(wr * 128 + l16) * kMPad];
+    const u64* bs = &Bs[buf][(wc * 128 + l16) * kMPad];
+#pragma unroll 2
+    for (int q = 0; q < kMChunk; ++q) {
+      // a wave whose 128 rows have no set bit in this word of k has nothing to add
+      u64 aw[8];
+      int anyw = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        aw[i] = as[i * 16 * kMPad + q];
+        anyw |= aw[i] != 0ull;
+      }
+      if (__ballot(anyw) == 0ull) continue;
+      v4i_t bf[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bf[j] = expand_frag(bs[j * 16 * kMPad + q], g);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const v4i_t af = expand_frag(aw[i], g);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+
+  // epilogue: per block row, ballot "> 0", assemble 16 rows x 2 words, OR with Cold
+  const i64 nw = (N + 63) >> 6;
+  int ch = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const u64 b0 = __ballot(acc[i][j].x > 0);
+      const u64 b1 = __ballot(acc[i][j].y > 0);
+      const u64 b2 = __ballot(acc[i][j].z > 0);
+      const u64 b3 = __ballot(acc[i][j].w > 0);
+      if (lane == 0) {
+        bal[wave][j * 4 + 0] = b0;
+        bal[wave][j * 4 + 1] = b1;
+        bal[wave][j * 4 + 2] = b2;
+        bal[wave][j * 4 + 3] = b3;
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 32) {
+      const int r = lane >> 1, half = lane & 1;  // r = 4 * gg + v
+      const int v = r & 3, gg = r >> 2;
+      u64 word = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const u64 b = bal[wave][(half * 4 + q) * 4 + v];
+        word |= ((b >> (16 * gg)) & 0xFFFFull) << (16 * q);
+      }
+      const i64 row = row0 + wr * 128 + i * 16 + r;
+      const i64 w = (col0 + wc * 128) / 64 + half;
+      if (row < M && w < nw) {
+        const u64 old = Cold ? Cold[row * ldco + w] : 0ull;
+        const u64 nv = word | old;
+        C[row * ldc + w] = nv;
+        if (D) D[row * ldd + w] = nv & ~old;
+        ch |= (nv != old);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (changed) {
+    const u64 any = __ballot(ch);
+    if (any && lane == 0) atomicOr(changed, 1u);
+  }
+}
+
+}  // namespace
+
 hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s) {
-  (void)BT;
-  (void)ldbt;
-  return launch_gemm_valu(g, s);
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const i64 tiles = ((g.M + kMT - 1) / kMT) * ((g.N + kMT - 1) / kMT);
+  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)tiles), dim3(256), 0, s, g.A, g.lda, BT, ldbt, g.Cold, g.ldco, g.C,
+                     g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed);
+  return hipGetLastError();
+}
+
+
+hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  constexpr i64 kTargetBlocks = 1024;  // 4 workgroups per CU on 256 CUs
+  if (g.M <= 64) return launch_rpw<4>(g, s, kTargetBlocks);
+  return launch_rpw<16>(g, s, kTargetBlocks);
 }
 
 }  // namespace bmlp

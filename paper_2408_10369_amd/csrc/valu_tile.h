@@ -1,0 +1,105 @@
+// The bit-packed (VALU) product tile, shared by the single-product kernel and
+// the batched round kernel.
+//
+// Row-OR formulation of the Boolean product (Section 2): C[i,:] |= B[k,:] for
+// every set bit A[i,k].  A workgroup of 256 threads owns a tile of 4*RPW rows
+// x 64*WPL words of the output.  Wave w owns rows row0 .. row0+RPW-1 (row0 is
+// wave-uniform), lane l owns words w0 + l + 64*j (j < WPL).  For each word kw
+// of k (64 values of k) the workgroup stages B[64 kw .. 64 kw + 63, tile words]
+// in LDS; the A word of each of the wave's rows is wave-uniform, so the AND
+// mask for (i, k) is one scalar value and each lane spends one v_and_or_b32 per
+// 32 bit-MACs.  Words of k for which no row of the tile has a set bit are
+// skipped, B staging included (sparse A).
+#pragma once
+#include "bmlp_internal.h"
+
+namespace bmlp {
+
+// all-ones when bit `b` of the wave-uniform word x is set, else zero
+__device__ __forceinline__ u32 bit_mask(u32 x, int b) { return (u32)(((int)(x << (31 - b))) >> 31); }
+
+// acc | (b & m) as one v_and_or_b32 (m is a scalar operand)
+__device__ __forceinline__ u32 and_or(u32 b, u32 m, u32 acc) {
+  u32 r;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(b), "s"(m), "v"(acc));
+  return r;
+}
+
+// acc |= A[row0 .. row0+RPW, k words kw_begin..kw_end) . B[those k, w0 .. w0 + 64 WPL)
+// All threads of the workgroup must call it with the same kw range and w0.
+template <int RPW, int WPL>
+__device__ __forceinline__ void valu_tile_accumulate(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B,
+                                                     i64 ldb, i64 M, i64 K, i64 nw, i64 row0, i64 w0, i64 kw_begin,
+                                                     i64 kw_end, u64 (*Bs)[64 * WPL], u32 (&acc)[RPW][WPL][2]) {
+  constexpr int TW = 64 * WPL;
+  const int lane = threadIdx.x & 63;
+  for (i64 kw = kw_begin; kw < kw_end; ++kw) {
+    u32 alo[RPW], ahi[RPW];
+    u32 any = 0;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const i64 row = row0 + r;
+      const u64 a = (row < M) ? A[row * lda + kw] : 0ull;
+      alo[r] = (u32)a;
+      ahi[r] = (u32)(a >> 32);
+      any |= alo[r] | ahi[r];
+    }
+    if (!__syncthreads_or(any != 0)) continue;
+    for (int idx = threadIdx.x; idx < 64 * TW; idx += 256) {
+      const int t = idx / TW, c = idx - (idx / TW) * TW;
+      const i64 k = kw * 64 + t, w = w0 + c;
+      Bs[t][c] = (k < K && w < nw) ? B[k * ldb + w] : 0ull;
+    }
+    __syncthreads();
+    if (any) {
+#pragma unroll
+      for (int kk = 0; kk < 64; ++kk) {
+        u32 blo[WPL], bhi[WPL];
+#pragma unroll
+        for (int wl = 0; wl < WPL; ++wl) {
+          const u64 b = Bs[kk][lane + 64 * wl];
+          blo[wl] = (u32)b;
+          bhi[wl] = (u32)(b >> 32);
+        }
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const u32 m = bit_mask(kk < 32 ? alo[r] : ahi[r], kk & 31);
+#pragma unroll
+          for (int wl = 0; wl < WPL; ++wl) {
+            acc[r][wl][0] = and_or(blo[wl], m, acc[r][wl][0]);
+            acc[r][wl][1] = and_or(bhi[wl], m, acc[r][wl][1]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// C = Cold | acc for the tile (D = C & ~Cold when D is given); returns whether
+// any word of this lane changed.
+template <int RPW, int WPL>
+__device__ __forceinline__ int valu_tile_store(const u32 (&acc)[RPW][WPL][2], const u64* __restrict__ Cold, i64 ldco,
+                                               u64* __restrict__ C, i64 ldc, u64* __restrict__ D, i64 ldd, i64 M,
+                                               i64 nw, i64 row0, i64 w0) {
+  const int lane = threadIdx.x & 63;
+  int ch = 0;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const i64 row = row0 + r;
+    if (row >= M) break;
+#pragma unroll
+    for (int wl = 0; wl < WPL; ++wl) {
+      const i64 w = w0 + lane + 64 * wl;
+      if (w < nw) {
+        const u64 old = Cold ? Cold[row * ldco + w] : 0ull;
+        const u64 v = (((u64)acc[r][wl][1] << 32) | (u64)acc[r][wl][0]) | old;
+        C[row * ldc + w] = v;
+        if (D) D[row * ldd + w] = v & ~old;
+        ch |= (v != old);
+      }
+    }
+  }
+  return ch;
+}
+
+}  // namespace bmlp

@@ -129,9 +129,22 @@ def test_rms_random(ctx, n, variant):
 def test_rms_first_config(ctx):
     n, s, d, _ = gen.c1()
     R = gpu_pack(ctx, n, s, d)
+    want = oracle.closure_rows(n, s, d)
     for variant in (0, 1):
-        got = host(ctx.rms(R, n, opts=B.make_opts(rms_variant=variant)))
-        assert np.array_equal(got, oracle.closure_rows(n, s, d))
+        for parm in (B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA):
+            got = host(ctx.rms(R, n, opts=B.make_opts(rms_variant=variant, product_arm=parm)))
+            assert np.array_equal(got, want), (variant, parm)
+
+
+@pytest.mark.parametrize("n", [1, 65, 257, 700, 2100])
+def test_rms_mfma_arm(ctx, n):
+    rng = np.random.default_rng(4000 + n)
+    for p in (1.5 / n, 0.05):
+        A, s, d = rand_graph(rng, n, min(p, 1.0))
+        R = gpu_pack(ctx, n, s, d)
+        st = {}
+        got = host(ctx.rms(R, n, opts=B.make_opts(product_arm=B.ARM_PRODUCT_MFMA), stats=st))
+        assert np.array_equal(got, oracle.closure_rows(n, s, d)), (n, p)
 
 
 @pytest.mark.parametrize("n", [2, 3, 5, 9, 17, 100, 1000, 1025])
@@ -174,10 +187,13 @@ def test_rms_padding_words_zeroed(ctx):
 
 
 # ----------------------------------------------------------------- SMP
+@pytest.mark.parametrize("parm", [B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA])
 @pytest.mark.parametrize("reflexive", [0, 1])
 @pytest.mark.parametrize("arm", ARMS_SMP)
 @pytest.mark.parametrize("n", [1, 2, 63, 65, 129, 700, 2000])
-def test_smp_random(ctx, n, arm, reflexive):
+def test_smp_random(ctx, n, arm, reflexive, parm):
+    if parm == B.ARM_PRODUCT_MFMA and arm == B.ARM_SMP_SPARSE:
+        pytest.skip("the sparse arm launches no product")
     rng = np.random.default_rng(2000 + n)
     for p in (1.2 / n, 5.0 / n):
         A, s, d = rand_graph(rng, n, min(p, 1.0))
@@ -188,7 +204,8 @@ def test_smp_random(ctx, n, arm, reflexive):
         Vb = boolops.to_bits(V)
         R = gpu_pack(ctx, n, s, d)
         st = {}
-        got = host(ctx.smp(R, n, dev(Vb), opts=forced(smp_arm=arm, smp_reflexive=reflexive), stats=st))
+        got = host(ctx.smp(R, n, dev(Vb), opts=forced(smp_arm=arm, smp_reflexive=reflexive, product_arm=parm),
+                           stats=st))
         want = oracle.smp(n, s, d, Vb, reflexive=bool(reflexive))
         assert np.array_equal(got, want), (n, p, arm, reflexive)
         assert st["arm"] == arm
@@ -237,14 +254,16 @@ def test_smp_hub_node(ctx):
 
 
 # ----------------------------------------------------------------- composition
+@pytest.mark.parametrize("parm", [B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA])
 @pytest.mark.parametrize("arm", [B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE])
 @pytest.mark.parametrize("n", [1, 3, 64, 65, 300, 1000])
-def test_compose_random(ctx, n, arm):
+def test_compose_random(ctx, n, arm, parm):
     rng = np.random.default_rng(3000 + n)
     for pb, ps in ((0.01, 1.5 / n), (0.002, 3.0 / n), (0.2, 0.01)):
         Bm, bs, bd = rand_graph(rng, n, min(pb, 1.0))
         S, ss, sd = rand_graph(rng, n, min(ps, 1.0))
-        got = host(ctx.compose_linear(gpu_pack(ctx, n, bs, bd), gpu_pack(ctx, n, ss, sd), n, opts=forced(compose_arm=arm)))
+        got = host(ctx.compose_linear(gpu_pack(ctx, n, bs, bd), gpu_pack(ctx, n, ss, sd), n,
+                                      opts=forced(compose_arm=arm, product_arm=parm)))
         assert np.array_equal(got, oracle.compose_rows(n, bs, bd, ss, sd)), (n, pb, ps, arm)
 
 
@@ -290,11 +309,12 @@ def test_isforeign_pipeline(ctx, golden_dir):
 
 
 # ----------------------------------------------------------------- full-size density sweep (sampled)
+@pytest.mark.parametrize("parm", [B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA])
 @pytest.mark.parametrize("pi", [0, 2, 4])
-def test_density_sweep_rms_sampled_rows(ctx, pi):
+def test_density_sweep_rms_sampled_rows(ctx, pi, parm):
     n, s, d = gen.c2(pi)
     R = gpu_pack(ctx, n, s, d)
-    got = host(ctx.rms(R, n))
+    got = host(ctx.rms(R, n, opts=B.make_opts(product_arm=parm)))
     rng = np.random.default_rng(77 + pi)
     rows = np.sort(rng.choice(n, 96, replace=False))
     assert np.array_equal(got[rows], oracle.closure_rows(n, s, d, rows=rows))
