@@ -77,7 +77,9 @@ typedef enum {
   BMLP_ARM_SMP_SPARSE = 3,    /* selection by sparse-frontier expansion, whole fixpoint per row in one launch */
   BMLP_ARM_SMP_CLOSURE = 4,   /* selection as V . R1+ after BMLP-RMS (closure reuse, Section 4) */
   BMLP_ARM_COMPOSE_RMS = 5,   /* compose: Rs+ by BMLP-RMS, then P = Rb | Rs+ . Rb */
-  BMLP_ARM_COMPOSE_SEMINAIVE = 6 /* compose: P = Rb; delta' = (Rs . delta) & ~P until empty */
+  BMLP_ARM_COMPOSE_SEMINAIVE = 6, /* compose: P^T = Rb^T (Rs^T)*, reflexive selections over the transposed step */
+  BMLP_ARM_SMP_SPARSE_ROUNDS = 7, /* selection by rounds, every round by sparse-frontier expansion */
+  BMLP_ARM_SMP_ADAPTIVE = 8   /* selection by rounds, each round's kernel chosen on the device by the model */
 } bmlp_arm;
 
 typedef enum {
@@ -204,6 +206,64 @@ typedef struct {
    different descriptors must not overlap. */
 bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc *graphs, int32_t count, const bmlp_opts *opts,
                          void *stream, bmlp_stats *stats);
+
+/* ------------------------------------------------------------ sessions over one relation */
+/* A session answers a stream of selections over one relation R1 (n x n, ld; the caller keeps it
+   alive and unchanged while the session is open).  It keeps the relation's CSR and statistics and,
+   once computed, its closure R1+, so that later queries are answered by reading rows of the closure
+   (reuse of intermediate results, Section 4).  Under the plain schedule a session never computes
+   the closure; under the learned schedule it does so when the model's predicted cost of the
+   closure falls below the time already spent answering this relation's queries iteratively
+   (ski-rental rule).  The session owns its closure buffer (n x ceil(n/64) words). */
+typedef struct bmlp_graph_s *bmlp_graph;
+bmlp_status bmlp_graph_open(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, void *stream, bmlp_graph *g);
+/* Vstar = V x R1+ (Eq. 5), like bmlp_smp; stats->arm tells which arm answered. */
+bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t *V, uint64_t *Vstar, int64_t k, int64_t ldv,
+                             const bmlp_opts *opts, void *stream, bmlp_stats *stats);
+/* Whether the session holds the closure (1) or not (0). */
+int32_t bmlp_graph_has_closure(bmlp_graph g);
+bmlp_status bmlp_graph_close(bmlp_graph g);
+
+/* ------------------------------------------------------------ the learned dispatcher */
+/* The dispatcher is a small FP32 network (16 features -> 64 -> 64 -> 4 outputs, ReLU) predicting
+   the log device time (ms) of kernel arms.  Outputs mean, for a round-level query (feature 8 = 0):
+   [0] one round by the dense product, [1] one round by sparse-frontier expansion; for a call-level
+   query (feature 8 = 1): [0] the whole selection by rounds, [2] by the closure, [3] by the
+   one-launch sparse-frontier kernel.  It chooses kernels only; every arm returns the same bits. */
+typedef struct {
+  int32_t rounds;             /* rounds recorded (at most 64) */
+  int32_t call_arm;           /* arm that served the call */
+  int32_t arm[64];            /* arm of each round (BMLP_ARM_SMP_DENSE or _SMP_SPARSE) */
+  float round_ms[64];         /* device time of each round */
+  float features[64][16];     /* round-level features at the start of each round */
+  float call_features[16];    /* call-level features */
+  float pred[64][4];          /* model outputs per round (learned schedule) */
+  float call_pred[4];         /* model outputs for the call decision (learned schedule) */
+  float total_ms;             /* device time of the whole call */
+} bmlp_trace;
+/* Record per-round features and timings of subsequent selection calls into *trace (owned by the
+   caller; NULL stops recording).  Recording synchronises after every round. */
+bmlp_status bmlp_set_trace(bmlp_handle h, bmlp_trace *trace);
+/* Load / save the dispatcher model (versioned header + CRC-32).  A missing, corrupt or mismatched
+   file gives BMLP_EMODEL and leaves the handle's model unchanged; without a model the learned
+   schedule falls back to the plain one. */
+bmlp_status bmlp_dispatcher_load(bmlp_handle h, const char *path);
+bmlp_status bmlp_dispatcher_save(bmlp_handle h, const char *path);
+/* 1 when the handle has a model. */
+int32_t bmlp_dispatcher_loaded(bmlp_handle h);
+/* Train the handle's model on the GPU (hand-written forward, backward and Adam kernels), full batch:
+   X rows x 16 features, T rows x 4 targets (log ms), M rows x 4 mask (1 = target present); host
+   arrays.  Inputs are standardised with the data's mean and deviation, parameters initialised from
+   `seed`.  *loss_out receives the final masked mean-squared error. */
+bmlp_status bmlp_dispatcher_train(bmlp_handle h, const float *X, const float *T, const float *M, int64_t rows,
+                                  int32_t epochs, float lr, uint64_t seed, float *loss_out);
+/* Y (rows x 4) = model outputs for X (rows x 16); host arrays, GPU compute. */
+bmlp_status bmlp_dispatcher_forward(bmlp_handle h, const float *X, int64_t rows, float *Y);
+/* One forward and backward pass on the GPU with the given parameters (5,508 floats in the layout
+   W1[64][16] b1[64] W2[64][64] b2[64] W3[4][64] b3[4]) and standardisation (mu, sd: 16 each):
+   *loss = masked mean-squared error, grad (5,508) = its gradient.  Host arrays. */
+bmlp_status bmlp_mlp_loss_grad(bmlp_handle h, const float *params, const float *mu, const float *sd, const float *X,
+                               const float *T, const float *M, int64_t rows, float *loss, float *grad);
 
 #ifdef __cplusplus
 }

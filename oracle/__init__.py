@@ -19,6 +19,9 @@ Contents
 * ``boolops``: Boolean matrix addition, multiplication, transpose and
   negation (Section 2) on dense 0/1 arrays, and the oracle's own conversion
   between dense 0/1 arrays and the LSB-first uint64 bit rows.
+* ``mlp``: FP64 forward pass, masked MSE loss and its gradient for the
+  dispatcher network (the reference its GPU training kernels are checked
+  against).
 """
 from __future__ import annotations
 
@@ -140,4 +143,4 @@ def warshall(bits, n):
     return R
 
 
-from . import boolops, algorithms, datalog  # noqa: E402,F401
+from . import boolops, algorithms, datalog, mlp  # noqa: E402,F401

@@ -26,14 +26,37 @@ ARM_AUTO = -1
 ARM_PRODUCT_VALU, ARM_PRODUCT_MFMA = 0, 1
 ARM_SMP_DENSE, ARM_SMP_SPARSE, ARM_SMP_CLOSURE = 2, 3, 4
 ARM_COMPOSE_RMS, ARM_COMPOSE_SEMINAIVE = 5, 6
+ARM_SMP_SPARSE_ROUNDS, ARM_SMP_ADAPTIVE = 7, 8
 DISPATCH_PLAIN, DISPATCH_LEARNED, DISPATCH_FORCED = 0, 1, 2
+N_FEATURES, N_OUTPUTS, N_PARAMS = 16, 4, 5508
 
 EXPORTS = [
     "bmlp_create", "bmlp_destroy", "bmlp_last_error", "bmlp_opts_init", "bmlp_version",
     "bmlp_pack_u8", "bmlp_pack_coo", "bmlp_unpack_u8",
     "bmlp_or", "bmlp_and", "bmlp_andnot", "bmlp_not", "bmlp_transpose", "bmlp_product",
     "bmlp_rms", "bmlp_smp", "bmlp_compose_linear", "bmlp_batched",
+    "bmlp_graph_open", "bmlp_graph_query", "bmlp_graph_has_closure", "bmlp_graph_close",
+    "bmlp_set_trace", "bmlp_dispatcher_load", "bmlp_dispatcher_save", "bmlp_dispatcher_loaded",
+    "bmlp_dispatcher_train", "bmlp_dispatcher_forward", "bmlp_mlp_loss_grad",
 ]
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("call_arm", ctypes.c_int32), ("arm", ctypes.c_int32 * 64),
+                ("round_ms", ctypes.c_float * 64), ("features", (ctypes.c_float * 16) * 64),
+                ("call_features", ctypes.c_float * 16), ("pred", (ctypes.c_float * 4) * 64),
+                ("call_pred", ctypes.c_float * 4), ("total_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        import numpy as np
+        r = int(self.rounds)
+        return {"rounds": r, "call_arm": int(self.call_arm), "arm": [int(a) for a in self.arm[:r]],
+                "round_ms": [float(x) for x in self.round_ms[:r]],
+                "features": np.array([[float(v) for v in self.features[i]] for i in range(r)], np.float32),
+                "call_features": np.array([float(v) for v in self.call_features], np.float32),
+                "pred": np.array([[float(v) for v in self.pred[i]] for i in range(r)], np.float32),
+                "call_pred": np.array([float(v) for v in self.call_pred], np.float32),
+                "total_ms": float(self.total_ms)}
 
 
 class GraphDesc(ctypes.Structure):
@@ -103,9 +126,23 @@ def lib():
     L.bmlp_smp.argtypes = [vp, vp, i64, i64, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_compose_linear.argtypes = [vp, vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_batched.argtypes = [vp, P(GraphDesc), ctypes.c_int32, P(Opts), vp, P(Stats)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.bmlp_graph_open.argtypes = [vp, vp, i64, i64, vp, P(vp)]
+    L.bmlp_graph_query.argtypes = [vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
+    L.bmlp_graph_has_closure.argtypes = [vp]
+    L.bmlp_graph_close.argtypes = [vp]
+    L.bmlp_set_trace.argtypes = [vp, P(Trace)]
+    L.bmlp_dispatcher_load.argtypes = [vp, ctypes.c_char_p]
+    L.bmlp_dispatcher_save.argtypes = [vp, ctypes.c_char_p]
+    L.bmlp_dispatcher_loaded.argtypes = [vp]
+    L.bmlp_dispatcher_train.argtypes = [vp, fp, fp, fp, i64, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, fp]
+    L.bmlp_dispatcher_forward.argtypes = [vp, fp, i64, fp]
+    L.bmlp_mlp_loss_grad.argtypes = [vp, fp, fp, fp, fp, fp, fp, i64, fp, fp]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("bmlp_last_error", "bmlp_opts_init", "bmlp_version"):
+        if name in ("bmlp_graph_has_closure", "bmlp_dispatcher_loaded"):
+            f.restype = ctypes.c_int32
+        elif name not in ("bmlp_last_error", "bmlp_opts_init", "bmlp_version"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -321,3 +358,109 @@ class Context:
         if st is not None:
             stats.update(st.as_dict())
         return graphs
+
+    # -------------------------------------------------------------- the learned dispatcher
+    def set_trace(self, trace):
+        """Record per-round features and timings into ``trace`` (a Trace) or stop (None)."""
+        self._trace = trace
+        _check(lib().bmlp_set_trace(self._h, ctypes.byref(trace) if trace is not None else None))
+
+    def dispatcher_loaded(self) -> bool:
+        return bool(lib().bmlp_dispatcher_loaded(self._h))
+
+    def dispatcher_load(self, path: str):
+        _check(lib().bmlp_dispatcher_load(self._h, os.fsencode(path)))
+
+    def dispatcher_save(self, path: str):
+        _check(lib().bmlp_dispatcher_save(self._h, os.fsencode(path)))
+
+    @staticmethod
+    def _f32(a, shape):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if a.shape != shape:
+            raise ValueError(f"expected shape {shape}, got {a.shape}")
+        return a
+
+    def dispatcher_train(self, X, T, M, epochs=2000, lr=3e-3, seed=0):
+        import numpy as np
+        X = self._f32(X, (len(X), N_FEATURES))
+        T = self._f32(T, (len(X), N_OUTPUTS))
+        M = self._f32(M, (len(X), N_OUTPUTS))
+        loss = ctypes.c_float(0.0)
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(lib().bmlp_dispatcher_train(self._h, X.ctypes.data_as(fp), T.ctypes.data_as(fp), M.ctypes.data_as(fp),
+                                           len(X), int(epochs), float(lr), int(seed), ctypes.byref(loss)))
+        return float(loss.value)
+
+    def dispatcher_forward(self, X):
+        import numpy as np
+        X = self._f32(X, (len(X), N_FEATURES))
+        Y = np.zeros((len(X), N_OUTPUTS), np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(lib().bmlp_dispatcher_forward(self._h, X.ctypes.data_as(fp), len(X), Y.ctypes.data_as(fp)))
+        return Y
+
+    def mlp_loss_grad(self, params, mu, sd, X, T, M):
+        import numpy as np
+        fp = ctypes.POINTER(ctypes.c_float)
+        P = self._f32(params, (N_PARAMS,))
+        mu = self._f32(mu, (N_FEATURES,))
+        sd = self._f32(sd, (N_FEATURES,))
+        X = self._f32(X, (len(X), N_FEATURES))
+        T = self._f32(T, (len(X), N_OUTPUTS))
+        M = self._f32(M, (len(X), N_OUTPUTS))
+        loss = ctypes.c_float(0.0)
+        G = np.zeros(N_PARAMS, np.float32)
+        _check(lib().bmlp_mlp_loss_grad(self._h, P.ctypes.data_as(fp), mu.ctypes.data_as(fp), sd.ctypes.data_as(fp),
+                                        X.ctypes.data_as(fp), T.ctypes.data_as(fp), M.ctypes.data_as(fp), len(X),
+                                        ctypes.byref(loss), G.ctypes.data_as(fp)))
+        return float(loss.value), G
+
+    # -------------------------------------------------------------- sessions
+    def graph(self, R1, n: int, stream=None):
+        return Session(self, R1, n, stream)
+
+
+class Session:
+    """A stream of selections over one relation (closure kept once computed)."""
+
+    def __init__(self, ctx: Context, R1, n: int, stream=None):
+        _, ld = _bits_shape(R1, n)
+        self.ctx, self.R1, self.n = ctx, R1, n
+        g = ctypes.c_void_p()
+        _check(lib().bmlp_graph_open(ctx._h, _ptr(R1), n, ld, _stream(stream), ctypes.byref(g)))
+        self._g = g
+
+    def query(self, V, out=None, opts=None, stream=None, stats=None):
+        k, ldv = _bits_shape(V)
+        if out is None:
+            out = self.ctx.zeros(k, self.n, ldv)
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_graph_query(self._g, _ptr(V), _ptr(out), k, ldv,
+                                      ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                      ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return out
+
+    @property
+    def has_closure(self) -> bool:
+        return bool(lib().bmlp_graph_has_closure(self._g))
+
+    def close(self):
+        if getattr(self, "_g", None):
+            lib().bmlp_graph_close(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -3,8 +3,11 @@
 // in the kernels of k_bits.hip, k_gemm.hip and k_smp.hip.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -13,6 +16,7 @@
 
 #include "../../include/bmlp.h"
 #include "bmlp_batch.h"
+#include "bmlp_mlp.h"
 #include "bmlp_internal.h"
 
 using namespace bmlp;
@@ -54,9 +58,29 @@ struct bmlp_ctx {
   hipGraph_t bgraph = nullptr;
   hipGraphExec_t bexec = nullptr;
   uint64_t bkey = 0;
+  // dispatcher model on the device: params (5,508) | mu (16) | sd (16); host copy beside it
+  float* d_model = nullptr;
+  bool model = false;
+  std::vector<float> h_model;
+  bmlp_trace* trace = nullptr;
 };
 
 namespace {
+
+// Slots of the handle's small device flag buffer (and its pinned host mirror), in 32-bit words.
+enum FlagSlot {
+  F_CHANGED = 0,   // change flag of the current product / round
+  F_PAD = 1,       // padding check
+  F_ROUNDS = 2,    // rounds of the one-launch sparse selection
+  F_COO = 3,       // out-of-range fact in packing
+  F_CNT = 4,       // 64-bit bit count
+  F_NEW = 6,       // 64-bit count of new bits of a round
+  F_DEC = 8,       // dispatcher decision
+  F_PRED = 12,     // 4 predicted log times
+  F_FEAT = 16,     // 16 features
+  F_GSTATS = 32,   // 3 x 64-bit graph statistics
+  F_WORDS = 128
+};
 
 enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH };
 
@@ -308,7 +332,7 @@ i64 count_bits(bmlp_ctx* c, const u64* R, i64 rows, i64 n, i64 ld, hipStream_t s
   return (i64)m;
 }
 
-// Plain schedule for the selection, from a timing sweep of the three arms on
+// Plain schedule for the selection, from a timing sweep of the arms on
 // n = 16,384 random digraphs (mean out-degree 1.6 .. 164, k = 1 .. 1024): the
 // sparse-frontier arm wins while the mean out-degree is low (its work grows with
 // the edges it visits); the dense semi-naive arm wins on dense relations (its
@@ -321,20 +345,196 @@ int smp_plain_arm(i64 n, i64 k, i64 m) {
   return BMLP_ARM_SMP_DENSE;
 }
 
-// Vstar = V . R1+ (or V . R1* when reflexive).
-void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vstar, i64 k, i64 ldv, int reflexive,
-              int arm, const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
+// ------------------------------------------------------------ dispatcher features
+struct GraphInfo {
+  i64 n = 0, m = 0, maxdeg = 0, nonempty = 0;
+};
+
+GraphInfo graph_info(bmlp_ctx* c, const u64* R, i64 ld, i64 n, hipStream_t s) {
+  GraphInfo g;
+  g.n = n;
+  if (n <= 0) return g;
+  unsigned long long* out = (unsigned long long*)(c->d_flags + F_GSTATS);
+  hip_check(hipMemsetAsync(out, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
+  hip_check(launch_graph_stats(R, n, n, ld, out, s), "graph_stats");
+  hip_check(hipMemcpyAsync(c->h_flags + F_GSTATS, out, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+            "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");
+  unsigned long long v[3];
+  std::memcpy(v, c->h_flags + F_GSTATS, sizeof v);
+  g.m = (i64)v[0];
+  g.maxdeg = (i64)v[1];
+  g.nonempty = (i64)v[2];
+  return g;
+}
+
+// The 16 dispatcher features (all O(1) to compute from counters the drivers keep):
+//  0 log2(1+n)/16            1 log2(1+m)/24             2 log2(1+m/n)/8 (mean degree)
+//  3 log2(1+maxdeg/(1+m/n))/8 (degree skew)             4 nonempty rows / n
+//  5 log2(1+k)/16            6 min(k/n, 4)              7 composition request (0/1)
+//  8 call-level query (1) or round-level query (0)       9 round / 64
+// 10 |delta| / (k n)         11 |visited| / (k n)        12 log2(1+|delta|)/32
+// 13 min(|delta| / |previous delta|, 16) / 16            14 log2(1 + |delta| m/n)/40 (edges to visit)
+// 15 reflexive answer (0/1)
+void make_features(float* f, const GraphInfo& g, i64 k, int compose, int call_level, int round, double delta,
+                   double prev_delta, double vis, int reflexive) {
+  const double n = (double)std::max<i64>(g.n, 1), m = (double)g.m, kk = (double)std::max<i64>(k, 1);
+  const double deg = m / n;
+  f[0] = (float)(std::log2(1.0 + n) / 16.0);
+  f[1] = (float)(std::log2(1.0 + m) / 24.0);
+  f[2] = (float)(std::log2(1.0 + deg) / 8.0);
+  f[3] = (float)(std::log2(1.0 + (double)g.maxdeg / (1.0 + deg)) / 8.0);
+  f[4] = (float)((double)g.nonempty / n);
+  f[5] = (float)(std::log2(1.0 + (double)k) / 16.0);
+  f[6] = (float)std::min(4.0, (double)k / n);
+  f[7] = compose ? 1.f : 0.f;
+  f[8] = call_level ? 1.f : 0.f;
+  f[9] = (float)(round / 64.0);
+  f[10] = (float)(delta / (kk * n));
+  f[11] = (float)(vis / (kk * n));
+  f[12] = (float)(std::log2(1.0 + delta) / 32.0);
+  f[13] = (float)(std::min(16.0, delta / std::max(prev_delta, 1.0)) / 16.0);
+  f[14] = (float)(std::log2(1.0 + delta * deg) / 40.0);
+  f[15] = reflexive ? 1.f : 0.f;
+}
+
+struct Csr {
+  const i64* rp = nullptr;
+  const int32_t* ci = nullptr;
+};
+
+// model inference for one feature vector on the device; returns the chosen output index
+int model_decide(bmlp_ctx* c, const float* f, u32 allowed, hipStream_t s, float* pred_out) {
+  std::memcpy(c->h_flags + F_FEAT, f, kIn * sizeof(float));
+  hip_check(hipMemcpyAsync(c->d_flags + F_FEAT, c->h_flags + F_FEAT, kIn * sizeof(float), hipMemcpyHostToDevice, s),
+            "memcpy");
+  hip_check(launch_mlp_decide(c->d_model, c->d_model + kParams, c->d_model + kParams + kIn,
+                              (const float*)(c->d_flags + F_FEAT), (float*)(c->d_flags + F_PRED), c->d_flags + F_DEC,
+                              allowed, s),
+            "mlp_decide");
+  hip_check(hipMemcpyAsync(c->h_flags + F_DEC, c->d_flags + F_DEC, 8 * sizeof(u32), hipMemcpyDeviceToHost, s),
+            "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");
+  if (pred_out) std::memcpy(pred_out, c->h_flags + F_PRED, 4 * sizeof(float));
+  return (int)c->h_flags[F_DEC];
+}
+
+enum RoundMode { RM_DENSE = 0, RM_SPARSE = 1, RM_LEARNED = 2 };
+
+// The selection by semi-naive rounds: the selection of Eq. 5 pushed into the sum (v R1, v R1^2, ...),
+// with every new bit expanded exactly once.  State in global memory: the frontier fr (k x nw) and the
+// visited set vis, kept in Vstar.  Round: nxt = fr . R1, fr' = nxt & ~vis, vis |= fr'; it stops when
+// fr' is empty (Algorithm 2's v* = v' test, the iterates being monotone).  The state is the same
+// whichever arm serves a round, so each round may be served by the dense product or by sparse-frontier
+// expansion; in learned mode the model chooses on the device, round by round.
+void smp_rounds(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vstar, i64 k, i64 ldv, int reflexive,
+                int mode, const GraphInfo& gi, int compose, Csr csr, const bmlp_opts& o, hipStream_t s,
+                StatsRec& sr) {
   const i64 nw = words_for(n);
+  u64* fa = ws_bits(c, S_W3, k, nw, o);
+  u64* fb = ws_bits(c, S_W4, k, nw, o);
   const int parm = product_arm(o, k, n);
-  if (sr.st) sr.st->arm = arm;
-  if (arm == BMLP_ARM_SMP_SPARSE) {
-    need(n <= smp_rows_max_n(), BMLP_EINVAL, "sparse SMP arm supports n <= %lld", (long long)smp_rows_max_n());
+  const bool learned = mode == RM_LEARNED;
+  if ((mode == RM_SPARSE || learned) && !csr.rp) {
     i64* rp;
     int32_t* ci;
     build_csr(c, R1, ld, n, o, s, &rp, &ci);
-    hip_check(hipMemsetAsync(c->d_flags + 2, 0, sizeof(u32), s), "hipMemsetAsync");
-    hip_check(launch_smp_rows(V, ldv, k, rp, ci, R1, ld, n, reflexive, Vstar, ldv, c->d_flags + 2, s), "smp_rows");
-    const u32 rounds = read_flag(c, s, 2);
+    csr.rp = rp;
+    csr.ci = ci;
+  }
+  const u64* r1t = nullptr;
+  i64 ldr1t = 0;
+  if (mode != RM_SPARSE && parm == BMLP_ARM_PRODUCT_MFMA) r1t = transpose_b(c, R1, ld, n, n, o, s, &ldr1t);
+  // state 0: fr = V, vis = 0 (or V for the reflexive answer)
+  hip_check(launch_ewise(4, V, ldv, nullptr, 0, fa, nw, k, n, s), "copy");
+  if (reflexive) hip_check(launch_ewise(4, V, ldv, nullptr, 0, Vstar, ldv, k, n, s), "copy");
+  else hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
+  double delta = (double)count_bits(c, V, k, n, ldv, s);
+  double prev = delta, vis = reflexive ? delta : 0.0;
+  bmlp_trace* tr = c->trace;
+  float f[kIn];
+  int t = 0;
+  for (;; ++t) {
+    need(t <= n + 1, BMLP_EITER, "selection exceeded %lld rounds", (long long)(n + 1));
+    hip_check(hipMemsetAsync(c->d_flags, 0, 8 * sizeof(u32), s), "hipMemsetAsync");
+    if (tr) hip_check(hipEventRecord(c->evp0, s), "hipEventRecord");
+    make_features(f, gi, k, compose, 0, t, delta, prev, vis, reflexive);
+    const u32* pred = nullptr;
+    if (learned) {
+      std::memcpy(c->h_flags + F_FEAT, f, kIn * sizeof(float));
+      hip_check(hipMemcpyAsync(c->d_flags + F_FEAT, c->h_flags + F_FEAT, kIn * sizeof(float), hipMemcpyHostToDevice,
+                               s),
+                "memcpy");
+      hip_check(launch_mlp_decide(c->d_model, c->d_model + kParams, c->d_model + kParams + kIn,
+                                  (const float*)(c->d_flags + F_FEAT), (float*)(c->d_flags + F_PRED),
+                                  c->d_flags + F_DEC, 0x3u, s),
+                "mlp_decide");
+      pred = c->d_flags + F_DEC;
+    }
+    unsigned long long* nb = (unsigned long long*)(c->d_flags + F_NEW);
+    if (mode != RM_SPARSE) {
+      GemmArgs g{fa, nw, R1, ld, Vstar, ldv, Vstar, ldv, fb, nw, k, n, n, c->d_flags + F_CHANGED};
+      g.newbits = nb;
+      g.pred = pred;
+      g.pred_val = 0;
+      if (parm == BMLP_ARM_PRODUCT_MFMA) hip_check(launch_gemm_mfma(g, r1t, ldr1t, s), "gemm_mfma");
+      else hip_check(launch_gemm_valu(g, s), "gemm_valu");
+    }
+    if (mode != RM_DENSE)
+      hip_check(launch_smp_round(fa, fb, nw, Vstar, ldv, k, csr.rp, csr.ci, R1, ld, n, c->d_flags + F_CHANGED, nb,
+                                 pred, 1u, s),
+                "smp_round");
+    if (tr) hip_check(hipEventRecord(c->evp1, s), "hipEventRecord");
+    hip_check(hipMemcpyAsync(c->h_flags, c->d_flags, 16 * sizeof(u32), hipMemcpyDeviceToHost, s), "memcpy");
+    hip_check(hipStreamSynchronize(s), "sync");
+    const u32 changed = c->h_flags[F_CHANGED];
+    unsigned long long newbits = 0;
+    std::memcpy(&newbits, c->h_flags + F_NEW, sizeof newbits);
+    const int arm = learned ? (c->h_flags[F_DEC] == 0 ? BMLP_ARM_SMP_DENSE : BMLP_ARM_SMP_SPARSE)
+                            : (mode == RM_DENSE ? BMLP_ARM_SMP_DENSE : BMLP_ARM_SMP_SPARSE);
+    sr.trace(t, arm);
+    if (sr.st && arm == BMLP_ARM_SMP_DENSE) {
+      sr.st->products += 1;
+      sr.st->bool_ops += (uint64_t)2 * (uint64_t)k * (uint64_t)n * (uint64_t)n;
+    }
+    if (tr && t < 64) {
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, c->evp0, c->evp1), "hipEventElapsedTime");
+      tr->round_ms[t] = ms;
+      tr->arm[t] = arm;
+      std::memcpy(tr->features[t], f, sizeof f);
+      if (learned) std::memcpy(tr->pred[t], c->h_flags + F_PRED, 4 * sizeof(float));
+      tr->rounds = t + 1;
+    }
+    prev = delta;
+    delta = (double)newbits;
+    vis += (double)newbits;
+    std::swap(fa, fb);
+    if (!changed) break;
+  }
+  if (sr.st) sr.st->iterations = t + 1;
+  hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
+}
+
+// Vstar = V . R1+ (or V . R1* when reflexive) by the given call-level arm.
+void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vstar, i64 k, i64 ldv, int reflexive,
+              int arm, const GraphInfo& gi, int compose, Csr csr, const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
+  const i64 nw = words_for(n);
+  if (sr.st) sr.st->arm = arm;
+  if (c->trace) c->trace->call_arm = arm;
+  if (arm == BMLP_ARM_SMP_SPARSE) {
+    need(n <= smp_rows_max_n(), BMLP_EINVAL, "sparse SMP arm supports n <= %lld", (long long)smp_rows_max_n());
+    if (!csr.rp) {
+      i64* rp;
+      int32_t* ci;
+      build_csr(c, R1, ld, n, o, s, &rp, &ci);
+      csr.rp = rp;
+      csr.ci = ci;
+    }
+    hip_check(hipMemsetAsync(c->d_flags + F_ROUNDS, 0, sizeof(u32), s), "hipMemsetAsync");
+    hip_check(launch_smp_rows(V, ldv, k, csr.rp, csr.ci, R1, ld, n, reflexive, Vstar, ldv, c->d_flags + F_ROUNDS, s),
+              "smp_rows");
+    const u32 rounds = read_flag(c, s, F_ROUNDS);
     need((i64)rounds <= n + 2, BMLP_EITER, "SMP exceeded the round cap");
     if (sr.st) {
       sr.st->iterations = (int32_t)rounds;
@@ -346,37 +546,34 @@ void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vsta
     u64* clo = ws_bits(c, S_W2, n, nw, o);
     rms_core(c, R1, ld, clo, nw, n, o, s, sr);
     // V . R1+ (strict) or V | V . R1+ (reflexive)
-    product(c, V, ldv, clo, nw, reflexive ? V : nullptr, ldv, Vstar, ldv, nullptr, 0, k, n, n, nullptr, parm, s, sr);
+    product(c, V, ldv, clo, nw, reflexive ? V : nullptr, ldv, Vstar, ldv, nullptr, 0, k, n, n, nullptr,
+            product_arm(o, k, n), s, sr);
     hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
     return;
   }
-  // dense semi-naive: delta_0 = V.R1 (strict) or V (reflexive); then
-  // delta' = (delta . R1) & ~Vis ; Vis |= delta' until delta' is empty.
-  u64* da = ws_bits(c, S_W3, k, nw, o);
-  u64* db = ws_bits(c, S_W4, k, nw, o);
-  const u64* r1t = nullptr;
-  i64 ldr1t = 0;
-  if (parm == BMLP_ARM_PRODUCT_MFMA) r1t = transpose_b(c, R1, ld, n, n, o, s, &ldr1t);
-  int it = 0;
-  if (reflexive) {
-    hip_check(launch_ewise(4, V, ldv, nullptr, 0, Vstar, ldv, k, n, s), "copy");
-    hip_check(launch_ewise(4, V, ldv, nullptr, 0, da, nw, k, n, s), "copy");
-  } else {
-    product(c, V, ldv, R1, ld, nullptr, 0, Vstar, ldv, da, nw, k, n, n, nullptr, parm, s, sr, r1t, ldr1t);
-    sr.trace(it++, arm);
+  const int mode = arm == BMLP_ARM_SMP_DENSE ? RM_DENSE : arm == BMLP_ARM_SMP_SPARSE_ROUNDS ? RM_SPARSE : RM_LEARNED;
+  need(mode != RM_LEARNED || c->model, BMLP_EMODEL, "the adaptive arm needs a dispatcher model");
+  smp_rounds(c, R1, ld, n, V, Vstar, k, ldv, reflexive, mode, gi, compose, csr, o, s, sr);
+}
+
+// Call-level arm of a selection: forced, plain rule, or the model's choice among the rounds arm
+// (per-round choice), the closure arm and the one-launch sparse arm.
+int smp_choose_arm(bmlp_ctx* c, const bmlp_opts& o, const GraphInfo& gi, i64 k, int compose, int reflexive,
+                   double delta0, hipStream_t s, float* pred_out) {
+  float f[kIn];
+  make_features(f, gi, k, compose, 1, 0, delta0, delta0, reflexive ? delta0 : 0.0, reflexive);
+  if (c->trace) std::memcpy(c->trace->call_features, f, sizeof f);
+  if (o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO) return o.smp_arm;
+  if (o.dispatch == BMLP_DISPATCH_LEARNED && c->model) {
+    u32 allowed = 0x5u;  // rounds, closure
+    if (gi.n <= smp_rows_max_n()) allowed |= 0x8u;  // one-launch sparse
+    float pred[4];
+    const int d = model_decide(c, f, allowed, s, pred);
+    if (pred_out) std::memcpy(pred_out, pred, sizeof pred);
+    if (c->trace) std::memcpy(c->trace->call_pred, pred, sizeof pred);
+    return d == 2 ? BMLP_ARM_SMP_CLOSURE : d == 3 ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_ADAPTIVE;
   }
-  const i64 cap = n + 2;
-  for (;;) {
-    zero_flag(c, s);
-    product(c, da, nw, R1, ld, Vstar, ldv, Vstar, ldv, db, nw, k, n, n, c->d_flags, parm, s, sr, r1t, ldr1t);
-    sr.trace(it++, arm);
-    const u32 changed = read_flag(c, s);
-    std::swap(da, db);
-    if (!changed) break;
-    need(it < cap, BMLP_EITER, "SMP exceeded %lld rounds", (long long)cap);
-  }
-  if (sr.st) sr.st->iterations = it;
-  hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
+  return smp_plain_arm(gi.n, k, gi.m);
 }
 
 template <class F>
@@ -430,16 +627,30 @@ bmlp_status bmlp_create(bmlp_handle* h, int device) {
     DeviceGuard dg(device);
     bmlp_ctx* c = new bmlp_ctx;
     c->device = device;
-    if (hipMalloc((void**)&c->d_flags, 64 * sizeof(u32)) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_flags, 64 * sizeof(u32), hipHostMallocDefault) != hipSuccess ||
+    if (hipMalloc((void**)&c->d_flags, F_WORDS * sizeof(u32)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_flags, F_WORDS * sizeof(u32), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipEventCreate(&c->evp0) != hipSuccess || hipEventCreate(&c->evp1) != hipSuccess) {
       (void)hipGetLastError();
       bmlp_destroy(c);
       fail(BMLP_ENOMEM, "handle allocation failed");
     }
-    hip_check(hipMemset(c->d_flags, 0, 64 * sizeof(u32)), "hipMemset");
+    hip_check(hipMemset(c->d_flags, 0, F_WORDS * sizeof(u32)), "hipMemset");
     *h = c;
+    // default dispatcher model: $BMLP_DISPATCHER_MODEL, else dispatcher_model.bin beside the library
+    // (an empty variable disables it); a missing or bad file leaves the plain schedule in force
+    std::string path;
+    if (const char* env = std::getenv("BMLP_DISPATCHER_MODEL")) {
+      path = env;
+    } else {
+      Dl_info info;
+      if (dladdr((const void*)&bmlp_create, &info) && info.dli_fname) {
+        path = info.dli_fname;
+        const size_t slash = path.find_last_of('/');
+        path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/dispatcher_model.bin";
+      }
+    }
+    if (!path.empty() && bmlp_dispatcher_load(c, path.c_str()) != BMLP_OK) g_last_error.clear();
   });
 }
 
@@ -457,6 +668,7 @@ bmlp_status bmlp_destroy(bmlp_handle h) {
       if (h->ev1) (void)hipEventDestroy(h->ev1);
       if (h->evp0) (void)hipEventDestroy(h->evp0);
       if (h->evp1) (void)hipEventDestroy(h->evp1);
+      if (h->d_model) (void)hipFree(h->d_model);
       if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
       if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
       if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
@@ -626,24 +838,34 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, c
     need(!overlap(rv, range_of(V, k, ldv)), BMLP_EALIAS, "Vstar overlaps V");
     need(!overlap(rv, range_of(R1, n, ld)), BMLP_EALIAS, "Vstar overlaps R1");
     const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
-    int arm = o.smp_arm;
     if (forced)
-      need(arm == BMLP_ARM_SMP_DENSE || arm == BMLP_ARM_SMP_SPARSE || arm == BMLP_ARM_SMP_CLOSURE, BMLP_EINVAL,
-           "smp_arm %d is not a selection arm", arm);
+      need(o.smp_arm == BMLP_ARM_SMP_DENSE || o.smp_arm == BMLP_ARM_SMP_SPARSE || o.smp_arm == BMLP_ARM_SMP_CLOSURE ||
+               o.smp_arm == BMLP_ARM_SMP_SPARSE_ROUNDS || o.smp_arm == BMLP_ARM_SMP_ADAPTIVE,
+           BMLP_EINVAL, "smp_arm %d is not a selection arm", o.smp_arm);
     DeviceGuard dg(h->device);
     hipStream_t s = (hipStream_t)stream;
-    if (!forced) arm = (n > 0 && k > 0) ? smp_plain_arm(n, k, count_bits(h, R1, n, n, ld, s)) : BMLP_ARM_SMP_SPARSE;
     if (o.check_padding) {
       check_padding(h, R1, n, n, ld, s, "R1");
       check_padding(h, V, k, n, ldv, s, "V");
     }
     StatsRec sr(stats, h, s, &o);
+    int arm = BMLP_ARM_SMP_SPARSE;
+    const int refl = o.smp_reflexive ? 1 : 0;
     if (k > 0) {
-      if (n == 0) hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
-      else smp_core(h, R1, ld, n, V, Vstar, k, ldv, o.smp_reflexive ? 1 : 0, arm, o, s, sr);
+      if (n == 0) {
+        hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
+      } else {
+        const GraphInfo gi = graph_info(h, R1, ld, n, s);
+        const double delta0 = (forced && o.smp_arm != BMLP_ARM_SMP_ADAPTIVE) && !h->trace
+                                  ? 0.0
+                                  : (double)count_bits(h, V, k, n, ldv, s);
+        arm = smp_choose_arm(h, o, gi, k, 0, refl, delta0, s, nullptr);
+        smp_core(h, R1, ld, n, V, Vstar, k, ldv, refl, arm, gi, 0, Csr{}, o, s, sr);
+      }
     }
     if (stats) stats->arm = arm;
     sr.finish();
+    if (h->trace && stats) h->trace->total_ms = (float)stats->device_ms;
   });
 }
 
@@ -658,10 +880,10 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
     const Range rp = range_of(P, n, ld);
     need(!overlap(rp, range_of(Rbase, n, ld)), BMLP_EALIAS, "P overlaps Rbase");
     need(!overlap(rp, range_of(Rstep, n, ld)), BMLP_EALIAS, "P overlaps Rstep");
-    int arm = o.compose_arm;
-    if (o.dispatch != BMLP_DISPATCH_FORCED || arm == BMLP_ARM_AUTO) arm = BMLP_ARM_COMPOSE_SEMINAIVE;
-    need(arm == BMLP_ARM_COMPOSE_RMS || arm == BMLP_ARM_COMPOSE_SEMINAIVE, BMLP_EINVAL,
-         "compose_arm %d is not a composition arm", arm);
+    const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.compose_arm != BMLP_ARM_AUTO;
+    if (forced)
+      need(o.compose_arm == BMLP_ARM_COMPOSE_RMS || o.compose_arm == BMLP_ARM_COMPOSE_SEMINAIVE, BMLP_EINVAL,
+           "compose_arm %d is not a composition arm", o.compose_arm);
     DeviceGuard dg(h->device);
     hipStream_t s = (hipStream_t)stream;
     if (o.check_padding) {
@@ -669,32 +891,41 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
       check_padding(h, Rstep, n, n, ld, s, "Rstep");
     }
     StatsRec sr(stats, h, s, &o);
+    int arm = forced ? o.compose_arm : BMLP_ARM_COMPOSE_SEMINAIVE;
     if (n > 0) {
       const i64 nw = words_for(n);
-      const int parm = product_arm(o, n, n);
+      // Route (ii) works on the transposes: P^T = Rb^T . (Rs^T)*, the columns of P being reflexive
+      // selections over the transposed step relation.  Route (i) is the closure: P = Rb | Rs+ . Rb.
+      u64* rbt = ws_bits(h, S_T0, n, nw, o);
+      u64* rst = ws_bits(h, S_T1, n, nw, o);
+      int sarm = BMLP_ARM_AUTO;
+      if (!(forced && o.compose_arm == BMLP_ARM_COMPOSE_RMS) || h->trace) {
+        hip_check(launch_transpose(Rbase, n, n, ld, rbt, nw, s), "transpose");
+        hip_check(launch_transpose(Rstep, n, n, ld, rst, nw, s), "transpose");
+        const GraphInfo gi = graph_info(h, rst, nw, n, s);
+        const double delta0 = (double)count_bits(h, rbt, n, n, nw, s);
+        sarm = smp_choose_arm(h, o, gi, n, 1, 1, delta0, s, nullptr);
+        if (!forced) arm = sarm == BMLP_ARM_SMP_CLOSURE ? BMLP_ARM_COMPOSE_RMS : BMLP_ARM_COMPOSE_SEMINAIVE;
+        if (arm == BMLP_ARM_COMPOSE_SEMINAIVE) {
+          if (sarm == BMLP_ARM_SMP_CLOSURE) sarm = smp_plain_arm(n, n, gi.m);
+          u64* pt = ws_bits(h, S_T2, n, nw, o);
+          smp_core(h, rst, nw, n, rbt, pt, n, nw, 1, sarm, gi, 1, Csr{}, o, s, sr);
+          hip_check(launch_transpose(pt, n, n, nw, P, ld, s), "transpose");
+        }
+      }
       if (arm == BMLP_ARM_COMPOSE_RMS) {
-        // Rs+ by RMS, then P = Rb | Rs+ . Rb
         u64* sp = ws_bits(h, S_W2, n, nw, o);
         bmlp_opts o2 = o;
         o2.rms_variant = 0;
         rms_core(h, Rstep, ld, sp, nw, n, o2, s, sr);
-        product(h, sp, nw, Rbase, ld, Rbase, ld, P, ld, nullptr, 0, n, n, n, nullptr, parm, s, sr);
+        product(h, sp, nw, Rbase, ld, Rbase, ld, P, ld, nullptr, 0, n, n, n, nullptr, product_arm(o, n, n), s, sr);
         hip_check(launch_zero_pad(P, n, n, ld, s), "zero_pad");
-      } else {
-        // P^T = Rb^T . (Rs^T)*: the columns of P are reflexive selections over the transposed step
-        // relation, evaluated by the selection driver; then transpose back.
-        u64* rbt = ws_bits(h, S_T0, n, nw, o);
-        u64* rst = ws_bits(h, S_T1, n, nw, o);
-        u64* pt = ws_bits(h, S_T2, n, nw, o);
-        hip_check(launch_transpose(Rbase, n, n, ld, rbt, nw, s), "transpose");
-        hip_check(launch_transpose(Rstep, n, n, ld, rst, nw, s), "transpose");
-        const int sarm = smp_plain_arm(n, n, count_bits(h, rst, n, n, nw, s));
-        smp_core(h, rst, nw, n, rbt, pt, n, nw, 1, sarm, o, s, sr);
-        hip_check(launch_transpose(pt, n, n, nw, P, ld, s), "transpose");
       }
+      if (h->trace) h->trace->call_arm = arm;
     }
     if (stats) stats->arm = arm;
     sr.finish();
+    if (h->trace && stats) h->trace->total_ms = (float)stats->device_ms;
   });
 }
 
@@ -827,6 +1058,409 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       stats->product_bool_ops = stats->bool_ops;
       stats->product_ms = stats->device_ms;
     }
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ sessions over one relation
+struct bmlp_graph_s {
+  bmlp_ctx* c = nullptr;
+  const u64* R1 = nullptr;
+  i64 n = 0, ld = 0;
+  GraphInfo gi;
+  i64* rp = nullptr;        // owned CSR of R1
+  int32_t* ci = nullptr;
+  u64* closure = nullptr;   // owned R1+ (n x ceil(n/64)) once computed
+  double spent_ms = 0.0;    // device time spent answering queries without the closure
+};
+
+namespace {
+
+// ------------------------------------------------------------ model file
+uint32_t crc32_bytes(const void* data, size_t n, uint32_t crc = 0) {
+  // CRC-32 (IEEE 802.3, reflected polynomial 0xEDB88320), bit by bit
+  const unsigned char* p = (const unsigned char*)data;
+  crc = ~crc;
+  for (size_t i = 0; i < n; ++i) {
+    crc ^= p[i];
+    for (int b = 0; b < 8; ++b) crc = (crc >> 1) ^ (0xEDB88320u & (0u - (crc & 1u)));
+  }
+  return ~crc;
+}
+
+constexpr char kMagic[8] = {'B', 'M', 'L', 'P', 'M', 'L', 'P', '1'};
+struct ModelHeader {
+  char magic[8];
+  uint32_t version, n_in, h1, h2, n_out, n_params;
+};
+
+void model_to_device(bmlp_ctx* c) {
+  if (!c->d_model) hip_check(hipMalloc((void**)&c->d_model, (kParams + 2 * kIn) * sizeof(float)), "hipMalloc");
+  hip_check(hipMemcpy(c->d_model, c->h_model.data(), (kParams + 2 * kIn) * sizeof(float), hipMemcpyHostToDevice),
+            "hipMemcpy");
+  c->model = true;
+}
+
+// splitmix64: a small counter-based generator for the initial weights
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  DevBuf() = default;
+  explicit DevBuf(size_t bytes) {
+    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(BMLP_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  DevBuf(DevBuf&& o) noexcept : p(o.p) { o.p = nullptr; }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  float* f() const { return (float*)p; }
+};
+
+// one forward + backward pass over (X, T, M) with parameters P; returns the loss, G receives the gradient
+float mlp_pass(const float* P, const float* mu, const float* sd, const float* X, const float* T, const float* M,
+               i64 rows, float inv_m, DevBuf* act, float* G, hipStream_t s) {
+  float* H1 = act[0].f();
+  float* H2 = act[1].f();
+  float* Y = act[2].f();
+  float* dY = act[3].f();
+  float* dH2 = act[4].f();
+  float* dH1 = act[5].f();
+  float* loss = act[6].f();
+  hip_check(launch_mlp_forward(P, mu, sd, X, rows, H1, H2, Y, s), "mlp_forward");
+  hip_check(hipMemsetAsync(loss, 0, sizeof(float), s), "hipMemsetAsync");
+  hip_check(launch_mlp_backward(P, mu, sd, X, H1, H2, Y, T, M, rows, inv_m, dY, dH2, dH1, G, loss, s), "mlp_backward");
+  float l = 0.f;
+  hip_check(hipMemcpyAsync(&l, loss, sizeof(float), hipMemcpyDeviceToHost, s), "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");
+  return l;
+}
+
+void alloc_acts(DevBuf* act, i64 rows) {
+  new (&act[0]) DevBuf((size_t)rows * kH1 * sizeof(float));
+  new (&act[1]) DevBuf((size_t)rows * kH2 * sizeof(float));
+  new (&act[2]) DevBuf((size_t)rows * kOut * sizeof(float));
+  new (&act[3]) DevBuf((size_t)rows * kOut * sizeof(float));
+  new (&act[4]) DevBuf((size_t)rows * kH2 * sizeof(float));
+  new (&act[5]) DevBuf((size_t)rows * kH1 * sizeof(float));
+  new (&act[6]) DevBuf(sizeof(float));
+}
+
+DevBuf upload(const float* host, size_t count, hipStream_t s) {
+  DevBuf b(count * sizeof(float));
+  if (count) hip_check(hipMemcpyAsync(b.p, host, count * sizeof(float), hipMemcpyHostToDevice, s), "memcpy");
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+bmlp_status bmlp_set_trace(bmlp_handle h, bmlp_trace* trace) {
+  return guarded([&] {
+    need_handle(h);
+    h->trace = trace;
+    if (trace) {
+      std::memset(trace, 0, sizeof *trace);
+      trace->call_arm = -1;
+    }
+  });
+}
+
+int32_t bmlp_dispatcher_loaded(bmlp_handle h) { return (h && h->model) ? 1 : 0; }
+
+bmlp_status bmlp_dispatcher_load(bmlp_handle h, const char* path) {
+  return guarded([&] {
+    need_handle(h);
+    need(path != nullptr, BMLP_EINVAL, "path: null pointer");
+    FILE* fp = std::fopen(path, "rb");
+    need(fp != nullptr, BMLP_EMODEL, "cannot open model file %s", path);
+    std::vector<unsigned char> buf;
+    unsigned char tmp[4096];
+    size_t got;
+    while ((got = std::fread(tmp, 1, sizeof tmp, fp)) > 0) buf.insert(buf.end(), tmp, tmp + got);
+    std::fclose(fp);
+    const size_t body = sizeof(ModelHeader) + (size_t)(kParams + 2 * kIn) * sizeof(float);
+    need(buf.size() == body + 4, BMLP_EMODEL, "model file %s has %zu bytes, expected %zu", path, buf.size(), body + 4);
+    ModelHeader hd;
+    std::memcpy(&hd, buf.data(), sizeof hd);
+    need(std::memcmp(hd.magic, kMagic, 8) == 0 && hd.version == 1 && hd.n_in == (uint32_t)kIn &&
+             hd.h1 == (uint32_t)kH1 && hd.h2 == (uint32_t)kH2 && hd.n_out == (uint32_t)kOut &&
+             hd.n_params == (uint32_t)kParams,
+         BMLP_EMODEL, "model file %s: wrong header", path);
+    uint32_t crc;
+    std::memcpy(&crc, buf.data() + body, 4);
+    need(crc32_bytes(buf.data(), body) == crc, BMLP_EMODEL, "model file %s: checksum mismatch", path);
+    std::vector<float> m((size_t)(kParams + 2 * kIn));
+    std::memcpy(m.data(), buf.data() + sizeof(ModelHeader), m.size() * sizeof(float));
+    // file layout: mu | sd | params; device layout: params | mu | sd
+    std::vector<float> dev((size_t)(kParams + 2 * kIn));
+    std::memcpy(dev.data(), m.data() + 2 * kIn, kParams * sizeof(float));
+    std::memcpy(dev.data() + kParams, m.data(), 2 * kIn * sizeof(float));
+    for (int i = 0; i < kIn; ++i) need(dev[kParams + kIn + i] > 0.f, BMLP_EMODEL, "model file %s: bad scale", path);
+    DeviceGuard dg(h->device);
+    h->h_model = dev;
+    model_to_device(h);
+  });
+}
+
+bmlp_status bmlp_dispatcher_save(bmlp_handle h, const char* path) {
+  return guarded([&] {
+    need_handle(h);
+    need(path != nullptr, BMLP_EINVAL, "path: null pointer");
+    need(h->model, BMLP_EMODEL, "no model to save");
+    ModelHeader hd;
+    std::memcpy(hd.magic, kMagic, 8);
+    hd.version = 1;
+    hd.n_in = kIn;
+    hd.h1 = kH1;
+    hd.h2 = kH2;
+    hd.n_out = kOut;
+    hd.n_params = kParams;
+    std::vector<unsigned char> buf(sizeof hd + (size_t)(kParams + 2 * kIn) * sizeof(float));
+    std::memcpy(buf.data(), &hd, sizeof hd);
+    std::memcpy(buf.data() + sizeof hd, h->h_model.data() + kParams, 2 * kIn * sizeof(float));
+    std::memcpy(buf.data() + sizeof hd + 2 * kIn * sizeof(float), h->h_model.data(), kParams * sizeof(float));
+    const uint32_t crc = crc32_bytes(buf.data(), buf.size());
+    FILE* fp = std::fopen(path, "wb");
+    need(fp != nullptr, BMLP_EINVAL, "cannot write %s", path);
+    const bool ok = std::fwrite(buf.data(), 1, buf.size(), fp) == buf.size() && std::fwrite(&crc, 4, 1, fp) == 1;
+    std::fclose(fp);
+    need(ok, BMLP_EINVAL, "short write to %s", path);
+  });
+}
+
+bmlp_status bmlp_dispatcher_train(bmlp_handle h, const float* X, const float* T, const float* M, int64_t rows,
+                                  int32_t epochs, float lr, uint64_t seed, float* loss_out) {
+  return guarded([&] {
+    need_handle(h);
+    need(rows > 0 && X && T && M, BMLP_EINVAL, "training data: empty or null");
+    need(epochs >= 0 && lr > 0.f, BMLP_EINVAL, "bad epochs / learning rate");
+    // standardisation of the inputs from the data
+    std::vector<float> model((size_t)(kParams + 2 * kIn), 0.f);
+    float* mu = model.data() + kParams;
+    float* sd = mu + kIn;
+    for (int f = 0; f < kIn; ++f) {
+      double a = 0.0, b = 0.0;
+      for (int64_t i = 0; i < rows; ++i) {
+        a += X[i * kIn + f];
+        b += (double)X[i * kIn + f] * X[i * kIn + f];
+      }
+      const double mean = a / rows, var = std::max(0.0, b / rows - mean * mean);
+      mu[f] = (float)mean;
+      sd[f] = (float)std::max(std::sqrt(var), 1e-3);
+    }
+    // Glorot-uniform weights, zero biases
+    uint64_t st = seed;
+    auto uni = [&]() { return (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0); };
+    auto fill = [&](float* w, int fan_out, int fan_in) {
+      const double a = std::sqrt(6.0 / (fan_in + fan_out));
+      for (int i = 0; i < fan_out * fan_in; ++i) w[i] = (float)((2.0 * uni() - 1.0) * a);
+    };
+    float* P = model.data();
+    fill(P, kH1, kIn);
+    fill(P + kH1 * kIn + kH1, kH2, kH1);
+    fill(P + kH1 * kIn + kH1 + kH2 * kH1 + kH2, kOut, kH2);
+    double msum = 0.0;
+    for (int64_t i = 0; i < rows * kOut; ++i) msum += M[i];
+    need(msum > 0.0, BMLP_EINVAL, "training data: empty mask");
+    DeviceGuard dg(h->device);
+    hipStream_t s = nullptr;
+    DevBuf dX = upload(X, (size_t)rows * kIn, s), dT = upload(T, (size_t)rows * kOut, s),
+           dM = upload(M, (size_t)rows * kOut, s), dP = upload(model.data(), model.size(), s);
+    DevBuf dG((size_t)kParams * sizeof(float)), m1((size_t)kParams * sizeof(float)), m2((size_t)kParams * sizeof(float));
+    hip_check(hipMemsetAsync(m1.p, 0, kParams * sizeof(float), s), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(m2.p, 0, kParams * sizeof(float), s), "hipMemsetAsync");
+    DevBuf act[7];
+    alloc_acts(act, rows);
+    const float inv_m = (float)(1.0 / msum);
+    const float* dmu = dP.f() + kParams;
+    const float* dsd = dmu + kIn;
+    float loss = 0.f;
+    for (int e = 1; e <= epochs; ++e) {
+      hip_check(launch_mlp_forward(dP.f(), dmu, dsd, dX.f(), rows, act[0].f(), act[1].f(), act[2].f(), s), "forward");
+      hip_check(launch_mlp_backward(dP.f(), dmu, dsd, dX.f(), act[0].f(), act[1].f(), act[2].f(), dT.f(), dM.f(), rows,
+                                    inv_m, act[3].f(), act[4].f(), act[5].f(), dG.f(), act[6].f(), s),
+                "backward");
+      hip_check(launch_adam(dP.f(), dG.f(), m1.f(), m2.f(), lr, 0.9f, 0.999f, 1e-8f, e, s), "adam");
+    }
+    loss = mlp_pass(dP.f(), dmu, dsd, dX.f(), dT.f(), dM.f(), rows, inv_m, act, dG.f(), s);
+    hip_check(hipMemcpy(model.data(), dP.p, model.size() * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+    h->h_model = model;
+    model_to_device(h);
+    if (loss_out) *loss_out = loss;
+  });
+}
+
+bmlp_status bmlp_dispatcher_forward(bmlp_handle h, const float* X, int64_t rows, float* Y) {
+  return guarded([&] {
+    need_handle(h);
+    need(h->model, BMLP_EMODEL, "no model");
+    need(rows >= 0 && (rows == 0 || (X && Y)), BMLP_EINVAL, "bad arguments");
+    if (rows == 0) return;
+    DeviceGuard dg(h->device);
+    hipStream_t s = nullptr;
+    DevBuf dX = upload(X, (size_t)rows * kIn, s);
+    DevBuf dY((size_t)rows * kOut * sizeof(float));
+    hip_check(launch_mlp_forward(h->d_model, h->d_model + kParams, h->d_model + kParams + kIn, dX.f(), rows, nullptr,
+                                 nullptr, dY.f(), s),
+              "forward");
+    hip_check(hipMemcpy(Y, dY.p, (size_t)rows * kOut * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+  });
+}
+
+bmlp_status bmlp_mlp_loss_grad(bmlp_handle h, const float* params, const float* mu, const float* sd, const float* X,
+                               const float* T, const float* M, int64_t rows, float* loss, float* grad) {
+  return guarded([&] {
+    need_handle(h);
+    need(rows > 0 && params && mu && sd && X && T && M && loss && grad, BMLP_EINVAL, "bad arguments");
+    double msum = 0.0;
+    for (int64_t i = 0; i < rows * kOut; ++i) msum += M[i];
+    need(msum > 0.0, BMLP_EINVAL, "empty mask");
+    DeviceGuard dg(h->device);
+    hipStream_t s = nullptr;
+    DevBuf dP = upload(params, kParams, s), dmu = upload(mu, kIn, s), dsd = upload(sd, kIn, s),
+           dX = upload(X, (size_t)rows * kIn, s), dT = upload(T, (size_t)rows * kOut, s),
+           dM = upload(M, (size_t)rows * kOut, s);
+    DevBuf dG((size_t)kParams * sizeof(float));
+    DevBuf act[7];
+    alloc_acts(act, rows);
+    *loss = mlp_pass(dP.f(), dmu.f(), dsd.f(), dX.f(), dT.f(), dM.f(), rows, (float)(1.0 / msum), act, dG.f(), s);
+    hip_check(hipMemcpy(grad, dG.p, kParams * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+  });
+}
+
+bmlp_status bmlp_graph_open(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, void* stream, bmlp_graph* g) {
+  return guarded([&] {
+    need_handle(h);
+    need(g != nullptr, BMLP_EINVAL, "g: null pointer");
+    *g = nullptr;
+    check_bits_arg(R1, "R1", n, n, ld);
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    bmlp_graph_s* G = new bmlp_graph_s;
+    G->c = h;
+    G->R1 = R1;
+    G->n = n;
+    G->ld = ld;
+    try {
+      if (n > 0) {
+        bmlp_opts o;
+        bmlp_opts_init(&o);
+        G->gi = graph_info(h, R1, ld, n, s);
+        i64* rp;
+        int32_t* ci;
+        build_csr(h, R1, ld, n, o, s, &rp, &ci);
+        DevBuf b1((size_t)(n + 1) * sizeof(i64)), b2((size_t)std::max<i64>(G->gi.m, 1) * sizeof(int32_t));
+        hip_check(hipMemcpyAsync(b1.p, rp, (size_t)(n + 1) * sizeof(i64), hipMemcpyDeviceToDevice, s), "memcpy");
+        hip_check(hipMemcpyAsync(b2.p, ci, (size_t)G->gi.m * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "memcpy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        G->rp = (i64*)b1.p;
+        G->ci = (int32_t*)b2.p;
+        b1.p = b2.p = nullptr;
+      }
+    } catch (...) {
+      if (G->rp) (void)hipFree(G->rp);
+      if (G->ci) (void)hipFree(G->ci);
+      delete G;
+      throw;
+    }
+    *g = G;
+  });
+}
+
+int32_t bmlp_graph_has_closure(bmlp_graph g) { return (g && g->closure) ? 1 : 0; }
+
+bmlp_status bmlp_graph_close(bmlp_graph g) {
+  if (!g) return BMLP_OK;
+  return guarded([&] {
+    DeviceGuard dg(g->c->device);
+    (void)hipDeviceSynchronize();
+    if (g->rp) (void)hipFree(g->rp);
+    if (g->ci) (void)hipFree(g->ci);
+    if (g->closure) (void)hipFree(g->closure);
+    delete g;
+  });
+}
+
+bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t* V, uint64_t* Vstar, int64_t k, int64_t ldv,
+                             const bmlp_opts* opts, void* stream, bmlp_stats* stats) {
+  return guarded([&] {
+    need(g != nullptr, BMLP_EINVAL, "null session");
+    bmlp_ctx* h = g->c;
+    const bmlp_opts o = opts_or_default(opts);
+    const i64 n = g->n;
+    check_bits_arg(V, "V", k, n, ldv);
+    check_bits_arg(Vstar, "Vstar", k, n, ldv);
+    need(!overlap(range_of(Vstar, k, ldv), range_of(V, k, ldv)), BMLP_EALIAS, "Vstar overlaps V");
+    need(!overlap(range_of(Vstar, k, ldv), range_of(g->R1, n, g->ld)), BMLP_EALIAS, "Vstar overlaps R1");
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    StatsRec sr(stats, h, s, &o);
+    const int refl = o.smp_reflexive ? 1 : 0;
+    int arm = BMLP_ARM_SMP_CLOSURE;
+    if (k > 0 && n == 0) hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
+    if (k > 0 && n > 0) {
+      const i64 nw = words_for(n);
+      bool use_closure = g->closure != nullptr;
+      if (!use_closure) {
+        const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
+        const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
+        const double delta0 = (double)count_bits(h, V, k, n, ldv, s);
+        float pred[4] = {0, 0, 0, 0};
+        arm = smp_choose_arm(h, o, g->gi, k, 0, refl, delta0, s, learned ? pred : nullptr);
+        if (arm == BMLP_ARM_SMP_CLOSURE) use_closure = true;  // and keep it for later queries
+        if (learned && !forced) {
+          // ski rental: build the closure once its predicted cost is below the time already spent on
+          // this relation plus this query's predicted cost without it
+          const double p_iter = std::exp(std::min(pred[0], g->gi.n <= smp_rows_max_n() ? pred[3] : pred[0]));
+          const double p_clo = std::exp(pred[2]);
+          if (p_clo <= g->spent_ms + p_iter) use_closure = true;
+        }
+        if (use_closure) {
+          u64* clo = nullptr;
+          if (hipMalloc((void**)&clo, (size_t)std::max<i64>(n * nw, 1) * sizeof(u64)) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(BMLP_ENOMEM, "closure allocation failed");
+          }
+          try {
+            rms_core(h, g->R1, g->ld, clo, nw, n, o, s, sr);
+          } catch (...) {
+            (void)hipFree(clo);
+            throw;
+          }
+          g->closure = clo;
+        } else {
+          hip_check(hipEventRecord(h->ev1, s), "hipEventRecord");
+          if (h->trace) h->trace->call_arm = arm;
+          smp_core(h, g->R1, g->ld, n, V, Vstar, k, ldv, refl, arm, g->gi, 0, Csr{g->rp, g->ci}, o, s, sr);
+          hip_check(hipEventRecord(h->evp1, s), "hipEventRecord");
+          hip_check(hipEventSynchronize(h->evp1), "hipEventSynchronize");
+          float ms = 0.f;
+          hip_check(hipEventElapsedTime(&ms, h->ev1, h->evp1), "hipEventElapsedTime");
+          g->spent_ms += ms;
+        }
+      }
+      if (use_closure) {
+        arm = BMLP_ARM_SMP_CLOSURE;
+        product(h, V, ldv, g->closure, nw, refl ? V : nullptr, ldv, Vstar, ldv, nullptr, 0, k, n, n, nullptr,
+                product_arm(o, k, n), s, sr);
+        hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
+      }
+    }
+    if (stats) stats->arm = arm;
+    sr.finish();
   });
 }
 

@@ -57,6 +57,9 @@ struct GemmArgs {
   u64* D; i64 ldd;
   i64 M, K, N;
   u32* changed;
+  unsigned long long* newbits = nullptr;  // += number of bits of C not in Cold (optional)
+  const u32* pred = nullptr;              // when given, the kernel runs only if *pred == pred_val
+  u32 pred_val = 0;
 };
 enum ProductKernel { PK_VALU = 0, PK_MFMA = 1 };
 hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s);
@@ -70,5 +73,13 @@ hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStrea
 hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const u64* R, i64 ldr,
                            i64 n, int reflexive, u64* out, i64 ldo, u32* iters_max, hipStream_t s);
 i64 smp_rows_max_n();
+// One semi-naive round for k rows with the state in global memory: nxt = fr . R1 (CSR),
+// fr_out = nxt & ~vis, vis |= fr_out.  Runs only when *pred == pred_val (pred optional).
+hipError_t launch_smp_round(const u64* fr, u64* fr_out, i64 ldf, u64* vis, i64 ldvis, i64 k, const i64* rp,
+                            const int32_t* ci, const u64* R, i64 ldr, i64 n, u32* changed, unsigned long long* newbits,
+                            const u32* pred, u32 pred_val, hipStream_t s);
+// out[0] += set bits, out[1] = max(out[1], largest row count), out[2] += rows with a set bit
+// (out must be zeroed)
+hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* out, hipStream_t s);
 
 }  // namespace bmlp

@@ -189,6 +189,42 @@ __global__ void k_popcount_total(const u64* __restrict__ a, i64 rows, i64 nw, i6
   if (threadIdx.x == 0) atomicAdd(total, part[0] + part[1] + part[2] + part[3]);
 }
 
+// degree statistics of a relation: total, largest row, nonempty rows (one wave
+// per row, one set of atomics per workgroup)
+__global__ void k_graph_stats(const u64* __restrict__ a, i64 rows, i64 nw, i64 ld, unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long s_tot[4], s_max[4], s_ne[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  unsigned long long tot = 0, mx = 0, ne = 0;
+  for (i64 row = wave; row < rows; row += nwaves) {
+    unsigned long long c = 0;
+    for (i64 w = lane; w < nw; w += 64) c += (unsigned long long)__popcll(a[row * ld + w]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    tot += c;
+    mx = c > mx ? c : mx;
+    ne += c ? 1u : 0u;
+  }
+  if (lane == 0) {
+    s_tot[wv] = tot;
+    s_max[wv] = mx;
+    s_ne[wv] = ne;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0, m = 0, e = 0;
+    for (int i = 0; i < 4; ++i) {
+      t += s_tot[i];
+      m = s_max[i] > m ? s_max[i] : m;
+      e += s_ne[i];
+    }
+    if (t) atomicAdd(&out[0], t);
+    if (m) atomicMax(&out[1], m);
+    if (e) atomicAdd(&out[2], e);
+  }
+}
+
 // single workgroup exclusive scan: rp[0] = 0, rp[i+1] = rp[i] + deg[i]
 __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict__ deg, i64 n, i64* __restrict__ rp) {
   __shared__ i64 part[1024];
@@ -322,6 +358,13 @@ hipError_t launch_popcount_total(const u64* a, i64 rows, i64 n, i64 ld, unsigned
   if (rows <= 0 || n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_popcount_total, dim3(grid_for(rows * words_for(n), kBlock, 2048)), dim3(kBlock), 0, s, a, rows,
                      words_for(n), ld, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* out, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(rows * 64, kBlock, 1024)), dim3(kBlock), 0, s, a, rows,
+                     words_for(n), ld, out);
   return hipGetLastError();
 }
 

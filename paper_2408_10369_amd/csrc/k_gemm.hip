@@ -28,10 +28,12 @@ template <int RPW, int WPL>
 __global__ void __launch_bounds__(256)
 k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 ldb, const u64* __restrict__ Cold,
             i64 ldco, u64* __restrict__ C, i64 ldc, u64* __restrict__ D, i64 ldd, i64 M, i64 K, i64 N,
-            u32* __restrict__ changed, int ksplit, int chunks_per_split) {
+            u32* __restrict__ changed, int ksplit, int chunks_per_split, unsigned long long* __restrict__ newbits,
+            const u32* __restrict__ pred, u32 pred_val) {
   constexpr int TW = 64 * WPL;
   constexpr int TR = 4 * RPW;
   __shared__ u64 Bs[64][TW];
+  if (pred && *pred != pred_val) return;  // another arm serves this round
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const i64 nw = (N + 63) >> 6;
@@ -58,8 +60,9 @@ k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 l
   valu_tile_accumulate<RPW, WPL>(A, lda, B, ldb, M, K, nw, row0, w0, kw_begin, kw_end, Bs, acc);
 
   int ch = 0;
+  u32 pop = 0;
   if (ksplit == 1) {
-    ch = valu_tile_store<RPW, WPL>(acc, Cold, ldco, C, ldc, D, ldd, M, nw, row0, w0);
+    ch = valu_tile_store<RPW, WPL>(acc, Cold, ldco, C, ldc, D, ldd, M, nw, row0, w0, &pop);
   } else {
     // C already holds Cold and D is zero (the launcher sees to both)
 #pragma unroll
@@ -76,11 +79,13 @@ k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 l
           if (nb) {
             if (D) atomicOr((unsigned long long*)&D[row * ldd + w], (unsigned long long)nb);
             ch = 1;
+            pop += (u32)__popcll(nb);
           }
         }
       }
     }
   }
+  wave_count(pop, newbits);
   if (changed) {
     const u64 bal = __ballot(ch);
     if (bal && lane == 0) atomicOr(changed, 1u);
@@ -119,7 +124,8 @@ hipError_t launch_rpw(const GemmArgs& g, hipStream_t s, i64 target_blocks) {
     }
   }
   hipLaunchKernelGGL((k_gemm_valu<RPW, WPL>), dim3((unsigned)(tiles * ksplit)), dim3(256), 0, s, g.A, g.lda, g.B,
-                     g.ldb, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed, (int)ksplit, (int)cps);
+                     g.ldb, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed, (int)ksplit, (int)cps,
+                     g.newbits, g.pred, g.pred_val);
   return hipGetLastError();
 }
 
@@ -165,11 +171,13 @@ __device__ __forceinline__ v4i_t expand_frag(u64 w, int g) {
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 ldbt, const u64* __restrict__ Cold,
             i64 ldco, u64* __restrict__ C, i64 ldc, u64* __restrict__ D, i64 ldd, i64 M, i64 K, i64 N,
-            u32* __restrict__ changed) {
+            u32* __restrict__ changed, unsigned long long* __restrict__ newbits, const u32* __restrict__ pred,
+            u32 pred_val) {
   // two LDS stages: while one is consumed, the next chunk is already in registers
   __shared__ u64 As[2][kMT * kMPad];
   __shared__ u64 Bs[2][kMT * kMPad];
   __shared__ u64 bal[4][32];
+  if (pred && *pred != pred_val) return;  // another arm serves this round
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
@@ -241,6 +249,7 @@ k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 
   // epilogue: per block row, ballot "> 0", assemble 16 rows x 2 words, OR with Cold
   const i64 nw = (N + 63) >> 6;
   int ch = 0;
+  u32 pop = 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
 #pragma unroll
@@ -275,10 +284,12 @@ k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 
         C[row * ldc + w] = nv;
         if (D) D[row * ldd + w] = nv & ~old;
         ch |= (nv != old);
+        pop += (u32)__popcll(nv & ~old);
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
+  wave_count(pop, newbits);
   if (changed) {
     const u64 any = __ballot(ch);
     if (any && lane == 0) atomicOr(changed, 1u);
@@ -291,7 +302,7 @@ hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStrea
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const i64 tiles = ((g.M + kMT - 1) / kMT) * ((g.N + kMT - 1) / kMT);
   hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)tiles), dim3(256), 0, s, g.A, g.lda, BT, ldbt, g.Cold, g.ldco, g.C,
-                     g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed);
+                     g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed, g.newbits, g.pred, g.pred_val);
   return hipGetLastError();
 }
 

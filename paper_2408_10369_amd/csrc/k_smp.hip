@@ -121,9 +121,113 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
   }
 }
 
+// One round of the semi-naive selection for every query row, state in global
+// memory (the same round as one dense product): nxt = fr[r] . R1 by CSR
+// expansion in LDS, fr_out[r] = nxt & ~vis[r], vis[r] |= fr_out[r].  Rows with
+// an empty frontier only write their empty fr_out row.  Sets *changed and adds
+// the number of new bits to *newbits.  Runs only if *pred == pred_val (when
+// pred is given), so that the host can queue both arms of a round and let the
+// device-side choice decide.
+__global__ void __launch_bounds__(kSmpThreads)
+k_smp_round(const u64* __restrict__ fr, u64* __restrict__ fr_out, i64 ldf, u64* __restrict__ vis, i64 ldvis, i64 k,
+            const i64* __restrict__ rp, const int32_t* __restrict__ ci, const u64* __restrict__ R, i64 ldr, i64 n,
+            u32* __restrict__ changed, unsigned long long* __restrict__ newbits, const u32* __restrict__ pred,
+            u32 pred_val) {
+  extern __shared__ u64 smem[];
+  __shared__ int32_t hubs[kHubCap];
+  __shared__ int nhubs;
+  if (pred && *pred != pred_val) return;
+  const i64 nw = (n + 63) >> 6;
+  u64* nxt = smem;
+  u32* nxt32 = (u32*)nxt;
+  const int t = threadIdx.x;
+  const u64 last_mask = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
+  u32 cnt = 0;
+  int any = 0;
+  for (i64 row = blockIdx.x; row < k; row += gridDim.x) {
+    for (i64 w = t; w < nw; w += kSmpThreads) nxt[w] = 0ull;
+    if (t == 0) nhubs = 0;
+    __syncthreads();
+    for (i64 w = t; w < nw; w += kSmpThreads) {
+      u64 x = fr[row * ldf + w] & (w == nw - 1 ? last_mask : ~0ull);
+      while (x) {
+        const int b = __ffsll((unsigned long long)x) - 1;
+        x &= x - 1;
+        const i64 u = w * 64 + b;
+        const i64 e0 = rp[u], e1 = rp[u + 1];
+        if (e1 - e0 > kHubDeg) {
+          const int slot = atomicAdd(&nhubs, 1);
+          if (slot < kHubCap) {
+            hubs[slot] = (int32_t)u;
+            continue;
+          }
+        }
+        for (i64 e = e0; e < e1; ++e) {
+          const int32_t v = ci[e];
+          atomicOr(&nxt32[v >> 5], 1u << (v & 31));
+        }
+      }
+    }
+    __syncthreads();
+    const int nh = nhubs < kHubCap ? nhubs : kHubCap;
+    for (int h = 0; h < nh; ++h) {
+      const i64 u = hubs[h];
+      const i64 e0 = rp[u], e1 = rp[u + 1];
+      if (R && (e1 - e0) * 2 > nw) {
+        for (i64 w = t; w < nw; w += kSmpThreads) {
+          const u64 x = R[u * ldr + w];
+          if (x) {
+            atomicOr(&nxt32[2 * w], (u32)x);
+            atomicOr(&nxt32[2 * w + 1], (u32)(x >> 32));
+          }
+        }
+      } else {
+        for (i64 e = e0 + t; e < e1; e += kSmpThreads) {
+          const int32_t v = ci[e];
+          atomicOr(&nxt32[v >> 5], 1u << (v & 31));
+        }
+      }
+    }
+    __syncthreads();
+    for (i64 w = t; w < nw; w += kSmpThreads) {
+      const u64 old = vis[row * ldvis + w];
+      const u64 nv = nxt[w] & ~old & (w == nw - 1 ? last_mask : ~0ull);
+      if (nv) {
+        vis[row * ldvis + w] = old | nv;
+        cnt += (u32)__popcll(nv);
+        any = 1;
+      }
+      fr_out[row * ldf + w] = nv;
+    }
+    __syncthreads();
+  }
+  // per-wave totals
+  u64 s = cnt;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const u64 bal = __ballot(any);
+  if ((t & 63) == 0) {
+    if (s && newbits) atomicAdd(newbits, (unsigned long long)s);
+    if (bal && changed) atomicOr(changed, 1u);
+  }
+}
+
 }  // namespace
 
 i64 smp_rows_max_n() { return (kMaxLdsWords / 3) * 64; }
+
+hipError_t launch_smp_round(const u64* fr, u64* fr_out, i64 ldf, u64* vis, i64 ldvis, i64 k, const i64* rp,
+                            const int32_t* ci, const u64* R, i64 ldr, i64 n, u32* changed, unsigned long long* newbits,
+                            const u32* pred, u32 pred_val, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  const i64 nw = words_for(n);
+  if (nw > kMaxLdsWords) return hipErrorInvalidValue;
+  const size_t lds = (size_t)nw * sizeof(u64);
+  const unsigned grid = (unsigned)(k < 4096 ? k : 4096);
+  hipLaunchKernelGGL(k_smp_round, dim3(grid), dim3(kSmpThreads), lds, s, fr, fr_out, ldf, vis, ldvis, k, rp, ci, R, ldr,
+                     n, changed, newbits, pred, pred_val);
+  return hipGetLastError();
+}
 
 hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const u64* R, i64 ldr,
                            i64 n, int reflexive, u64* out, i64 ldo, u32* iters_max, hipStream_t s) {

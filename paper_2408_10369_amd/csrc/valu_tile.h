@@ -76,13 +76,14 @@ __device__ __forceinline__ void valu_tile_accumulate(const u64* __restrict__ A, 
 }
 
 // C = Cold | acc for the tile (D = C & ~Cold when D is given); returns whether
-// any word of this lane changed.
+// any word of this lane changed and adds the number of new bits to *pop.
 template <int RPW, int WPL>
 __device__ __forceinline__ int valu_tile_store(const u32 (&acc)[RPW][WPL][2], const u64* __restrict__ Cold, i64 ldco,
                                                u64* __restrict__ C, i64 ldc, u64* __restrict__ D, i64 ldd, i64 M,
-                                               i64 nw, i64 row0, i64 w0) {
+                                               i64 nw, i64 row0, i64 w0, u32* pop = nullptr) {
   const int lane = threadIdx.x & 63;
   int ch = 0;
+  u32 cnt = 0;
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const i64 row = row0 + r;
@@ -96,10 +97,21 @@ __device__ __forceinline__ int valu_tile_store(const u32 (&acc)[RPW][WPL][2], co
         C[row * ldc + w] = v;
         if (D) D[row * ldd + w] = v & ~old;
         ch |= (v != old);
+        cnt += (u32)__popcll(v & ~old);
       }
     }
   }
+  if (pop) *pop += cnt;
   return ch;
+}
+
+// adds the wave's sum of `v` into *counter (one atomic per wave)
+__device__ __forceinline__ void wave_count(u32 v, unsigned long long* counter) {
+  if (!counter) return;
+  u64 s = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(counter, (unsigned long long)s);
 }
 
 }  // namespace bmlp
