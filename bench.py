@@ -26,24 +26,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 32 * 2 / 1e12  # bool-ops/s: 64 lanes x 32 bits x (AND+OR) per CU-clock
+# Peaks in Boolean operations per second (one AND + one OR per bit-MAC, like the 2 flops of an FMA):
+# VALU: 256 CUs x 64 lanes x 2.4 GHz x 32 bits x 2 ops (one v_and_or_b32 = 32 ANDs + 32 ORs);
+# int8 MFMA: the published dense int8 rate, 5.0 POPS (2 ops per multiply-accumulate).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 32 * 2 / 1e12
+MFMA_INT8_PEAK_TOPS = 5.0e15 / 1e12
+KERNELS = {0: ("k_gemm_valu", "bit-packed Boolean product on the VALU", "alu", VALU_PEAK_TOPS),
+           1: ("k_gemm_mfma", "Boolean product on int8 matrix cores (exact int32 count > 0)", "mfma",
+               MFMA_INT8_PEAK_TOPS)}
 
-# HBM bytes per launch of the product kernel on this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
-# dispatch) scaled by the same counters on a plain 256 MiB copy (fetch x2.000, write x1.000); the summary is
-# profiles/k_gemm_valu_er16384_density_sweep.md.  Valid only for the kernel source it was measured on.
-GEMM_TRAFFIC = {"source": "paper_2408_10369_amd/csrc/k_gemm.hip",
-                "sha256": "5ccb7508fd01657d6439160d53dea3f119adddd9bf423655e162c26ec0ba5de9",
-                "bytes_per_launch": 496.6e6}
+# HBM bytes per launch of the product kernels on this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) scaled by the same counters on a plain 256 MiB copy; the summaries are under profiles/.  A figure
+# is valid only for the kernel source it was measured on (sha256 of the file).
+GEMM_TRAFFIC = {"k_gemm_valu": {"source": "paper_2408_10369_amd/csrc/k_gemm.hip",
+                                "sha256": "5ccb7508fd01657d6439160d53dea3f119adddd9bf423655e162c26ec0ba5de9",
+                                "bytes_per_launch": 496.6e6}}
 
 
-def measured_traffic():
+def measured_traffic(kernel):
     import hashlib
-    path = os.path.join(ROOT, GEMM_TRAFFIC["source"])
+    rec = GEMM_TRAFFIC.get(kernel)
+    if rec is None:
+        return None
     try:
-        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+        digest = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
     except OSError:
         return None
-    return GEMM_TRAFFIC["bytes_per_launch"] if digest == GEMM_TRAFFIC["sha256"] else None
+    return rec["bytes_per_launch"] if digest == rec["sha256"] else None
 
 
 def main():
@@ -54,6 +63,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
                     help="bound the oracle's closure rows per graph (0: all rows)")
+    ap.add_argument("--workloads", default="batch,programs,stream",
+                    help="held-out workloads measured after the main one, plain vs learned schedule "
+                         "(comma list of batch, programs, stream; empty for none)")
+    ap.add_argument("--stream-queries", type=int, default=10000,
+                    help="queries of the n=65,536 stream to run (a prefix of the 10,000)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device-to-device copy (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -114,6 +128,7 @@ def main():
                 prod["ms"] += st["product_ms"]
                 prod["ops"] += st["product_bool_ops"]
                 prod["launches"] += st["products"]
+                prod["arm"] = st["arm"]
                 if len(per_graph) < len(graphs):
                     per_graph.append({"p": g["p"], "edges": g["m"], "rms_products": st["products"],
                                       "rms_ms": round(st["device_ms"], 3), "smp_ms_k1_k64_k1024":
@@ -134,9 +149,10 @@ def main():
     avg_launch_ms = prod["ms"] / max(prod["launches"], 1)
     ops_per_launch = prod["ops"] / max(prod["launches"], 1)
     achieved_tops = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12 if avg_launch_ms > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": "k_gemm_valu (bit-packed Boolean product, RMS squarings)",
-                "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tbool-op/s",
-                "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(),
+    kname, kdesc, bound, peak = KERNELS[prod.get("arm", 0)]
+    roofline = {"bound": bound, "kernel": "%s (%s; the RMS squarings of the step)" % (kname, kdesc),
+                "achieved": round(achieved_tops, 2), "peak": round(peak, 1), "unit": "Tbool-op/s",
+                "frac": round(achieved_tops / peak, 4), "traffic": measured_traffic(kname),
                 "traffic_unit": "HBM bytes per launch",
                 "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": prod["launches"] // args.steps}
 
@@ -154,8 +170,161 @@ def main():
                    "n": n, "graphs": len(graphs), "query_rows_per_step": rows_per_step},
         "roofline": roofline, "cpu_baseline": cpu, "per_graph": per_graph,
     }
+    wl = [w for w in args.workloads.split(",") if w]
+    if wl:
+        # the main workload's buffers are no longer needed
+        del graphs
+        torch.cuda.empty_cache()
+        out["workloads"] = {}
+        for name in wl:
+            fn = {"batch": wl_batch, "programs": wl_programs, "stream": wl_stream}[name]
+            out["workloads"][name] = fn(ctx, args)
+            print(json.dumps({"workload_done": name}), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def _modes(B):
+    return {"plain": B.make_opts(dispatch=B.DISPATCH_PLAIN), "learned": B.make_opts(dispatch=B.DISPATCH_LEARNED)}
+
+
+def _hash(t, W):
+    """Order-dependent 64-bit fingerprint of a bit matrix (wrapping integer arithmetic)."""
+    flat = t.reshape(-1)
+    return int((flat * W[: flat.numel()]).sum().item())
+
+
+def wl_batch(ctx, args):
+    """512 uneven graphs (n log-uniform in [64, 4096], mean degree U(2, 8), 64 queries each): every
+    closure and every query answer in one hipGraph launch; plain vs learned schedule."""
+    import torch
+
+    import gen
+    import paper_2408_10369_amd as B
+
+    bg = gen.batch_graphs()
+    graphs = []
+    for g in bg:
+        R = ctx.pack_coo(torch.as_tensor(g.src), torch.as_tensor(g.dst), g.n, g.n)
+        r, c = gen.query_lists(g.srcs)
+        V = ctx.pack_coo(torch.as_tensor(r), torch.as_tensor(c), len(g.srcs), g.n)
+        graphs.append({"n": g.n, "R1": R, "closure": torch.zeros_like(R), "V": V, "Vstar": torch.zeros_like(V)})
+    W = torch.randint(-2**62, 2**62, (4096 * 64,), dtype=torch.int64, device="cuda")
+    res, fp = {}, {}
+    for mode, o in _modes(B).items():
+        ctx.batched(graphs, opts=o)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            ctx.batched(graphs, opts=o)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        st = {}
+        ctx.batched(graphs, opts=o, stats=st)
+        fp[mode] = [(_hash(g["closure"], W), _hash(g["Vstar"], W)) for g in graphs]
+        ms = sorted(ts)[len(ts) // 2]
+        res[mode] = {"ms": round(ms, 3), "graphs_per_s": round(len(graphs) / (ms / 1e3), 1),
+                     "bool_ops": st["bool_ops"], "tops": round(st["bool_ops"] / (ms / 1e3) / 1e12, 1)}
+    return {"workload": "512 ER digraphs, n log-uniform [64,4096], mean degree U(2,8), closure + 64 queries each, "
+                        "one hipGraph launch",
+            "plain": res["plain"], "learned": res["learned"],
+            "speedup_learned_over_plain": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
+            "bit_identical": fp["plain"] == fp["learned"]}
+
+
+def wl_programs(ctx, args):
+    """100 linear-recursion programs p <- r_base; p <- r_step, p over the synthetic multi-relational
+    graph (14,951 entities, 1,345 relations, 592,000 facts); plain vs learned schedule."""
+    import torch
+
+    import gen
+    import paper_2408_10369_amd as B
+
+    mr = gen.multirel()
+    progs = gen.programs(mr, count=100, base_seed=4000)
+    n = mr.n
+    packed = {}
+    for (b, s) in progs:
+        for r in (b, s):
+            if r not in packed:
+                packed[r] = ctx.pack_coo(torch.as_tensor(mr.rel_src[r]), torch.as_tensor(mr.rel_dst[r]), n, n)
+    P = ctx.zeros(n, n)
+    W = torch.randint(-2**62, 2**62, (P.numel(),), dtype=torch.int64, device="cuda")
+    modes = _modes(B)
+    # each route forced on every program, for the best fixed choice beside the two schedules
+    for name, arm in (("rms", B.ARM_COMPOSE_RMS), ("seminaive", B.ARM_COMPOSE_SEMINAIVE),
+                      ("rowwise", B.ARM_COMPOSE_ROWWISE)):
+        modes["forced_" + name] = B.make_opts(dispatch=B.DISPATCH_FORCED, compose_arm=arm)
+    for (b, s) in progs[:4]:
+        for o in modes.values():
+            ctx.compose_linear(packed[b], packed[s], n, out=P, opts=o)
+    res, fp = {}, {}
+    for mode, o in modes.items():
+        arms, hs = {}, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (b, s) in progs:
+            st = {}
+            ctx.compose_linear(packed[b], packed[s], n, out=P, opts=o, stats=st)
+            arms[st["arm"]] = arms.get(st["arm"], 0) + 1
+            hs.append(_hash(P, W))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        fp[mode] = hs
+        res[mode] = {"ms": round(ms, 2), "programs_per_s": round(len(progs) / (ms / 1e3), 2),
+                     "arms": {str(k): v for k, v in sorted(arms.items())}}
+    return {"workload": "100 programs over 14,951 entities / 1,345 relations / 592,000 facts (held-out seeds)",
+            "plain": res["plain"], "learned": res["learned"],
+            "forced": {k[7:]: v["ms"] for k, v in res.items() if k.startswith("forced_")},
+            "speedup_learned_over_plain": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
+            "bit_identical": all(h == fp["plain"] for h in fp.values())}
+
+
+def wl_stream(ctx, args):
+    """A stream of selection queries (k log-uniform in [1, 4096]) over one scale-free digraph,
+    n = 65,536, m = 262,144, answered through a session; plain vs learned schedule."""
+    import torch
+
+    import gen
+    import paper_2408_10369_amd as B
+
+    n = 65536
+    s, d = gen.scalefree_digraph()
+    R = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n)
+    queries = gen.query_stream(count=args.stream_queries)
+    qr = [tuple(torch.as_tensor(x).cuda() for x in gen.query_lists(q)) for q in queries]
+    V = ctx.zeros(4096, n)
+    Vs = ctx.zeros(4096, n)
+    W = torch.randint(-2**62, 2**62, (Vs.numel(),), dtype=torch.int64, device="cuda")
+    res, fp = {}, {}
+    for mode, o in _modes(B).items():
+        arms, hs = {}, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        closure_at = None
+        with ctx.graph(R, n) as g:
+            for qi, (r, c) in enumerate(qr):
+                k = len(queries[qi])
+                Vk, Vsk = V[:k], Vs[:k]
+                ctx.pack_coo(r, c, k, n, out=Vk)
+                st = {}
+                g.query(Vk, out=Vsk, opts=o, stats=st)
+                arms[st["arm"]] = arms.get(st["arm"], 0) + 1
+                if closure_at is None and g.has_closure:
+                    closure_at = qi
+                hs.append(_hash(Vsk, W))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        fp[mode] = hs
+        res[mode] = {"ms": round(ms, 1), "queries_per_s": round(len(queries) / (ms / 1e3), 1),
+                     "rows_per_s": round(sum(len(q) for q in queries) / (ms / 1e3), 1),
+                     "arms": {str(k): v for k, v in sorted(arms.items())}, "closure_built_at_query": closure_at}
+    return {"workload": "scale-free digraph n=65536 m=262144, %d queries, k log-uniform [1,4096] "
+                        "(%d rows), one session" % (len(queries), sum(len(q) for q in queries)),
+            "plain": res["plain"], "learned": res["learned"],
+            "speedup_learned_over_plain": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
+            "bit_identical": fp["plain"] == fp["learned"]}
 
 
 def cpu_baseline(graphs, n, sample_rows):

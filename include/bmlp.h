@@ -79,7 +79,9 @@ typedef enum {
   BMLP_ARM_COMPOSE_RMS = 5,   /* compose: Rs+ by BMLP-RMS, then P = Rb | Rs+ . Rb */
   BMLP_ARM_COMPOSE_SEMINAIVE = 6, /* compose: P^T = Rb^T (Rs^T)*, reflexive selections over the transposed step */
   BMLP_ARM_SMP_SPARSE_ROUNDS = 7, /* selection by rounds, every round by sparse-frontier expansion */
-  BMLP_ARM_SMP_ADAPTIVE = 8   /* selection by rounds, each round's kernel chosen on the device by the model */
+  BMLP_ARM_SMP_ADAPTIVE = 8,  /* selection by rounds, each round's kernel chosen on the device by the model */
+  BMLP_ARM_COMPOSE_ROWWISE = 9 /* compose: P[X] = Rb[X] | OR of Rb[Z] over Z in e_X Rs+, only for rows X with
+                                  a step edge (selections over Rs, rows of Rb gathered; n <= 131072) */
 } bmlp_arm;
 
 typedef enum {
@@ -93,7 +95,7 @@ typedef struct {
   int32_t dispatch;       /* bmlp_dispatch */
   int32_t product_arm;    /* BMLP_ARM_AUTO, _PRODUCT_VALU or _PRODUCT_MFMA */
   int32_t smp_arm;        /* BMLP_ARM_AUTO, _SMP_DENSE, _SMP_SPARSE or _SMP_CLOSURE */
-  int32_t compose_arm;    /* BMLP_ARM_AUTO, _COMPOSE_RMS or _COMPOSE_SEMINAIVE */
+  int32_t compose_arm;    /* BMLP_ARM_AUTO, _COMPOSE_RMS, _COMPOSE_SEMINAIVE or _COMPOSE_ROWWISE */
   int32_t rms_variant;    /* 0: R <- R | R.R to a fixpoint (default);
                              1: Algorithm 1 as printed: R = I + R1, square to a fixpoint, times R1 */
   int32_t smp_reflexive;  /* 0: V . R1+ (the paper's answer, default); 1: V . R1* = V | V . R1+ */

@@ -59,7 +59,8 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n\n".join(f"{s}:\n{t}" for s, t in failed))
     tmp = OUT + ".tmp%d" % os.getpid()
-    subprocess.check_call([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs])
+    subprocess.check_call([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs,
+                           "-ldl"])
     os.replace(tmp, OUT)
     return OUT
 

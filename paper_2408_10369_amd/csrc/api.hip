@@ -516,6 +516,19 @@ void smp_rounds(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vs
   hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
 }
 
+// Vstar = V . C for a closure C = R1+ (| V when reflexive): rows of the closure gathered for the set
+// bits of each query row, or a product when n is beyond the gather kernel.
+void read_off_closure(bmlp_ctx* c, const u64* V, i64 ldv, i64 k, const u64* clo, i64 ldc, i64 n, int reflexive,
+                      u64* Vstar, const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
+  if (n <= gather_rows_max_n()) {
+    hip_check(launch_gather_rows(V, ldv, k, clo, ldc, n, reflexive, Vstar, ldv, s), "gather_rows");
+    return;
+  }
+  product(c, V, ldv, clo, ldc, reflexive ? V : nullptr, ldv, Vstar, ldv, nullptr, 0, k, n, n, nullptr,
+          product_arm(o, k, n), s, sr);
+  hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
+}
+
 // Vstar = V . R1+ (or V . R1* when reflexive) by the given call-level arm.
 void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vstar, i64 k, i64 ldv, int reflexive,
               int arm, const GraphInfo& gi, int compose, Csr csr, const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
@@ -545,10 +558,7 @@ void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vsta
   if (arm == BMLP_ARM_SMP_CLOSURE) {
     u64* clo = ws_bits(c, S_W2, n, nw, o);
     rms_core(c, R1, ld, clo, nw, n, o, s, sr);
-    // V . R1+ (strict) or V | V . R1+ (reflexive)
-    product(c, V, ldv, clo, nw, reflexive ? V : nullptr, ldv, Vstar, ldv, nullptr, 0, k, n, n, nullptr,
-            product_arm(o, k, n), s, sr);
-    hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
+    read_off_closure(c, V, ldv, k, clo, nw, n, reflexive, Vstar, o, s, sr);
     return;
   }
   const int mode = arm == BMLP_ARM_SMP_DENSE ? RM_DENSE : arm == BMLP_ARM_SMP_SPARSE_ROUNDS ? RM_SPARSE : RM_LEARNED;
@@ -881,9 +891,17 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
     need(!overlap(rp, range_of(Rbase, n, ld)), BMLP_EALIAS, "P overlaps Rbase");
     need(!overlap(rp, range_of(Rstep, n, ld)), BMLP_EALIAS, "P overlaps Rstep");
     const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.compose_arm != BMLP_ARM_AUTO;
-    if (forced)
-      need(o.compose_arm == BMLP_ARM_COMPOSE_RMS || o.compose_arm == BMLP_ARM_COMPOSE_SEMINAIVE, BMLP_EINVAL,
-           "compose_arm %d is not a composition arm", o.compose_arm);
+    if (forced) {
+      need(o.compose_arm == BMLP_ARM_COMPOSE_RMS || o.compose_arm == BMLP_ARM_COMPOSE_SEMINAIVE ||
+               o.compose_arm == BMLP_ARM_COMPOSE_ROWWISE,
+           BMLP_EINVAL, "compose_arm %d is not a composition arm", o.compose_arm);
+      need(o.compose_arm != BMLP_ARM_COMPOSE_ROWWISE || n <= gather_rows_max_n(), BMLP_EINVAL,
+           "the row-wise composition arm supports n <= %lld", (long long)gather_rows_max_n());
+    }
+    if (o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO)
+      need(o.smp_arm == BMLP_ARM_SMP_DENSE || o.smp_arm == BMLP_ARM_SMP_SPARSE || o.smp_arm == BMLP_ARM_SMP_CLOSURE ||
+               o.smp_arm == BMLP_ARM_SMP_SPARSE_ROUNDS || o.smp_arm == BMLP_ARM_SMP_ADAPTIVE,
+           BMLP_EINVAL, "smp_arm %d is not a selection arm", o.smp_arm);
     DeviceGuard dg(h->device);
     hipStream_t s = (hipStream_t)stream;
     if (o.check_padding) {
@@ -894,26 +912,72 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
     int arm = forced ? o.compose_arm : BMLP_ARM_COMPOSE_SEMINAIVE;
     if (n > 0) {
       const i64 nw = words_for(n);
-      // Route (ii) works on the transposes: P^T = Rb^T . (Rs^T)*, the columns of P being reflexive
-      // selections over the transposed step relation.  Route (i) is the closure: P = Rb | Rs+ . Rb.
-      u64* rbt = ws_bits(h, S_T0, n, nw, o);
-      u64* rst = ws_bits(h, S_T1, n, nw, o);
-      int sarm = BMLP_ARM_AUTO;
-      if (!(forced && o.compose_arm == BMLP_ARM_COMPOSE_RMS) || h->trace) {
-        hip_check(launch_transpose(Rbase, n, n, ld, rbt, nw, s), "transpose");
-        hip_check(launch_transpose(Rstep, n, n, ld, rst, nw, s), "transpose");
-        const GraphInfo gi = graph_info(h, rst, nw, n, s);
-        const double delta0 = (double)count_bits(h, rbt, n, n, nw, s);
-        sarm = smp_choose_arm(h, o, gi, n, 1, 1, delta0, s, nullptr);
-        if (!forced) arm = sarm == BMLP_ARM_SMP_CLOSURE ? BMLP_ARM_COMPOSE_RMS : BMLP_ARM_COMPOSE_SEMINAIVE;
-        if (arm == BMLP_ARM_COMPOSE_SEMINAIVE) {
-          if (sarm == BMLP_ARM_SMP_CLOSURE) sarm = smp_plain_arm(n, n, gi.m);
-          u64* pt = ws_bits(h, S_T2, n, nw, o);
-          smp_core(h, rst, nw, n, rbt, pt, n, nw, 1, sarm, gi, 1, Csr{}, o, s, sr);
-          hip_check(launch_transpose(pt, n, n, nw, P, ld, s), "transpose");
+      // Three routes to P = Rs* . Rb:
+      //  (i)   closure: Rs+ by BMLP-RMS, then P = Rb | Rs+ . Rb;
+      //  (ii)  columns: P^T = Rb^T . (Rs^T)*, the columns of P as reflexive selections over the
+      //        transposed step relation (n query rows);
+      //  (iii) rows: P[X] = Rb[X] | OR of Rb[Z] over Z in e_X . Rs+, a strict selection from each
+      //        row X that has a step edge, then the rows of Rb gathered; other rows are Rb's.
+      const GraphInfo gs = graph_info(h, Rstep, ld, n, s);
+      const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model && !forced;
+      const bool rowwise_ok = n <= gather_rows_max_n();
+      int sarm = (o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO) ? o.smp_arm : BMLP_ARM_AUTO;
+      if (learned || h->trace) {
+        const double delta0 = (double)count_bits(h, Rbase, n, n, ld, s);
+        float f[kIn];
+        make_features(f, gs, n, 1, 1, 0, delta0, delta0, delta0, 1);
+        if (h->trace) std::memcpy(h->trace->call_features, f, sizeof f);
+        if (learned) {
+          // outputs: 0 columns by adaptive rounds, 1 rows, 2 closure, 3 columns by the one-launch kernel
+          u32 allowed = 0x5u;
+          if (rowwise_ok) allowed |= 0x2u;
+          if (n <= smp_rows_max_n()) allowed |= 0x8u;
+          float pred[4];
+          const int d = model_decide(h, f, allowed, s, pred);
+          if (h->trace) std::memcpy(h->trace->call_pred, pred, sizeof pred);
+          arm = d == 1 ? BMLP_ARM_COMPOSE_ROWWISE : d == 2 ? BMLP_ARM_COMPOSE_RMS : BMLP_ARM_COMPOSE_SEMINAIVE;
+          if (d == 0) sarm = BMLP_ARM_SMP_ADAPTIVE;
+          if (d == 3) sarm = BMLP_ARM_SMP_SPARSE;
         }
       }
-      if (arm == BMLP_ARM_COMPOSE_RMS) {
+      if (arm == BMLP_ARM_COMPOSE_SEMINAIVE) {
+        u64* rbt = ws_bits(h, S_T0, n, nw, o);
+        u64* rst = ws_bits(h, S_T1, n, nw, o);
+        u64* pt = ws_bits(h, S_T2, n, nw, o);
+        hip_check(launch_transpose(Rbase, n, n, ld, rbt, nw, s), "transpose");
+        hip_check(launch_transpose(Rstep, n, n, ld, rst, nw, s), "transpose");
+        if (sarm == BMLP_ARM_AUTO) sarm = smp_plain_arm(n, n, gs.m);
+        smp_core(h, rst, nw, n, rbt, pt, n, nw, 1, sarm, gs, 1, Csr{}, o, s, sr);
+        hip_check(launch_transpose(pt, n, n, nw, P, ld, s), "transpose");
+      } else if (arm == BMLP_ARM_COMPOSE_ROWWISE) {
+        i64* rp;
+        int32_t* ci;
+        build_csr(h, Rstep, ld, n, o, s, &rp, &ci);
+        const int32_t* deg = (const int32_t*)ws(h, S_DEG, (size_t)n * sizeof(int32_t), o);
+        std::vector<int32_t> hdeg((size_t)n), rows;
+        hip_check(hipMemcpyAsync(hdeg.data(), deg, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        rows.reserve((size_t)gs.nonempty);
+        for (i64 i = 0; i < n; ++i)
+          if (hdeg[(size_t)i] > 0) rows.push_back((int32_t)i);
+        const i64 kr = (i64)rows.size();
+        hip_check(launch_ewise(4, Rbase, ld, nullptr, 0, P, ld, n, n, s), "copy");
+        if (kr > 0) {
+          int32_t* drows = (int32_t*)ws(h, S_T2, (size_t)kr * sizeof(int32_t), o);
+          u64* v1 = ws_bits(h, S_T0, kr, nw, o);
+          u64* sel = ws_bits(h, S_T1, kr, nw, o);
+          hip_check(hipMemcpyAsync(drows, rows.data(), (size_t)kr * sizeof(int32_t), hipMemcpyHostToDevice, s),
+                    "memcpy");
+          hip_check(launch_fill_zero(v1, kr * nw, s), "fill_zero");
+          hip_check(launch_set_onehot(v1, nw, drows, kr, s), "set_onehot");
+          if (sarm == BMLP_ARM_AUTO || sarm == BMLP_ARM_SMP_ADAPTIVE) sarm = smp_plain_arm(n, kr, gs.m);
+          smp_core(h, Rstep, ld, n, v1, sel, kr, nw, 0, sarm, gs, 1, Csr{rp, ci}, o, s, sr);
+          hip_check(launch_gather_rows(sel, nw, kr, Rbase, ld, n, 2, P, ld, s, drows), "gather_rows");
+          // the host list is read by the upload above; wait before it goes out of scope
+          hip_check(hipStreamSynchronize(s), "sync");
+        }
+        hip_check(launch_zero_pad(P, n, n, ld, s), "zero_pad");
+      } else {
         u64* sp = ws_bits(h, S_W2, n, nw, o);
         bmlp_opts o2 = o;
         o2.rms_variant = 0;
@@ -961,7 +1025,13 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return graphs[a].n > graphs[b].n; });
-    BatchPlan plan{0, 0, 0, 0};
+    BatchPlan plan{0, 0, 0, 0, 0, false};
+    // Query answers: the plain schedule takes the paper's mapping of a partially grounded query to
+    // BMLP-SMP (a selection per query row); otherwise the rows are read off the closures the batch
+    // computes anyway (reuse of intermediate results).  Graphs beyond the selection kernel's size
+    // always read the closure.
+    const bool forced_sel = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
+    plan.select_by_bfs = forced_sel ? o.smp_arm != BMLP_ARM_SMP_CLOSURE : o.dispatch == BMLP_DISPATCH_PLAIN;
     size_t buf_words = 0;
     for (int i = 0; i < count; ++i) {
       const bmlp_graph_desc& d = graphs[i];
@@ -969,7 +1039,7 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       buf_words += (size_t)(2 * d.n * words_for(d.n));
     }
     const size_t table_bytes = ((size_t)count * sizeof(BatchGraph) + 255) & ~(size_t)255;
-    const size_t nflags = (size_t)count * plan.rounds + 2 * (size_t)plan.rounds + 1;
+    const size_t nflags = (size_t)count * plan.rounds + 2 * (size_t)plan.rounds + 2;
     const size_t flag_bytes = (nflags * sizeof(u32) + 255) & ~(size_t)255;
     char* base = (char*)ws(h, S_BATCH, table_bytes + flag_bytes + buf_words * sizeof(u64), o);
     BatchGraph* d_table = (BatchGraph*)base;
@@ -998,9 +1068,11 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       G.tile_begin = plan.total_tiles;
       G.rtiles = batch_rtiles(d.n);
       G.smp_tile_begin = plan.total_select_tiles;
+      G.qrow_begin = plan.total_qrows;
       plan.total_rows += std::max<int64_t>(d.n, d.k);
       plan.total_tiles += batch_tiles(d.n);
       plan.total_select_tiles += d.k > 0 ? batch_select_tiles(d.k, d.n) : 0;
+      plan.total_qrows += d.k;
     }
     // the captured chain is reused while the batch (and its workspace) is unchanged
     uint64_t key = 1469598103934665603ull;
@@ -1010,6 +1082,7 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
     };
     mix(graphs, sizeof(bmlp_graph_desc) * (size_t)count);
     mix(&base, sizeof base);
+    mix(&plan.select_by_bfs, sizeof plan.select_by_bfs);
     if (!h->bexec || key != h->bkey) {
       if (h->bexec) {
         hip_check(hipGraphExecDestroy(h->bexec), "hipGraphExecDestroy");
@@ -1050,11 +1123,12 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
         const int prods = r + 1;  // the rounds that changed plus the one that found the fixpoint
         max_rounds = std::max(max_rounds, prods);
         const uint64_t nn = (uint64_t)tab[j].n;
-        stats->products += prods + (tab[j].k > 0 ? 1 : 0);
-        stats->bool_ops += (uint64_t)prods * 2u * nn * nn * nn + 2u * (uint64_t)tab[j].k * nn * nn;
+        const bool gathered = tab[j].k > 0 && !(plan.select_by_bfs && tab[j].n <= batch_bfs_max_n());
+        stats->products += prods + (gathered ? 1 : 0);
+        stats->bool_ops += (uint64_t)prods * 2u * nn * nn * nn + (gathered ? 2u * (uint64_t)tab[j].k * nn * nn : 0u);
       }
       stats->iterations = max_rounds;
-      stats->arm = BMLP_ARM_SMP_CLOSURE;
+      stats->arm = plan.select_by_bfs ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_CLOSURE;
       stats->product_bool_ops = stats->bool_ops;
       stats->product_ms = stats->device_ms;
     }
@@ -1454,9 +1528,7 @@ bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t* V, uint64_t* Vstar, i
       }
       if (use_closure) {
         arm = BMLP_ARM_SMP_CLOSURE;
-        product(h, V, ldv, g->closure, nw, refl ? V : nullptr, ldv, Vstar, ldv, nullptr, 0, k, n, n, nullptr,
-                product_arm(o, k, n), s, sr);
-        hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
+        read_off_closure(h, V, ldv, k, g->closure, nw, n, refl, Vstar, o, s, sr);
       }
     }
     if (stats) stats->arm = arm;

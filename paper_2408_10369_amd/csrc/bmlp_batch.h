@@ -15,12 +15,18 @@ struct BatchGraph {
   i64 tile_begin;        // first product tile of this graph (tiles per round = batch_tiles(n))
   i64 rtiles;            // row tiles of the graph
   i64 smp_tile_begin;    // first selection tile of this graph
+  i64 qrow_begin;        // first query row of this graph in the batch-wide query-row numbering
 };
 
 struct BatchPlan {
   int rounds;            // kernels in the chain = largest round cap of the batch
   i64 total_rows, total_tiles, total_select_tiles;
+  i64 total_qrows;       // query rows of all graphs
+  bool select_by_bfs;    // answer queries by selection (BMLP-SMP) instead of reading the closure
 };
+
+// largest n whose queries the per-row selection kernel answers (bitmaps in registers)
+i64 batch_bfs_max_n();
 
 i64 batch_tiles(i64 n);
 i64 batch_rtiles(i64 n);

@@ -29,6 +29,8 @@ hipError_t launch_ewise(int op, const u64* a, i64 lda, const u64* b, i64 ldb, u6
 hipError_t launch_zero_pad(u64* a, i64 rows, i64 n, i64 ld, hipStream_t s);
 // set the diagonal bits (i, i) for i < min(rows, n)
 hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s);
+// row i of a gets bit idx[i] (0 <= idx[i] < columns; rows zeroed beforehand)
+hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, hipStream_t s);
 // out (cols x rows) = transpose of in (rows x cols)
 hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out, i64 ldo, hipStream_t s);
 // nonzero padding bits (columns >= n) in any row -> *bad = 1
@@ -78,6 +80,11 @@ i64 smp_rows_max_n();
 hipError_t launch_smp_round(const u64* fr, u64* fr_out, i64 ldf, u64* vis, i64 ldvis, i64 k, const i64* rp,
                             const int32_t* ci, const u64* R, i64 ldr, i64 n, u32* changed, unsigned long long* newbits,
                             const u32* pred, u32 pred_val, hipStream_t s);
+// out[map(r)] = init | OR of Cl[u, :] over the set bits u of V[r], with init = 0 (0), V[r] (1) or the
+// current out[map(r)] (2); map(r) = row_map[r], or r without a map; n <= gather_rows_max_n()
+hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 ldc, i64 n, int init, u64* out,
+                              i64 ldo, hipStream_t s, const int32_t* row_map = nullptr);
+i64 gather_rows_max_n();
 // out[0] += set bits, out[1] = max(out[1], largest row count), out[2] += rows with a set bit
 // (out must be zeroed)
 hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* out, hipStream_t s);

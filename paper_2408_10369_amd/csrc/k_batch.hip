@@ -105,7 +105,7 @@ k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int
 
 __global__ void __launch_bounds__(256)
 k_batch_select(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int rounds,
-               const u32* __restrict__ changed, u32* __restrict__ counter) {
+               const u32* __restrict__ changed, u32* __restrict__ counter, i64 skip_nw_upto) {
   __shared__ u64 Bs[64][kTileWords];
   __shared__ i64 item;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -117,6 +117,7 @@ k_batch_select(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, in
     if (t >= total_tiles) break;
     const int g = find_graph(gs, count, t, true);
     const BatchGraph& G = gs[g];
+    if (G.nw <= skip_nw_upto) continue;  // answered by the selection kernel
     const int fr = final_round(changed, g, rounds);
     const u64* clo = ((fr + 1) & 1) ? G.buf1 : G.buf0;  // buffer written by the last round
     const i64 local = t - G.smp_tile_begin;
@@ -129,6 +130,81 @@ k_batch_select(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, in
     for (int r = 0; r < kRPW; ++r) acc[r][0][0] = acc[r][0][1] = 0u;
     valu_tile_accumulate<kRPW, 1>(G.V, G.ldv, clo, G.nw, G.k, G.n, G.nw, row0, w0, 0, G.nw, Bs, acc);
     (void)valu_tile_store<kRPW, 1>(acc, nullptr, 0, G.Vstar, G.ldv, nullptr, 0, G.k, G.nw, row0, w0);
+  }
+}
+
+// Selection without the closure (the plain schedule's reading of a partially grounded query as
+// BMLP-SMP): one wave per query row runs the semi-naive fixpoint of Eq. 5 with its frontier,
+// visited and successor bitmaps in registers (lane l owns words l, l + 64, ...; up to kBfsWords
+// words), expanding a frontier node u by OR-ing its bit row R1[u, :].  The set bits of the
+// frontier are walked uniformly across the wave (ballot of nonzero words, then the bits of each).
+constexpr int kBfsWords = 256;  // n <= 16,384
+constexpr int kBfsPer = kBfsWords / 64;
+
+__global__ void __launch_bounds__(256)
+k_batch_select_bfs(const BatchGraph* __restrict__ gs, int count, i64 total_qrows, u32* __restrict__ counter) {
+  __shared__ i64 item[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (;;) {
+    if (lane == 0) item[wv] = (i64)atomicAdd(counter, 1u);
+    __builtin_amdgcn_wave_barrier();
+    const i64 it = item[wv];
+    __builtin_amdgcn_wave_barrier();
+    if (it >= total_qrows) break;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (gs[mid].qrow_begin <= it) lo = mid; else hi = mid - 1;
+    }
+    const BatchGraph& G = gs[lo];
+    const i64 row = it - G.qrow_begin;
+    if (row >= G.k || G.nw > kBfsWords) continue;  // larger graphs read their answers off the closure
+    const u64 lm = (G.n & 63) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
+    u64 fr[kBfsPer], vis[kBfsPer], nxt[kBfsPer];
+#pragma unroll
+    for (int j = 0; j < kBfsPer; ++j) {
+      const i64 w = lane + 64 * j;
+      fr[j] = (w < G.nw) ? (G.V[row * G.ldv + w] & (w == G.nw - 1 ? lm : ~0ull)) : 0ull;
+      vis[j] = 0ull;
+    }
+    for (i64 round = 0; round <= G.n + 1; ++round) {
+#pragma unroll
+      for (int j = 0; j < kBfsPer; ++j) nxt[j] = 0ull;
+#pragma unroll
+      for (int j = 0; j < kBfsPer; ++j) {
+        u64 lanes = __ballot(fr[j] != 0ull);
+        while (lanes) {
+          const int src = __ffsll((unsigned long long)lanes) - 1;
+          lanes &= lanes - 1;
+          u64 x = __shfl(fr[j], src, 64);
+          while (x) {
+            const int b = __ffsll((unsigned long long)x) - 1;
+            x &= x - 1;
+            const i64 u = (i64)(src + 64 * j) * 64 + b;
+#pragma unroll
+            for (int q = 0; q < kBfsPer; ++q) {
+              const i64 w = lane + 64 * q;
+              if (w < G.nw) nxt[q] |= G.R1[u * G.ld + w];
+            }
+          }
+        }
+      }
+      int any = 0;
+#pragma unroll
+      for (int j = 0; j < kBfsPer; ++j) {
+        const i64 w = lane + 64 * j;
+        const u64 nv = nxt[j] & ~vis[j] & (w == G.nw - 1 ? lm : ~0ull);
+        vis[j] |= nv;
+        fr[j] = nv;
+        any |= nv != 0ull;
+      }
+      if (__ballot(any) == 0ull) break;
+    }
+#pragma unroll
+    for (int j = 0; j < kBfsPer; ++j) {
+      const i64 w = lane + 64 * j;
+      if (w < G.nw) G.Vstar[row * G.ldv + w] = vis[j];
+    }
   }
 }
 
@@ -170,6 +246,8 @@ i64 batch_tiles(i64 n) {
 
 i64 batch_rtiles(i64 n) { return (n + kTileRows - 1) / kTileRows; }
 
+i64 batch_bfs_max_n() { return (i64)kBfsWords * 64; }
+
 i64 batch_select_tiles(i64 k, i64 n) {
   const i64 nw = words_for(n);
   return ((k + kTileRows - 1) / kTileRows) * ((nw + kTileWords - 1) / kTileWords);
@@ -180,7 +258,7 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
   u32* changed = flags;
   u32* any_active = flags + (i64)count * p.rounds;
   u32* counters = any_active + p.rounds;
-  const i64 nflags = (i64)count * p.rounds + 2 * (i64)p.rounds + 1;
+  const i64 nflags = (i64)count * p.rounds + 2 * (i64)p.rounds + 2;
   hipLaunchKernelGGL(k_batch_setup, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
                      count, p.total_rows, flags, nflags);
   hipError_t e = hipGetLastError();
@@ -192,10 +270,16 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  if (p.select_by_bfs && p.total_qrows > 0) {
+    hipLaunchKernelGGL(k_batch_select_bfs, dim3(grid_cap((p.total_qrows + 3) / 4, 2048)), dim3(256), 0, s,
+                       (const BatchGraph*)d_graphs, count, p.total_qrows, counters + p.rounds + 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (p.total_select_tiles > 0) {
     hipLaunchKernelGGL(k_batch_select, dim3(grid_cap(p.total_select_tiles, 1024)), dim3(256), 0, s,
                        (const BatchGraph*)d_graphs, count, p.total_select_tiles, p.rounds, (const u32*)changed,
-                       counters + p.rounds);
+                       counters + p.rounds, p.select_by_bfs ? (i64)kBfsWords : (i64)0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -103,6 +103,14 @@ __global__ void k_set_diag(u64* __restrict__ a, i64 ld, i64 cnt) {
     a[i * ld + (i >> 6)] |= 1ull << (i & 63);
 }
 
+// row i gets the single bit idx[i] (rows zeroed beforehand)
+__global__ void k_set_onehot(u64* __restrict__ a, i64 ld, const int32_t* __restrict__ idx, i64 k) {
+  for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < k; i += (i64)gridDim.x * blockDim.x) {
+    const i64 j = idx[i];
+    a[i * ld + (j >> 6)] = 1ull << (j & 63);
+  }
+}
+
 // 64x64 bit-block transpose, one wave per block: lane l holds input row
 // (64 rb + l), word cw; output row (64 cw + j) word rb is the ballot of bit j.
 __global__ void k_transpose(const u64* __restrict__ in, i64 rows, i64 cols, i64 ldi, u64* __restrict__ out, i64 ldo) {
@@ -324,6 +332,12 @@ hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s) {
   const i64 cnt = rows < n ? rows : n;
   if (cnt <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_set_diag, dim3(grid_for(cnt)), dim3(kBlock), 0, s, a, ld, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_onehot, dim3(grid_for(k)), dim3(kBlock), 0, s, a, ld, idx, k);
   return hipGetLastError();
 }
 

@@ -212,10 +212,96 @@ k_smp_round(const u64* __restrict__ fr, u64* __restrict__ fr_out, i64 ldf, u64* 
   }
 }
 
+// Selection read off a closure: out[r] = OR of C[u, :] over the set bits u of V[r] (V[r] R1+ when C
+// is R1+; reflexive adds V[r] itself).  One workgroup per row.  Thread t counts the set bits of its
+// contiguous share of V[r], a workgroup prefix scan numbers them, and the source rows are listed in
+// LDS in passes of 1,024 and OR-ed, each a coalesced row of C, into the answer held in registers
+// (thread t owns words t, t + 256, ...; n <= 131,072).  The answer of row r goes to output row
+// row_map[r] (r without a map) and starts from zero, from V[r] (init 1) or from the output row's
+// current content (init 2).
+constexpr int kGatherWords = 2048;
+
+__global__ void __launch_bounds__(256)
+k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__ Cl, i64 ldc, i64 n, int init,
+              u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map) {
+  __shared__ int32_t srcs[1024];
+  __shared__ int scan[256];
+  const i64 nw = (n + 63) >> 6;
+  const u64 last_mask = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
+  const int t = threadIdx.x;
+  const i64 chunk = (nw + 255) / 256;
+  const i64 wb = t * chunk, we = (wb + chunk < nw) ? wb + chunk : nw;
+  for (i64 row = blockIdx.x; row < k; row += gridDim.x) {
+    const i64 orow = row_map ? (i64)row_map[row] : row;
+    u64 acc[kGatherWords / 256];
+#pragma unroll
+    for (int j = 0; j < kGatherWords / 256; ++j) {
+      const i64 w = t + 256 * j;
+      u64 a = 0ull;
+      if (w < nw && init == 1) a = V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
+      if (w < nw && init == 2) a = out[orow * ldo + w];
+      acc[j] = a;
+    }
+    int cnt = 0;
+    for (i64 w = wb; w < we; ++w) cnt += __popcll(V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull));
+    scan[t] = cnt;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int v = t >= off ? scan[t - off] : 0;
+      __syncthreads();
+      scan[t] += v;
+      __syncthreads();
+    }
+    const int total = scan[255];
+    const int first = scan[t] - cnt;  // global index of this thread's first source
+    __syncthreads();
+    for (int base = 0; base < total; base += 1024) {
+      int idx = first;
+      for (i64 w = wb; w < we && idx < base + 1024; ++w) {
+        u64 x = V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
+        while (x) {
+          const int b = __ffsll((unsigned long long)x) - 1;
+          x &= x - 1;
+          if (idx >= base && idx < base + 1024) srcs[idx - base] = (int32_t)(w * 64 + b);
+          ++idx;
+        }
+      }
+      __syncthreads();
+      const int c = (total - base) < 1024 ? (total - base) : 1024;
+      for (int i = 0; i < c; ++i) {
+        const i64 u = srcs[i];
+#pragma unroll
+        for (int j = 0; j < kGatherWords / 256; ++j) {
+          const i64 w = t + 256 * j;
+          if (w < nw) acc[j] |= Cl[u * ldc + w];
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kGatherWords / 256; ++j) {
+      const i64 w = t + 256 * j;
+      if (w < nw) out[orow * ldo + w] = acc[j];
+    }
+    for (i64 w = nw + t; w < ldo; w += 256) out[orow * ldo + w] = 0ull;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 i64 smp_rows_max_n() { return (kMaxLdsWords / 3) * 64; }
 
+i64 gather_rows_max_n() { return (i64)kGatherWords * 64; }
+
+hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 ldc, i64 n, int init, u64* out,
+                              i64 ldo, hipStream_t s, const int32_t* row_map) {
+  if (k <= 0) return hipSuccess;
+  if (words_for(n) > kGatherWords) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)(k < 65535 ? k : 65535);
+  hipLaunchKernelGGL(k_gather_rows, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo, row_map);
+  return hipGetLastError();
+}
 hipError_t launch_smp_round(const u64* fr, u64* fr_out, i64 ldf, u64* vis, i64 ldvis, i64 k, const i64* rp,
                             const int32_t* ci, const u64* R, i64 ldr, i64 n, u32* changed, unsigned long long* newbits,
                             const u32* pred, u32 pred_val, hipStream_t s) {

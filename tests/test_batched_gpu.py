@@ -50,7 +50,19 @@ def check(graphs, refs):
             assert np.array_equal(host(g["Vstar"]), oracle.smp(n, s, d, host(g["V"]))), n
 
 
-def test_batched_mixed_sizes(ctx):
+MODES = {"plain": None, "learned": "learned", "closure": "closure"}
+
+
+def mode_opts(mode):
+    if mode == "learned":
+        return B.make_opts(dispatch=B.DISPATCH_LEARNED)
+    if mode == "closure":
+        return B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE)
+    return None
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_batched_mixed_sizes(ctx, mode):
     rng = np.random.default_rng(11)
     specs = []
     for n in [1, 2, 63, 64, 65, 129, 300, 700, 1100, 2049, 5, 40]:
@@ -60,7 +72,7 @@ def test_batched_mixed_sizes(ctx):
         specs.append((n, s, d, rng.choice(n, k, replace=False) if k else []))
     graphs, refs = make_batch(ctx, specs)
     st = {}
-    ctx.batched(graphs, stats=st)
+    ctx.batched(graphs, opts=mode_opts(mode), stats=st)
     check(graphs, refs)
     assert st["iterations"] >= 1 and st["bool_ops"] > 0
 
@@ -98,12 +110,13 @@ def test_batched_edge_cases(ctx):
     assert not host(g2[1]["Vstar"]).any()
 
 
-def test_batched_512_graph_workload(ctx):
+@pytest.mark.parametrize("mode", ["plain", "learned"])
+def test_batched_512_graph_workload(ctx, mode):
     """All 512 graphs (n log-uniform in [64, 4096], mean degree U(2, 8), 64 queries each)."""
     bg = gen.batch_graphs()
     specs = [(g.n, g.src, g.dst, g.srcs) for g in bg]
     graphs, refs = make_batch(ctx, specs)
     st = {}
-    ctx.batched(graphs, stats=st)
+    ctx.batched(graphs, opts=mode_opts(mode), stats=st)
     check(graphs, refs)
     assert st["iterations"] <= 14

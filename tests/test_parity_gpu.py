@@ -255,7 +255,7 @@ def test_smp_hub_node(ctx):
 
 # ----------------------------------------------------------------- composition
 @pytest.mark.parametrize("parm", [B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA])
-@pytest.mark.parametrize("arm", [B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE])
+@pytest.mark.parametrize("arm", [B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE, B.ARM_COMPOSE_ROWWISE])
 @pytest.mark.parametrize("n", [1, 3, 64, 65, 300, 1000])
 def test_compose_random(ctx, n, arm, parm):
     rng = np.random.default_rng(3000 + n)
@@ -267,10 +267,41 @@ def test_compose_random(ctx, n, arm, parm):
         assert np.array_equal(got, oracle.compose_rows(n, bs, bd, ss, sd)), (n, pb, ps, arm)
 
 
+@pytest.mark.parametrize("sarm", [B.ARM_SMP_DENSE, B.ARM_SMP_SPARSE, B.ARM_SMP_CLOSURE, B.ARM_SMP_SPARSE_ROUNDS])
+def test_compose_rowwise_selection_arms(ctx, sarm):
+    # the row-wise route under every selection arm; a padded leading dimension, rows of the step
+    # relation without edges (copied from the base), a hub row and a long chain
+    rng = np.random.default_rng(515)
+    n, ld = 777, 16
+    _, bs, bd = rand_graph(rng, n, 0.004)
+    _, ss, sd = rand_graph(rng, n, 0.0008)
+    ss = np.r_[ss, np.zeros(300, np.int32), np.arange(400, 700, dtype=np.int32)].astype(np.int32)
+    sd = np.r_[sd, rng.choice(n, 300, replace=False).astype(np.int32), np.arange(401, 701, dtype=np.int32)]
+    keep = np.unique(ss.astype(np.int64) * n + sd, return_index=True)[1]
+    ss, sd = ss[keep], sd[keep]
+    out = ctx.zeros(n, n, ld)
+    out.fill_(-1)  # every word of the output is written, padding words included
+    P = host(ctx.compose_linear(gpu_pack(ctx, n, bs, bd, ld), gpu_pack(ctx, n, ss, sd, ld), n, out=out,
+                                opts=forced(compose_arm=B.ARM_COMPOSE_ROWWISE, smp_arm=sarm)))
+    nw = (n + 63) // 64
+    assert not P[:, nw:].any()
+    assert np.array_equal(P[:, :nw], oracle.compose_rows(n, bs, bd, ss, sd)), sarm
+
+
+def test_compose_rowwise_empty_step(ctx):
+    rng = np.random.default_rng(516)
+    n = 300
+    _, bs, bd = rand_graph(rng, n, 0.01)
+    got = host(ctx.compose_linear(gpu_pack(ctx, n, bs, bd), ctx.zeros(n, n), n,
+                                  opts=forced(compose_arm=B.ARM_COMPOSE_ROWWISE)))
+    none = np.zeros(0, np.int32)
+    assert np.array_equal(got, oracle.compose_rows(n, bs, bd, none, none))
+
+
 def test_compose_of_same_relation_is_closure(ctx):
     n, s, d, _ = gen.c1()
     R = gpu_pack(ctx, n, s, d)
-    for arm in (B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE):
+    for arm in (B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE, B.ARM_COMPOSE_ROWWISE):
         got = host(ctx.compose_linear(R, R, n, opts=forced(compose_arm=arm)))
         assert np.array_equal(got, oracle.closure_rows(n, s, d))
 
@@ -299,7 +330,7 @@ def test_isforeign_pipeline(ctx, golden_dir):
     adj = pack(facts["adjoins"])
     base = ctx.or_(adj, ctx.transpose(adj, n), n)
     step = ctx.transpose(has_place, n)
-    for arm in (B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE):
+    for arm in (B.ARM_COMPOSE_RMS, B.ARM_COMPOSE_SEMINAIVE, B.ARM_COMPOSE_ROWWISE):
         ipo = ctx.compose_linear(base, step, n, opts=forced(compose_arm=arm))
         foreign = ctx.unpack_u8(ctx.not_(ipo, n), n).cpu().numpy()
         want = np.ones((n, n), np.uint8)
@@ -356,6 +387,12 @@ def test_errors(ctx):
     assert e.value.status == B.EINVAL
     with pytest.raises(B.BmlpError) as e:
         ctx.smp(R, n, ctx.zeros(2, n), opts=forced(smp_arm=B.ARM_COMPOSE_RMS))
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.BmlpError) as e:
+        ctx.compose_linear(R, R, n, opts=forced(compose_arm=B.ARM_SMP_DENSE))
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.BmlpError) as e:
+        ctx.compose_linear(R, R, n, opts=forced(compose_arm=B.ARM_COMPOSE_ROWWISE, smp_arm=B.ARM_COMPOSE_RMS))
     assert e.value.status == B.EINVAL
 
 
