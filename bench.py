@@ -38,9 +38,9 @@ KERNELS = {0: ("k_gemm_valu", "bit-packed Boolean product on the VALU", "alu", V
 # HBM bytes per launch of the product kernels on this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the same counters on a plain 256 MiB copy; the summaries are under profiles/.  A figure
 # is valid only for the kernel source it was measured on (sha256 of the file).
-GEMM_TRAFFIC = {"k_gemm_valu": {"source": "paper_2408_10369_amd/csrc/k_gemm.hip",
-                                "sha256": "5ccb7508fd01657d6439160d53dea3f119adddd9bf423655e162c26ec0ba5de9",
-                                "bytes_per_launch": 496.6e6}}
+GEMM_TRAFFIC = {"k_gemm_mfma": {"source": "paper_2408_10369_amd/csrc/k_gemm.hip",
+                                "sha256": "b0ddeecdd2833881aea3d33b62ee7adcd7465bf235753967379e42fa9465bfa9",
+                                "bytes_per_launch": 668.1e6}}
 
 
 def measured_traffic(kernel):
@@ -110,7 +110,18 @@ def main():
                            V=[ctx.zeros(k, n) for (_, _, k) in qs], Vs=[ctx.zeros(k, n) for (_, _, k) in qs]))
     torch.cuda.synchronize()
 
-    prod = {"ms": 0.0, "ops": 0, "launches": 0}
+    # product launches of the timed steps, per kernel (0 VALU, 1 MFMA): RMS squarings and dense selection rounds
+    prod = {arm: {"ms": 0.0, "ops": 0, "launches": 0} for arm in KERNELS}
+
+    def add_products(st):
+        mf = prod[1]
+        mf["ms"] += st["product_ms_mfma"]
+        mf["ops"] += st["product_bool_ops_mfma"]
+        mf["launches"] += st["products_mfma"]
+        va = prod[0]
+        va["ms"] += st["product_ms"] - st["product_ms_mfma"]
+        va["ops"] += st["product_bool_ops"] - st["product_bool_ops_mfma"]
+        va["launches"] += st["products"] - st["products_mfma"]
     per_graph = []
 
     def step(record: bool):
@@ -124,11 +135,10 @@ def main():
                 st2 = {}
                 ctx.smp(g["R"], n, g["V"][qi], out=g["Vs"][qi], stats=st2)
                 smp_ms.append(st2["device_ms"])
+                if record:
+                    add_products(st2)
             if record:
-                prod["ms"] += st["product_ms"]
-                prod["ops"] += st["product_bool_ops"]
-                prod["launches"] += st["products"]
-                prod["arm"] = st["arm"]
+                add_products(st)
                 if len(per_graph) < len(graphs):
                     per_graph.append({"p": g["p"], "edges": g["m"], "rms_products": st["products"],
                                       "rms_ms": round(st["device_ms"], 3), "smp_ms_k1_k64_k1024":
@@ -146,15 +156,21 @@ def main():
     rows_per_step = sum(n + sum(k for (_, _, k) in g["queries"]) for g in graphs)
     value = rows_per_step / (ms_per_step / 1000.0)
 
-    avg_launch_ms = prod["ms"] / max(prod["launches"], 1)
-    ops_per_launch = prod["ops"] / max(prod["launches"], 1)
+    # the dominant kernel: the product kernel with the most device time in the step
+    arm = max(prod, key=lambda a: prod[a]["ms"])
+    pk = prod[arm]
+    avg_launch_ms = pk["ms"] / max(pk["launches"], 1)
+    ops_per_launch = pk["ops"] / max(pk["launches"], 1)
     achieved_tops = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12 if avg_launch_ms > 0 else 0.0
-    kname, kdesc, bound, peak = KERNELS[prod.get("arm", 0)]
-    roofline = {"bound": bound, "kernel": "%s (%s; the RMS squarings of the step)" % (kname, kdesc),
+    kname, kdesc, bound, peak = KERNELS[arm]
+    roofline = {"bound": bound, "kernel": "%s (%s; every launch of it in the step: RMS squarings and dense "
+                                          "selection rounds)" % (kname, kdesc),
                 "achieved": round(achieved_tops, 2), "peak": round(peak, 1), "unit": "Tbool-op/s",
                 "frac": round(achieved_tops / peak, 4), "traffic": measured_traffic(kname),
                 "traffic_unit": "HBM bytes per launch",
-                "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": prod["launches"] // args.steps}
+                "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": pk["launches"] // args.steps,
+                "other_product_kernel_ms_per_step": round(sum(prod[a]["ms"] for a in prod if a != arm) / args.steps,
+                                                          3)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -108,12 +108,14 @@ typedef struct {
   int32_t products;        /* Boolean matrix products launched (incl. Algorithm 1's final one) */
   int32_t arm_trace[64];   /* arm used in each round (first 64 rounds); -1 past the end */
   int32_t arm;             /* the arm that served the call */
-  int32_t reserved;
+  int32_t products_mfma;   /* of the timed product launches, those of the matrix-core (MFMA) kernel */
   uint64_t bool_ops;       /* algorithmic Boolean operations: 2*m*k*n per dense (m x k).(k x n) product */
   uint64_t bytes_moved;    /* algorithmic device bytes read + written */
   double device_ms;        /* device time of the call (HIP events on the call's stream) */
   double product_ms;       /* device time inside the product kernels alone (events around each launch) */
   uint64_t product_bool_ops; /* algorithmic Boolean operations of those product launches */
+  double product_ms_mfma;    /* the part of product_ms spent in matrix-core (MFMA) product launches */
+  uint64_t product_bool_ops_mfma; /* the part of product_bool_ops done by those launches */
 } bmlp_stats;
 
 /* ------------------------------------------------------------ handles */

@@ -75,16 +75,19 @@ class Opts(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("products", ctypes.c_int32), ("arm_trace", ctypes.c_int32 * 64),
-                ("arm", ctypes.c_int32), ("reserved", ctypes.c_int32), ("bool_ops", ctypes.c_uint64),
+                ("arm", ctypes.c_int32), ("products_mfma", ctypes.c_int32), ("bool_ops", ctypes.c_uint64),
                 ("bytes_moved", ctypes.c_uint64), ("device_ms", ctypes.c_double), ("product_ms", ctypes.c_double),
-                ("product_bool_ops", ctypes.c_uint64)]
+                ("product_bool_ops", ctypes.c_uint64), ("product_ms_mfma", ctypes.c_double),
+                ("product_bool_ops_mfma", ctypes.c_uint64)]
 
     def as_dict(self):
         tr = [int(a) for a in self.arm_trace if a != -1]
         return {"iterations": int(self.iterations), "products": int(self.products), "arm": int(self.arm),
                 "arm_trace": tr, "bool_ops": int(self.bool_ops), "bytes_moved": int(self.bytes_moved),
                 "device_ms": float(self.device_ms), "product_ms": float(self.product_ms),
-                "product_bool_ops": int(self.product_bool_ops)}
+                "product_bool_ops": int(self.product_bool_ops), "products_mfma": int(self.products_mfma),
+                "product_ms_mfma": float(self.product_ms_mfma),
+                "product_bool_ops_mfma": int(self.product_bool_ops_mfma)}
 
 
 class BmlpError(RuntimeError):

@@ -192,7 +192,7 @@ struct StatsRec {
   void product_begin() {
     if (st) hip_check(hipEventRecord(c->evp0, s), "hipEventRecord");
   }
-  void product(i64 m, i64 k, i64 n) {
+  void product(i64 m, i64 k, i64 n, int arm) {
     if (!st) return;
     hip_check(hipEventRecord(c->evp1, s), "hipEventRecord");
     hip_check(hipEventSynchronize(c->evp1), "hipEventSynchronize");
@@ -203,6 +203,11 @@ struct StatsRec {
     st->bool_ops += ops;
     st->product_bool_ops += ops;
     st->product_ms += ms;
+    if (arm == BMLP_ARM_PRODUCT_MFMA) {
+      st->products_mfma += 1;
+      st->product_bool_ops_mfma += ops;
+      st->product_ms_mfma += ms;
+    }
     st->bytes_moved += (uint64_t)(m * words_for(k) + k * words_for(n) + 2 * m * words_for(n)) * 8u;
   }
   void finish() {
@@ -251,7 +256,7 @@ void product(bmlp_ctx* c, const u64* A, i64 lda, const u64* B, i64 ldb, const u6
     sr.product_begin();
     hip_check(launch_gemm_valu(g, s), "gemm_valu");
   }
-  sr.product(M, K, N);
+  sr.product(M, K, N, arm);
 }
 
 int ceil_log2(i64 x) {
@@ -261,11 +266,15 @@ int ceil_log2(i64 x) {
 }
 
 // Plain choice of the product kernel for an (M x K).(K x N) product: the matrix-core arm once both
-// output dimensions fill its 256 x 256 workgroup tiles (measured faster from n = 4,096 up), the
-// bit-packed VALU arm (which also splits K) for thin or small products.
-int product_arm(const bmlp_opts& o, i64 M, i64 N) {
+// output dimensions fill its 256 x 256 workgroup tiles (measured faster from n = 4,096 up) and K is
+// within its exact int32 range, the bit-packed VALU arm (which also splits K) for thin or small products.
+int product_arm(const bmlp_opts& o, i64 M, i64 N, i64 K) {
+  if (o.product_arm == BMLP_ARM_PRODUCT_MFMA)
+    need(words_for(K) <= gemm_mfma_max_kwords(), BMLP_EINVAL, "the MFMA product arm supports K <= %lld",
+         (long long)(64 * gemm_mfma_max_kwords()));
   if (o.product_arm == BMLP_ARM_PRODUCT_VALU || o.product_arm == BMLP_ARM_PRODUCT_MFMA) return o.product_arm;
-  return (M >= 1024 && N >= 1024) ? BMLP_ARM_PRODUCT_MFMA : BMLP_ARM_PRODUCT_VALU;
+  return (M >= 1024 && N >= 1024 && words_for(K) <= gemm_mfma_max_kwords()) ? BMLP_ARM_PRODUCT_MFMA
+                                                                              : BMLP_ARM_PRODUCT_VALU;
 }
 
 // R1+ into `out` (n x ldo) -- the RMS fixpoint driver shared by rms, the closure arm of smp and the RMS
@@ -276,7 +285,7 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   const i64 ldi = nw;
   u64* cur = ws_bits(c, S_W0, n, ldi, o);
   u64* nxt = ws_bits(c, S_W1, n, ldi, o);
-  const int arm = product_arm(o, n, n);
+  const int arm = product_arm(o, n, n, n);
   hip_check(launch_ewise(4, R1, ld1, nullptr, 0, cur, ldi, n, n, s), "copy");
   if (o.rms_variant == 1) hip_check(launch_set_diag(cur, ldi, n, n, s), "set_diag");
   const int cap = ceil_log2(std::max<i64>(n, 2)) + 2;
@@ -433,7 +442,7 @@ void smp_rounds(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vs
   const i64 nw = words_for(n);
   u64* fa = ws_bits(c, S_W3, k, nw, o);
   u64* fb = ws_bits(c, S_W4, k, nw, o);
-  const int parm = product_arm(o, k, n);
+  const int parm = product_arm(o, k, n, n);
   const bool learned = mode == RM_LEARNED;
   if ((mode == RM_SPARSE || learned) && !csr.rp) {
     i64* rp;
@@ -472,13 +481,17 @@ void smp_rounds(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vs
       pred = c->d_flags + F_DEC;
     }
     unsigned long long* nb = (unsigned long long*)(c->d_flags + F_NEW);
+    // an all-dense schedule times each product launch (the round events serve traces instead)
+    const bool timed = mode == RM_DENSE && !tr;
     if (mode != RM_SPARSE) {
       GemmArgs g{fa, nw, R1, ld, Vstar, ldv, Vstar, ldv, fb, nw, k, n, n, c->d_flags + F_CHANGED};
       g.newbits = nb;
       g.pred = pred;
       g.pred_val = 0;
+      if (timed) sr.product_begin();
       if (parm == BMLP_ARM_PRODUCT_MFMA) hip_check(launch_gemm_mfma(g, r1t, ldr1t, s), "gemm_mfma");
       else hip_check(launch_gemm_valu(g, s), "gemm_valu");
+      if (timed) sr.product(k, n, n, parm);
     }
     if (mode != RM_DENSE)
       hip_check(launch_smp_round(fa, fb, nw, Vstar, ldv, k, csr.rp, csr.ci, R1, ld, n, c->d_flags + F_CHANGED, nb,
@@ -493,7 +506,7 @@ void smp_rounds(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vs
     const int arm = learned ? (c->h_flags[F_DEC] == 0 ? BMLP_ARM_SMP_DENSE : BMLP_ARM_SMP_SPARSE)
                             : (mode == RM_DENSE ? BMLP_ARM_SMP_DENSE : BMLP_ARM_SMP_SPARSE);
     sr.trace(t, arm);
-    if (sr.st && arm == BMLP_ARM_SMP_DENSE) {
+    if (sr.st && arm == BMLP_ARM_SMP_DENSE && !timed) {
       sr.st->products += 1;
       sr.st->bool_ops += (uint64_t)2 * (uint64_t)k * (uint64_t)n * (uint64_t)n;
     }
@@ -525,7 +538,7 @@ void read_off_closure(bmlp_ctx* c, const u64* V, i64 ldv, i64 k, const u64* clo,
     return;
   }
   product(c, V, ldv, clo, ldc, reflexive ? V : nullptr, ldv, Vstar, ldv, nullptr, 0, k, n, n, nullptr,
-          product_arm(o, k, n), s, sr);
+          product_arm(o, k, n, n), s, sr);
   hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
 }
 
@@ -808,11 +821,12 @@ bmlp_status bmlp_product(bmlp_handle h, const uint64_t* A, int64_t lda, const ui
         if (Cold) hip_check(launch_ewise(4, Cold, ldc, nullptr, 0, C, ldc, m, n, s), "copy");
         else hip_check(launch_fill_zero(C, m * ldc, s), "fill_zero");
       } else {
-        product(h, A, lda, B, ldb, Cold, ldc, C, ldc, nullptr, 0, m, kdim, n, nullptr, product_arm(o, m, n), s, sr);
+        product(h, A, lda, B, ldb, Cold, ldc, C, ldc, nullptr, 0, m, kdim, n, nullptr, product_arm(o, m, n, kdim), s,
+                sr);
       }
     }
     if (m > 0) hip_check(launch_zero_pad(C, m, n, ldc, s), "zero_pad");
-    if (stats) stats->arm = product_arm(o, m, n);
+    if (stats) stats->arm = product_arm(o, m, n, kdim);
     sr.finish();
   });
 }
@@ -830,7 +844,7 @@ bmlp_status bmlp_rms(bmlp_handle h, const uint64_t* R1, uint64_t* Rstar, int64_t
     hipStream_t s = (hipStream_t)stream;
     if (o.check_padding) check_padding(h, R1, n, n, ld, s, "R1");
     StatsRec sr(stats, h, s, &o);
-    if (stats) stats->arm = product_arm(o, n, n);
+    if (stats) stats->arm = product_arm(o, n, n, n);
     if (n > 0) rms_core(h, R1, ld, Rstar, ld, n, o, s, sr);
     sr.finish();
   });
@@ -982,7 +996,7 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
         bmlp_opts o2 = o;
         o2.rms_variant = 0;
         rms_core(h, Rstep, ld, sp, nw, n, o2, s, sr);
-        product(h, sp, nw, Rbase, ld, Rbase, ld, P, ld, nullptr, 0, n, n, n, nullptr, product_arm(o, n, n), s, sr);
+        product(h, sp, nw, Rbase, ld, Rbase, ld, P, ld, nullptr, 0, n, n, n, nullptr, product_arm(o, n, n, n), s, sr);
         hip_check(launch_zero_pad(P, n, n, ld, s), "zero_pad");
       }
       if (h->trace) h->trace->call_arm = arm;

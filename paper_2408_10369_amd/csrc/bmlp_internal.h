@@ -65,8 +65,10 @@ struct GemmArgs {
 };
 enum ProductKernel { PK_VALU = 0, PK_MFMA = 1 };
 hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s);
-// MFMA int8 arm: needs B transposed (BT: N x K bits, ldbt) instead of B.
+// MFMA int8 arm: needs B transposed (BT: N x K bits, ldbt) instead of B; K <= 64 * gemm_mfma_max_kwords()
+// (the int32 sums stay exact).
 hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s);
+i64 gemm_mfma_max_kwords();
 
 // ---------------------------------------------------------------- selection
 // Per-row fixpoint of the semi-naive selection in one launch (one workgroup

@@ -132,23 +132,33 @@ hipError_t launch_rpw(const GemmArgs& g, hipStream_t s, i64 target_blocks) {
 // ---------------------------------------------------------------------------
 // MFMA arm: int8 matrix cores, int32 accumulation, "> 0" threshold.
 //
-// A 0/1 count of witnesses k is at most K < 2^31, so the int32 sum is exact and
-// "sum > 0" is exactly the OR of ANDs.  The operands stay bit-packed in memory;
-// each lane expands the bits it feeds to one v_mfma_i32_16x16x64_i8 into 16
-// bytes of 0/1: dword (h, j) = (half h of the 64-bit word >> j) & 0x01010101
-// holds bits j, j+8, j+16, j+24 of that half.  Lane group g = lane / 16 takes
-// j in {g, g+4} of both halves, so the four groups cover all 64 bits.  A and B
-// use the same bit -> (lane group, byte) map, and a sum over k does not depend
-// on the order of its terms, so the product is exact whatever k order the
-// instruction assigns to (group, byte) -- it only has to be the same for both
-// operands.  B is consumed transposed (B^T rows = columns of B), so that a
-// column's 64 k-bits are one word, like a row of A.
+// The operands stay bit-packed in memory; each lane expands the bits it feeds
+// to one v_mfma_i32_16x16x64_i8 into 16 bytes with one AND per dword: dword
+// (h, j) = (half h of the 64-bit word) & (0x01010101 << j) keeps bits j, j+8,
+// j+16, j+24 of that half in place, so byte b holds 0 or 2^j.  Lane group
+// g = lane / 16 takes j in {g, g+4} of both halves, so the four groups cover
+// all 64 bits.  A and B use the same bit -> (lane group, byte, value) map, so
+// every product term is 0 or (+-2^j)^2 = 4^j > 0 (the byte 2^7 reads as -128,
+// whose square is positive), and the int32 sum is positive exactly when some
+// k has A_ik = B_kj = 1: the OR of ANDs.  The sum per 64-bit word of k is at
+// most 8 * (4^0 + ... + 4^7) = 174,760, so it stays exact below 2^31 for up to
+// kMaxKWords words of k.  A sum does not depend on the order of its terms, so
+// the result is exact whatever k order the instruction assigns to (group,
+// byte) -- it only has to be the same for both operands.  B is consumed
+// transposed (B^T rows = columns of B), so that a column's 64 k-bits are one
+// word, like a row of A.
 //
-// Tile: a workgroup of 4 waves owns 256 x 256 outputs, wave (wr, wc) owns a
-// 128 x 128 block = 8 x 8 MFMA blocks of 16 x 16.  Per chunk of kMChunk words
-// of k the workgroup stages 256 rows of A and 256 rows of B^T (bits) in LDS,
+// Tile: a workgroup of 8 waves (two per SIMD, so that one wave's expansion and
+// LDS reads overlap the other's matrix-core work) owns 256 x 256 outputs; wave
+// (wr, wc) owns rows 128 wr .. +128 and columns 64 wc .. +64 = 8 x 4 MFMA blocks
+// of 16 x 16.  Per chunk of kMChunk words of k the workgroup stages 256 rows of
+// A (threads 0..255) and 256 rows of B^T (threads 256..511) in LDS,
 // double-buffered: the next chunk is loaded into registers while the current
-// one is consumed, so one barrier per chunk suffices.
+// one is consumed, so one barrier per chunk suffices.  While staging, the A
+// waves also record which words of the chunk are nonzero in any of their rows;
+// a consuming wave skips the words of k where all 128 of its rows are zero (a
+// wave-uniform test on that mask, which keeps the LDS reads of the next word in
+// flight).
 // A 16 x 16 int32 block sits in lane l as rows 4*(l/16)+v, column l%16
 // (v = 0..3), so a ballot of "acc[v] > 0" holds, in bits 16g..16g+15, the 16
 // output bits of row 4g+v.
@@ -157,103 +167,119 @@ typedef int v4i_t __attribute__((ext_vector_type(4)));
 constexpr int kMT = 256;     // workgroup tile (rows and columns)
 constexpr int kMChunk = 8;   // words of k per LDS stage
 constexpr int kMPad = 9;     // padded LDS row stride in words (no bank conflicts)
+constexpr i64 kMaxKWords = 12288;  // 12,288 * 174,760 < 2^31
 
-__device__ __forceinline__ v4i_t expand_frag(u64 w, int g) {
+__device__ __forceinline__ v4i_t expand_frag(u64 w, u32 m0, u32 m1) {
   const u32 lo = (u32)w, hi = (u32)(w >> 32);
   v4i_t f;
-  f.x = (int)((lo >> g) & 0x01010101u);
-  f.y = (int)((lo >> (g + 4)) & 0x01010101u);
-  f.z = (int)((hi >> g) & 0x01010101u);
-  f.w = (int)((hi >> (g + 4)) & 0x01010101u);
+  f.x = (int)(lo & m0);
+  f.y = (int)(lo & m1);
+  f.z = (int)(hi & m0);
+  f.w = (int)(hi & m1);
   return f;
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 ldbt, const u64* __restrict__ Cold,
             i64 ldco, u64* __restrict__ C, i64 ldc, u64* __restrict__ D, i64 ldd, i64 M, i64 K, i64 N,
             u32* __restrict__ changed, unsigned long long* __restrict__ newbits, const u32* __restrict__ pred,
             u32 pred_val) {
-  // two LDS stages: while one is consumed, the next chunk is already in registers
   __shared__ u64 As[2][kMT * kMPad];
   __shared__ u64 Bs[2][kMT * kMPad];
-  __shared__ u64 bal[4][32];
+  __shared__ u64 bal[8][16];
+  __shared__ u32 zmask[2][4];  // per stage and A-staging wave: bit q = some row has a nonzero word q
   if (pred && *pred != pred_val) return;  // another arm serves this round
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 2, wc = wave & 3;  // wave owns rows wr*128 .. +128, columns wc*64 .. +64
   const int g = lane >> 4, l16 = lane & 15;
+  const u32 m0 = 0x01010101u << g, m1 = 0x10101010u << g;
   const i64 ctiles = (N + kMT - 1) / kMT;
   const i64 tr = blockIdx.x / ctiles, tc = blockIdx.x % ctiles;
   const i64 row0 = tr * kMT, col0 = tc * kMT;
   const i64 kwords = (K + 63) >> 6;
 
-  v4i_t acc[8][8];
+  v4i_t acc[8][4];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = v4i_t{0, 0, 0, 0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4i_t{0, 0, 0, 0};
 
-  // this thread stages row t of the A tile and row t of the B^T tile
-  const i64 ra = row0 + t, rb = col0 + t;
-  const u64* pa = A + (ra < M ? ra : 0) * lda;
-  const u64* pb = BT + (rb < N ? rb : 0) * ldbt;
-  const bool va = ra < M, vb = rb < N;
-  u64 sa[kMChunk], sb[kMChunk];
+  // threads 0..255 stage row t of the A tile, threads 256..511 row t-256 of the B^T tile
+  const bool isa = t < 256;
+  const int tt = t & 255;
+  const i64 rr = (isa ? row0 : col0) + tt;
+  const bool vr = rr < (isa ? M : N);
+  const u64* pr = isa ? A + (vr ? rr : 0) * lda : BT + (vr ? rr : 0) * ldbt;
+  u64* stage0 = isa ? &As[0][tt * kMPad] : &Bs[0][tt * kMPad];
+  u64* stage1 = isa ? &As[1][tt * kMPad] : &Bs[1][tt * kMPad];
+  u64 sr[kMChunk];
 #pragma unroll
-  for (int q = 0; q < kMChunk; ++q) {
-    sa[q] = (va && q < kwords) ? pa[q] : 0ull;
-    sb[q] = (vb && q < kwords) ? pb[q] : 0ull;
-  }
+  for (int q = 0; q < kMChunk; ++q) sr[q] = (vr && q < kwords) ? pr[q] : 0ull;
   int buf = 0;
   for (i64 kc = 0; kc < kwords; kc += kMChunk, buf ^= 1) {
+    u64* st = buf ? stage1 : stage0;
 #pragma unroll
-    for (int q = 0; q < kMChunk; ++q) {
-      As[buf][t * kMPad + q] = sa[q];
-      Bs[buf][t * kMPad + q] = sb[q];
+    for (int q = 0; q < kMChunk; ++q) st[q] = sr[q];
+    if (isa) {
+      u32 zm = 0;
+#pragma unroll
+      for (int q = 0; q < kMChunk; ++q) zm |= (__ballot(sr[q] != 0ull) != 0ull ? 1u : 0u) << q;
+      if (lane == 0) zmask[buf][wave] = zm;
     }
     __syncthreads();
     const i64 kn = kc + kMChunk;
     if (kn < kwords) {
 #pragma unroll
-      for (int q = 0; q < kMChunk; ++q) {
-        sa[q] = (va && kn + q < kwords) ? pa[kn + q] : 0ull;
-        sb[q] = (vb && kn + q < kwords) ? pb[kn + q] : 0ull;
-      }
+      for (int q = 0; q < kMChunk; ++q) sr[q] = (vr && kn + q < kwords) ? pr[kn + q] : 0ull;
     }
     const u64* as = &As[buf][(wr * 128 + l16) * kMPad];
-    const u64* bs = &Bs[buf][(wc * 128 + l16) * kMPad];
-#pragma unroll 2
+    const u64* bs = &Bs[buf][(wc * 64 + l16) * kMPad];
+    // rows of this wave with a nonzero word q of k (wave-uniform)
+    const u32 mask = __builtin_amdgcn_readfirstlane(zmask[buf][2 * wr] | zmask[buf][2 * wr + 1]);
+    u64 aw[8], bw[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) aw[i] = as[i * 16 * kMPad];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bw[j] = bs[j * 16 * kMPad];
+#pragma unroll
     for (int q = 0; q < kMChunk; ++q) {
-      // a wave whose 128 rows have no set bit in this word of k has nothing to add
-      u64 aw[8];
-      int anyw = 0;
+      u64 an[8], bn[4];
+      if (q + 1 < kMChunk) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        aw[i] = as[i * 16 * kMPad + q];
-        anyw |= aw[i] != 0ull;
+        for (int i = 0; i < 8; ++i) an[i] = as[i * 16 * kMPad + q + 1];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bn[j] = bs[j * 16 * kMPad + q + 1];
       }
-      if (__ballot(anyw) == 0ull) continue;
-      v4i_t bf[8];
+      if ((mask >> q) & 1u) {
+        v4i_t bf[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) bf[j] = expand_frag(bs[j * 16 * kMPad + q], g);
+        for (int j = 0; j < 4; ++j) bf[j] = expand_frag(bw[j], m0, m1);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const v4i_t af = expand_frag(aw[i], g);
+        for (int i = 0; i < 8; ++i) {
+          const v4i_t af = expand_frag(aw[i], m0, m1);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      if (q + 1 < kMChunk) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) aw[i] = an[i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bw[j] = bn[j];
       }
     }
   }
 
-  // epilogue: per block row, ballot "> 0", assemble 16 rows x 2 words, OR with Cold
+  // epilogue: per block row, ballot "> 0", assemble 16 rows x 1 word, OR with Cold
   const i64 nw = (N + 63) >> 6;
   int ch = 0;
   u32 pop = 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < 4; ++j) {
       const u64 b0 = __ballot(acc[i][j].x > 0);
       const u64 b1 = __ballot(acc[i][j].y > 0);
       const u64 b2 = __ballot(acc[i][j].z > 0);
@@ -267,17 +293,17 @@ k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    if (lane < 32) {
-      const int r = lane >> 1, half = lane & 1;  // r = 4 * gg + v
+    if (lane < 16) {
+      const int r = lane;  // r = 4 * gg + v
       const int v = r & 3, gg = r >> 2;
       u64 word = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const u64 b = bal[wave][(half * 4 + q) * 4 + v];
+        const u64 b = bal[wave][q * 4 + v];
         word |= ((b >> (16 * gg)) & 0xFFFFull) << (16 * q);
       }
       const i64 row = row0 + wr * 128 + i * 16 + r;
-      const i64 w = (col0 + wc * 128) / 64 + half;
+      const i64 w = (col0 + wc * 64) / 64;
       if (row < M && w < nw) {
         const u64 old = Cold ? Cold[row * ldco + w] : 0ull;
         const u64 nv = word | old;
@@ -298,10 +324,13 @@ k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 
 
 }  // namespace
 
+i64 gemm_mfma_max_kwords() { return kMaxKWords; }
+
 hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (words_for(g.K) > kMaxKWords) return hipErrorInvalidValue;
   const i64 tiles = ((g.M + kMT - 1) / kMT) * ((g.N + kMT - 1) / kMT);
-  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)tiles), dim3(256), 0, s, g.A, g.lda, BT, ldbt, g.Cold, g.ldco, g.C,
+  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)tiles), dim3(512), 0, s, g.A, g.lda, BT, ldbt, g.Cold, g.ldco, g.C,
                      g.ldc, g.D, g.ldd, g.M, g.K, g.N, g.changed, g.newbits, g.pred, g.pred_val);
   return hipGetLastError();
 }

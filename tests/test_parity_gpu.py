@@ -111,6 +111,39 @@ def test_product(ctx, arm, shape):
     assert np.array_equal(got, boolops.to_bits(boolops.mul(A2, B2)))
 
 
+def test_product_mfma_skipped_words(ctx):
+    # k-words that are zero in every row of a 128-row block are skipped by the matrix-core arm;
+    # a pattern that differs per row block and per word exercises mixed skip masks
+    m, k, n = 600, 64 * 40, 300
+    rng = np.random.default_rng(4242)
+    A = (rng.random((m, k)) < 0.05).astype(np.uint8)
+    for r in range(m):
+        for w in range(k // 64):
+            if (w + r // 128) % 3 != 0 or (w % 8 == 7 and r // 128 == 1):
+                A[r, 64 * w:64 * w + 64] = 0
+    Bm = (rng.random((k, n)) < 0.05).astype(np.uint8)
+    want = boolops.to_bits(boolops.mul(A, Bm))
+    for arm in (B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA):
+        got = host(ctx.product(dev(boolops.to_bits(A)), dev(boolops.to_bits(Bm)), k, n, opts=forced(product_arm=arm)))
+        assert np.array_equal(got, want), arm
+
+
+def test_product_mfma_longest_k(ctx):
+    # all-ones operands at the largest K the matrix-core arm accepts: every int32 sum takes its
+    # largest value (12,288 words x 174,760 < 2^31) and must still read as "> 0"
+    kw = 12288
+    k = 64 * kw
+    A = torch.full((256, kw), -1, dtype=torch.int64, device="cuda")
+    Bm = torch.full((k, 4), -1, dtype=torch.int64, device="cuda")
+    got = host(ctx.product(A, Bm, k, 256, opts=forced(product_arm=B.ARM_PRODUCT_MFMA)))
+    assert (got == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    A1 = torch.zeros((256, kw + 1), dtype=torch.int64, device="cuda")
+    B1 = torch.zeros((k + 64, 4), dtype=torch.int64, device="cuda")
+    with pytest.raises(B.BmlpError) as e:
+        ctx.product(A1, B1, k + 64, 256, opts=forced(product_arm=B.ARM_PRODUCT_MFMA))
+    assert e.value.status == B.EINVAL
+
+
 # ----------------------------------------------------------------- RMS
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n", SIZES)
