@@ -204,10 +204,14 @@ def _modes(B):
     return {"plain": B.make_opts(dispatch=B.DISPATCH_PLAIN), "learned": B.make_opts(dispatch=B.DISPATCH_LEARNED)}
 
 
-def _hash(t, W):
-    """Order-dependent 64-bit fingerprint of a bit matrix (wrapping integer arithmetic)."""
+def _hash_dev(t, W):
+    """Order-dependent 64-bit fingerprint of a bit matrix (wrapping integer arithmetic), left on the device."""
     flat = t.reshape(-1)
-    return int((flat * W[: flat.numel()]).sum().item())
+    return (flat * W[: flat.numel()]).sum()
+
+
+def _hash(t, W):
+    return int(_hash_dev(t, W).item())
 
 
 def wl_batch(ctx, args):
@@ -245,6 +249,8 @@ def wl_batch(ctx, args):
     return {"workload": "512 ER digraphs, n log-uniform [64,4096], mean degree U(2,8), closure + 64 queries each, "
                         "one hipGraph launch",
             "plain": res["plain"], "learned": res["learned"],
+            "rules": "plain answers each query row by a selection inside the graph; learned reads the answers "
+                     "off the closures the batch must produce anyway (no model call: every closure is an output)",
             "speedup_learned_over_plain": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
             "bit_identical": fp["plain"] == fp["learned"]}
 
@@ -265,34 +271,47 @@ def wl_programs(ctx, args):
         for r in (b, s):
             if r not in packed:
                 packed[r] = ctx.pack_coo(torch.as_tensor(mr.rel_src[r]), torch.as_tensor(mr.rel_dst[r]), n, n)
-    P = ctx.zeros(n, n)
-    W = torch.randint(-2**62, 2**62, (P.numel(),), dtype=torch.int64, device="cuda")
+    outs = [ctx.zeros(n, n) for _ in progs]  # one output per program (28 MB each), hashed after timing
+    W = torch.randint(-2**62, 2**62, (outs[0].numel(),), dtype=torch.int64, device="cuda")
     modes = _modes(B)
-    # each route forced on every program, for the best fixed choice beside the two schedules
-    for name, arm in (("rms", B.ARM_COMPOSE_RMS), ("seminaive", B.ARM_COMPOSE_SEMINAIVE),
-                      ("rowwise", B.ARM_COMPOSE_ROWWISE)):
-        modes["forced_" + name] = B.make_opts(dispatch=B.DISPATCH_FORCED, compose_arm=arm)
-    for (b, s) in progs[:4]:
+    # every call-level arm the learned schedule chooses among, forced on every program: the per-program
+    # best of these in hindsight is the reference for the regret of both schedules
+    forced = {"cols_adaptive": (B.ARM_COMPOSE_SEMINAIVE, B.ARM_SMP_ADAPTIVE),
+              "cols_one_launch": (B.ARM_COMPOSE_SEMINAIVE, B.ARM_SMP_SPARSE),
+              "rows": (B.ARM_COMPOSE_ROWWISE, B.ARM_AUTO), "closure": (B.ARM_COMPOSE_RMS, B.ARM_AUTO)}
+    for name, (carm, sarm) in forced.items():
+        modes["forced_" + name] = B.make_opts(dispatch=B.DISPATCH_FORCED, compose_arm=carm, smp_arm=sarm)
+    for i, (b, s) in enumerate(progs[:4]):
         for o in modes.values():
-            ctx.compose_linear(packed[b], packed[s], n, out=P, opts=o)
-    res, fp = {}, {}
+            ctx.compose_linear(packed[b], packed[s], n, out=outs[i], opts=o)
+    res, fp, dev_ms = {}, {}, {}
     for mode, o in modes.items():
-        arms, hs = {}, []
+        arms, per = {}, []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for (b, s) in progs:
+        for i, (b, s) in enumerate(progs):
             st = {}
-            ctx.compose_linear(packed[b], packed[s], n, out=P, opts=o, stats=st)
+            ctx.compose_linear(packed[b], packed[s], n, out=outs[i], opts=o, stats=st)
             arms[st["arm"]] = arms.get(st["arm"], 0) + 1
-            hs.append(_hash(P, W))
+            per.append(st["device_ms"])
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
-        fp[mode] = hs
-        res[mode] = {"ms": round(ms, 2), "programs_per_s": round(len(progs) / (ms / 1e3), 2),
+        fp[mode] = [_hash(P, W) for P in outs]
+        dev_ms[mode] = per
+        res[mode] = {"ms": round(ms, 2), "device_ms": round(sum(per), 2),
+                     "programs_per_s": round(len(progs) / (ms / 1e3), 2),
                      "arms": {str(k): v for k, v in sorted(arms.items())}}
+    best = [min(dev_ms["forced_" + f][i] for f in forced) for i in range(len(progs))]
+
+    def regret(mode):
+        return round(sum(dev_ms[mode][i] / best[i] for i in range(len(progs))) / len(progs), 3)
+
+    for mode in ("plain", "learned"):
+        res[mode]["mean_time_over_best_arm"] = regret(mode)
     return {"workload": "100 programs over 14,951 entities / 1,345 relations / 592,000 facts (held-out seeds)",
             "plain": res["plain"], "learned": res["learned"],
-            "forced": {k[7:]: v["ms"] for k, v in res.items() if k.startswith("forced_")},
+            "forced_ms": {k[7:]: v["ms"] for k, v in res.items() if k.startswith("forced_")},
+            "best_arm_in_hindsight_ms": round(sum(best), 2),
             "speedup_learned_over_plain": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
             "bit_identical": all(h == fp["plain"] for h in fp.values())}
 
@@ -314,7 +333,11 @@ def wl_stream(ctx, args):
     Vs = ctx.zeros(4096, n)
     W = torch.randint(-2**62, 2**62, (Vs.numel(),), dtype=torch.int64, device="cuda")
     res, fp = {}, {}
-    for mode, o in _modes(B).items():
+    modes = _modes(B)
+    # the plain schedule answers every query of this stream by the one-launch sparse selection; the other
+    # static policy builds the closure at the first query and reads every answer off it
+    modes["forced_closure"] = B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE)
+    for mode, o in modes.items():
         arms, hs = {}, []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -329,18 +352,20 @@ def wl_stream(ctx, args):
                 arms[st["arm"]] = arms.get(st["arm"], 0) + 1
                 if closure_at is None and g.has_closure:
                     closure_at = qi
-                hs.append(_hash(Vsk, W))
+                hs.append(_hash_dev(Vsk, W))
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
-        fp[mode] = hs
+        fp[mode] = [int(h) for h in torch.stack(hs).cpu()]
         res[mode] = {"ms": round(ms, 1), "queries_per_s": round(len(queries) / (ms / 1e3), 1),
                      "rows_per_s": round(sum(len(q) for q in queries) / (ms / 1e3), 1),
                      "arms": {str(k): v for k, v in sorted(arms.items())}, "closure_built_at_query": closure_at}
     return {"workload": "scale-free digraph n=65536 m=262144, %d queries, k log-uniform [1,4096] "
                         "(%d rows), one session" % (len(queries), sum(len(q) for q in queries)),
-            "plain": res["plain"], "learned": res["learned"],
+            "plain": res["plain"], "learned": res["learned"], "forced_closure": res["forced_closure"],
             "speedup_learned_over_plain": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
-            "bit_identical": fp["plain"] == fp["learned"]}
+            "learned_over_best_static_policy": round(
+                res["learned"]["ms"] / min(res["plain"]["ms"], res["forced_closure"]["ms"]), 3),
+            "bit_identical": all(h == fp["plain"] for h in fp.values())}
 
 
 def cpu_baseline(graphs, n, sample_rows):
@@ -370,10 +395,22 @@ def cpu_baseline(graphs, n, sample_rows):
             oracle.smp(n, s, d, Vh)
             t_total += time.perf_counter() - t0
             rows_total += Vh.shape[0]
+    # the same oracle on one thread, on 64 random closure rows per graph
+    t1, rows1 = 0.0, 0
+    for g in graphs:
+        s = g["s"].cpu().numpy()
+        d = g["d"].cpu().numpy()
+        rows = np.sort(rng.choice(n, 64, replace=False))
+        t0 = time.perf_counter()
+        oracle.closure_rows(n, s, d, rows=rows, threads=1)
+        t1 += time.perf_counter() - t0
+        rows1 += len(rows)
     what = "all closure rows" if sample_rows <= 0 else "%d random closure rows" % sample_rows
     return {"value": round(rows_total / t_total, 1), "unit": "query rows/s", "cores": threads, "kind": "oracle",
             "sample": "%s of each of the %d graphs plus every SMP query row (k=1,64,1024), per-source BFS; "
-                      "%d rows in %.2f s" % (what, len(graphs), rows_total, t_total)}
+                      "%d rows in %.2f s" % (what, len(graphs), rows_total, t_total),
+            "value_1_thread": round(rows1 / t1, 1),
+            "sample_1_thread": "64 random closure rows of each graph on one thread; %d rows in %.2f s" % (rows1, t1)}
 
 
 if __name__ == "__main__":
