@@ -72,7 +72,7 @@ typedef enum {
 typedef enum {
   BMLP_ARM_AUTO = -1,
   BMLP_ARM_PRODUCT_VALU = 0,  /* bit-packed product: LDS-staged 64-bit words, wave AND/OR */
-  BMLP_ARM_PRODUCT_MFMA = 1,  /* int8 matrix-core product, int32 accumulate, > 0 threshold */
+  BMLP_ARM_PRODUCT_MFMA = 1,  /* 4-bit (e2m1) matrix-core product, exact fp32 accumulate, > 0 threshold */
   BMLP_ARM_SMP_DENSE = 2,     /* selection by repeated dense products (semi-naive delta . R1) */
   BMLP_ARM_SMP_SPARSE = 3,    /* selection by sparse-frontier expansion, whole fixpoint per row in one launch */
   BMLP_ARM_SMP_CLOSURE = 4,   /* selection as V . R1+ after BMLP-RMS (closure reuse, Section 4) */
@@ -116,6 +116,9 @@ typedef struct {
   uint64_t product_bool_ops; /* algorithmic Boolean operations of those product launches */
   double product_ms_mfma;    /* the part of product_ms spent in matrix-core (MFMA) product launches */
   uint64_t product_bool_ops_mfma; /* the part of product_bool_ops done by those launches */
+  uint64_t mfma_ops_issued;  /* matrix-core operations those launches actually issued: less than their
+                                Boolean operations when output tiles are already saturated or words of k
+                                are zero across a row block, more on ragged tile edges */
 } bmlp_stats;
 
 /* ------------------------------------------------------------ handles */
@@ -161,7 +164,9 @@ bmlp_status bmlp_transpose(bmlp_handle h, const uint64_t *A, int64_t rows, int64
                            uint64_t *AT, int64_t ldat, void *stream);
 /* C = Cold + A x B over the Boolean semiring (Section 2); Cold may be NULL (then C = A x B) and may
    equal C.  A: m x kdim (lda), B: kdim x n (ldb), C: m x n (ldc).  C must not overlap A or B.
-   opts may be NULL (defaults); opts->product_arm selects the kernel. */
+   opts may be NULL (defaults); opts->product_arm selects the kernel.  The matrix-core arm keeps its
+   sums exact up to kdim = 4,194,304 and returns BMLP_EINVAL beyond (the default choice then takes
+   the VALU arm). */
 bmlp_status bmlp_product(bmlp_handle h, const uint64_t *A, int64_t lda, const uint64_t *B, int64_t ldb,
                          const uint64_t *Cold, uint64_t *C, int64_t ldc, int64_t m, int64_t kdim, int64_t n,
                          const bmlp_opts *opts, void *stream, bmlp_stats *stats);

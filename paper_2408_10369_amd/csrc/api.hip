@@ -79,6 +79,7 @@ enum FlagSlot {
   F_PRED = 12,     // 4 predicted log times
   F_FEAT = 16,     // 16 features
   F_GSTATS = 32,   // 3 x 64-bit graph statistics
+  F_EXEC = 40,     // 64-bit count of matrix-core ops issued by a timed product
   F_WORDS = 128
 };
 
@@ -189,15 +190,27 @@ struct StatsRec {
   void trace(int round, int arm) {
     if (st && round >= 0 && round < 64) st->arm_trace[round] = arm;
   }
+  // counter of matrix-core work for the next timed product (null when no statistics are kept)
+  unsigned long long* exec_counter() const {
+    return st ? (unsigned long long*)(c->d_flags + F_EXEC) : nullptr;
+  }
   void product_begin() {
-    if (st) hip_check(hipEventRecord(c->evp0, s), "hipEventRecord");
+    if (!st) return;
+    hip_check(hipMemsetAsync(c->d_flags + F_EXEC, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+    hip_check(hipEventRecord(c->evp0, s), "hipEventRecord");
   }
   void product(i64 m, i64 k, i64 n, int arm) {
     if (!st) return;
     hip_check(hipEventRecord(c->evp1, s), "hipEventRecord");
+    hip_check(hipMemcpyAsync(c->h_flags + F_EXEC, c->d_flags + F_EXEC, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s),
+              "hipMemcpyAsync");
     hip_check(hipEventSynchronize(c->evp1), "hipEventSynchronize");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, c->evp0, c->evp1), "hipEventElapsedTime");
+    unsigned long long issued = 0;
+    std::memcpy(&issued, c->h_flags + F_EXEC, sizeof issued);
     const uint64_t ops = (uint64_t)2 * (uint64_t)m * (uint64_t)k * (uint64_t)n;
     st->products += 1;
     st->bool_ops += ops;
@@ -207,6 +220,7 @@ struct StatsRec {
       st->products_mfma += 1;
       st->product_bool_ops_mfma += ops;
       st->product_ms_mfma += ms;
+      st->mfma_ops_issued += issued;
     }
     st->bytes_moved += (uint64_t)(m * words_for(k) + k * words_for(n) + 2 * m * words_for(n)) * 8u;
   }
@@ -246,6 +260,7 @@ void product(bmlp_ctx* c, const u64* A, i64 lda, const u64* B, i64 ldb, const u6
              u64* D, i64 ldd, i64 M, i64 K, i64 N, u32* changed, int arm, hipStream_t s, StatsRec& sr,
              const u64* BT = nullptr, i64 ldbt = 0) {
   GemmArgs g{A, lda, B, ldb, Cold, ldco, C, ldc, D, ldd, M, K, N, changed};
+  g.executed = sr.exec_counter();
   if (arm == BMLP_ARM_PRODUCT_MFMA) {
     bmlp_opts dflt;
     bmlp_opts_init(&dflt);
@@ -488,6 +503,7 @@ void smp_rounds(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vs
       g.newbits = nb;
       g.pred = pred;
       g.pred_val = 0;
+      if (timed) g.executed = sr.exec_counter();
       if (timed) sr.product_begin();
       if (parm == BMLP_ARM_PRODUCT_MFMA) hip_check(launch_gemm_mfma(g, r1t, ldr1t, s), "gemm_mfma");
       else hip_check(launch_gemm_valu(g, s), "gemm_valu");

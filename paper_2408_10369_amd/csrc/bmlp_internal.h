@@ -47,7 +47,8 @@ hipError_t launch_bits_to_csr(const u64* a, i64 rows, i64 n, i64 ld, const i64* 
 
 // ---------------------------------------------------------------- products
 // C = Cold | A.B over the Boolean semiring; D = C & ~Cold (optional);
-// *changed |= 1 when any word of C differs from Cold.
+// *changed |= 1 when any word of C differs from Cold.  The MFMA arm skips output tiles whose Cold bits
+// are all set and words of k that are zero in every row of a 128-row block.
 //   A: M x K bits (lda), B: K x N bits (ldb), Cold/C/D: M x N bits.
 //   Cold may be null (treated as 0).  C may equal Cold (element-wise in place);
 //   A and B must not overlap C or D.  Words >= ceil(N/64) are not written.
@@ -62,6 +63,7 @@ struct GemmArgs {
   unsigned long long* newbits = nullptr;  // += number of bits of C not in Cold (optional)
   const u32* pred = nullptr;              // when given, the kernel runs only if *pred == pred_val
   u32 pred_val = 0;
+  unsigned long long* executed = nullptr;  // += matrix-core ops actually issued (MFMA arm, optional)
 };
 enum ProductKernel { PK_VALU = 0, PK_MFMA = 1 };
 hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s);

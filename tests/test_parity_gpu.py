@@ -128,15 +128,47 @@ def test_product_mfma_skipped_words(ctx):
         assert np.array_equal(got, want), arm
 
 
+@pytest.mark.parametrize("inplace", [False, True])
+def test_product_mfma_saturated_tiles(ctx, inplace):
+    # output tiles whose C_old bits are all set are copied without a product; a tile one bit short
+    # of full, and a full ragged corner tile, sit beside them
+    m, k, n = 700, 300, 600
+    rng = np.random.default_rng(99)
+    A = (rng.random((m, k)) < 0.02).astype(np.uint8)
+    Bm = (rng.random((k, n)) < 0.02).astype(np.uint8)
+    Co = (rng.random((m, n)) < 0.01).astype(np.uint8)
+    Co[0:256, 0:256] = 1
+    Co[256:512, 256:512] = 1
+    Co[300, 400] = 0
+    Co[512:, 512:] = 1
+    Co[0:256, 512:] = 1
+    want = boolops.to_bits(boolops.add(Co, boolops.mul(A, Bm)))
+    bc = dev(boolops.to_bits(Co))
+    o = forced(product_arm=B.ARM_PRODUCT_MFMA)
+    got = host(ctx.product(dev(boolops.to_bits(A)), dev(boolops.to_bits(Bm)), k, n, Cold=bc,
+                           out=bc if inplace else None, opts=o))
+    assert np.array_equal(got, want)
+
+
 def test_product_mfma_longest_k(ctx):
-    # all-ones operands at the largest K the matrix-core arm accepts: every int32 sum takes its
-    # largest value (12,288 words x 174,760 < 2^31) and must still read as "> 0"
-    kw = 12288
+    # all-ones operands at the largest K the matrix-core arm accepts (65,536 words): every fp32 sum
+    # takes its largest value and must still be exact and read as "> 0"; one word more is refused
+    kw = 65536
     k = 64 * kw
     A = torch.full((256, kw), -1, dtype=torch.int64, device="cuda")
     Bm = torch.full((k, 4), -1, dtype=torch.int64, device="cuda")
     got = host(ctx.product(A, Bm, k, 256, opts=forced(product_arm=B.ARM_PRODUCT_MFMA)))
     assert (got == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    # a single witness at the far end of k
+    A.zero_()
+    Bm.zero_()
+    A[5, kw - 1] = -(1 << 63)  # bit 63 of the last word
+    Bm[k - 1, 2] = 1 << 7
+    got = host(ctx.product(A, Bm, k, 256, opts=forced(product_arm=B.ARM_PRODUCT_MFMA)))
+    want = np.zeros((256, 4), np.uint64)
+    want[5, 2] = np.uint64(1 << 7)
+    assert np.array_equal(got, want)
+    del A, Bm
     A1 = torch.zeros((256, kw + 1), dtype=torch.int64, device="cuda")
     B1 = torch.zeros((k + 64, 4), dtype=torch.int64, device="cuda")
     with pytest.raises(B.BmlpError) as e:
