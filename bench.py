@@ -41,7 +41,7 @@ KERNELS = {0: ("k_gemm_valu", "bit-packed Boolean product on the VALU", "alu", V
 # is valid only for the kernel source it was measured on (sha256 of the file).
 GEMM_TRAFFIC = {"k_gemm_mfma": {"source": "paper_2408_10369_amd/csrc/k_gemm.hip",
                                 "sha256": "5c3e40c6fb99510d32cd7d35259f3db1f88651295ffca41653723d8028c697d5",
-                                "bytes_per_launch": 590.2e6}}
+                                "bytes_per_launch": 481.8e6}}
 
 
 def measured_traffic(kernel):
@@ -142,7 +142,8 @@ def main():
             if record:
                 add_products(st)
                 if len(per_graph) < len(graphs):
-                    per_graph.append({"p": g["p"], "edges": g["m"], "rms_products": st["products"],
+                    per_graph.append({"p": g["p"], "edges": g["m"], "rms_squarings": st["iterations"],
+                                      "rms_squarings_by_gather": st["arm_trace"].count(B.ARM_PRODUCT_GATHER),
                                       "rms_ms": round(st["device_ms"], 3), "smp_ms_k1_k64_k1024":
                                       [round(x, 3) for x in smp_ms]})
 

@@ -80,8 +80,10 @@ typedef enum {
   BMLP_ARM_COMPOSE_SEMINAIVE = 6, /* compose: P^T = Rb^T (Rs^T)*, reflexive selections over the transposed step */
   BMLP_ARM_SMP_SPARSE_ROUNDS = 7, /* selection by rounds, every round by sparse-frontier expansion */
   BMLP_ARM_SMP_ADAPTIVE = 8,  /* selection by rounds, each round's kernel chosen on the device by the model */
-  BMLP_ARM_COMPOSE_ROWWISE = 9 /* compose: P[X] = Rb[X] | OR of Rb[Z] over Z in e_X Rs+, only for rows X with
+  BMLP_ARM_COMPOSE_ROWWISE = 9, /* compose: P[X] = Rb[X] | OR of Rb[Z] over Z in e_X Rs+, only for rows X with
                                   a step edge (selections over Rs, rows of Rb gathered; n <= 131072) */
+  BMLP_ARM_PRODUCT_GATHER = 10 /* (in arm traces) a squaring of a sparse R done as row gathers: row i of
+                                  R | R.R = R[i] | OR of the rows k over the set bits k of R[i] */
 } bmlp_arm;
 
 typedef enum {
@@ -105,7 +107,8 @@ typedef struct {
 
 typedef struct {
   int32_t iterations;      /* fixpoint rounds (squarings for RMS, rounds for SMP/compose) */
-  int32_t products;        /* Boolean matrix products launched (incl. Algorithm 1's final one) */
+  int32_t products;        /* launches of the product kernels (incl. Algorithm 1's final product); a
+                              squaring done by row gathers counts in iterations and arm_trace only */
   int32_t arm_trace[64];   /* arm used in each round (first 64 rounds); -1 past the end */
   int32_t arm;             /* the arm that served the call */
   int32_t products_mfma;   /* of the timed product launches, those of the matrix-core (MFMA) kernel */

@@ -18,6 +18,7 @@
 // queued and expanded by the whole workgroup, either through CSR or, when the
 // node's row is dense, by OR-ing its bit row of R1 word by word.
 #include "bmlp_internal.h"
+#include "valu_tile.h"
 
 namespace bmlp {
 
@@ -218,12 +219,13 @@ k_smp_round(const u64* __restrict__ fr, u64* __restrict__ fr_out, i64 ldf, u64* 
 // LDS in passes of 1,024 and OR-ed, each a coalesced row of C, into the answer held in registers
 // (thread t owns words t, t + 256, ...; n <= 131,072).  The answer of row r goes to output row
 // row_map[r] (r without a map) and starts from zero, from V[r] (init 1) or from the output row's
-// current content (init 2).
+// current content (init 2); the bits added to those starting rows are counted into *newbits.
 constexpr int kGatherWords = 2048;
 
 __global__ void __launch_bounds__(256)
 k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__ Cl, i64 ldc, i64 n, int init,
-              u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map) {
+              u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map,
+              unsigned long long* __restrict__ newbits) {
   __shared__ int32_t srcs[1024];
   __shared__ int scan[256];
   const i64 nw = (n + 63) >> 6;
@@ -231,9 +233,10 @@ k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__
   const int t = threadIdx.x;
   const i64 chunk = (nw + 255) / 256;
   const i64 wb = t * chunk, we = (wb + chunk < nw) ? wb + chunk : nw;
+  u32 added = 0;  // bits of the answers not in their starting rows
   for (i64 row = blockIdx.x; row < k; row += gridDim.x) {
     const i64 orow = row_map ? (i64)row_map[row] : row;
-    u64 acc[kGatherWords / 256];
+    u64 acc[kGatherWords / 256], start[kGatherWords / 256];
 #pragma unroll
     for (int j = 0; j < kGatherWords / 256; ++j) {
       const i64 w = t + 256 * j;
@@ -241,6 +244,7 @@ k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__
       if (w < nw && init == 1) a = V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
       if (w < nw && init == 2) a = out[orow * ldo + w];
       acc[j] = a;
+      start[j] = a;
     }
     int cnt = 0;
     for (i64 w = wb; w < we; ++w) cnt += __popcll(V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull));
@@ -281,11 +285,15 @@ k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__
 #pragma unroll
     for (int j = 0; j < kGatherWords / 256; ++j) {
       const i64 w = t + 256 * j;
-      if (w < nw) out[orow * ldo + w] = acc[j];
+      if (w < nw) {
+        out[orow * ldo + w] = acc[j];
+        added += (u32)__popcll(acc[j] & ~start[j]);
+      }
     }
     for (i64 w = nw + t; w < ldo; w += 256) out[orow * ldo + w] = 0ull;
     __syncthreads();
   }
+  wave_count(added, newbits);
 }
 
 }  // namespace
@@ -295,11 +303,12 @@ i64 smp_rows_max_n() { return (kMaxLdsWords / 3) * 64; }
 i64 gather_rows_max_n() { return (i64)kGatherWords * 64; }
 
 hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 ldc, i64 n, int init, u64* out,
-                              i64 ldo, hipStream_t s, const int32_t* row_map) {
+                              i64 ldo, hipStream_t s, const int32_t* row_map, unsigned long long* newbits) {
   if (k <= 0) return hipSuccess;
   if (words_for(n) > kGatherWords) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(k < 65535 ? k : 65535);
-  hipLaunchKernelGGL(k_gather_rows, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo, row_map);
+  hipLaunchKernelGGL(k_gather_rows, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo, row_map,
+                     newbits);
   return hipGetLastError();
 }
 hipError_t launch_smp_round(const u64* fr, u64* fr_out, i64 ldf, u64* vis, i64 ldvis, i64 k, const i64* rp,

@@ -188,7 +188,7 @@ def test_rms_random(ctx, n, variant):
         got = host(ctx.rms(R, n, opts=B.make_opts(rms_variant=variant), stats=st))
         want = oracle.closure_rows(n, s, d)
         assert np.array_equal(got, want), (n, p, variant)
-        assert st["products"] >= 1 and st["iterations"] <= math.ceil(math.log2(max(n, 2))) + 2
+        assert 1 <= st["iterations"] <= math.ceil(math.log2(max(n, 2))) + 2
 
 
 def test_rms_first_config(ctx):
@@ -219,11 +219,18 @@ def test_rms_path_graph_loop_counts(ctx, n):
     st = {}
     got = host(ctx.rms(R, n, stats=st))
     assert np.array_equal(got, oracle.closure_rows(n, s, d))
-    assert st["products"] == math.ceil(math.log2(n - 1)) + 1
+    # squarings (by the product kernels or, while R is sparse, by row gathers)
+    assert st["iterations"] == math.ceil(math.log2(n - 1)) + 1
+    assert st["products"] + st["arm_trace"].count(B.ARM_PRODUCT_GATHER) == st["iterations"]
     st1 = {}
     ctx.rms(R, n, opts=B.make_opts(rms_variant=1), stats=st1)
     assert st1["iterations"] == math.ceil(math.log2(n - 1)) + 1
-    assert st1["products"] == st1["iterations"] + 1
+    # plus Algorithm 1's final product by R1
+    assert st1["products"] + st1["arm_trace"].count(B.ARM_PRODUCT_GATHER) == st1["iterations"] + 1
+    for parm in (B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA):
+        st2 = {}
+        ctx.rms(R, n, opts=B.make_opts(product_arm=parm), stats=st2)
+        assert st2["products"] == st2["iterations"] == math.ceil(math.log2(n - 1)) + 1
 
 
 def test_rms_special_graphs(ctx):
@@ -405,7 +412,7 @@ def test_isforeign_pipeline(ctx, golden_dir):
 
 
 # ----------------------------------------------------------------- full-size density sweep (sampled)
-@pytest.mark.parametrize("parm", [B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA])
+@pytest.mark.parametrize("parm", [B.ARM_AUTO, B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA])
 @pytest.mark.parametrize("pi", [0, 2, 4])
 def test_density_sweep_rms_sampled_rows(ctx, pi, parm):
     n, s, d = gen.c2(pi)
