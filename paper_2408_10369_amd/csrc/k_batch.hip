@@ -68,11 +68,56 @@ __global__ void k_batch_setup(BatchGraph* __restrict__ gs, int count, i64 total_
   }
 }
 
+// Rows row0 .. row0 + kRPW - 1 of R | R.R by row gathers (row i = R[i] | OR of the rows k over the
+// set bits k of R[i]), one wave, lane l owning word l (nw <= 64).  The set bits of a row are walked in
+// batches of eight (across its words), so that eight row loads are in flight at a time.
+__device__ __forceinline__ int gather_square_rows(const u64* __restrict__ cur, u64* __restrict__ nxt, i64 n, i64 nw,
+                                                  i64 row0, int lane) {
+  int ch = 0;
+  for (int r = 0; r < kRPW; ++r) {
+    const i64 row = row0 + r;
+    if (row >= n) break;
+    const u64 mine = lane < nw ? cur[row * nw + lane] : 0ull;
+    u64 acc = mine;
+    u64 nzw = __ballot(mine != 0ull);  // words of the row with set bits (wave-uniform)
+    int w = 0;
+    u64 x = 0ull;
+    for (;;) {
+      i64 src[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (!x && nzw) {
+          w = __ffsll((unsigned long long)nzw) - 1;
+          nzw &= nzw - 1;
+          x = __shfl(mine, w, 64);
+        }
+        src[q] = -1;
+        if (x) {
+          src[q] = 64 * (i64)w + (__ffsll((unsigned long long)x) - 1);
+          x &= x - 1;
+        }
+      }
+      if (src[0] < 0) break;
+      u64 v = 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (src[q] >= 0 && lane < nw) v |= cur[src[q] * nw + lane];
+      acc |= v;
+    }
+    if (lane < nw) {
+      nxt[row * nw + lane] = acc;
+      ch |= acc != mine;
+    }
+  }
+  return ch;
+}
+
 __global__ void __launch_bounds__(256)
 k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int round, int rounds,
               u32* __restrict__ changed, u32* __restrict__ counters, u32* __restrict__ any_active) {
   __shared__ u64 Bs[64][kTileWords];
   __shared__ i64 item;
+  __shared__ u32 tile_bits[4];
   if (round > 0 && any_active[round - 1] == 0u) return;  // every graph has converged
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -91,11 +136,32 @@ k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int
     u64* nxt = (round & 1) ? G.buf0 : G.buf1;
     const i64 row0 = rt * kTileRows + (i64)wave * kRPW;
     const i64 w0 = ct * kTileWords;
-    u32 acc[kRPW][1][2];
+    // A tile of a still sparse R (fewer set bits than n in its 64 rows, i.e. density under 1/64) is
+    // squared by row gathers; the dense tile product costs the same whatever the density.
+    bool gather = false;
+    if (G.nw <= kTileWords) {
+      u32 pc = 0;
+      for (int r = 0; r < kRPW; ++r) {
+        const i64 row = row0 + r;
+        if (row < G.n && lane < G.nw) pc += (u32)__popcll(cur[row * G.nw + lane]);
+      }
 #pragma unroll
-    for (int r = 0; r < kRPW; ++r) acc[r][0][0] = acc[r][0][1] = 0u;
-    valu_tile_accumulate<kRPW, 1>(cur, G.nw, cur, G.nw, G.n, G.n, G.nw, row0, w0, 0, G.nw, Bs, acc);
-    const int ch = valu_tile_store<kRPW, 1>(acc, cur, G.nw, nxt, G.nw, nullptr, 0, G.n, G.nw, row0, w0);
+      for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
+      if (lane == 0) tile_bits[wave] = pc;
+      __syncthreads();
+      gather = (i64)tile_bits[0] + tile_bits[1] + tile_bits[2] + tile_bits[3] < G.n;
+      __syncthreads();
+    }
+    int ch;
+    if (gather) {
+      ch = gather_square_rows(cur, nxt, G.n, G.nw, row0, lane);
+    } else {
+      u32 acc[kRPW][1][2];
+#pragma unroll
+      for (int r = 0; r < kRPW; ++r) acc[r][0][0] = acc[r][0][1] = 0u;
+      valu_tile_accumulate<kRPW, 1>(cur, G.nw, cur, G.nw, G.n, G.n, G.nw, row0, w0, 0, G.nw, Bs, acc);
+      ch = valu_tile_store<kRPW, 1>(acc, cur, G.nw, nxt, G.nw, nullptr, 0, G.n, G.nw, row0, w0);
+    }
     if (__ballot(ch) && lane == 0) {
       atomicOr(&changed[(i64)g * rounds + round], 1u);
       atomicOr(&any_active[round], 1u);

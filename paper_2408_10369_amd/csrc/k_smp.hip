@@ -272,7 +272,24 @@ k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__
       }
       __syncthreads();
       const int c = (total - base) < 1024 ? (total - base) : 1024;
-      for (int i = 0; i < c; ++i) {
+      // eight source rows per step, so that eight independent loads per word are in flight
+      int i = 0;
+      for (; i + 8 <= c; i += 8) {
+        i64 u[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) u[q] = srcs[i + q];
+#pragma unroll
+        for (int j = 0; j < kGatherWords / 256; ++j) {
+          const i64 w = t + 256 * j;
+          if (w < nw) {
+            u64 x = 0ull;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x |= Cl[u[q] * ldc + w];
+            acc[j] |= x;
+          }
+        }
+      }
+      for (; i < c; ++i) {
         const i64 u = srcs[i];
 #pragma unroll
         for (int j = 0; j < kGatherWords / 256; ++j) {
