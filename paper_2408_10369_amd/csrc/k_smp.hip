@@ -313,6 +313,81 @@ k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__
   wave_count(added, newbits);
 }
 
+// The same gather with one wave per row, for n <= 16,384 (lane l owns words l + 64 j, j < WPL): no
+// workgroup scan, and the set bits of the row are walked in batches of eight (across its words), so
+// that eight source-row loads per word are in flight at a time.
+template <int WPL>
+__global__ void __launch_bounds__(256)
+k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__ Cl, i64 ldc, i64 n, int init,
+                u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map,
+                unsigned long long* __restrict__ newbits) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const i64 nwaves = (i64)gridDim.x * 4;
+  const i64 nw = (n + 63) >> 6;
+  const u64 last_mask = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
+  u32 added = 0;  // bits of the answers not in their starting rows
+  for (i64 row = wave; row < k; row += nwaves) {
+    const i64 orow = row_map ? (i64)row_map[row] : row;
+    u64 vr[WPL], acc[WPL], start[WPL], nz[WPL];
+#pragma unroll
+    for (int j = 0; j < WPL; ++j) {
+      const i64 w = lane + 64 * j;
+      vr[j] = w < nw ? V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull) : 0ull;
+      u64 a = 0ull;
+      if (w < nw && init == 1) a = vr[j];
+      if (w < nw && init == 2) a = out[orow * ldo + w];
+      acc[j] = a;
+      start[j] = a;
+      nz[j] = __ballot(vr[j] != 0ull);  // words of the row with set bits (wave-uniform)
+    }
+    i64 w = 0;
+    u64 x = 0ull;
+    for (;;) {
+      i64 src[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+#pragma unroll
+        for (int j = 0; j < WPL; ++j) {
+          if (!x && nz[j]) {
+            const int b = __ffsll((unsigned long long)nz[j]) - 1;
+            nz[j] &= nz[j] - 1;
+            w = 64 * j + b;
+            x = __shfl(vr[j], b, 64);
+          }
+        }
+        src[q] = -1;
+        if (x) {
+          src[q] = 64 * w + (__ffsll((unsigned long long)x) - 1);
+          x &= x - 1;
+        }
+      }
+      if (src[0] < 0) break;
+#pragma unroll
+      for (int j = 0; j < WPL; ++j) {
+        const i64 ww = lane + 64 * j;
+        if (ww < nw) {
+          u64 v = 0ull;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (src[q] >= 0) v |= Cl[src[q] * ldc + ww];
+          acc[j] |= v;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < WPL; ++j) {
+      const i64 ww = lane + 64 * j;
+      if (ww < nw) {
+        out[orow * ldo + ww] = acc[j];
+        added += (u32)__popcll(acc[j] & ~start[j]);
+      }
+    }
+    for (i64 ww = nw + lane; ww < ldo; ww += 64) out[orow * ldo + ww] = 0ull;
+  }
+  wave_count(added, newbits);
+}
+
 }  // namespace
 
 i64 smp_rows_max_n() { return (kMaxLdsWords / 3) * 64; }
@@ -322,7 +397,22 @@ i64 gather_rows_max_n() { return (i64)kGatherWords * 64; }
 hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 ldc, i64 n, int init, u64* out,
                               i64 ldo, hipStream_t s, const int32_t* row_map, unsigned long long* newbits) {
   if (k <= 0) return hipSuccess;
-  if (words_for(n) > kGatherWords) return hipErrorInvalidValue;
+  const i64 nw = words_for(n);
+  if (nw > kGatherWords) return hipErrorInvalidValue;
+  if (nw <= 256) {
+    const i64 blocks = (k + 3) / 4;
+    const unsigned grid = (unsigned)(blocks < 16384 ? blocks : 16384);
+    if (nw <= 64)
+      hipLaunchKernelGGL(k_gather_rows_w<1>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
+                         row_map, newbits);
+    else if (nw <= 128)
+      hipLaunchKernelGGL(k_gather_rows_w<2>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
+                         row_map, newbits);
+    else
+      hipLaunchKernelGGL(k_gather_rows_w<4>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
+                         row_map, newbits);
+    return hipGetLastError();
+  }
   const unsigned grid = (unsigned)(k < 65535 ? k : 65535);
   hipLaunchKernelGGL(k_gather_rows, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo, row_map,
                      newbits);
