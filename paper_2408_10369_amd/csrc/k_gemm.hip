@@ -160,8 +160,10 @@ hipError_t launch_rpw(const GemmArgs& g, hipStream_t s, i64 target_blocks) {
 // rows of A (threads 0..255) and 256 rows of B^T (threads 256..511) in LDS as
 // ready operands: for every row, word and lane half the 4 masked dwords above,
 // so a consuming lane reads its operand with one 16-byte LDS load and spends no
-// ALU on it.  LDS stages are double-buffered and the global loads run two
-// chunks ahead, so one barrier per chunk suffices.  Word slots are XOR-swizzled
+// ALU on it.  LDS stages are double-buffered and software-pipelined: after the
+// barrier that opens chunk c the threads stage chunk c + 1 into the other buffer
+// (its global loads were issued two chunks earlier) while the waves consume
+// chunk c, so one barrier per chunk suffices.  Word slots are XOR-swizzled
 // by bits 2-3 of the row so that the 16 rows a quarter-wave reads fall on
 // distinct LDS banks.  While staging, the A waves also record which words of
 // the chunk are nonzero in any of their rows; a consuming wave skips the words
@@ -233,18 +235,18 @@ k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 
   const bool vr = rr < (isa ? M : N);
   const u64* pr = isa ? A + (vr ? rr : 0) * lda : BT + (vr ? rr : 0) * ldbt;
   const int ssw = (tt >> 2) & 3;  // word-slot swizzle of the staged row
-  // global loads run two chunks ahead of the LDS stage that consumes them: chunk c is staged from one
-  // register set while chunk c + 1 is in flight into the other
+  // Software pipeline over chunks of kMChunk words: after the barrier that opens chunk c, every thread
+  // stages chunk c + 1 (already in registers) into the other LDS buffer and issues the global loads of
+  // chunk c + 3, then the waves consume chunk c.  Two register sets alternate, so a load has two chunk
+  // times to arrive before it is staged.
+  const i64 nchunks = (kwords + kMChunk - 1) / kMChunk;
   u64 s0[kMChunk], s1[kMChunk];
+  auto load = [&](u64 (&sr)[kMChunk], i64 chunk) {
+    const i64 kb = chunk * kMChunk;
 #pragma unroll
-  for (int q = 0; q < kMChunk; ++q) {
-    s0[q] = (vr && q < kwords) ? pr[q] : 0ull;
-    s1[q] = (vr && kMChunk + q < kwords) ? pr[kMChunk + q] : 0ull;
-  }
-  u32 done_words = 0;  // words of k this wave ran the matrix cores on
-  const int csw = (l32 >> 2) & 3;  // word-slot swizzle of every row this lane reads
-
-  auto chunk = [&](u64 (&sr)[kMChunk], i64 kc, int buf) {
+    for (int q = 0; q < kMChunk; ++q) sr[q] = (vr && kb + q < kwords) ? pr[kb + q] : 0ull;
+  };
+  auto stage = [&](const u64 (&sr)[kMChunk], int buf) {
     uint4 (*X)[kMT][kMChunk] = isa ? Ax[buf] : Bx[buf];
 #pragma unroll
     for (int q = 0; q < kMChunk; ++q) {
@@ -259,23 +261,14 @@ k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 
       for (int q = 0; q < kMChunk; ++q) zm |= (__ballot(sr[q] != 0ull) != 0ull ? 1u : 0u) << q;
       if (lane == 0) zmask[buf][wave] = zm;
     }
-    __syncthreads();
-    const i64 kn = kc + 2 * kMChunk;
-    if (kn < kwords) {
-#pragma unroll
-      for (int q = 0; q < kMChunk; ++q) sr[q] = (vr && kn + q < kwords) ? pr[kn + q] : 0ull;
-    }
+  };
+  u32 done_words = 0;  // words of k this wave ran the matrix cores on
+  const int csw = (l32 >> 2) & 3;  // word-slot swizzle of every row this lane reads
+  auto compute = [&](int buf, uint4 (&av)[4], uint4 (&bv)[2], u32 mask) {
     const uint4* as = &Ax[buf][h][wr * 128 + l32][0];
     const uint4* bs = &Bx[buf][h][wc * 64 + l32][0];
-    // rows of this wave with a nonzero word q of k (wave-uniform)
-    const u32 mask = __builtin_amdgcn_readfirstlane(zmask[buf][2 * wr] | zmask[buf][2 * wr + 1]);
     done_words += __builtin_popcount(mask);
     // operands of word q + 1 are read while word q is consumed
-    uint4 av[4], bv[2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) av[i] = as[i * 32 * kMChunk + (0 ^ csw)];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) bv[j] = bs[j * 32 * kMChunk + (0 ^ csw)];
 #pragma unroll
     for (int q = 0; q < kMChunk; ++q) {
       uint4 an[4], bn[2];
@@ -304,9 +297,32 @@ k_gemm_mfma(const u64* __restrict__ A, i64 lda, const u64* __restrict__ BT, i64 
       }
     }
   };
-  for (i64 kc = 0; kc < kwords; kc += 2 * kMChunk) {
-    chunk(s0, kc, 0);
-    if (kc + kMChunk < kwords) chunk(s1, kc + kMChunk, 1);
+  // sn holds chunk c + 1 on entry; on exit it holds (the loads of) chunk c + 3
+  auto step = [&](u64 (&sn)[kMChunk], i64 c) {
+    __syncthreads();
+    const int buf = (int)(c & 1);
+    // the first word's operands and the skip mask of chunk c are read before the staging of chunk c + 1,
+    // so that their LDS latency overlaps it
+    uint4 av[4], bv[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) av[i] = Ax[buf][h][wr * 128 + l32 + 32 * i][0 ^ csw];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bv[j] = Bx[buf][h][wc * 64 + l32 + 32 * j][0 ^ csw];
+    // rows of this wave with a nonzero word q of k (wave-uniform)
+    const u32 mask = __builtin_amdgcn_readfirstlane(zmask[buf][2 * wr] | zmask[buf][2 * wr + 1]);
+    if (c + 1 < nchunks) {
+      stage(sn, buf ^ 1);
+      if (c + 3 < nchunks) load(sn, c + 3);
+    }
+    compute(buf, av, bv, mask);
+  };
+  load(s0, 0);
+  load(s1, 1);
+  stage(s0, 0);
+  if (2 < nchunks) load(s0, 2);
+  for (i64 c = 0; c < nchunks; c += 2) {
+    step(s1, c);
+    if (c + 1 < nchunks) step(s0, c + 1);
   }
 
   // epilogue: a 32 x 32 fp32 block sits in lane l as column l % 32, register r holding row
