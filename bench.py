@@ -38,22 +38,25 @@ KERNELS = {0: ("k_gemm_valu", "bit-packed Boolean product on the VALU", "alu", V
 
 # HBM bytes per launch of the product kernels on this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the same counters on a plain 256 MiB copy; the summaries are under profiles/.  A figure
-# is valid only for the kernel source it was measured on (sha256 of the file).
-GEMM_TRAFFIC = {"k_gemm_mfma": {"source": "paper_2408_10369_amd/csrc/k_gemm.hip",
-                                "sha256": "1acbc315c9f4a6b206ce0e5f1d452c1de1c1441bfb9ec54ee91cff6fe0274395",
-                                "bytes_per_launch": 498.2e6}}
+# is valid only for the kernel source it was measured on (sha256 of its files, in order).
+GEMM_TRAFFIC = {"k_gemm_mfma": {"sources": ["paper_2408_10369_amd/csrc/k_gemm.hip",
+                                            "paper_2408_10369_amd/csrc/mfma_tile.h"],
+                                "sha256": None,
+                                "bytes_per_launch": None}}
 
 
 def measured_traffic(kernel):
     import hashlib
     rec = GEMM_TRAFFIC.get(kernel)
-    if rec is None:
+    if rec is None or rec["sha256"] is None:
         return None
+    h = hashlib.sha256()
     try:
-        digest = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
     except OSError:
         return None
-    return rec["bytes_per_launch"] if digest == rec["sha256"] else None
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["sha256"] else None
 
 
 def main():

@@ -1092,7 +1092,7 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return graphs[a].n > graphs[b].n; });
-    BatchPlan plan{0, 0, 0, 0, 0, false};
+    BatchPlan plan{0, 0, 0, 0, 0, false, 0, 0, 0};
     // Query answers: the plain schedule takes the paper's mapping of a partially grounded query to
     // BMLP-SMP (a selection per query row); otherwise the rows are read off the closures the batch
     // computes anyway (reuse of intermediate results).  Graphs beyond the selection kernel's size
@@ -1100,13 +1100,18 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
     const bool forced_sel = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
     plan.select_by_bfs = forced_sel ? o.smp_arm != BMLP_ARM_SMP_CLOSURE : o.dispatch == BMLP_DISPATCH_PLAIN;
     size_t buf_words = 0;
+    BatchPlan sizes{0, 0, 0, 0, 0, false, 0, 0, 0};  // the totals the flag area depends on
     for (int i = 0; i < count; ++i) {
       const bmlp_graph_desc& d = graphs[i];
       plan.rounds = std::max(plan.rounds, ceil_log2(std::max<int64_t>(d.n, 2)) + 2);
-      buf_words += (size_t)(2 * d.n * words_for(d.n));
+      // ping-pong pair, plus R^T for the graphs that square on the matrix cores
+      const bool mfma = d.n >= batch_mfma_min_n();
+      buf_words += (size_t)((mfma ? 3 : 2) * d.n * words_for(d.n));
+      if (mfma) sizes.total_mblocks += (d.n + 255) / 256;
     }
+    sizes.rounds = plan.rounds;
     const size_t table_bytes = ((size_t)count * sizeof(BatchGraph) + 255) & ~(size_t)255;
-    const size_t nflags = (size_t)count * plan.rounds + 2 * (size_t)plan.rounds + 2;
+    const size_t nflags = (size_t)batch_flag_words(count, sizes);
     const size_t flag_bytes = (nflags * sizeof(u32) + 255) & ~(size_t)255;
     char* base = (char*)ws(h, S_BATCH, table_bytes + flag_bytes + buf_words * sizeof(u64), o);
     BatchGraph* d_table = (BatchGraph*)base;
@@ -1136,11 +1141,24 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       G.rtiles = batch_rtiles(d.n);
       G.smp_tile_begin = plan.total_select_tiles;
       G.qrow_begin = plan.total_qrows;
+      G.mfma_tile_begin = plan.total_mfma_tiles;
+      G.tblock_begin = plan.total_tblocks;
+      G.mblock_begin = plan.total_mblocks;
+      const bool mfma = d.n >= batch_mfma_min_n();
+      G.bt = mfma ? bufs + off : nullptr;
+      G.mfma_rtiles = mfma ? (d.n + 255) / 256 : 0;
+      if (mfma) {
+        off += (size_t)(d.n * G.nw);
+        plan.total_mfma_tiles += G.mfma_rtiles * G.mfma_rtiles;
+        plan.total_tblocks += G.nw * G.nw;
+        plan.total_mblocks += G.mfma_rtiles;
+      }
       plan.total_rows += std::max<int64_t>(d.n, d.k);
-      plan.total_tiles += batch_tiles(d.n);
+      plan.total_tiles += mfma ? 4 * G.mfma_rtiles : batch_tiles(d.n);  // 64-row tiles of an MFMA graph
       plan.total_select_tiles += d.k > 0 ? batch_select_tiles(d.k, d.n) : 0;
       plan.total_qrows += d.k;
     }
+    need((size_t)batch_flag_words(count, plan) == nflags, BMLP_EDEVICE, "batched plan: flag area mismatch");
     // the captured chain is reused while the batch (and its workspace) is unchanged
     uint64_t key = 1469598103934665603ull;
     auto mix = [&](const void* p, size_t nb) {

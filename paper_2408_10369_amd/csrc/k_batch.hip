@@ -18,6 +18,7 @@
 // boundaries make each round's writes visible to the next round on every XCD.
 #include "bmlp_batch.h"
 #include "valu_tile.h"
+#include "mfma_tile.h"
 
 namespace bmlp {
 
@@ -27,14 +28,26 @@ constexpr int kRPW = 16;                 // rows per wave -> 64-row tiles
 constexpr int kTileRows = 4 * kRPW;
 constexpr int kTileWords = 64;           // one lane per word
 
-__device__ __forceinline__ int find_graph(const BatchGraph* __restrict__ gs, int count, i64 t, bool smp) {
+// the last graph whose first item of the given kind (0 VALU tile, 1 selection tile, 2 matrix-core tile,
+// 3 transpose block, 4 256-row block) is at or before item t: the graph that owns t (graphs without items of that kind
+// share the next graph's start and are never the last one)
+__device__ __forceinline__ int find_item(const BatchGraph* __restrict__ gs, int count, i64 t, int kind) {
   int lo = 0, hi = count - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const i64 b = smp ? gs[mid].smp_tile_begin : gs[mid].tile_begin;
+    const BatchGraph& G = gs[mid];
+    const i64 b = kind == 0   ? G.tile_begin
+                  : kind == 1 ? G.smp_tile_begin
+                  : kind == 2 ? G.mfma_tile_begin
+                  : kind == 3 ? G.tblock_begin
+                              : G.mblock_begin;
     if (b <= t) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+__device__ __forceinline__ int find_graph(const BatchGraph* __restrict__ gs, int count, i64 t, bool smp) {
+  return find_item(gs, count, t, smp ? 1 : 0);
 }
 
 // round at which graph g stopped changing (its last product), or -1 if it
@@ -112,9 +125,49 @@ __device__ __forceinline__ int gather_square_rows(const u64* __restrict__ cur, u
   return ch;
 }
 
+// Sparse or dense, per 256-row block of the graphs that square on the matrix cores, for this round: a
+// block with fewer than n set bits (density under 1/256) is squared by row gathers, a denser one on the
+// matrix cores (whose graph then needs R^T).  The gathers of a wave walk a row's bits in batches of
+// eight loads, so they are latency-bound and pay only well below the density where a VALU tile would
+// break even (measured on the 512-graph batch: thresholds n / 4, n and 4 n gave 17.9, 16.6 and
+// 21.2 ms).  One workgroup per block.
+__global__ void __launch_bounds__(256)
+k_batch_decide(const BatchGraph* __restrict__ gs, int count, i64 total_blocks, int round, int rounds,
+               const u32* __restrict__ changed, const u32* __restrict__ any_active, u32* __restrict__ bdense,
+               u32* __restrict__ gdense) {
+  __shared__ u32 bits_w[4];
+  if (round > 0 && any_active[round - 1] == 0u) return;  // every graph has converged
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (i64 b = blockIdx.x; b < total_blocks; b += gridDim.x) {
+    const int g = find_item(gs, count, b, 4);
+    if (round > 0 && !changed[(i64)g * rounds + round - 1]) continue;
+    const BatchGraph& G = gs[g];
+    const i64 blk = b - G.mblock_begin;
+    const u64* cur = (round & 1) ? G.buf1 : G.buf0;
+    u32 pc = 0;
+    for (i64 e = threadIdx.x; e < 256 * G.nw; e += 256) {
+      const i64 row = blk * 256 + e / G.nw;
+      if (row < G.n) pc += (u32)__popcll(cur[row * G.nw + e % G.nw]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
+    if (lane == 0) bits_w[wave] = pc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const i64 bits = (i64)bits_w[0] + bits_w[1] + bits_w[2] + bits_w[3];
+      const u32 dense = (bits >= G.n || G.nw > 64) ? 1u : 0u;
+      bdense[b] = dense;
+      if (dense) atomicOr(&gdense[(i64)g * rounds + round], 1u);
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int round, int rounds,
-              u32* __restrict__ changed, u32* __restrict__ counters, u32* __restrict__ any_active) {
+              u32* __restrict__ changed, u32* __restrict__ counters, u32* __restrict__ any_active,
+              const u32* __restrict__ bdense) {
   __shared__ u64 Bs[64][kTileWords];
   __shared__ i64 item;
   __shared__ u32 tile_bits[4];
@@ -131,9 +184,20 @@ k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int
     if (round > 0 && !changed[(i64)g * rounds + round - 1]) continue;
     const BatchGraph& G = gs[g];
     const i64 local = t - G.tile_begin;
-    const i64 rt = local % G.rtiles, ct = local / G.rtiles;
     const u64* cur = (round & 1) ? G.buf1 : G.buf0;
     u64* nxt = (round & 1) ? G.buf0 : G.buf1;
+    if (G.mfma_rtiles) {
+      // 64-row tile `local` of a graph that squares on the matrix cores: squared here by row gathers while
+      // its 256-row block is sparse, by k_batch_round_mfma once it is dense
+      if (bdense[G.mblock_begin + (local >> 2)]) continue;
+      const int ch = gather_square_rows(cur, nxt, G.n, G.nw, local * kTileRows + (i64)wave * kRPW, lane);
+      if (__ballot(ch) && lane == 0) {
+        atomicOr(&changed[(i64)g * rounds + round], 1u);
+        atomicOr(&any_active[round], 1u);
+      }
+      continue;
+    }
+    const i64 rt = local % G.rtiles, ct = local / G.rtiles;
     const i64 row0 = rt * kTileRows + (i64)wave * kRPW;
     const i64 w0 = ct * kTileWords;
     // A tile of a still sparse R (fewer set bits than n in its 64 rows, i.e. density under 1/64) is
@@ -167,6 +231,59 @@ k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int
       atomicOr(&any_active[round], 1u);
     }
   }
+}
+
+// R^T of the current round for the graphs that square on the matrix cores (the product consumes B^T):
+// one wave per 64 x 64 bit block, 64 ballots.
+__global__ void __launch_bounds__(256)
+k_batch_transpose(const BatchGraph* __restrict__ gs, int count, i64 total_blocks, int round, int rounds,
+                  const u32* __restrict__ changed, const u32* __restrict__ any_active,
+                  const u32* __restrict__ gdense) {
+  if (round > 0 && any_active[round - 1] == 0u) return;  // every graph has converged
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 bi = wave; bi < total_blocks; bi += nwaves) {
+    const int g = find_item(gs, count, bi, 3);
+    if (round > 0 && !changed[(i64)g * rounds + round - 1]) continue;
+    if (!gdense[(i64)g * rounds + round]) continue;  // every block of the graph is squared by gathers
+    const BatchGraph& G = gs[g];
+    const i64 local = bi - G.tblock_begin;
+    const i64 rb = local / G.nw, cw = local - rb * G.nw;  // rows 64 rb .., word cw of R
+    const u64* cur = (round & 1) ? G.buf1 : G.buf0;
+    const i64 r = rb * 64 + lane;
+    const u64 x = r < G.n ? cur[r * G.nw + cw] : 0ull;
+    u64 mine = 0;
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) {
+      const u64 b = __ballot((x >> j) & 1ull);
+      if (lane == j) mine = b;
+    }
+    const i64 orow = cw * 64 + lane;  // row of R^T = column of R
+    if (orow < G.n) G.bt[orow * G.nw + rb] = mine;
+  }
+}
+
+// One round for the graphs that square on the matrix cores: one 8-wave workgroup per (graph, 256 x 256
+// tile), a matrix-core product of R by R^T; the tiles of a block k_batch_decide found sparse are left
+// to the row gathers of k_batch_round.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_batch_round_mfma(const BatchGraph* __restrict__ gs, int count, int round, int rounds, u32* __restrict__ changed,
+                   u32* __restrict__ any_active, const u32* __restrict__ bdense) {
+  __shared__ MfmaLds L;
+  if (round > 0 && any_active[round - 1] == 0u) return;  // every graph has converged
+  const i64 t = blockIdx.x;  // one workgroup per tile; tiles are numbered biggest graphs first
+  const int g = find_item(gs, count, t, 2);
+  if (round > 0 && !changed[(i64)g * rounds + round - 1]) return;
+  const BatchGraph& G = gs[g];
+  const i64 local = t - G.mfma_tile_begin;
+  const i64 tr = local / G.mfma_rtiles, tc = local - tr * G.mfma_rtiles;
+  const u64* cur = (round & 1) ? G.buf1 : G.buf0;
+  u64* nxt = (round & 1) ? G.buf0 : G.buf1;
+  if (!bdense[G.mblock_begin + tr]) return;  // a still sparse block: squared by k_batch_round
+  const MfmaTile mt{cur, G.nw, G.bt, G.nw, cur, G.nw, nxt, G.nw, nullptr, 0, G.n, G.n, G.n,
+                    &changed[(i64)g * rounds + round], nullptr, nullptr, &any_active[round]};
+  mfma_tile(L, mt, tr, tc);
 }
 
 __global__ void __launch_bounds__(256)
@@ -314,27 +431,56 @@ i64 batch_rtiles(i64 n) { return (n + kTileRows - 1) / kTileRows; }
 
 i64 batch_bfs_max_n() { return (i64)kBfsWords * 64; }
 
+i64 batch_mfma_min_n() { return 1024; }
+
+i64 batch_flag_words(int count, const BatchPlan& p) {
+  return 2 * (i64)count * p.rounds + 2 * (i64)p.rounds + 2 + p.total_mblocks;
+}
+
 i64 batch_select_tiles(i64 k, i64 n) {
   const i64 nw = words_for(n);
   return ((k + kTileRows - 1) / kTileRows) * ((nw + kTileWords - 1) / kTileWords);
 }
 
 hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& p, u32* flags, hipStream_t s) {
-  // flags layout: changed[count * rounds] | any_active[rounds] | counters[rounds + 1]
+  // flags layout: changed[count * rounds] | any_active[rounds] | counters[rounds + 2] |
+  //               gdense[count * rounds] | bdense[total_mblocks]
   u32* changed = flags;
   u32* any_active = flags + (i64)count * p.rounds;
   u32* counters = any_active + p.rounds;
-  const i64 nflags = (i64)count * p.rounds + 2 * (i64)p.rounds + 2;
+  u32* gdense = counters + p.rounds + 2;
+  u32* bdense = gdense + (i64)count * p.rounds;
+  const i64 nflags = batch_flag_words(count, p);
   hipLaunchKernelGGL(k_batch_setup, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
                      count, p.total_rows, flags, nflags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int pgrid = grid_cap(p.total_tiles, 1024);
   for (int r = 0; r < p.rounds; ++r) {
-    hipLaunchKernelGGL(k_batch_round, dim3(pgrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count, p.total_tiles,
-                       r, p.rounds, changed, counters, any_active);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (p.total_mblocks > 0) {
+      hipLaunchKernelGGL(k_batch_decide, dim3(grid_cap(p.total_mblocks, 4096)), dim3(256), 0, s,
+                         (const BatchGraph*)d_graphs, count, p.total_mblocks, r, p.rounds, (const u32*)changed,
+                         (const u32*)any_active, bdense, gdense);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (p.total_tiles > 0) {
+      hipLaunchKernelGGL(k_batch_round, dim3(pgrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count,
+                         p.total_tiles, r, p.rounds, changed, counters, any_active, (const u32*)bdense);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (p.total_mfma_tiles > 0) {
+      hipLaunchKernelGGL(k_batch_transpose, dim3(grid_cap((p.total_tblocks * 64 + 255) / 256, 8192)), dim3(256), 0, s,
+                         (const BatchGraph*)d_graphs, count, p.total_tblocks, r, p.rounds, (const u32*)changed,
+                         (const u32*)any_active, (const u32*)gdense);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_batch_round_mfma, dim3((unsigned)p.total_mfma_tiles), dim3(512), 0, s,
+                         (const BatchGraph*)d_graphs, count, r, p.rounds, changed, any_active, (const u32*)bdense);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   if (p.select_by_bfs && p.total_qrows > 0) {
     hipLaunchKernelGGL(k_batch_select_bfs, dim3(grid_cap((p.total_qrows + 3) / 4, 2048)), dim3(256), 0, s,

@@ -77,6 +77,29 @@ def test_batched_mixed_sizes(ctx, mode):
     assert st["iterations"] >= 1 and st["bool_ops"] > 0
 
 
+@pytest.mark.parametrize("mode", ["plain", "learned"])
+def test_batched_matrix_core_graphs(ctx, mode):
+    # graphs at and above the matrix-core size: dense from the first round, ragged (n not a multiple
+    # of 256 or 64), and one whose first 256-row block is empty while the others are dense, so row
+    # blocks of one graph take different kernels in the same round; small graphs beside them
+    rng = np.random.default_rng(21)
+    specs = []
+    for n, p in ((1024, 0.03), (1300, 0.02), (2049, 1.5 / 2049), (1500, 0.0)):
+        A = (rng.random((n, n)) < p).astype(np.uint8)
+        if p == 0.0:
+            A = (rng.random((n, n)) < 0.01).astype(np.uint8)
+            A[:256, :] = 0
+            A[300, 5] = 1  # a path into the empty block's columns
+        s, d = np.nonzero(A)
+        specs.append((n, s, d, rng.choice(n, 40, replace=False)))
+    for n in (70, 500, 1023):
+        ss, dd = gen.er_digraph(n, 3.0 / n, int(rng.integers(1 << 30)))
+        specs.append((n, ss, dd, rng.choice(n, 10, replace=False)))
+    graphs, refs = make_batch(ctx, specs)
+    ctx.batched(graphs, opts=mode_opts(mode))
+    check(graphs, refs)
+
+
 def test_batched_reuses_and_rereads_inputs(ctx):
     rng = np.random.default_rng(12)
     specs = []
