@@ -93,28 +93,33 @@ __device__ __forceinline__ int gather_square_rows(const u64* __restrict__ cur, u
     const u64 mine = lane < nw ? cur[row * nw + lane] : 0ull;
     u64 acc = mine;
     u64 nzw = __ballot(mine != 0ull);  // words of the row with set bits (wave-uniform)
+    // the walk over the row's set bits is wave-uniform and kept in scalar registers
     int w = 0;
     u64 x = 0ull;
+    const int lc = lane < nw ? lane : (int)nw - 1;
     for (;;) {
-      i64 src[8];
+      int src[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         if (!x && nzw) {
           w = __ffsll((unsigned long long)nzw) - 1;
           nzw &= nzw - 1;
-          x = __shfl(mine, w, 64);
+          x = uniform64(__shfl(mine, w, 64));
         }
         src[q] = -1;
         if (x) {
-          src[q] = 64 * (i64)w + (__ffsll((unsigned long long)x) - 1);
+          src[q] = 64 * w + (__ffsll((unsigned long long)x) - 1);
           x &= x - 1;
         }
       }
       if (src[0] < 0) break;
+      // unguarded loads, all eight in flight: a missing source repeats src[0] and is masked out
+      u64 t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = cur[(i64)(src[q] >= 0 ? src[q] : src[0]) * nw + lc];
       u64 v = 0ull;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (src[q] >= 0 && lane < nw) v |= cur[src[q] * nw + lane];
+      for (int q = 0; q < 8; ++q) v |= src[q] >= 0 ? t[q] : 0ull;
       acc |= v;
     }
     if (lane < nw) {
@@ -205,10 +210,13 @@ k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int
     bool gather = false;
     if (G.nw <= kTileWords) {
       u32 pc = 0;
-      for (int r = 0; r < kRPW; ++r) {
-        const i64 row = row0 + r;
-        if (row < G.n && lane < G.nw) pc += (u32)__popcll(cur[row * G.nw + lane]);
-      }
+      const i64 lc = lane < G.nw ? lane : G.nw - 1;
+      u64 t[kRPW];
+#pragma unroll
+      for (int r = 0; r < kRPW; ++r) t[r] = cur[(row0 + r < G.n ? row0 + r : G.n - 1) * G.nw + lc];
+#pragma unroll
+      for (int r = 0; r < kRPW; ++r)
+        if (row0 + r < G.n && lane < G.nw) pc += (u32)__popcll(t[r]);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
       if (lane == 0) tile_bits[wave] = pc;

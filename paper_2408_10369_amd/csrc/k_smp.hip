@@ -341,10 +341,12 @@ k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict
       start[j] = a;
       nz[j] = __ballot(vr[j] != 0ull);  // words of the row with set bits (wave-uniform)
     }
-    i64 w = 0;
+    // The walk over the row's set bits is wave-uniform: its state (word, remaining bits, sources)
+    // lives in scalar registers, so the sources address their rows from scalar bases.
+    int w = 0;
     u64 x = 0ull;
     for (;;) {
-      i64 src[8];
+      int src[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
 #pragma unroll
@@ -353,7 +355,7 @@ k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict
             const int b = __ffsll((unsigned long long)nz[j]) - 1;
             nz[j] &= nz[j] - 1;
             w = 64 * j + b;
-            x = __shfl(vr[j], b, 64);
+            x = uniform64(__shfl(vr[j], b, 64));
           }
         }
         src[q] = -1;
@@ -363,16 +365,30 @@ k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict
         }
       }
       if (src[0] < 0) break;
+      // Every load is issued unguarded so that all 8 x WPL of them are in flight together: a
+      // missing source repeats src[0] and is masked out, and a lane past the row's last word
+      // re-reads that word and drops it.
+      const u64* rowp[8];
+      u64 keep[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        keep[q] = src[q] >= 0 ? ~0ull : 0ull;
+        rowp[q] = Cl + (i64)(src[q] >= 0 ? src[q] : src[0]) * ldc;
+      }
+      u64 t[WPL][8];
 #pragma unroll
       for (int j = 0; j < WPL; ++j) {
-        const i64 ww = lane + 64 * j;
-        if (ww < nw) {
-          u64 v = 0ull;
+        const int ww = lane + 64 * j;
+        const int wc = ww < nw ? ww : (int)nw - 1;
 #pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (src[q] >= 0) v |= Cl[src[q] * ldc + ww];
-          acc[j] |= v;
-        }
+        for (int q = 0; q < 8; ++q) t[j][q] = rowp[q][wc];
+      }
+#pragma unroll
+      for (int j = 0; j < WPL; ++j) {
+        u64 v = 0ull;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v |= t[j][q] & keep[q];
+        if (lane + 64 * j < nw) acc[j] |= v;
       }
     }
 #pragma unroll

@@ -15,6 +15,13 @@
 
 namespace bmlp {
 
+// a wave-uniform 64-bit value moved to scalar registers (each half zero-extended)
+__device__ __forceinline__ u64 uniform64(u64 v) {
+  const u32 lo = (u32)__builtin_amdgcn_readfirstlane((int)(u32)v);
+  const u32 hi = (u32)__builtin_amdgcn_readfirstlane((int)(u32)(v >> 32));
+  return ((u64)hi << 32) | (u64)lo;
+}
+
 // all-ones when bit `b` of the wave-uniform word x is set, else zero
 __device__ __forceinline__ u32 bit_mask(u32 x, int b) { return (u32)(((int)(x << (31 - b))) >> 31); }
 
@@ -45,10 +52,26 @@ __device__ __forceinline__ void valu_tile_accumulate(const u64* __restrict__ A, 
       any |= alo[r] | ahi[r];
     }
     if (!__syncthreads_or(any != 0)) continue;
-    for (int idx = threadIdx.x; idx < 64 * TW; idx += 256) {
-      const int t = idx / TW, c = idx - (idx / TW) * TW;
-      const i64 k = kw * 64 + t, w = w0 + c;
-      Bs[t][c] = (k < K && w < nw) ? B[k * ldb + w] : 0ull;
+    // stage the 64 x TW chunk of B: every thread's loads are issued before any is waited for.
+    // They are clamped into the matrix, so they need no guard (words outside it are stored as
+    // zero), and addressed by 32-bit offsets from the chunk's first row.
+    constexpr int kPer = 64 * TW / 256;
+    const u64* Bk = B + kw * 64 * ldb;
+    const int klast = (int)(K - 1 - kw * 64 < 63 ? K - 1 - kw * 64 : 63);  // last row of the chunk in B
+    const int clast = (int)(nw - 1 - w0 < TW - 1 ? nw - 1 - w0 : TW - 1);   // last column of the tile in B
+    u64 st[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int idx = threadIdx.x + 256 * i;
+      const int r = idx / TW, c = idx % TW;
+      const u32 off = (u32)(r < klast ? r : klast) * (u32)ldb + (u32)w0 + (u32)(c < clast ? c : clast);
+      st[i] = Bk[off];
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int idx = threadIdx.x + 256 * i;
+      const int r = idx / TW, c = idx % TW;
+      Bs[r][c] = (r <= klast && c <= clast) ? st[i] : 0ull;
     }
     __syncthreads();
     if (any) {
@@ -84,6 +107,18 @@ __device__ __forceinline__ int valu_tile_store(const u32 (&acc)[RPW][WPL][2], co
   const int lane = threadIdx.x & 63;
   int ch = 0;
   u32 cnt = 0;
+  // C_old is read first, all RPW x WPL words at once (clamped to the matrix, unguarded, so that the
+  // loads overlap instead of each being waited for behind its bounds check)
+  u64 old[RPW][WPL];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const i64 rc = row0 + r < M ? row0 + r : M - 1;
+#pragma unroll
+    for (int wl = 0; wl < WPL; ++wl) {
+      const i64 w = w0 + lane + 64 * wl;
+      old[r][wl] = Cold ? Cold[rc * ldco + (w < nw ? w : nw - 1)] : 0ull;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     const i64 row = row0 + r;
@@ -92,12 +127,11 @@ __device__ __forceinline__ int valu_tile_store(const u32 (&acc)[RPW][WPL][2], co
     for (int wl = 0; wl < WPL; ++wl) {
       const i64 w = w0 + lane + 64 * wl;
       if (w < nw) {
-        const u64 old = Cold ? Cold[row * ldco + w] : 0ull;
-        const u64 v = (((u64)acc[r][wl][1] << 32) | (u64)acc[r][wl][0]) | old;
+        const u64 v = (((u64)acc[r][wl][1] << 32) | (u64)acc[r][wl][0]) | old[r][wl];
         C[row * ldc + w] = v;
-        if (D) D[row * ldd + w] = v & ~old;
-        ch |= (v != old);
-        cnt += (u32)__popcll(v & ~old);
+        if (D) D[row * ldd + w] = v & ~old[r][wl];
+        ch |= (v != old[r][wl]);
+        cnt += (u32)__popcll(v & ~old[r][wl]);
       }
     }
   }
