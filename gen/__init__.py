@@ -240,3 +240,70 @@ def query_stream(n: int = 65536, count: int = 10000, kmax: int = 4096,
         k = min(max(k, 1), kmax)
         out.append(rng.choice(n, size=k, replace=False).astype(np.int32))
     return out
+
+
+# --- the composition benchmark of Section 3.4 at knowledge-graph scale --------
+@dataclass
+class Geo:
+    n: int
+    contains_src: np.ndarray
+    contains_dst: np.ndarray
+    adjoins_src: np.ndarray
+    adjoins_dst: np.ndarray
+    location: np.ndarray      # indices of the constants that are locations
+
+
+def geo(n: int = 14541, levels=(20, 200, 1000, 2780), seed: int = 6,
+        extra_parent: float = 0.05, adjoin_p: float = 0.73) -> Geo:
+    """Synthetic geography shaped like the FB15K-237 location facts.
+
+    Locations are a random subset of the n constants arranged in levels
+    (countries, regions, counties, cities).  contains(parent, child): each
+    location below the top level has a parent one level up, and with
+    probability ``extra_parent`` a second one (a place inside two regions).
+    adjoins(x, y): each location makes two tries, each succeeding with
+    probability ``adjoin_p``, at adjoining another location of the same parent
+    (a sibling).  The defaults give 4,172 contains and 3,811 adjoins facts,
+    7,983 in all (the paper's table lists 7,991 over 14,541 constants).
+    ``location`` lists the constants of the hierarchy; the paper's reading
+    makes every constant a location, which callers get by passing all n.
+    """
+    rng = np.random.default_rng(seed)
+    total = int(sum(levels))
+    loc = rng.permutation(n)[:total].astype(np.int32)
+    lv = []
+    off = 0
+    for c in levels:
+        lv.append(loc[off:off + c])
+        off += c
+    cs, cd, parent = [], [], {}
+    for li in range(1, len(lv)):
+        up = lv[li - 1]
+        for x in lv[li]:
+            p = int(up[rng.integers(len(up))])
+            parent[int(x)] = p
+            cs.append(p)
+            cd.append(int(x))
+            if rng.random() < extra_parent:
+                q = int(up[rng.integers(len(up))])
+                if q != p:
+                    cs.append(q)
+                    cd.append(int(x))
+    sib = {}
+    for x, p in parent.items():
+        sib.setdefault(p, []).append(x)
+    sib[-1] = [int(x) for x in lv[0]]
+    as_, ad = [], []
+    for group in sib.values():
+        if len(group) < 2:
+            continue
+        for x in group:
+            for _ in range(2):
+                if rng.random() < adjoin_p:
+                    y = group[rng.integers(len(group))]
+                    if y != x:
+                        as_.append(x)
+                        ad.append(y)
+    cs, cd = _dedupe_sorted(np.asarray(cs, np.int32), np.asarray(cd, np.int32), n)
+    as_, ad = _dedupe_sorted(np.asarray(as_, np.int32), np.asarray(ad, np.int32), n)
+    return Geo(n, cs, cd, as_, ad, np.sort(loc))

@@ -144,3 +144,41 @@ def warshall(bits, n):
 
 
 from . import boolops, algorithms, datalog, mlp  # noqa: E402,F401
+
+
+def is_foreign_rows(n, contains, adjoins, location=None, threads=0):
+    """P3 u P4 u P5 of Section 3.4 on bit rows; returns (hasPlace, indirectlyPartOf, isForeign).
+
+    hasPlace is the closure of contains (its rows by breadth-first search);
+    indirectlyPartOf is the least model of the linear recursion whose base is
+    adjoins together with its inverse and whose step is the inverse of
+    hasPlace (Theorem 1, P = Rs* Rb); isForeign holds between two locations
+    unless indirectlyPartOf does (negation of a finished lower stratum).
+    ``location`` defaults to every constant.  Inverses are taken on the pair
+    lists, the negation and the location mask on the bit rows with numpy.
+    """
+    cs, cd = _edges(*contains)
+    as_, ad = _edges(*adjoins)
+    ld = max(words(n), 1)
+    has_place = closure_rows(n, cs, cd, ld=ld, threads=threads)
+    hp_src, hp_dst = _bits_pairs(has_place, n)
+    base_src = np.concatenate([as_, ad])
+    base_dst = np.concatenate([ad, as_])
+    ipo = compose_rows(n, base_src, base_dst, hp_dst, hp_src, ld=ld, threads=threads)
+    loc = np.zeros(n, dtype=bool)
+    if location is None:
+        loc[:] = True
+    else:
+        loc[np.asarray(location, dtype=np.int64)] = True
+    mask = np.zeros(ld * 64, dtype=np.uint8)
+    mask[:n] = loc
+    row_mask = np.packbits(mask, bitorder="little").view(np.uint64)
+    foreign = np.where(loc[:, None], ~ipo & row_mask[None, :], np.uint64(0))
+    return has_place, ipo, foreign
+
+
+def _bits_pairs(bits, n):
+    """(row, col) pairs of the set bits of uint64 bit rows (LSB first)."""
+    dense = np.unpackbits(np.ascontiguousarray(bits).view(np.uint8), axis=1, bitorder="little")[:, :n]
+    r, c = np.nonzero(dense)
+    return r.astype(np.int32), c.astype(np.int32)

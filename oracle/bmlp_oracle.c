@@ -100,8 +100,13 @@ static void reach_from(const oracle_graph *g, const int32_t *S, int64_t ns,
     for (int64_t s = 0; s < ns; ++s) bit_set(out, S[s]);
 }
 
+/* threads <= 0: the OpenMP default of the process (taken at the first call), so that an earlier call
+   that asked for a fixed count does not leave it in force */
+static int default_threads = 0;
+
 static int set_threads(int threads) {
-  if (threads > 0) omp_set_num_threads(threads);
+  if (default_threads == 0) default_threads = omp_get_max_threads();
+  omp_set_num_threads(threads > 0 ? threads : default_threads);
   int used = 1;
 #pragma omp parallel
   {

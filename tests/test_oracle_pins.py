@@ -102,6 +102,29 @@ def test_isforeign_example(golden_dir):
     assert ipo2 == {(i, j) for i in range(n) for j in range(n) if ipo[i, j]}
 
 
+@pytest.mark.parametrize("seed,all_locations", [(1, True), (2, False), (3, True)])
+def test_isforeign_bit_pipeline_matches_clauses(seed, all_locations):
+    """The oracle's bit-row pipeline for P3 u P4 u P5 (closure, composition,
+    negation, location mask) against the clause-by-clause evaluator, on a
+    small hierarchy shaped like the knowledge-graph workload."""
+    import gen
+    g = gen.geo(n=420, levels=(4, 20, 60, 150), seed=seed, extra_parent=0.15)
+    n = g.n
+    loc = None if all_locations else g.location
+    hp, ipo, fr = oracle.is_foreign_rows(n, (g.contains_src, g.contains_dst),
+                                         (g.adjoins_src, g.adjoins_dst), loc)
+    hp2, ipo2, fr2 = datalog.is_foreign(range(n), set(zip(g.contains_src.tolist(), g.contains_dst.tolist())),
+                                        set(zip(g.adjoins_src.tolist(), g.adjoins_dst.tolist())),
+                                        None if loc is None else loc.tolist())
+    as_set = lambda bits: {(int(i), int(j)) for i, j in zip(*np.nonzero(boolops.from_bits(bits, n)))}
+    assert as_set(hp) == hp2
+    assert as_set(ipo) == ipo2
+    assert as_set(fr) == fr2
+    assert len(ipo2) > len(g.adjoins_src)          # the recursion derived new facts
+    # padding bits of the negated rows stay zero
+    assert boolops.to_bits(boolops.from_bits(fr, n), ld=fr.shape[1]).tolist() == fr.tolist()
+
+
 # ---------------------------------------------------------------- closed forms
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 63, 64, 65, 130])
 def test_closed_forms(n):
@@ -321,3 +344,8 @@ def test_oracle_threads_reported():
     s, d = np.arange(99), np.arange(1, 100)
     oracle.closure_rows(100, s, d, threads=2)
     assert oracle.last_threads == 2
+    # a later call with the default does not inherit the fixed count
+    oracle.closure_rows(100, s, d, threads=1)
+    oracle.closure_rows(100, s, d)
+    expect = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    assert oracle.last_threads == expect
