@@ -111,26 +111,86 @@ __global__ void k_set_onehot(u64* __restrict__ a, i64 ld, const int32_t* __restr
   }
 }
 
-// 64x64 bit-block transpose, one wave per block: lane l holds input row
-// (64 rb + l), word cw; output row (64 cw + j) word rb is the ballot of bit j.
-__global__ void k_transpose(const u64* __restrict__ in, i64 rows, i64 cols, i64 ldi, u64* __restrict__ out, i64 ldo) {
+// Transpose of a bit matrix, 512 input rows x 16 input words (1,024 columns) per workgroup of eight
+// waves, staged through LDS so that both sides move whole lines:
+//  1. the tile is read row by row (a wave instruction covers 4 rows x 128 bytes) into LDS;
+//  2. wave w takes input words 2w and 2w+1; lane l holds rows 64 b + l of a word column (b < 8),
+//     each 64 x 64 bit block is turned by lane shuffles, and lane j then holds output row
+//     64 cw + j, words 8 rt + b, which go back to LDS (the same buffer, after a barrier);
+//  3. the 1,024 output rows x 8 words (64 contiguous bytes each) are written row by row.
+constexpr int kTpRows = 512;
+constexpr int kTpWords = 16;
+constexpr int kTpInLd = kTpWords + 1;  // padded LDS row strides (u64 words)
+constexpr int kTpOutLd = 8 + 1;
+constexpr int kTpLds = (kTpRows * kTpInLd > 64 * kTpWords * kTpOutLd) ? kTpRows * kTpInLd : 64 * kTpWords * kTpOutLd;
+
+// 64 x 64 bit block held one row per lane (bit j = column j) -> one column per lane, in six
+// butterfly stages: at stage s the lanes whose bit s is clear trade their columns with bit s set
+// for the partner lane's (lane ^ s) columns with bit s clear.
+__device__ __forceinline__ u64 transpose_block64(u64 x) {
   const int lane = threadIdx.x & 63;
-  const i64 rblocks = (rows + 63) >> 6, cwords = (cols + 63) >> 6;
-  const i64 nblocks = rblocks * cwords;
-  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
-  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
-  for (i64 bi = wave; bi < nblocks; bi += nwaves) {
-    const i64 rb = bi / cwords, cw = bi - rb * cwords;
-    const i64 r = rb * 64 + lane;
-    const u64 x = (r < rows) ? in[r * ldi + cw] : 0ull;
-    u64 mine = 0;
-#pragma unroll 8
-    for (int j = 0; j < 64; ++j) {
-      const u64 bal = __ballot((int)((x >> j) & 1ull));
-      mine = (lane == j) ? bal : mine;
-    }
-    const i64 orow = cw * 64 + lane;
-    if (orow < cols) out[orow * ldo + rb] = mine;
+  constexpr u64 kLow[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                           0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int s = 32 >> st;
+    const u64 lo = kLow[st];
+    const u64 y = __shfl_xor(x, s, 64);
+    x = (lane & s) ? ((x & ~lo) | ((y & ~lo) >> s)) : ((x & lo) | ((y & lo) << s));
+  }
+  return x;
+}
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))  // two workgroups per CU
+k_transpose(const u64* __restrict__ in, i64 rows, i64 cols, i64 ldi, u64* __restrict__ out, i64 ldo) {
+  __shared__ u64 buf[kTpLds];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const i64 rwords = (rows + 63) >> 6, cwords = (cols + 63) >> 6;
+  const i64 rtiles = (rows + kTpRows - 1) / kTpRows;
+  const i64 tile = blockIdx.x;  // one tile per workgroup
+  const i64 rt = tile % rtiles, ct = tile / rtiles;  // row tiles fastest: neighbours share output lines
+  // 1. rows of the tile -> LDS (rows past the matrix read as zero, words past it are never used);
+  //    32-bit offsets from the tile's first word, clamped into the matrix
+  const u64* src = in + rt * kTpRows * ldi + ct * kTpWords;
+  const int rlast = (int)(rows - 1 - rt * kTpRows < kTpRows - 1 ? rows - 1 - rt * kTpRows : kTpRows - 1);
+  const int clast = (int)(cwords - 1 - ct * kTpWords < kTpWords - 1 ? cwords - 1 - ct * kTpWords : kTpWords - 1);
+  u64 v[kTpRows * kTpWords / 512];
+#pragma unroll
+  for (int i = 0; i < kTpRows * kTpWords / 512; ++i) {
+    const int f = t + 512 * i, r = f / kTpWords, c = f % kTpWords;
+    v[i] = src[(u32)(r < rlast ? r : rlast) * (u32)ldi + (u32)(c < clast ? c : clast)];
+  }
+#pragma unroll
+  for (int i = 0; i < kTpRows * kTpWords / 512; ++i) {
+    const int f = t + 512 * i, r = f / kTpWords, c = f % kTpWords;
+    buf[r * kTpInLd + c] = r <= rlast ? v[i] : 0ull;
+  }
+  __syncthreads();
+  // 2. turn the 64 x 64 blocks
+  u64 x[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) x[h][b] = buf[(64 * b + lane) * kTpInLd + 2 * wave + h];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) x[h][b] = transpose_block64(x[h][b]);
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) buf[((2 * wave + h) * 64 + lane) * kTpOutLd + b] = x[h][b];
+  __syncthreads();
+  // 3. output rows 64 ct kTpWords .. , words 8 rt .. 8 rt + 7
+  u64* dst = out + ct * (64 * kTpWords) * ldo + rt * 8;
+  const i64 olast = cols - 1 - ct * (64 * kTpWords), wlast = rwords - 1 - rt * 8;
+#pragma unroll
+  for (int i = 0; i < 64 * kTpWords * 8 / 512; ++i) {
+    const int f = t + 512 * i, o = f / 8, b = f % 8;
+    if (o <= olast && b <= wlast) dst[(u32)o * (u32)ldo + (u32)b] = buf[o * kTpOutLd + b];
   }
 }
 
@@ -348,9 +408,11 @@ hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out
     hipError_t e = launch_fill_zero(out, cols * ldo, s);
     if (e != hipSuccess) return e;
   }
-  const i64 blocks = words_for(rows) * words_for(cols);
-  hipLaunchKernelGGL(k_transpose, dim3(grid_for(blocks * 64, kBlock, 16384)), dim3(kBlock), 0, s, in, rows, cols, ldi,
-                     out, ldo);
+  // the kernel addresses a tile with 32-bit offsets
+  if ((i64)kTpRows * ldi >= (1ll << 32) || (i64)64 * kTpWords * ldo >= (1ll << 32)) return hipErrorInvalidValue;
+  const i64 tiles = ((rows + kTpRows - 1) / kTpRows) * ((words_for(cols) + kTpWords - 1) / kTpWords);
+  if (tiles >= (1ll << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)tiles), dim3(512), 0, s, in, rows, cols, ldi, out, ldo);
   return hipGetLastError();
 }
 

@@ -85,6 +85,19 @@ def test_elementwise_and_transpose(ctx, n):
         assert np.array_equal(got, boolops.to_bits(boolops.transp(X), ldt))
 
 
+@pytest.mark.parametrize("rows,cols", [(1, 1), (1, 5000), (5000, 1), (511, 1025), (513, 1023), (1500, 3000),
+                                       (4100, 70), (33, 9000), (2048, 2048)])
+def test_transpose_tiles(ctx, rows, cols):
+    """Transposes spanning several 512-row x 1,024-column tiles, ragged in both directions."""
+    rng = np.random.default_rng(rows * 31 + cols)
+    X = (rng.random((rows, cols)) < 0.2).astype(np.uint8)
+    ld = boolops.words(cols) + (cols % 3)
+    bx = dev(boolops.to_bits(X, ld))
+    for ldt in (boolops.words(rows), boolops.words(rows) + 1):
+        got = host(ctx.transpose(bx, cols, ldat=ldt))
+        assert np.array_equal(got, boolops.to_bits(boolops.transp(X), ldt)), (rows, cols, ldt)
+
+
 @pytest.mark.parametrize("arm", [B.ARM_PRODUCT_VALU, B.ARM_PRODUCT_MFMA])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (5, 70, 3), (64, 64, 64), (65, 129, 200), (130, 1000, 70),
                                    (300, 77, 4100), (1000, 1000, 1000)])
