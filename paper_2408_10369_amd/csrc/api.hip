@@ -397,15 +397,18 @@ i64 count_bits(bmlp_ctx* c, const u64* R, i64 rows, i64 n, i64 ld, hipStream_t s
 }
 
 // Plain schedule for the selection, from a timing sweep of the arms on
-// n = 16,384 random digraphs (mean out-degree 1.6 .. 164, k = 1 .. 1024): the
-// sparse-frontier arm wins while the mean out-degree is low (its work grows with
-// the edges it visits); the dense semi-naive arm wins on dense relations (its
-// work is independent of the degree).
+// n = 4,096 and 16,384 random digraphs (mean out-degree 1.6 .. 164, k = 1 .. 1024):
+// the sparse-frontier arm wins while the mean out-degree is low (its work grows
+// with the edges it visits); the dense semi-naive arm wins on dense relations (its
+// work is independent of the degree).  Between degree 12 and 30 the sparse arm
+// still wins once 16 or more rows share the launch (degree 16, n = 16,384: k = 1
+// 0.42 ms dense vs 0.62 sparse, k = 64 0.75 vs 0.43); at degree 40 the dense arm
+// wins at every k (k = 1,024: 0.95 vs 2.75 ms).
 int smp_plain_arm(i64 n, i64 k, i64 m) {
   if (n > smp_rows_max_n()) return BMLP_ARM_SMP_DENSE;
   const double deg = n > 0 ? (double)m / (double)n : 0.0;
   if (deg < 12.0) return BMLP_ARM_SMP_SPARSE;
-  if (deg < 40.0 && k >= 32) return BMLP_ARM_SMP_SPARSE;
+  if (deg < 30.0 && k >= 16) return BMLP_ARM_SMP_SPARSE;
   return BMLP_ARM_SMP_DENSE;
 }
 
@@ -936,9 +939,9 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, c
         hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
       } else {
         const GraphInfo gi = graph_info(h, R1, ld, n, s);
-        const double delta0 = (forced && o.smp_arm != BMLP_ARM_SMP_ADAPTIVE) && !h->trace
-                                  ? 0.0
-                                  : (double)count_bits(h, V, k, n, ldv, s);
+        // the source count is a feature of the model's call-level choice (and of the trace) only
+        const bool model_call = !forced && o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
+        const double delta0 = (model_call || h->trace) ? (double)count_bits(h, V, k, n, ldv, s) : 0.0;
         arm = smp_choose_arm(h, o, gi, k, 0, refl, delta0, s, nullptr);
         smp_core(h, R1, ld, n, V, Vstar, k, ldv, refl, arm, gi, 0, Csr{}, o, s, sr);
       }

@@ -222,6 +222,25 @@ __device__ inline int wave_excl_scan(int v, int lane) {
   return x - v;
 }
 
+// Set bits of one row, summed over the wave (every lane gets the sum).  Each lane reads four words
+// per step (lane + 64 j), all four loads issued before any is used: they are clamped into the row
+// instead of guarded, and words past it are dropped.
+__device__ __forceinline__ u32 wave_row_bits(const u64* __restrict__ row, i64 nw, int lane) {
+  u32 c = 0;
+  for (i64 w0 = 0; w0 < nw; w0 += 256) {
+    u64 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const i64 w = w0 + lane + 64 * j;
+      v[j] = row[w < nw ? w : nw - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (w0 + lane + 64 * j < nw) c += (u32)__popcll(v[j]);
+  }
+  return (u32)wave_reduce_add((int)c);
+}
+
 // one wave per row
 __global__ void k_row_popcount(const u64* __restrict__ a, i64 rows, i64 n, i64 ld, int32_t* __restrict__ deg,
                                unsigned long long* __restrict__ total) {
@@ -230,31 +249,29 @@ __global__ void k_row_popcount(const u64* __restrict__ a, i64 rows, i64 n, i64 l
   const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
   const i64 nw = (n + 63) >> 6;
   for (i64 row = wave; row < rows; row += nwaves) {
-    int c = 0;
-    for (i64 w = lane; w < nw; w += 64) c += __popcll(a[row * ld + w]);
-    c = wave_reduce_add(c);
+    const u32 c = wave_row_bits(a + row * ld, nw, lane);
     if (lane == 0) {
-      deg[row] = c;
+      deg[row] = (int32_t)c;
       if (total) atomicAdd(total, (unsigned long long)c);
     }
   }
 }
 
-// total number of set bits: block reduction, one atomic per block
+// total number of set bits: one wave per row, one atomic per workgroup
 __global__ void k_popcount_total(const u64* __restrict__ a, i64 rows, i64 nw, i64 ld,
                                  unsigned long long* __restrict__ total) {
   __shared__ unsigned long long part[4];
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
   unsigned long long c = 0;
-  const i64 all = rows * nw;
-  for (i64 t = blockIdx.x * (i64)blockDim.x + threadIdx.x; t < all; t += (i64)gridDim.x * blockDim.x) {
-    const i64 row = t / nw, w = t - row * nw;
-    c += (unsigned long long)__popcll(a[row * ld + w]);
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  for (i64 row = wave; row < rows; row += nwaves) c += wave_row_bits(a + row * ld, nw, lane);
+  if (lane == 0) part[threadIdx.x >> 6] = c;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(total, part[0] + part[1] + part[2] + part[3]);
+  if (threadIdx.x == 0) {
+    const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+    if (t) atomicAdd(total, t);
+  }
 }
 
 // degree statistics of a relation: total, largest row, nonempty rows (one wave
@@ -266,10 +283,7 @@ __global__ void k_graph_stats(const u64* __restrict__ a, i64 rows, i64 nw, i64 l
   const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
   unsigned long long tot = 0, mx = 0, ne = 0;
   for (i64 row = wave; row < rows; row += nwaves) {
-    unsigned long long c = 0;
-    for (i64 w = lane; w < nw; w += 64) c += (unsigned long long)__popcll(a[row * ld + w]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    const unsigned long long c = wave_row_bits(a + row * ld, nw, lane);
     tot += c;
     mx = c > mx ? c : mx;
     ne += c ? 1u : 0u;
@@ -293,28 +307,57 @@ __global__ void k_graph_stats(const u64* __restrict__ a, i64 rows, i64 nw, i64 l
   }
 }
 
-// single workgroup exclusive scan: rp[0] = 0, rp[i+1] = rp[i] + deg[i]
+// single workgroup exclusive scan: rp[0] = 0, rp[i+1] = rp[i] + deg[i].  Segments of 8,192 degrees:
+// each thread sums eight consecutive ones (loads clamped and issued together), the sums are scanned
+// by wave shuffles and then across the 16 waves, and the running total carries to the next segment.
+constexpr int kScanPer = 8;
+
 __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict__ deg, i64 n, i64* __restrict__ rp) {
-  __shared__ i64 part[1024];
-  const int t = threadIdx.x;
-  const i64 chunk = (n + 1023) / 1024;
-  const i64 lo = t * chunk, hi = (lo + chunk < n) ? lo + chunk : n;
-  i64 s = 0;
-  for (i64 i = lo; i < hi; ++i) s += deg[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    i64 v = (t >= off) ? part[t - off] : 0;
+  __shared__ i64 wsum[16];
+  __shared__ i64 wpre[17];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  i64 carry = 0;
+  for (i64 base = 0; base < n; base += 1024 * kScanPer) {
+    int v[kScanPer];
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      const i64 i = base + (i64)t * kScanPer + j;
+      v[j] = deg[i < n ? i : n - 1];
+    }
+    i64 sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      if (base + (i64)t * kScanPer + j >= n) v[j] = 0;
+      sum += v[j];
+    }
+    i64 x = sum;  // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const i64 y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    part[t] += v;
+    if (t == 0) {
+      i64 r = 0;
+      for (int w = 0; w < 16; ++w) {
+        wpre[w] = r;
+        r += wsum[w];
+      }
+      wpre[16] = r;
+    }
     __syncthreads();
+    i64 run = carry + wpre[wave] + x - sum;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      const i64 i = base + (i64)t * kScanPer + j;
+      if (i < n) rp[i] = run;
+      run += v[j];
+    }
+    carry += wpre[16];
+    __syncthreads();  // wsum and wpre are rewritten by the next segment
   }
-  i64 run = part[t] - s;
-  for (i64 i = lo; i < hi; ++i) {
-    rp[i] = run;
-    run += deg[i];
-  }
-  if (t == 1023) rp[n] = part[1023];
+  if (t == 0) rp[n] = carry;
 }
 
 // one wave per row; lanes own consecutive words
@@ -432,7 +475,7 @@ hipError_t launch_row_popcount(const u64* a, i64 rows, i64 n, i64 ld, int32_t* d
 
 hipError_t launch_popcount_total(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* total, hipStream_t s) {
   if (rows <= 0 || n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_popcount_total, dim3(grid_for(rows * words_for(n), kBlock, 2048)), dim3(kBlock), 0, s, a, rows,
+  hipLaunchKernelGGL(k_popcount_total, dim3(grid_for(rows * 64, kBlock, 2048)), dim3(kBlock), 0, s, a, rows,
                      words_for(n), ld, total);
   return hipGetLastError();
 }

@@ -202,3 +202,40 @@ def test_sessions_plain_learned_and_cached_closure(ctx, random_model):
         st = {}
         g.query(V, stats=st)
         assert st["arm"] == B.ARM_SMP_CLOSURE
+
+
+@pytest.mark.parametrize("n", [1, 130, 3000, 20000])
+def test_call_features_match_graph_statistics(ctx, n):
+    """The call-level features come from the library's device counts (edges, largest row, nonempty
+    rows, source bits); they must equal the counts taken on the host, also for rows of more than
+    256 words and for a degree table scanned in several segments."""
+    rng = np.random.default_rng(n + 3)
+    m_target = max(1, n * 3)
+    s = rng.integers(0, n, m_target).astype(np.int32)
+    d = rng.integers(0, n, m_target).astype(np.int32)
+    hub = 0
+    extra = np.arange(min(n, 700), dtype=np.int32)
+    s = np.concatenate([s, np.full(len(extra), hub, np.int32)])
+    d = np.concatenate([d, extra])
+    A = np.zeros((n, n), np.uint8)
+    A[s, d] = 1
+    m = int(A.sum())
+    rowdeg = A.sum(axis=1)
+    k = min(n, 37)
+    V = np.zeros((k, n), np.uint8)
+    V[np.arange(k), rng.integers(0, n, k)] = 1
+    V[0, : min(n, 90)] = 1
+    R = pack(ctx, n, s, d)
+    Vd = torch.from_numpy(boolops.to_bits(V).view(np.int64)).cuda()
+    tr = B.Trace()
+    ctx.set_trace(tr)
+    got = ctx.smp(R, n, Vd, opts=B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_SPARSE))
+    ctx.set_trace(None)
+    assert np.array_equal(host(got), oracle.smp(n, s, d, boolops.to_bits(V)))
+    f = tr.as_dict()["call_features"]
+    deg = m / n
+    want = {0: np.log2(1 + n) / 16, 1: np.log2(1 + m) / 24, 2: np.log2(1 + deg) / 8,
+            3: np.log2(1 + rowdeg.max() / (1 + deg)) / 8, 4: (rowdeg > 0).sum() / n, 5: np.log2(1 + k) / 16,
+            12: np.log2(1 + V.sum()) / 32}
+    for i, v in want.items():
+        assert abs(float(f[i]) - v) <= 1e-6 * max(1.0, abs(v)), (i, float(f[i]), v)
