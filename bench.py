@@ -67,9 +67,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
                     help="bound the oracle's closure rows per graph (0: all rows)")
-    ap.add_argument("--workloads", default="batch,programs,stream,isforeign",
+    ap.add_argument("--workloads", default="batch,programs,stream,isforeign,dynamic",
                     help="held-out workloads measured after the main one, plain vs learned schedule "
-                         "(comma list of batch, programs, stream, isforeign; empty for none)")
+                         "(comma list of batch, programs, stream, isforeign, dynamic; empty for none)")
     ap.add_argument("--stream-queries", type=int, default=10000,
                     help="queries of the n=65,536 stream to run (a prefix of the 10,000)")
     ap.add_argument("--workloads-only", action="store_true",
@@ -218,7 +218,8 @@ def main():
 def run_workloads(ctx, args):
     res = {}
     for name in [w for w in args.workloads.split(",") if w]:
-        fn = {"batch": wl_batch, "programs": wl_programs, "stream": wl_stream, "isforeign": wl_isforeign}[name]
+        fn = {"batch": wl_batch, "programs": wl_programs, "stream": wl_stream, "isforeign": wl_isforeign,
+              "dynamic": wl_dynamic}[name]
         res[name] = fn(ctx, args)
         print(json.dumps({"workload_done": name}), file=sys.stderr, flush=True)
     return res
@@ -449,6 +450,55 @@ def wl_isforeign(ctx, args):
     if not args.no_cpu_baseline:
         r["cpu_baseline"] = cpu_baseline_isforeign(g)
     return r
+
+
+def wl_dynamic(ctx, args):
+    """Closure maintenance under insertions: the closure of the sparsest density-sweep graph
+    (n = 16,384, p = 1e-4, 26,879 edges) updated in place with a batch of b new random edges, against
+    recomputing the closure of the enlarged relation from scratch; both results must be identical."""
+    import numpy as np
+    import torch
+
+    import gen
+
+    n, s, d = gen.c2(0)
+    dev = "cuda:0"
+    R0 = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n)
+    T0 = ctx.rms(R0, n)
+    W = torch.randint(-2**62, 2**62, (T0.numel(),), dtype=torch.int64, device=dev)
+    rng = np.random.default_rng(31337)
+    res = {}
+    for b in (1, 16, 256, 4096):
+        es = torch.as_tensor(rng.integers(0, n, b).astype(np.int32)).to(dev)
+        ed = torch.as_tensor(rng.integers(0, n, b).astype(np.int32)).to(dev)
+        T = T0.clone()
+        ctx.closure_insert(T, n, es, ed)  # warm-up (workspace)
+        ts = []
+        for _ in range(5):
+            T.copy_(T0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.closure_insert(T, n, es, ed)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        inc_ms = sorted(ts)[len(ts) // 2]
+        # from scratch: pack the enlarged edge list and take its closure
+        us = torch.cat([torch.as_tensor(s).to(dev), es])
+        ud = torch.cat([torch.as_tensor(d).to(dev), ed])
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            R = ctx.pack_coo(us, ud, n, n)
+            Tf = ctx.rms(R, n)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        full_ms = sorted(ts)[len(ts) // 2]
+        res[str(b)] = {"insert_ms": round(inc_ms, 3), "recompute_ms": round(full_ms, 3),
+                       "speedup": round(full_ms / inc_ms, 1), "bit_identical": _hash(T, W) == _hash(Tf, W)}
+    return {"workload": "closure of the n=16,384 p=1e-4 sweep graph, batches of b random edge insertions "
+                        "(in place) vs the closure recomputed from the enlarged edge list",
+            "by_batch": res, "bit_identical": all(v["bit_identical"] for v in res.values())}
 
 
 def cpu_baseline_isforeign(g):

@@ -11,6 +11,8 @@
  *                        source rows (Section 3.3, Eq. 5; Algorithm 2)
  *   bmlp_compose_linear  general linear recursion p <- b; p <- s, p, i.e.
  *                        P = Rs* Rb (Section 3.4, Theorem 1)
+ *   bmlp_closure_insert  a closure kept up to date under edge insertions
+ *                        (dynamic databases, the conclusion's future work)
  * plus the Boolean matrix operators they are built from (Section 2 and
  * Section 4: addition, multiplication, transpose, negation) and the packing
  * of facts into matrices (Section 3.2).
@@ -194,6 +196,19 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, c
    overlap Rbase or Rstep.  compose_linear(R1, R1) = rms(R1). */
 bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t *Rbase, const uint64_t *Rstep, uint64_t *P,
                                 int64_t n, int64_t ld, const bmlp_opts *opts, void *stream, bmlp_stats *stats);
+
+/* Closure under insertions: Rplus (n x n, ld) holds T = R1+ of some relation R1 on entry (the caller's
+   promise; it is not checked) and (R1 | E)+ on return, where E is the b edges (src[i], dst[i]).
+   Closures only grow under insertions (dynamic databases, named as future work in the paper's
+   conclusion), so with U = T | I the new paths are x ->U src_i -> dst_i ->U ... -> dst_j ->U y, and
+   (R1 | E)+ = T | A . M* . B with A = columns src_i of U, B = rows dst_j of U and
+   M[i][j] = U[dst_i][src_j] (b x b).  src, dst: DEVICE int32 arrays of b indices in [0, n)
+   (BMLP_EINVAL otherwise, Rplus unchanged); duplicate and already-implied edges are fine.  b = 0 is a
+   no-op.  Uses handle workspace of about 3 b n / 8 + 2 n b / 8 bytes plus that of a b x b closure.
+   stats: the products and the small closure, as for the other calls. */
+bmlp_status bmlp_closure_insert(bmlp_handle h, uint64_t *Rplus, int64_t n, int64_t ld, const int32_t *src,
+                                const int32_t *dst, int64_t b, const bmlp_opts *opts, void *stream,
+                                bmlp_stats *stats);
 
 /* ------------------------------------------------------------ batches of graphs */
 /* One graph of a batch: its relation, where its closure goes, and its query rows. */

@@ -36,7 +36,7 @@ EXPORTS = [
     "bmlp_create", "bmlp_destroy", "bmlp_last_error", "bmlp_opts_init", "bmlp_version",
     "bmlp_pack_u8", "bmlp_pack_coo", "bmlp_unpack_u8",
     "bmlp_or", "bmlp_and", "bmlp_andnot", "bmlp_not", "bmlp_transpose", "bmlp_product",
-    "bmlp_rms", "bmlp_smp", "bmlp_compose_linear", "bmlp_batched",
+    "bmlp_rms", "bmlp_smp", "bmlp_compose_linear", "bmlp_closure_insert", "bmlp_batched",
     "bmlp_graph_open", "bmlp_graph_query", "bmlp_graph_has_closure", "bmlp_graph_close",
     "bmlp_set_trace", "bmlp_dispatcher_load", "bmlp_dispatcher_save", "bmlp_dispatcher_loaded",
     "bmlp_dispatcher_train", "bmlp_dispatcher_forward", "bmlp_mlp_loss_grad",
@@ -131,6 +131,7 @@ def lib():
     L.bmlp_rms.argtypes = [vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_smp.argtypes = [vp, vp, i64, i64, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_compose_linear.argtypes = [vp, vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
+    L.bmlp_closure_insert.argtypes = [vp, vp, i64, i64, vp, vp, i64, P(Opts), vp, P(Stats)]
     L.bmlp_batched.argtypes = [vp, P(GraphDesc), ctypes.c_int32, P(Opts), vp, P(Stats)]
     fp = ctypes.POINTER(ctypes.c_float)
     L.bmlp_graph_open.argtypes = [vp, vp, i64, i64, vp, P(vp)]
@@ -338,6 +339,23 @@ class Context:
         if st is not None:
             stats.update(st.as_dict())
         return out
+
+    def closure_insert(self, Rplus, n: int, src, dst, opts=None, stream=None, stats=None):
+        """Rplus (n x n, the closure of some relation) becomes the closure with the edges (src[i], dst[i])
+        added, in place."""
+        import torch
+        _, ld = _bits_shape(Rplus, n)
+        src = torch.as_tensor(src).to(device=f"cuda:{self.device}", dtype=torch.int32).contiguous()
+        dst = torch.as_tensor(dst).to(device=f"cuda:{self.device}", dtype=torch.int32).contiguous()
+        if src.numel() != dst.numel():
+            raise ValueError("src and dst must have the same length")
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_closure_insert(self._h, _ptr(Rplus), n, ld, _ptr(src), _ptr(dst), src.numel(),
+                                         ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                         ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return Rplus
 
     def batched(self, graphs, opts=None, stream=None, stats=None):
         """One launch over many graphs.  ``graphs``: sequence of dicts with keys

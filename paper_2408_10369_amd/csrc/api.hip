@@ -952,6 +952,82 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, c
   });
 }
 
+// Closure under insertions (dynamic databases, a direction the conclusion names as future work).  With
+// T = R+ and U = T | I, a path of R | E either avoids E (it is in T) or runs x ->U u_i ->E v_i ->U ...
+// ->E v_j ->U y.  Hence (R | E)+ = T | A . M* . B, where for the b inserted edges (u_i, v_i)
+//   A = columns u_i of U (n x b), B = rows v_j of U (b x n), M[i][j] = U[v_i][u_j] (b x b),
+// and M* = I | M+ is the closure of the small relation among the inserted edges.  Every step is a
+// product, a gather, a transpose or a closure of the library; T is updated in place.
+bmlp_status bmlp_closure_insert(bmlp_handle h, uint64_t* Rplus, int64_t n, int64_t ld, const int32_t* src,
+                                const int32_t* dst, int64_t b, const bmlp_opts* opts, void* stream,
+                                bmlp_stats* stats) {
+  return guarded([&] {
+    need_handle(h);
+    const bmlp_opts o = opts_or_default(opts);
+    check_bits_arg(Rplus, "Rplus", n, n, ld);
+    need(b >= 0, BMLP_EINVAL, "b < 0");
+    if (b > 0) {
+      need(src && dst, BMLP_EINVAL, "src/dst: null pointer");
+      need(((uintptr_t)src & 3u) == 0 && ((uintptr_t)dst & 3u) == 0, BMLP_EALIGN, "src/dst: not 4-byte aligned");
+      need(n > 0, BMLP_EINVAL, "closure_insert: edges given for an empty relation");
+    }
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (o.check_padding) check_padding(h, Rplus, n, n, ld, s, "Rplus");
+    StatsRec sr(stats, h, s, &o);
+    if (b > 0) {
+      const i64 nw = words_for(n), bw = words_for(b);
+      hip_check(hipMemsetAsync(h->d_flags + F_COO, 0, sizeof(u32), s), "hipMemsetAsync");
+      hip_check(launch_check_index(src, b, n, h->d_flags + F_COO, s), "check_index");
+      hip_check(launch_check_index(dst, b, n, h->d_flags + F_COO, s), "check_index");
+      need(read_flag(h, s, F_COO) == 0, BMLP_EINVAL, "closure_insert: edge endpoint outside [0,%lld)", (long long)n);
+      // B = rows v_j of U (b x n): the one-hot rows of the targets, each OR-ed with its row of T
+      u64* ev = ws_bits(h, S_T1, b, nw, o);
+      hip_check(launch_fill_zero(ev, b * nw, s), "fill_zero");
+      hip_check(launch_set_onehot(ev, nw, dst, b, n, nullptr, s), "set_onehot");
+      u64* bm = ws_bits(h, S_W2, b, nw, o);
+      if (n <= gather_rows_max_n())
+        hip_check(launch_gather_rows(ev, nw, b, Rplus, ld, n, 1, bm, nw, s), "gather_rows");
+      else
+        product(h, ev, nw, Rplus, ld, ev, nw, bm, nw, nullptr, 0, b, n, n, nullptr, product_arm(o, b, n, n), s, sr);
+      hip_check(launch_zero_pad(bm, b, n, nw, s), "zero_pad");
+      // A = columns u_i of U (n x b); M[i][j] = B[i][u_j] (b x b)
+      u64* am = ws_bits(h, S_W3, n, bw, o);
+      u64* mm = ws_bits(h, S_W4, b, bw, o);
+      if (n <= gather_cols_max_n()) {
+        hip_check(launch_gather_cols(Rplus, ld, n, n, src, b, 1, am, bw, s), "gather_cols");
+        hip_check(launch_gather_cols(bm, nw, b, n, src, b, 0, mm, bw, s), "gather_cols");
+      } else {
+        // P[x][i] = (x == u_i), then A = P | T . P and M = B . P
+        u64* eu = ws_bits(h, S_T0, b, nw, o);
+        hip_check(launch_fill_zero(eu, b * nw, s), "fill_zero");
+        hip_check(launch_set_onehot(eu, nw, src, b, n, nullptr, s), "set_onehot");
+        u64* pt = ws_bits(h, S_T2, n, bw, o);
+        hip_check(launch_transpose(eu, b, n, nw, pt, bw, s), "transpose");
+        product(h, Rplus, ld, pt, bw, pt, bw, am, bw, nullptr, 0, n, n, b, nullptr, product_arm(o, n, b, n), s, sr);
+        product(h, bm, nw, pt, bw, nullptr, 0, mm, bw, nullptr, 0, b, n, b, nullptr, product_arm(o, b, b, n), s, sr);
+        hip_check(launch_zero_pad(am, n, b, bw, s), "zero_pad");
+        hip_check(launch_zero_pad(mm, b, b, bw, s), "zero_pad");
+      }
+      // M* = I | M+ (b x b)
+      u64* ms = ws_bits(h, S_T0, b, bw, o);
+      if (b <= 64) {
+        hip_check(launch_closure64(mm, bw, b, ms, bw, s), "closure64");  // one wave, no host round trip
+      } else {
+        rms_core(h, mm, bw, ms, bw, b, o, s, sr);
+        hip_check(launch_set_diag(ms, bw, b, b, s), "set_diag");
+      }
+      // X = M* . B (b x n), then T |= A . X
+      u64* xm = ws_bits(h, S_T1, b, nw, o);  // the one-hot targets are no longer needed
+      product(h, ms, bw, bm, nw, nullptr, 0, xm, nw, nullptr, 0, b, b, n, nullptr, product_arm(o, b, n, b), s, sr);
+      hip_check(launch_zero_pad(xm, b, n, nw, s), "zero_pad");
+      product(h, am, bw, xm, nw, Rplus, ld, Rplus, ld, nullptr, 0, n, b, n, nullptr, product_arm(o, n, n, b), s, sr);
+      hip_check(launch_zero_pad(Rplus, n, n, ld, s), "zero_pad");
+    }
+    sr.finish();
+  });
+}
+
 bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint64_t* Rstep, uint64_t* P, int64_t n,
                                 int64_t ld, const bmlp_opts* opts, void* stream, bmlp_stats* stats) {
   return guarded([&] {
@@ -1042,7 +1118,7 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
           hip_check(hipMemcpyAsync(drows, rows.data(), (size_t)kr * sizeof(int32_t), hipMemcpyHostToDevice, s),
                     "memcpy");
           hip_check(launch_fill_zero(v1, kr * nw, s), "fill_zero");
-          hip_check(launch_set_onehot(v1, nw, drows, kr, s), "set_onehot");
+          hip_check(launch_set_onehot(v1, nw, drows, kr, n, nullptr, s), "set_onehot");
           if (sarm == BMLP_ARM_AUTO || sarm == BMLP_ARM_SMP_ADAPTIVE) sarm = smp_plain_arm(n, kr, gs.m);
           smp_core(h, Rstep, ld, n, v1, sel, kr, nw, 0, sarm, gs, 1, Csr{rp, ci}, o, s, sr);
           hip_check(launch_gather_rows(sel, nw, kr, Rbase, ld, n, 2, P, ld, s, drows), "gather_rows");

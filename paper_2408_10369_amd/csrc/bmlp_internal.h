@@ -30,7 +30,14 @@ hipError_t launch_zero_pad(u64* a, i64 rows, i64 n, i64 ld, hipStream_t s);
 // set the diagonal bits (i, i) for i < min(rows, n)
 hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s);
 // row i of a gets bit idx[i] (0 <= idx[i] < columns; rows zeroed beforehand)
-hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, hipStream_t s);
+hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s);
+hipError_t launch_check_index(const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s);
+// out = I | M+ for b <= 64 (M, out: b rows of one significant word)
+hipError_t launch_closure64(const u64* M, i64 ldm, i64 b, u64* out, i64 ldo, hipStream_t s);
+// A[x][i] = T[x][cols[i]] (| (cols[i] == x) when diag) for rows x < rows of T (n columns); n <= gather_cols_max_n()
+hipError_t launch_gather_cols(const u64* T, i64 ldt, i64 rows, i64 n, const int32_t* cols, i64 b, int diag, u64* A,
+                              i64 lda, hipStream_t s);
+i64 gather_cols_max_n();
 // out (cols x rows) = transpose of in (rows x cols)
 hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out, i64 ldo, hipStream_t s);
 // nonzero padding bits (columns >= n) in any row -> *bad = 1

@@ -104,10 +104,68 @@ __global__ void k_set_diag(u64* __restrict__ a, i64 ld, i64 cnt) {
 }
 
 // row i gets the single bit idx[i] (rows zeroed beforehand)
-__global__ void k_set_onehot(u64* __restrict__ a, i64 ld, const int32_t* __restrict__ idx, i64 k) {
+// row i of a (zeroed by the caller) gets the single bit idx[i]; an index outside [0, n) is skipped and
+// raises *bad
+__global__ void k_set_onehot(u64* __restrict__ a, i64 ld, const int32_t* __restrict__ idx, i64 k, i64 n,
+                             u32* __restrict__ bad) {
   for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < k; i += (i64)gridDim.x * blockDim.x) {
     const i64 j = idx[i];
+    if (j < 0 || j >= n) {
+      if (bad) atomicOr(bad, 1u);
+      continue;
+    }
     a[i * ld + (j >> 6)] = 1ull << (j & 63);
+  }
+}
+
+// raises *bad when an index lies outside [0, n)
+__global__ void k_check_index(const int32_t* __restrict__ idx, i64 k, i64 n, u32* __restrict__ bad) {
+  for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < k; i += (i64)gridDim.x * blockDim.x) {
+    const i64 j = idx[i];
+    if (j < 0 || j >= n) atomicOr(bad, 1u);
+  }
+}
+
+// Column gather: A[x][i] = T[x][cols[i]] (| (cols[i] == x) when diag), one workgroup per row x of T
+// with the row staged in LDS; each wave turns 64 consecutive i into one word of A by a ballot.
+__global__ void __launch_bounds__(256)
+k_gather_cols(const u64* __restrict__ T, i64 ldt, i64 rows, i64 n, const int32_t* __restrict__ cols, i64 b,
+              int diag, u64* __restrict__ A, i64 lda) {
+  extern __shared__ u64 rowbuf[];
+  const i64 nw = (n + 63) >> 6, bw = (b + 63) >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  for (i64 x = blockIdx.x; x < rows; x += gridDim.x) {
+    for (i64 w = t; w < nw; w += 256) rowbuf[w] = T[x * ldt + w];
+    __syncthreads();
+    for (i64 i0 = (i64)(t >> 6) * 64; i0 < b; i0 += 256) {
+      const i64 i = i0 + lane;
+      int bit = 0;
+      if (i < b) {
+        const i64 c = cols[i];
+        bit = (int)((rowbuf[c >> 6] >> (c & 63)) & 1ull) | (diag && c == x ? 1 : 0);
+      }
+      const u64 word = __ballot(bit);
+      if (lane == 0) A[x * lda + (i0 >> 6)] = word;
+    }
+    for (i64 w = bw + t; w < lda; w += 256) A[x * lda + w] = 0ull;
+    __syncthreads();  // the row buffer is refilled for the next row
+  }
+}
+
+// I | M+ for a relation of b <= 64 nodes (one word per row), by Warshall's algorithm in one wave: lane
+// i holds row i; at step k every row with bit k set takes in row k (read by a shuffle, so it already
+// holds the paths through nodes < k).
+__global__ void k_closure64(const u64* __restrict__ M, i64 ldm, i64 b, u64* __restrict__ out, i64 ldo) {
+  const int lane = threadIdx.x & 63;
+  const u64 mask = b >= 64 ? ~0ull : ((1ull << b) - 1ull);
+  u64 row = lane < b ? (M[lane * ldm] & mask) : 0ull;
+  for (int k = 0; k < b; ++k) {
+    const u64 rk = __shfl(row, k, 64);
+    if ((row >> k) & 1ull) row |= rk;
+  }
+  if (lane < b) {
+    out[lane * ldo] = row | (1ull << lane);
+    for (i64 w = 1; w < ldo; ++w) out[lane * ldo + w] = 0ull;
   }
 }
 
@@ -438,9 +496,34 @@ hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, hipStream_t s) {
+hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s) {
   if (k <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_set_onehot, dim3(grid_for(k)), dim3(kBlock), 0, s, a, ld, idx, k);
+  hipLaunchKernelGGL(k_set_onehot, dim3(grid_for(k)), dim3(kBlock), 0, s, a, ld, idx, k, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_closure64(const u64* M, i64 ldm, i64 b, u64* out, i64 ldo, hipStream_t s) {
+  if (b <= 0) return hipSuccess;
+  if (b > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_closure64, dim3(1), dim3(64), 0, s, M, ldm, b, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_index(const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_index, dim3(grid_for(k)), dim3(kBlock), 0, s, idx, k, n, bad);
+  return hipGetLastError();
+}
+
+i64 gather_cols_max_n() { return (i64)64 * 8192; }  // the staged row: 64 KiB of LDS
+
+hipError_t launch_gather_cols(const u64* T, i64 ldt, i64 rows, i64 n, const int32_t* cols, i64 b, int diag, u64* A,
+                              i64 lda, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (n > gather_cols_max_n() || n <= 0) return hipErrorInvalidValue;
+  const size_t lds = (size_t)words_for(n) * sizeof(u64);
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)(rows < 65535 ? rows : 65535)), dim3(256), lds, s, T, ldt, rows, n,
+                     cols, b, diag, A, lda);
   return hipGetLastError();
 }
 

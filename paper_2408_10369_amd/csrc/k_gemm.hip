@@ -58,12 +58,13 @@ k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 l
   const i64 kwords = (K + 63) >> 6;
   const i64 kw_begin = ks * chunks_per_split;
   const i64 kw_end = (kw_begin + chunks_per_split < kwords) ? kw_begin + chunks_per_split : kwords;
-  valu_tile_accumulate<RPW, WPL>(A, lda, B, ldb, M, K, nw, row0, w0, kw_begin, kw_end, Bs, acc);
+  const bool worked = valu_tile_accumulate<RPW, WPL>(A, lda, B, ldb, M, K, nw, row0, w0, kw_begin, kw_end, Bs, acc);
 
   int ch = 0;
   u32 pop = 0;
   if (ksplit == 1) {
-    ch = valu_tile_store<RPW, WPL>(acc, Cold, ldco, C, ldc, D, ldd, M, nw, row0, w0, &pop);
+    // an in-place product (C is Cold, no delta) leaves a tile whose rows of A are all zero as it is
+    if (worked || C != Cold || D) ch = valu_tile_store<RPW, WPL>(acc, Cold, ldco, C, ldc, D, ldd, M, nw, row0, w0, &pop);
   } else {
     // C already holds Cold and D is zero (the launcher sees to both)
 #pragma unroll

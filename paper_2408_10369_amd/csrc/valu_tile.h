@@ -33,13 +33,15 @@ __device__ __forceinline__ u32 and_or(u32 b, u32 m, u32 acc) {
 }
 
 // acc |= A[row0 .. row0+RPW, k words kw_begin..kw_end) . B[those k, w0 .. w0 + 64 WPL)
-// All threads of the workgroup must call it with the same kw range and w0.
+// All threads of the workgroup must call it with the same kw range and w0.  Returns whether any word
+// of k had a set bit in a row of the tile (the same answer in every thread of the workgroup).
 template <int RPW, int WPL>
-__device__ __forceinline__ void valu_tile_accumulate(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B,
+__device__ __forceinline__ bool valu_tile_accumulate(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B,
                                                      i64 ldb, i64 M, i64 K, i64 nw, i64 row0, i64 w0, i64 kw_begin,
                                                      i64 kw_end, u64 (*Bs)[64 * WPL], u32 (&acc)[RPW][WPL][2]) {
   constexpr int TW = 64 * WPL;
   const int lane = threadIdx.x & 63;
+  bool worked = false;  // some word of k had a set bit in some row of the tile (workgroup-uniform)
   for (i64 kw = kw_begin; kw < kw_end; ++kw) {
     u32 alo[RPW], ahi[RPW];
     u32 any = 0;
@@ -52,6 +54,7 @@ __device__ __forceinline__ void valu_tile_accumulate(const u64* __restrict__ A, 
       any |= alo[r] | ahi[r];
     }
     if (!__syncthreads_or(any != 0)) continue;
+    worked = true;
     // stage the 64 x TW chunk of B: every thread's loads are issued before any is waited for.
     // They are clamped into the matrix, so they need no guard (words outside it are stored as
     // zero), and addressed by 32-bit offsets from the chunk's first row.
@@ -96,6 +99,7 @@ __device__ __forceinline__ void valu_tile_accumulate(const u64* __restrict__ A, 
       }
     }
   }
+  return worked;
 }
 
 // C = Cold | acc for the tile (D = C & ~Cold when D is given); returns whether
