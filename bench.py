@@ -67,9 +67,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
                     help="bound the oracle's closure rows per graph (0: all rows)")
-    ap.add_argument("--workloads", default="batch,programs,stream,isforeign,dynamic",
+    ap.add_argument("--workloads", default="batch,programs,stream,isforeign,dynamic,samegen",
                     help="held-out workloads measured after the main one, plain vs learned schedule "
-                         "(comma list of batch, programs, stream, isforeign, dynamic; empty for none)")
+                         "(comma list of batch, programs, stream, isforeign, dynamic, samegen; empty for none)")
     ap.add_argument("--stream-queries", type=int, default=10000,
                     help="queries of the n=65,536 stream to run (a prefix of the 10,000)")
     ap.add_argument("--workloads-only", action="store_true",
@@ -219,7 +219,7 @@ def run_workloads(ctx, args):
     res = {}
     for name in [w for w in args.workloads.split(",") if w]:
         fn = {"batch": wl_batch, "programs": wl_programs, "stream": wl_stream, "isforeign": wl_isforeign,
-              "dynamic": wl_dynamic}[name]
+              "dynamic": wl_dynamic, "samegen": wl_samegen}[name]
         res[name] = fn(ctx, args)
         print(json.dumps({"workload_done": name}), file=sys.stderr, flush=True)
     return res
@@ -499,6 +499,48 @@ def wl_dynamic(ctx, args):
     return {"workload": "closure of the n=16,384 p=1e-4 sweep graph, batches of b random edge insertions "
                         "(in place) vs the closure recomputed from the enlarged edge list",
             "by_batch": res, "bit_identical": all(v["bit_identical"] for v in res.values())}
+
+
+def wl_samegen(ctx, args):
+    """Same-generation, p <- flat; p <- up, p, down, on a random forest of n = 16,384 nodes (8 trees,
+    up to 4 children per node): the two-sided linear recursion with the library's choice per round
+    (row gathers while an operand is sparse) against every product on the bit-packed VALU kernel and
+    on the matrix cores."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2408_10369_amd as B
+
+    f = gen.forest()
+    n = f.n
+    roots = np.unique(f.root).astype(np.int32)
+
+    def pk(s, d):
+        return ctx.pack_coo(torch.as_tensor(np.asarray(s, np.int32)), torch.as_tensor(np.asarray(d, np.int32)), n, n)
+
+    flat, up, down = pk(roots, roots), pk(f.child, f.parent), pk(f.parent, f.child)
+    out = ctx.zeros(n, n)
+    W = torch.randint(-2**62, 2**62, (out.numel(),), dtype=torch.int64, device="cuda")
+    modes = {"auto": None,
+             "valu_products": B.make_opts(dispatch=B.DISPATCH_FORCED, product_arm=B.ARM_PRODUCT_VALU),
+             "mfma_products": B.make_opts(dispatch=B.DISPATCH_FORCED, product_arm=B.ARM_PRODUCT_MFMA)}
+    res, fp = {}, {}
+    for name, o in modes.items():
+        ctx.compose_two_sided(flat, up, down, n, out=out, opts=o)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = {}
+            ctx.compose_two_sided(flat, up, down, n, out=out, opts=o, stats=st)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        fp[name] = _hash(out, W)
+        res[name] = {"ms": round(sorted(ts)[1], 3), "rounds": st["iterations"]}
+    facts = int(np.unpackbits(out.cpu().numpy().view(np.uint8)).sum())
+    return {"workload": "same-generation on a random forest, n=16,384 nodes, 8 trees, depth %d" % int(f.depth.max()),
+            "by_mode": res, "derived_facts": facts, "bit_identical": len(set(fp.values())) == 1}
 
 
 def cpu_baseline_isforeign(g):

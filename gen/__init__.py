@@ -307,3 +307,37 @@ def geo(n: int = 14541, levels=(20, 200, 1000, 2780), seed: int = 6,
     cs, cd = _dedupe_sorted(np.asarray(cs, np.int32), np.asarray(cd, np.int32), n)
     as_, ad = _dedupe_sorted(np.asarray(as_, np.int32), np.asarray(ad, np.int32), n)
     return Geo(n, cs, cd, as_, ad, np.sort(loc))
+
+
+# --- forests for the two-sided (same-generation) program ----------------------
+@dataclass
+class Forest:
+    n: int
+    child: np.ndarray    # edge child -> parent, as (child, parent) pairs
+    parent: np.ndarray
+    depth: np.ndarray    # depth of every node (roots 0)
+    root: np.ndarray     # root of every node's tree
+
+
+def forest(n: int = 16384, trees: int = 8, seed: int = 8, max_children: int = 4) -> Forest:
+    """A random forest: nodes 0..trees-1 are roots; every later node picks a random parent among the
+    nodes before it whose child count is below ``max_children`` (shapes vary from bushy to deep)."""
+    rng = np.random.default_rng(seed)
+    parent = np.full(n, -1, np.int64)
+    depth = np.zeros(n, np.int64)
+    root = np.arange(n, dtype=np.int64)
+    kids = np.zeros(n, np.int64)
+    open_ = list(range(min(trees, n)))
+    for v in range(min(trees, n), n):
+        i = int(rng.integers(len(open_)))
+        p = open_[i]
+        parent[v] = p
+        depth[v] = depth[p] + 1
+        root[v] = root[p]
+        kids[p] += 1
+        if kids[p] >= max_children:
+            open_[i] = open_[-1]
+            open_.pop()
+        open_.append(v)
+    ch = np.nonzero(parent >= 0)[0]
+    return Forest(n, ch.astype(np.int32), parent[ch].astype(np.int32), depth, root)

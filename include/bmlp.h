@@ -11,6 +11,7 @@
  *                        source rows (Section 3.3, Eq. 5; Algorithm 2)
  *   bmlp_compose_linear  general linear recursion p <- b; p <- s, p, i.e.
  *                        P = Rs* Rb (Section 3.4, Theorem 1)
+ *   bmlp_compose_two_sided  p <- b; p <- l, p, r (e.g. same-generation)
  *   bmlp_closure_insert  a closure kept up to date under edge insertions
  *                        (dynamic databases, the conclusion's future work)
  * plus the Boolean matrix operators they are built from (Section 2 and
@@ -196,6 +197,17 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, c
    overlap Rbase or Rstep.  compose_linear(R1, R1) = rms(R1). */
 bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t *Rbase, const uint64_t *Rstep, uint64_t *P,
                                 int64_t n, int64_t ld, const bmlp_opts *opts, void *stream, bmlp_stats *stats);
+
+/* Two-sided linear recursion
+       p(X,Y) <- b(X,Y).    p(X,Y) <- l(X,X1), p(X1,Y1), r(Y1,Y).
+   as the least P with P = Rbase + Rleft x P x Rright, i.e. P = sum over k >= 0 of Rleft^k Rbase
+   Rright^k (same-generation when l = up and r = down; a multilinear extension the paper names as
+   future work).  Semi-naive rounds; stats->iterations is the number of rounds.  Rbase, Rleft, Rright,
+   P: n x n (ld); P must not overlap the others.  With Rright = I this is compose_linear(Rbase, Rleft);
+   with Rleft = I it is Rbase x Rright*. */
+bmlp_status bmlp_compose_two_sided(bmlp_handle h, const uint64_t *Rbase, const uint64_t *Rleft,
+                                   const uint64_t *Rright, uint64_t *P, int64_t n, int64_t ld,
+                                   const bmlp_opts *opts, void *stream, bmlp_stats *stats);
 
 /* Closure under insertions: Rplus (n x n, ld) holds T = R1+ of some relation R1 on entry (the caller's
    promise; it is not checked) and (R1 | E)+ on return, where E is the b edges (src[i], dst[i]).

@@ -6,6 +6,9 @@ code with the HIP library and never imports it.
 
 Contents
 --------
+* ``two_sided_rows``: the least P = B | L P R (a linear program with a
+  relation on each side of its recursive atom) by Kleene iteration from B,
+  each step two dense numpy products of 0/1 matrices; n up to a few thousand.
 * ``closure_rows``, ``smp``, ``compose_rows``, ``warshall``: the C oracle
   (``bmlp_oracle.c``): per-source breadth-first search, i.e. the plain
   definition of the transitive closure R1+ (Eq. 1), of the selection v R1+
@@ -182,3 +185,30 @@ def _bits_pairs(bits, n):
     dense = np.unpackbits(np.ascontiguousarray(bits).view(np.uint8), axis=1, bitorder="little")[:, :n]
     r, c = np.nonzero(dense)
     return r.astype(np.int32), c.astype(np.int32)
+
+
+def two_sided_rows(n, base, left, right, ld=None, max_rounds=None):
+    """Bit rows of the least P with P = B | L . P . R, by iterating P <- B | L . P . R from P = B until
+    nothing changes (the operator is monotone, so this reaches the least fixpoint).  base, left,
+    right: (src, dst) pairs.  Dense float32 products of 0/1 matrices, each thresholded at > 0 (the
+    counts stay below n <= 2**24, so they are exact)."""
+    def dense(pairs):
+        s, d = _edges(*pairs)
+        a = np.zeros((n, n), np.float32)
+        a[s, d] = 1.0
+        return a
+    B, L, R = dense(base), dense(left), dense(right)
+    P = B.copy()
+    rounds = 0
+    while True:
+        nxt = np.maximum(B, (((L @ P) > 0).astype(np.float32) @ R > 0).astype(np.float32))
+        rounds += 1
+        if np.array_equal(nxt, P):
+            break
+        P = nxt
+        if max_rounds is not None and rounds > max_rounds:
+            raise RuntimeError("two-sided oracle did not converge")
+    ld = ld or max(words(n), 1)
+    bits = np.zeros((n, ld * 64), np.uint8)
+    bits[:, :n] = P > 0
+    return np.packbits(bits, axis=1, bitorder="little").view(np.uint64)

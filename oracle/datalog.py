@@ -12,6 +12,9 @@ without matrices, so they pin the matrix formulations from outside:
 * ``is_foreign`` evaluates P3 u P4 u P5 of Section 3.4 stratum by stratum:
   hasPlace, then indirectlyPartOf, then isForeign with negation against the
   finished lower stratum.
+* ``two_sided`` evaluates  p(X,Y) <- b(X,Y).  p(X,Y) <- l(X,X1), p(X1,Y1), r(Y1,Y).
+  (same-generation when l = up and r = down), a linear program whose
+  recursive atom has a relation on each side.
 """
 from __future__ import annotations
 
@@ -51,3 +54,25 @@ def is_foreign(constants, contains, adjoins, location=None):
     ipo = linear(base, step)
     foreign = {(x, y) for x in location for y in location if (x, y) not in ipo}
     return has_place, ipo, foreign
+
+
+def two_sided(base, left, right):
+    """Least model of p <- b; p <- l, p, r (sets of (x, y) pairs), semi-naive."""
+    pre = {}
+    for (x, x1) in left:
+        pre.setdefault(x1, []).append(x)
+    post = {}
+    for (y1, y) in right:
+        post.setdefault(y1, []).append(y)
+    p = set(base)
+    delta = set(base)
+    while delta:
+        new = set()
+        for (x1, y1) in delta:
+            for x in pre.get(x1, ()):
+                for y in post.get(y1, ()):
+                    if (x, y) not in p:
+                        new.add((x, y))
+        p |= new
+        delta = new
+    return p

@@ -36,7 +36,7 @@ EXPORTS = [
     "bmlp_create", "bmlp_destroy", "bmlp_last_error", "bmlp_opts_init", "bmlp_version",
     "bmlp_pack_u8", "bmlp_pack_coo", "bmlp_unpack_u8",
     "bmlp_or", "bmlp_and", "bmlp_andnot", "bmlp_not", "bmlp_transpose", "bmlp_product",
-    "bmlp_rms", "bmlp_smp", "bmlp_compose_linear", "bmlp_closure_insert", "bmlp_batched",
+    "bmlp_rms", "bmlp_smp", "bmlp_compose_linear", "bmlp_compose_two_sided", "bmlp_closure_insert", "bmlp_batched",
     "bmlp_graph_open", "bmlp_graph_query", "bmlp_graph_has_closure", "bmlp_graph_close",
     "bmlp_set_trace", "bmlp_dispatcher_load", "bmlp_dispatcher_save", "bmlp_dispatcher_loaded",
     "bmlp_dispatcher_train", "bmlp_dispatcher_forward", "bmlp_mlp_loss_grad",
@@ -131,6 +131,7 @@ def lib():
     L.bmlp_rms.argtypes = [vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_smp.argtypes = [vp, vp, i64, i64, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_compose_linear.argtypes = [vp, vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
+    L.bmlp_compose_two_sided.argtypes = [vp, vp, vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_closure_insert.argtypes = [vp, vp, i64, i64, vp, vp, i64, P(Opts), vp, P(Stats)]
     L.bmlp_batched.argtypes = [vp, P(GraphDesc), ctypes.c_int32, P(Opts), vp, P(Stats)]
     fp = ctypes.POINTER(ctypes.c_float)
@@ -336,6 +337,21 @@ class Context:
         _check(lib().bmlp_compose_linear(self._h, _ptr(Rbase), _ptr(Rstep), _ptr(out), n, ld,
                                          ctypes.byref(opts) if opts is not None else None, _stream(stream),
                                          ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return out
+
+    def compose_two_sided(self, Rbase, Rleft, Rright, n: int, out=None, opts=None, stream=None, stats=None):
+        """Least P = Rbase | Rleft . P . Rright (p <- b; p <- l, p, r)."""
+        _, ld = _bits_shape(Rbase, n)
+        _bits_shape(Rleft, n)
+        _bits_shape(Rright, n)
+        if out is None:
+            out = self.zeros(n, n, ld)
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_compose_two_sided(self._h, _ptr(Rbase), _ptr(Rleft), _ptr(Rright), _ptr(out), n, ld,
+                                            ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                            ctypes.byref(st) if st is not None else None))
         if st is not None:
             stats.update(st.as_dict())
         return out

@@ -1028,6 +1028,80 @@ bmlp_status bmlp_closure_insert(bmlp_handle h, uint64_t* Rplus, int64_t n, int64
   });
 }
 
+// Two-sided linear recursion p(X,Y) <- b(X,Y).  p(X,Y) <- l(X,X1), p(X1,Y1), r(Y1,Y): the least P with
+// P = B | L . P . R, i.e. P = OR over k of L^k . B . R^k (same-generation when l = up, r = down; one
+// of the multilinear programs the paper names as future work).  Unlike P = Rs* . Rb it has no closure
+// form, so it runs semi-naive rounds: W = D . R, then P |= L . W with D the new bits.  Each of the
+// two products is done by row gathers while its left operand is sparse (the rule of the RMS
+// squarings), else by the product kernel, which also yields the new bits.
+bmlp_status bmlp_compose_two_sided(bmlp_handle h, const uint64_t* Rbase, const uint64_t* Rleft, const uint64_t* Rright,
+                                   uint64_t* P, int64_t n, int64_t ld, const bmlp_opts* opts, void* stream,
+                                   bmlp_stats* stats) {
+  return guarded([&] {
+    need_handle(h);
+    const bmlp_opts o = opts_or_default(opts);
+    check_bits_arg(Rbase, "Rbase", n, n, ld);
+    check_bits_arg(Rleft, "Rleft", n, n, ld);
+    check_bits_arg(Rright, "Rright", n, n, ld);
+    check_bits_arg(P, "P", n, n, ld);
+    const Range rp = range_of(P, n, ld);
+    need(!overlap(rp, range_of(Rbase, n, ld)), BMLP_EALIAS, "P overlaps Rbase");
+    need(!overlap(rp, range_of(Rleft, n, ld)), BMLP_EALIAS, "P overlaps Rleft");
+    need(!overlap(rp, range_of(Rright, n, ld)), BMLP_EALIAS, "P overlaps Rright");
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (o.check_padding) {
+      check_padding(h, Rbase, n, n, ld, s, "Rbase");
+      check_padding(h, Rleft, n, n, ld, s, "Rleft");
+      check_padding(h, Rright, n, n, ld, s, "Rright");
+    }
+    StatsRec sr(stats, h, s, &o);
+    int rounds = 0;
+    if (n > 0) {
+      const i64 nw = words_for(n);
+      const int arm = product_arm(o, n, n, n);
+      const bool may_gather = o.product_arm == BMLP_ARM_AUTO && n <= gather_rows_max_n();
+      u64* dl = ws_bits(h, S_T0, n, nw, o);   // the new bits of the last round
+      u64* wm = ws_bits(h, S_T1, n, nw, o);   // D . R
+      u64* aux = ws_bits(h, S_T2, n, nw, o);  // P before the round (gathers) or the next D (products)
+      hip_check(launch_ewise(4, Rbase, ld, nullptr, 0, P, ld, n, n, s), "copy");
+      hip_check(launch_ewise(4, Rbase, ld, nullptr, 0, dl, nw, n, n, s), "copy");
+      i64 dbits = count_bits(h, dl, n, n, nw, s);
+      const i64 lbits = may_gather ? count_bits(h, Rleft, n, n, ld, s) : 0;
+      unsigned long long* nb = (unsigned long long*)(h->d_flags + F_NEW);
+      const i64 cap = n * n + 1;  // every round but the last adds a fact
+      while (dbits > 0) {
+        need(rounds < cap, BMLP_EITER, "two-sided recursion exceeded %lld rounds", (long long)cap);
+        hip_check(hipMemsetAsync(h->d_flags, 0, 8 * sizeof(u32), s), "hipMemsetAsync");
+        // W = D . R
+        if (may_gather && rms_gather_pays(n, dbits, arm))
+          hip_check(launch_gather_rows(dl, nw, n, Rright, ld, n, 0, wm, nw, s), "gather_rows");
+        else
+          product(h, dl, nw, Rright, ld, nullptr, 0, wm, nw, nullptr, 0, n, n, n, nullptr, arm, s, sr);
+        // P |= L . W, D = the bits new to P
+        if (may_gather && rms_gather_pays(n, lbits, arm)) {
+          hip_check(launch_ewise(4, P, ld, nullptr, 0, aux, nw, n, n, s), "copy");
+          hip_check(launch_gather_rows(Rleft, ld, n, wm, nw, n, 2, P, ld, s, nullptr, nb), "gather_rows");
+          hip_check(launch_ewise(2, P, ld, aux, nw, dl, nw, n, n, s), "andnot");
+        } else {
+          product(h, Rleft, ld, wm, nw, P, ld, P, ld, aux, nw, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb);
+          std::swap(dl, aux);
+        }
+        if (sr.st) sr.st->bool_ops += (uint64_t)4 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
+        hip_check(hipMemcpyAsync(h->h_flags, h->d_flags, 8 * sizeof(u32), hipMemcpyDeviceToHost, s), "memcpy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        unsigned long long added = 0;
+        std::memcpy(&added, h->h_flags + F_NEW, sizeof added);
+        dbits = (i64)added;
+        ++rounds;
+      }
+      hip_check(launch_zero_pad(P, n, n, ld, s), "zero_pad");
+    }
+    if (sr.st) sr.st->iterations = rounds;
+    sr.finish();
+  });
+}
+
 bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint64_t* Rstep, uint64_t* P, int64_t n,
                                 int64_t ld, const bmlp_opts* opts, void* stream, bmlp_stats* stats) {
   return guarded([&] {

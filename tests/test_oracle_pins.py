@@ -125,6 +125,60 @@ def test_isforeign_bit_pipeline_matches_clauses(seed, all_locations):
     assert boolops.to_bits(boolops.from_bits(fr, n), ld=fr.shape[1]).tolist() == fr.tolist()
 
 
+def _pairs(A):
+    s, d = np.nonzero(A)
+    return s.astype(np.int32), d.astype(np.int32)
+
+
+def _bitset(bits, n):
+    return {(int(i), int(j)) for i, j in zip(*np.nonzero(boolops.from_bits(bits, n)))}
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_two_sided_oracle_against_clauses(seed):
+    """The Kleene iteration of P = B | L P R against the clause-by-clause evaluator."""
+    rng = np.random.default_rng(400 + seed)
+    n = int(rng.integers(1, 30))
+    b, l, r = (_pairs(rng.random((n, n)) < q) for q in (0.08, 0.12, 0.12))
+    want = datalog.two_sided(set(zip(*b)), set(zip(*l)), set(zip(*r)))
+    assert _bitset(oracle.two_sided_rows(n, b, l, r), n) == want
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_two_sided_reduces_to_one_sided(seed):
+    """With R = I the program is p <- b; p <- l, p, whose least model is L* B (the composition
+    oracle); with L = I it is B R*, the transpose of the composition over the transposes."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(2, 70))
+    B = rng.random((n, n)) < 0.05
+    S = rng.random((n, n)) < 0.04
+    eye = _pairs(np.eye(n, dtype=bool))
+    got = oracle.two_sided_rows(n, _pairs(B), _pairs(S), eye)
+    assert np.array_equal(got, oracle.compose_rows(n, *_pairs(B), *_pairs(S)))
+    got = oracle.two_sided_rows(n, _pairs(B), eye, _pairs(S))
+    want_t = boolops.from_bits(oracle.compose_rows(n, *_pairs(B.T), *_pairs(S.T)), n)
+    assert np.array_equal(boolops.from_bits(got, n), want_t.T)
+    # no left or right relation: P is B
+    none = (np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert np.array_equal(oracle.two_sided_rows(n, _pairs(B), none, _pairs(S)), boolops.to_bits(B.astype(np.uint8)))
+
+
+def test_same_generation_closed_form():
+    """Same-generation on a forest: flat holds on each root, up maps a node to its parent, down is its
+    inverse.  Then sg(x, y) holds exactly when x and y lie in the same tree at the same depth."""
+    import gen
+    g = gen.forest(n=300, trees=4, seed=3)
+    n = g.n
+    depth, root = g.depth, g.root
+    want = {(x, y) for x in range(n) for y in range(n) if depth[x] == depth[y] and root[x] == root[y]}
+    roots = np.unique(root)
+    flat = (roots.astype(np.int32), roots.astype(np.int32))
+    up = (g.child, g.parent)
+    down = (g.parent, g.child)
+    assert _bitset(oracle.two_sided_rows(n, flat, up, down), n) == want
+    assert datalog.two_sided(set(zip(*flat)), set(zip(*up)), set(zip(*down))) == want
+
+
 # ---------------------------------------------------------------- closed forms
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 63, 64, 65, 130])
 def test_closed_forms(n):
