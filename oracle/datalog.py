@@ -12,6 +12,8 @@ without matrices, so they pin the matrix formulations from outside:
 * ``is_foreign`` evaluates P3 u P4 u P5 of Section 3.4 stratum by stratum:
   hasPlace, then indirectlyPartOf, then isForeign with negation against the
   finished lower stratum.
+* ``quadratic_closure`` evaluates the non-linear transitive closure
+  p(X,Y) <- e(X,Y).  p(X,Y) <- p(X,Z), p(Z,Y).  (two recursive atoms).
 * ``two_sided`` evaluates  p(X,Y) <- b(X,Y).  p(X,Y) <- l(X,X1), p(X1,Y1), r(Y1,Y).
   (same-generation when l = up and r = down), a linear program whose
   recursive atom has a relation on each side.
@@ -73,6 +75,29 @@ def two_sided(base, left, right):
                 for y in post.get(y1, ()):
                     if (x, y) not in p:
                         new.add((x, y))
+        p |= new
+        delta = new
+    return p
+
+
+def quadratic_closure(edges):
+    """Least model of p <- e; p <- p, p (non-linear transitive closure), semi-naive: a new fact is
+    joined with every known fact on either side."""
+    p = set(edges)
+    delta = set(edges)
+    while delta:
+        succ, pred = {}, {}
+        for (x, y) in p:
+            succ.setdefault(x, set()).add(y)
+            pred.setdefault(y, set()).add(x)
+        new = set()
+        for (x, z) in delta:
+            for y in succ.get(z, ()):
+                if (x, y) not in p:
+                    new.add((x, y))
+            for w in pred.get(x, ()):
+                if (w, z) not in p:
+                    new.add((w, z))
         p |= new
         delta = new
     return p

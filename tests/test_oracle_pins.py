@@ -179,6 +179,21 @@ def test_same_generation_closed_form():
     assert datalog.two_sided(set(zip(*flat)), set(zip(*up)), set(zip(*down))) == want
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_quadratic_closure_is_the_squaring_closure(seed):
+    """The non-linear program p <- e; p <- p, p has the same least model as the linear P2, and it is
+    what the squaring R <- R | R.R computes: the clause evaluator, the linear evaluator, the oracle's
+    BFS closure and Algorithm 1's squaring all agree."""
+    rng = np.random.default_rng(600 + seed)
+    n = int(rng.integers(1, 24))
+    A = (rng.random((n, n)) < 0.1).astype(np.uint8)
+    e = set(zip(*[x.tolist() for x in np.nonzero(A)]))
+    q = datalog.quadratic_closure(e)
+    assert q == datalog.closure(e)
+    assert q == {(int(i), int(j)) for i, j in zip(*np.nonzero(dense_closure(n, *np.nonzero(A))))}
+    assert q == {(int(i), int(j)) for i, j in zip(*np.nonzero(algorithms.rms_squaring_or(A)[0]))}
+
+
 # ---------------------------------------------------------------- closed forms
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 63, 64, 65, 130])
 def test_closed_forms(n):
