@@ -67,9 +67,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
                     help="bound the oracle's closure rows per graph (0: all rows)")
-    ap.add_argument("--workloads", default="batch,programs,stream,isforeign,dynamic,samegen",
+    ap.add_argument("--workloads", default="batch,programs,stream,isforeign,dynamic,samegen,io",
                     help="held-out workloads measured after the main one, plain vs learned schedule "
-                         "(comma list of batch, programs, stream, isforeign, dynamic, samegen; empty for none)")
+                         "(comma list of batch, programs, stream, isforeign, dynamic, samegen, io; empty for none)")
     ap.add_argument("--stream-queries", type=int, default=10000,
                     help="queries of the n=65,536 stream to run (a prefix of the 10,000)")
     ap.add_argument("--workloads-only", action="store_true",
@@ -219,7 +219,7 @@ def run_workloads(ctx, args):
     res = {}
     for name in [w for w in args.workloads.split(",") if w]:
         fn = {"batch": wl_batch, "programs": wl_programs, "stream": wl_stream, "isforeign": wl_isforeign,
-              "dynamic": wl_dynamic, "samegen": wl_samegen}[name]
+              "dynamic": wl_dynamic, "samegen": wl_samegen, "io": wl_io}[name]
         res[name] = fn(ctx, args)
         print(json.dumps({"workload_done": name}), file=sys.stderr, flush=True)
     return res
@@ -541,6 +541,45 @@ def wl_samegen(ctx, args):
     facts = int(np.unpackbits(out.cpu().numpy().view(np.uint8)).sum())
     return {"workload": "same-generation on a random forest, n=16,384 nodes, 8 trees, depth %d" % int(f.depth.max()),
             "by_mode": res, "derived_facts": facts, "bit_identical": len(set(fp.values())) == 1}
+
+
+def wl_io(ctx, args):
+    """Facts in and out at device speed: packing the densest sweep graph's 2,686,179 edge pairs into an
+    n = 16,384 bit matrix, and decoding the isForeign relation of the knowledge-graph program (211 M
+    facts) into sorted (row, column) int32 pairs."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2408_10369_amd.programs import is_foreign
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return sorted(ts)[len(ts) // 2]
+
+    n, s, d = gen.c2(4)
+    S, D = torch.as_tensor(s).cuda(), torch.as_tensor(d).cuda()
+    R = ctx.zeros(n, n)
+    pack_ms = timed(lambda: ctx.pack_coo(S, D, n, n, out=R))
+    g = gen.geo()
+    facts = [torch.as_tensor(a).cuda() for a in (g.contains_src, g.contains_dst, g.adjoins_src, g.adjoins_dst)]
+    loc = torch.arange(g.n, dtype=torch.int32, device="cuda")
+    _, _, foreign = is_foreign(ctx, g.n, (facts[0], facts[1]), (facts[2], facts[3]), loc)
+    out = {}
+    unpack_ms = timed(lambda: out.__setitem__("rc", ctx.unpack_coo(foreign, g.n)), reps=3)
+    m = int(out["rc"][0].numel())
+    return {"workload": "pack 2,686,179 edges into a 16,384 x 16,384 bit matrix; decode the 14,541 x 14,541 "
+                        "isForeign relation into sorted int32 (row, column) pairs",
+            "pack": {"ms": round(pack_ms, 3), "facts": len(s), "facts_per_s": round(len(s) / (pack_ms / 1e3), 1)},
+            "unpack": {"ms": round(unpack_ms, 3), "facts": m, "facts_per_s": round(m / (unpack_ms / 1e3), 1),
+                       "output_GB_per_s": round(8 * m / (unpack_ms / 1e3) / 1e9, 1)}}
 
 
 def cpu_baseline_isforeign(g):

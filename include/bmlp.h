@@ -147,6 +147,14 @@ bmlp_status bmlp_pack_u8(bmlp_handle h, const uint8_t *dense, int64_t rows, int6
    An index outside [0,rows) x [0,n) gives BMLP_EINVAL.  Synchronises the stream (error check). */
 bmlp_status bmlp_pack_coo(bmlp_handle h, const int32_t *row, const int32_t *col, int64_t m, int64_t rows,
                           int64_t n, uint64_t *bits, int64_t ld, void *stream);
+/* Facts from a bit matrix (decoding, the inverse of bmlp_pack_coo): the set bits of `bits` (rows x n,
+   ld) as (row, column) pairs, sorted by row and then column, written to the DEVICE int32 arrays row_out
+   and col_out (either may be NULL) of capacity `cap` entries.  *count (HOST) receives the number of
+   set bits.  With both outputs NULL only the count is computed (the usual first call); with
+   cap < *count nothing is written and BMLP_EINVAL is returned.  Section 3.2 (each matrix row
+   encodes the facts r(c_i, c_j) of its set bits). */
+bmlp_status bmlp_unpack_coo(bmlp_handle h, const uint64_t *bits, int64_t rows, int64_t n, int64_t ld,
+                            int32_t *row_out, int32_t *col_out, int64_t cap, int64_t *count, void *stream);
 /* dense (rows x n bytes, stride ldd) := bits; the decoding of a matrix back into facts. */
 bmlp_status bmlp_unpack_u8(bmlp_handle h, const uint64_t *bits, int64_t rows, int64_t n, int64_t ld,
                            uint8_t *dense, int64_t ldd, void *stream);

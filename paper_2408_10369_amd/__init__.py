@@ -34,7 +34,7 @@ N_FEATURES, N_OUTPUTS, N_PARAMS = 16, 4, 5508
 
 EXPORTS = [
     "bmlp_create", "bmlp_destroy", "bmlp_last_error", "bmlp_opts_init", "bmlp_version",
-    "bmlp_pack_u8", "bmlp_pack_coo", "bmlp_unpack_u8",
+    "bmlp_pack_u8", "bmlp_pack_coo", "bmlp_unpack_coo", "bmlp_unpack_u8",
     "bmlp_or", "bmlp_and", "bmlp_andnot", "bmlp_not", "bmlp_transpose", "bmlp_product",
     "bmlp_rms", "bmlp_smp", "bmlp_compose_linear", "bmlp_compose_two_sided", "bmlp_closure_insert", "bmlp_batched",
     "bmlp_graph_open", "bmlp_graph_query", "bmlp_graph_has_closure", "bmlp_graph_close",
@@ -123,6 +123,7 @@ def lib():
     L.bmlp_pack_u8.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
     L.bmlp_pack_coo.argtypes = [vp, vp, vp, i64, i64, i64, vp, i64, vp]
     L.bmlp_unpack_u8.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
+    L.bmlp_unpack_coo.argtypes = [vp, vp, i64, i64, i64, vp, vp, i64, P(ctypes.c_int64), vp]
     for f in (L.bmlp_or, L.bmlp_and, L.bmlp_andnot):
         f.argtypes = [vp, vp, vp, vp, i64, i64, i64, vp]
     L.bmlp_not.argtypes = [vp, vp, vp, i64, i64, i64, vp]
@@ -250,6 +251,22 @@ class Context:
         _check(lib().bmlp_pack_u8(self._h, _ptr(dense), rows, n, dense.stride(0), _ptr(out), out.shape[1],
                                   _stream(stream)))
         return out
+
+    def unpack_coo(self, bits, n: int, stream=None):
+        """(row, col) int32 device tensors of the set bits, sorted by row then column."""
+        import torch
+        rows, ld = _bits_shape(bits)
+        cnt = ctypes.c_int64(0)
+        _check(lib().bmlp_unpack_coo(self._h, _ptr(bits), rows, n, ld, None, None, 0, ctypes.byref(cnt),
+                                     _stream(stream)))
+        m = int(cnt.value)
+        dev = f"cuda:{self.device}"
+        r = torch.empty(m, dtype=torch.int32, device=dev)
+        c = torch.empty(m, dtype=torch.int32, device=dev)
+        if m:
+            _check(lib().bmlp_unpack_coo(self._h, _ptr(bits), rows, n, ld, _ptr(r), _ptr(c), m, ctypes.byref(cnt),
+                                         _stream(stream)))
+        return r, c
 
     def unpack_u8(self, bits, n: int, stream=None):
         import torch

@@ -792,6 +792,37 @@ bmlp_status bmlp_pack_coo(bmlp_handle h, const int32_t* row, const int32_t* col,
   });
 }
 
+bmlp_status bmlp_unpack_coo(bmlp_handle h, const uint64_t* bits, int64_t rows, int64_t n, int64_t ld,
+                            int32_t* row_out, int32_t* col_out, int64_t cap, int64_t* count, void* stream) {
+  return guarded([&] {
+    need_handle(h);
+    check_bits_arg(bits, "bits", rows, n, ld);
+    need(count != nullptr, BMLP_EINVAL, "count: null pointer");
+    need(cap >= 0, BMLP_EINVAL, "cap < 0");
+    need(((uintptr_t)row_out & 3u) == 0 && ((uintptr_t)col_out & 3u) == 0, BMLP_EALIGN,
+         "row_out/col_out: not 4-byte aligned");
+    *count = 0;
+    if (rows == 0 || n == 0) return;
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    bmlp_opts o;
+    bmlp_opts_init(&o);
+    int32_t* deg = (int32_t*)ws(h, S_DEG, (size_t)rows * sizeof(int32_t), o);
+    i64* rp = (i64*)ws(h, S_RP, (size_t)(rows + 1) * sizeof(i64), o);
+    hip_check(launch_row_popcount(bits, rows, n, ld, deg, nullptr, s), "row_popcount");
+    hip_check(launch_scan_rowptr(deg, rows, rp, s), "scan");
+    hip_check(hipMemcpyAsync(h->h_flags + 4, rp + rows, sizeof(i64), hipMemcpyDeviceToHost, s), "memcpy");
+    hip_check(hipStreamSynchronize(s), "sync");
+    i64 m = 0;
+    std::memcpy(&m, h->h_flags + 4, sizeof m);
+    *count = m;
+    if (!row_out && !col_out) return;  // the count only
+    need(cap >= m, BMLP_EINVAL, "unpack_coo: %lld facts do not fit in cap = %lld", (long long)m, (long long)cap);
+    if (col_out) hip_check(launch_bits_to_csr(bits, rows, n, ld, rp, col_out, s), "bits_to_csr");
+    if (row_out) hip_check(launch_rows_from_rp(rp, rows, row_out, s), "rows_from_rp");
+  });
+}
+
 bmlp_status bmlp_unpack_u8(bmlp_handle h, const uint64_t* bits, int64_t rows, int64_t n, int64_t ld, uint8_t* dense,
                            int64_t ldd, void* stream) {
   return guarded([&] {

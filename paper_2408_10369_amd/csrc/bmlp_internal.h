@@ -32,6 +32,8 @@ hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s);
 // row i of a gets bit idx[i] (0 <= idx[i] < columns; rows zeroed beforehand)
 hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s);
 hipError_t launch_check_index(const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s);
+// out[rp[r] .. rp[r+1]) = r for r < rows
+hipError_t launch_rows_from_rp(const i64* rp, i64 rows, int32_t* out, hipStream_t s);
 // out = I | M+ for b <= 64 (M, out: b rows of one significant word)
 hipError_t launch_closure64(const u64* M, i64 ldm, i64 b, u64* out, i64 ldo, hipStream_t s);
 // A[x][i] = T[x][cols[i]] (| (cols[i] == x) when diag) for rows x < rows of T (n columns); n <= gather_cols_max_n()

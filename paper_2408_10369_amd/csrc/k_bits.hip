@@ -118,6 +118,15 @@ __global__ void k_set_onehot(u64* __restrict__ a, i64 ld, const int32_t* __restr
   }
 }
 
+// row index of every entry of a CSR layout: out[rp[r] .. rp[r+1]) = r, one wave per row
+__global__ void k_rows_from_rp(const i64* __restrict__ rp, i64 rows, int32_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 r = wave; r < rows; r += nwaves)
+    for (i64 e = rp[r] + lane; e < rp[r + 1]; e += 64) out[e] = (int32_t)r;
+}
+
 // raises *bad when an index lies outside [0, n)
 __global__ void k_check_index(const int32_t* __restrict__ idx, i64 k, i64 n, u32* __restrict__ bad) {
   for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < k; i += (i64)gridDim.x * blockDim.x) {
@@ -506,6 +515,12 @@ hipError_t launch_closure64(const u64* M, i64 ldm, i64 b, u64* out, i64 ldo, hip
   if (b <= 0) return hipSuccess;
   if (b > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_closure64, dim3(1), dim3(64), 0, s, M, ldm, b, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_from_rp(const i64* rp, i64 rows, int32_t* out, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_from_rp, dim3(grid_for(rows * 64, kBlock, 16384)), dim3(kBlock), 0, s, rp, rows, out);
   return hipGetLastError();
 }
 
