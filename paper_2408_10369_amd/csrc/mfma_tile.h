@@ -60,6 +60,7 @@ struct MfmaLds {
   uint4 Bx[2][2][kMT][kMChunk];
   u64 bal[8][2][16];
   u32 zmask[2][4];  // per stage and A-staging wave: bit q = some row has a nonzero word q
+  u32 satf[2][8];   // per vote (alternating) and wave: every output of the wave's 128 x 64 block is set
 };
 
 struct MfmaTile {
@@ -96,6 +97,7 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
   auto& Bx = L.Bx;
   auto& bal = L.bal;
   auto& zmask = L.zmask;
+  auto& satf = L.satf;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
@@ -203,9 +205,22 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
       }
     }
   };
-  // sn holds chunk c + 1 on entry; on exit it holds (the loads of) chunk c + 3
-  auto step = [&](u64 (&sn)[kMChunk], i64 c) {
+  // Saturation: the sums only grow, so once every accumulator of a wave is positive its 128 x 64 outputs
+  // are final (all ones), and the wave stops issuing matrix-core work.  The waves vote now and then (see
+  // the loop); a vote is read after the next barrier, and once all eight waves are saturated the
+  // workgroup leaves the loop (only whole tiles vote: rows or columns past the matrix never fill).
+  const bool whole = row0 + kMT <= M && col0 + kMT <= N;
+  bool wsat = false;  // wave-uniform
+  // sn holds chunk c + 1 on entry; on exit it holds (the loads of) chunk c + 3.  Returns whether every
+  // wave of the workgroup reported saturation in the last vote (the same answer in every thread).
+  auto step = [&](u64 (&sn)[kMChunk], i64 c, int vote) -> bool {
     __syncthreads();
+    if (vote >= 0) {
+      u32 all = 1u;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) all &= satf[vote][w];
+      if (all) return true;
+    }
     const int buf = (int)(c & 1);
     // the first word's operands and the skip mask of chunk c are read before the staging of chunk c + 1,
     // so that their LDS latency overlaps it
@@ -215,20 +230,41 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
 #pragma unroll
     for (int j = 0; j < 2; ++j) bv[j] = Bx[buf][h][wc * 64 + l32 + 32 * j][0 ^ csw];
     // rows of this wave with a nonzero word q of k (wave-uniform)
-    const u32 mask = __builtin_amdgcn_readfirstlane(zmask[buf][2 * wr] | zmask[buf][2 * wr + 1]);
+    const u32 mask = wsat ? 0u : __builtin_amdgcn_readfirstlane(zmask[buf][2 * wr] | zmask[buf][2 * wr + 1]);
     if (c + 1 < nchunks) {
       stage(sn, buf ^ 1);
       if (c + 3 < nchunks) load(sn, c + 3);
     }
     compute(buf, av, bv, mask);
+    return false;
   };
   load(s0, 0);
   load(s1, 1);
   stage(s0, 0);
   if (2 < nchunks) load(s0, 2);
-  for (i64 c = 0; c < nchunks; c += 2) {
-    step(s1, c);
-    if (c + 1 < nchunks) step(s0, c + 1);
+  int pending = -1;  // vote slot to read after the next barrier
+  int votes = 0;
+  for (i64 c = 0, it = 0; c < nchunks; c += 2, ++it) {
+    if (step(s1, c, pending)) break;
+    pending = -1;
+    if (c + 1 < nchunks) step(s0, c + 1, -1);
+    // votes after 2, 4, 8, 16, ... chunks: a product that saturates does so early, and one that does not
+    // pays for a handful of checks only
+    if (whole && ((it + 1) & it) == 0) {
+      if (!wsat) {
+        float mn = acc[0][0][0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) mn = fminf(mn, acc[i][j][e]);
+        wsat = __ballot(!(mn > 0.f)) == 0ull;
+      }
+      pending = votes & 1;
+      if (lane == 0) satf[pending][wave] = wsat ? 1u : 0u;
+      ++votes;
+    }
   }
 
   // epilogue: a 32 x 32 fp32 block sits in lane l as column l % 32, register r holding row
