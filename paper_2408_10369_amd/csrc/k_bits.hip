@@ -324,16 +324,51 @@ __global__ void k_row_popcount(const u64* __restrict__ a, i64 rows, i64 n, i64 l
   }
 }
 
-// total number of set bits: one wave per row, one atomic per workgroup
+// Set bits of four rows r0 + k stride (k < 4; rows past the matrix count 0), summed over the wave: all
+// 16 loads of a lane are in flight together.
+__device__ __forceinline__ void wave_rows_bits4(const u64* __restrict__ a, i64 ld, i64 nw, i64 rows, i64 r0,
+                                                i64 stride, int lane, u32 (&c)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c[k] = 0;
+  for (i64 w0 = 0; w0 < nw; w0 += 256) {
+    u64 v[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const i64 r = r0 + k * stride, rc = r < rows ? r : rows - 1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const i64 w = w0 + lane + 64 * j;
+        v[k][j] = a[rc * ld + (w < nw ? w : nw - 1)];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (r0 + k * stride < rows && w0 + lane + 64 * j < nw) c[k] += (u32)__popcll(v[k][j]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c[k] = (u32)wave_reduce_add((int)c[k]);
+}
+
+// The two reductions below end in a few global atomics per workgroup on one address each; those
+// serialize, so they run on few workgroups (kStatBlocks) whose waves read four rows at a time.
+constexpr int kStatBlocks = 256;
+
+// total number of set bits
 __global__ void k_popcount_total(const u64* __restrict__ a, i64 rows, i64 nw, i64 ld,
                                  unsigned long long* __restrict__ total) {
   __shared__ unsigned long long part[4];
   const int lane = threadIdx.x & 63;
   const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
   const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
-  unsigned long long c = 0;
-  for (i64 row = wave; row < rows; row += nwaves) c += wave_row_bits(a + row * ld, nw, lane);
-  if (lane == 0) part[threadIdx.x >> 6] = c;
+  unsigned long long tot = 0;
+  for (i64 r0 = wave; r0 < rows; r0 += 4 * nwaves) {
+    u32 c[4];
+    wave_rows_bits4(a, ld, nw, rows, r0, nwaves, lane, c);
+    tot += (unsigned long long)c[0] + c[1] + c[2] + c[3];
+  }
+  if (lane == 0) part[threadIdx.x >> 6] = tot;
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned long long t = part[0] + part[1] + part[2] + part[3];
@@ -341,19 +376,22 @@ __global__ void k_popcount_total(const u64* __restrict__ a, i64 rows, i64 nw, i6
   }
 }
 
-// degree statistics of a relation: total, largest row, nonempty rows (one wave
-// per row, one set of atomics per workgroup)
+// degree statistics of a relation: total, largest row, nonempty rows
 __global__ void k_graph_stats(const u64* __restrict__ a, i64 rows, i64 nw, i64 ld, unsigned long long* __restrict__ out) {
   __shared__ unsigned long long s_tot[4], s_max[4], s_ne[4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
   const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
   unsigned long long tot = 0, mx = 0, ne = 0;
-  for (i64 row = wave; row < rows; row += nwaves) {
-    const unsigned long long c = wave_row_bits(a + row * ld, nw, lane);
-    tot += c;
-    mx = c > mx ? c : mx;
-    ne += c ? 1u : 0u;
+  for (i64 r0 = wave; r0 < rows; r0 += 4 * nwaves) {
+    u32 c[4];
+    wave_rows_bits4(a, ld, nw, rows, r0, nwaves, lane, c);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      tot += c[k];
+      mx = c[k] > mx ? c[k] : mx;
+      ne += c[k] ? 1u : 0u;
+    }
   }
   if (lane == 0) {
     s_tot[wv] = tot;
@@ -573,14 +611,14 @@ hipError_t launch_row_popcount(const u64* a, i64 rows, i64 n, i64 ld, int32_t* d
 
 hipError_t launch_popcount_total(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* total, hipStream_t s) {
   if (rows <= 0 || n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_popcount_total, dim3(grid_for(rows * 64, kBlock, 2048)), dim3(kBlock), 0, s, a, rows,
+  hipLaunchKernelGGL(k_popcount_total, dim3(grid_for(rows * 64, kBlock, kStatBlocks)), dim3(kBlock), 0, s, a, rows,
                      words_for(n), ld, total);
   return hipGetLastError();
 }
 
 hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* out, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(rows * 64, kBlock, 1024)), dim3(kBlock), 0, s, a, rows,
+  hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(rows * 64, kBlock, kStatBlocks)), dim3(kBlock), 0, s, a, rows,
                      words_for(n), ld, out);
   return hipGetLastError();
 }
