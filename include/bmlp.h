@@ -85,8 +85,11 @@ typedef enum {
   BMLP_ARM_SMP_ADAPTIVE = 8,  /* selection by rounds, each round's kernel chosen on the device by the model */
   BMLP_ARM_COMPOSE_ROWWISE = 9, /* compose: P[X] = Rb[X] | OR of Rb[Z] over Z in e_X Rs+, only for rows X with
                                   a step edge (selections over Rs, rows of Rb gathered; n <= 131072) */
-  BMLP_ARM_PRODUCT_GATHER = 10 /* (in arm traces) a squaring of a sparse R done as row gathers: row i of
+  BMLP_ARM_PRODUCT_GATHER = 10, /* (in arm traces) a squaring of a sparse R done as row gathers: row i of
                                   R | R.R = R[i] | OR of the rows k over the set bits k of R[i] */
+  BMLP_ARM_PRODUCT_SEMINAIVE = 11 /* (in arm traces) a squaring done from the bits D new in the last one:
+                                  R | R.R = R | D.R | R.D (D.R by row gathers, R.D over the nonempty
+                                  rows of D) */
 } bmlp_arm;
 
 typedef enum {

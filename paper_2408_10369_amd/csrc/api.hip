@@ -47,7 +47,7 @@ void hip_check(hipError_t e, const char* what) {
 
 struct bmlp_ctx {
   int device = 0;
-  static constexpr int kSlots = 13;
+  static constexpr int kSlots = 17;
   void* slot[kSlots] = {};
   size_t slot_bytes[kSlots] = {};
   u32* d_flags = nullptr;  // device flags / counters
@@ -80,10 +80,12 @@ enum FlagSlot {
   F_FEAT = 16,     // 16 features
   F_GSTATS = 32,   // 3 x 64-bit graph statistics
   F_EXEC = 40,     // 64-bit count of matrix-core ops issued by a timed product
+  F_LIST = 44,     // length of a device row list
   F_WORDS = 128
 };
 
-enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH };
+// S_RD .. S_RL: the semi-naive squarings of rms_core (delta, its row-list, the column gather and the rows)
+enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH, S_RD, S_RA, S_RX, S_RL };
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -301,10 +303,11 @@ i64 count_bits(bmlp_ctx* c, const u64* R, i64 rows, i64 n, i64 ld, hipStream_t s
 // A squaring R.R of a sparse R is cheaper as row gathers (row i of R | R.R = R[i] | OR of the rows k
 // over the set bits k of R[i], the rows read whole) than as a dense product: the gathers move about
 // (bits + 3 n) rows of n bits, the dense product does 2 n^3 operations.  The rates are measured on
-// MI355X at n = 16,384: dense squarings on the matrix cores, gathers of rows from L2 / Infinity Cache.
-constexpr double kMfmaSquareOpsPerSec = 4.0e15;
+// MI355X at n = 16,384: dense squarings on the matrix cores (4.5e15 on a product that skips nothing),
+// gathers of rows from L2 / Infinity Cache (888 MB in 222 us with all of a wave's loads in flight).
+constexpr double kMfmaSquareOpsPerSec = 4.5e15;
 constexpr double kValuSquareOpsPerSec = 1.7e15;
-constexpr double kGatherBytesPerSec = 2.0e12;
+constexpr double kGatherBytesPerSec = 4.0e12;
 bool rms_gather_pays(i64 n, i64 bits, int arm) {
   if (n > gather_rows_max_n()) return false;
   const double nn = (double)n, row_bytes = 8.0 * (double)words_for(n);
@@ -312,6 +315,21 @@ bool rms_gather_pays(i64 n, i64 bits, int arm) {
   const double t_dense =
       2.0 * nn * nn * nn / (arm == BMLP_ARM_PRODUCT_MFMA ? kMfmaSquareOpsPerSec : kValuSquareOpsPerSec);
   return t_gather < t_dense;
+}
+
+// A squaring from the bits D new in the last one: with R_t = R_{t-1} | D and R_{t-1}.R_{t-1} inside R_t,
+//   R_t.R_t = R_t | R_t.D | D.R_t,
+// so it costs a row gather over the bits of D (D.R_t), a column gather of R_t at the nonempty rows of
+// D and a product with K = that number of rows (R_t.D), instead of a dense n^3 product.
+bool rms_semi_pays(i64 n, i64 dbits, i64 drows, int arm) {
+  if (n > gather_rows_max_n() || n > gather_cols_max_n()) return false;
+  const double nn = (double)n, row_bytes = 8.0 * (double)words_for(n);
+  const double t_gather = ((double)dbits + 3.0 * nn) * row_bytes / kGatherBytesPerSec;  // D.R and the copy of R
+  const double t_cols = 2.0 * nn * row_bytes / 4.0e12;
+  const double t_prod = 2.0 * nn * nn * (double)drows / (drows >= 512 ? 3.0e15 : 1.2e15);
+  const double t_dense =
+      2.0 * nn * nn * nn / (arm == BMLP_ARM_PRODUCT_MFMA ? kMfmaSquareOpsPerSec : kValuSquareOpsPerSec);
+  return t_gather + t_cols + t_prod + 50.0e-6 < t_dense;
 }
 
 // R1+ into `out` (n x ldo) -- the RMS fixpoint driver shared by rms, the closure arm of smp and the RMS
@@ -329,6 +347,11 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   if (o.rms_variant == 1) hip_check(launch_set_diag(cur, ldi, n, n, s), "set_diag");
   bool may_gather = o.product_arm == BMLP_ARM_AUTO && n <= gather_rows_max_n();
   i64 bits = may_gather ? count_bits(c, cur, n, n, ldi, s) : 0;
+  // Semi-naive squarings need D = R_t & ~R_{t-1}: it is formed at the start of a squaring (the other
+  // buffer still holds R_{t-1}) when the new-bit count of the last squaring says it may pay.
+  const bool may_semi = o.product_arm == BMLP_ARM_AUTO && n <= gather_rows_max_n() && n <= gather_cols_max_n();
+  bool have_prev = false;
+  i64 dbits = 0;
   unsigned long long* nb = (unsigned long long*)(c->d_flags + F_NEW);
   const int cap = ceil_log2(std::max<i64>(n, 2)) + 2;
   int it = 0;
@@ -338,20 +361,52 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
     // once gathers stop paying they never pay again and the bit count is no longer needed.
     may_gather = may_gather && rms_gather_pays(n, bits, arm);
     const bool gather = may_gather;  // the gathers count the new bits, which keeps `bits` exact
+    bool semi = false;
+    i64 drows = 0;
+    u64* dl = nullptr;
+    int32_t* list = nullptr;
+    if (!gather && may_semi && have_prev && rms_semi_pays(n, dbits, std::min(n, dbits), arm)) {
+      dl = ws_bits(c, S_RD, n, ldi, o);
+      list = (int32_t*)ws(c, S_RL, (size_t)n * sizeof(int32_t), o);
+      hip_check(launch_ewise(2, cur, ldi, nxt, ldi, dl, ldi, n, n, s), "andnot");
+      hip_check(hipMemsetAsync(c->d_flags + F_LIST, 0, sizeof(u32), s), "hipMemsetAsync");
+      hip_check(launch_nonempty_rows(dl, n, n, ldi, list, c->d_flags + F_LIST, s), "nonempty_rows");
+      drows = (i64)read_flag(c, s, F_LIST);
+      semi = drows > 0 && rms_semi_pays(n, dbits, drows, arm);
+    }
+    int tarm = arm;
     if (gather) {
       hip_check(launch_gather_rows(cur, ldi, n, cur, ldi, n, 1, nxt, ldi, s, nullptr, nb), "gather_rows");
       if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
+      tarm = BMLP_ARM_PRODUCT_GATHER;
+    } else if (semi) {
+      // nxt = cur | D.cur (rows of cur gathered over the bits of D), then nxt |= cur.D over the rows of D
+      // with a bit: A = those columns of cur, X = those rows of D
+      const i64 kw = words_for(drows);
+      u64* am = ws_bits(c, S_RA, n, kw, o);
+      u64* xm = ws_bits(c, S_RX, drows, ldi, o);
+      hip_check(launch_ewise(4, cur, ldi, nullptr, 0, nxt, ldi, n, n, s), "copy");
+      hip_check(launch_gather_rows(dl, ldi, n, cur, ldi, n, 2, nxt, ldi, s, nullptr, nb), "gather_rows");
+      hip_check(launch_gather_cols(cur, ldi, n, n, list, drows, 0, am, kw, s), "gather_cols");
+      hip_check(launch_copy_rows(dl, ldi, list, drows, n, xm, ldi, s), "copy_rows");
+      product(c, am, kw, xm, ldi, nxt, ldi, nxt, ldi, nullptr, 0, n, drows, n, nullptr, product_arm(o, n, n, drows), s,
+              sr, nullptr, 0, nb);
+      if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
+      tarm = BMLP_ARM_PRODUCT_SEMINAIVE;
     } else {
-      product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, c->d_flags, arm, s, sr);
+      product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, c->d_flags, arm, s, sr, nullptr, 0,
+              nb);
     }
-    sr.trace(it, gather ? BMLP_ARM_PRODUCT_GATHER : arm);
+    sr.trace(it, tarm);
     ++it;
     hip_check(hipMemcpyAsync(c->h_flags, c->d_flags, 8 * sizeof(u32), hipMemcpyDeviceToHost, s), "memcpy");
     hip_check(hipStreamSynchronize(s), "sync");
     unsigned long long added = 0;
     std::memcpy(&added, c->h_flags + F_NEW, sizeof added);
     bits += (i64)added;
-    const bool changed = gather ? added != 0 : c->h_flags[F_CHANGED] != 0;
+    dbits = (i64)added;
+    have_prev = true;
+    const bool changed = added != 0;
     std::swap(cur, nxt);
     if (!changed) break;
     need(it < cap, BMLP_EITER, "RMS exceeded %d products (n=%lld)", cap, (long long)n);

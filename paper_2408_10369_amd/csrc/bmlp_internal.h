@@ -32,6 +32,11 @@ hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s);
 // row i of a gets bit idx[i] (0 <= idx[i] < columns; rows zeroed beforehand)
 hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s);
 hipError_t launch_check_index(const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s);
+// list of the rows of a (rows x n) with a set bit, in no particular order; *count (zeroed by the caller) += their number
+hipError_t launch_nonempty_rows(const u64* a, i64 rows, i64 n, i64 ld, int32_t* list, u32* count, hipStream_t s);
+// dst row i = src row list[i] for i < k (n columns; padding words of dst up to ldd zeroed)
+hipError_t launch_copy_rows(const u64* src, i64 lds, const int32_t* list, i64 k, i64 n, u64* dst, i64 ldd,
+                            hipStream_t s);
 // out[rp[r] .. rp[r+1]) = r for r < rows
 hipError_t launch_rows_from_rp(const i64* rp, i64 rows, int32_t* out, hipStream_t s);
 // out = I | M+ for b <= 64 (M, out: b rows of one significant word)

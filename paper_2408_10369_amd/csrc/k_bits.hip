@@ -127,6 +127,31 @@ __global__ void k_rows_from_rp(const i64* __restrict__ rp, i64 rows, int32_t* __
     for (i64 e = rp[r] + lane; e < rp[r + 1]; e += 64) out[e] = (int32_t)r;
 }
 
+// list of the rows of a with a set bit (order unspecified), *count = their number; one wave per row
+__global__ void k_nonempty_rows(const u64* __restrict__ a, i64 rows, i64 nw, i64 ld, int32_t* __restrict__ list,
+                                u32* __restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 r = wave; r < rows; r += nwaves) {
+    u64 any = 0;
+    for (i64 w = lane; w < nw; w += 64) any |= a[r * ld + w];
+    if (__ballot(any != 0ull) && lane == 0) list[atomicAdd(count, 1u)] = (int32_t)r;
+  }
+}
+
+// dst row i = src row list[i] (nw words), one wave per row
+__global__ void k_copy_rows(const u64* __restrict__ src, i64 lds, const int32_t* __restrict__ list, i64 k, i64 nw,
+                            u64* __restrict__ dst, i64 ldd) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 i = wave; i < k; i += nwaves) {
+    const i64 r = list[i];
+    for (i64 w = lane; w < ldd; w += 64) dst[i * ldd + w] = w < nw ? src[r * lds + w] : 0ull;
+  }
+}
+
 // raises *bad when an index lies outside [0, n)
 __global__ void k_check_index(const int32_t* __restrict__ idx, i64 k, i64 n, u32* __restrict__ bad) {
   for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < k; i += (i64)gridDim.x * blockDim.x) {
@@ -559,6 +584,21 @@ hipError_t launch_closure64(const u64* M, i64 ldm, i64 b, u64* out, i64 ldo, hip
 hipError_t launch_rows_from_rp(const i64* rp, i64 rows, int32_t* out, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rows_from_rp, dim3(grid_for(rows * 64, kBlock, 16384)), dim3(kBlock), 0, s, rp, rows, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonempty_rows(const u64* a, i64 rows, i64 n, i64 ld, int32_t* list, u32* count, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nonempty_rows, dim3(grid_for(rows * 64, kBlock, 16384)), dim3(kBlock), 0, s, a, rows,
+                     words_for(n), ld, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const u64* src, i64 lds, const int32_t* list, i64 k, i64 n, u64* dst, i64 ldd,
+                            hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_rows, dim3(grid_for(k * 64, kBlock, 16384)), dim3(kBlock), 0, s, src, lds, list, k,
+                     words_for(n), dst, ldd);
   return hipGetLastError();
 }
 

@@ -246,6 +246,22 @@ def test_rms_path_graph_loop_counts(ctx, n):
         assert st2["products"] == st2["iterations"] == math.ceil(math.log2(n - 1)) + 1
 
 
+def test_rms_seminaive_squaring(ctx):
+    """A sparse random digraph at n = 8,192 (mean degree 1.6): its last squaring adds few bits, so the
+    next is done from them (R | D.R | R.D) rather than as a dense product.  Whole closure checked."""
+    n = 8192
+    s, d = gen.er_digraph(n, 2e-4, 5)
+    R = gpu_pack(ctx, n, s, d)
+    st = {}
+    got = host(ctx.rms(R, n, stats=st))
+    assert B.ARM_PRODUCT_SEMINAIVE in st["arm_trace"], st["arm_trace"]
+    assert st["products"] + st["arm_trace"].count(B.ARM_PRODUCT_GATHER) == st["iterations"]
+    assert np.array_equal(got, oracle.closure_rows(n, s, d))
+    # the same closure with every squaring a dense product
+    got2 = host(ctx.rms(R, n, opts=B.make_opts(product_arm=B.ARM_PRODUCT_MFMA)))
+    assert np.array_equal(got, got2)
+
+
 def test_rms_special_graphs(ctx):
     for n in (1, 64, 65, 300):
         cs, cd = gen.cycle_graph(n)
