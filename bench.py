@@ -42,7 +42,7 @@ KERNELS = {0: ("k_gemm_valu", "bit-packed Boolean product on the VALU", "alu", V
 GEMM_TRAFFIC = {"k_gemm_mfma": {"sources": ["paper_2408_10369_amd/csrc/k_gemm.hip",
                                             "paper_2408_10369_amd/csrc/mfma_tile.h"],
                                 "sha256": "7c8c9929377e6d58b86b270a7e5b7cd8fc4a7dd547de9ad7a25ff569da25e4d2",
-                                "bytes_per_launch": 376.6e6}}
+                                "bytes_per_launch": 316.4e6}}
 
 
 def measured_traffic(kernel):
