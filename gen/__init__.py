@@ -39,7 +39,7 @@ import numpy as np
 __all__ = [
     "er_digraph", "sources", "query_lists", "c1", "c2", "C2_PROBS", "C2_KS",
     "batch_graphs", "BatchGraph", "multirel", "MultiRel", "programs",
-    "scalefree_digraph", "query_stream", "path_graph", "cycle_graph",
+    "scalefree_digraph", "query_stream", "path_graph", "cycle_graph", "tail_core",
 ]
 
 
@@ -84,6 +84,25 @@ def path_graph(n: int):
 def cycle_graph(n: int):
     s = np.arange(n, dtype=np.int32)
     return s, ((s + 1) % n).astype(np.int32)
+
+
+def tail_core(n: int, core: int, tail: int, deg: float, seed: int):
+    """A strongly connected random core (nodes 0..core-1: a random Hamiltonian cycle plus ER edges of mean
+    out-degree ``deg``) and a chain of ``tail`` nodes (core .. core+tail-1) whose last node points into the
+    core; the remaining nodes are isolated.  Row c of the chain reaches the whole core at a distance that
+    grows along the chain, so late closure rounds add many bits to few rows."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(core).astype(np.int32)
+    s = [perm, np.zeros(0, np.int32)]
+    d = [np.roll(perm, -1), np.zeros(0, np.int32)]
+    es, ed = er_digraph(core, deg / max(core - 1, 1), seed + 1)
+    s.append(es)
+    d.append(ed)
+    ch = np.arange(core, core + tail, dtype=np.int32)
+    s.append(ch)
+    d.append(np.r_[ch[1:], np.int32(perm[0])].astype(np.int32))
+    src, dst = np.concatenate(s), np.concatenate(d)
+    return _dedupe_sorted(src, dst, n)
 
 
 # --- first configuration: one small ER graph ---------------------------------

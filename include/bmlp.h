@@ -87,9 +87,12 @@ typedef enum {
                                   a step edge (selections over Rs, rows of Rb gathered; n <= 131072) */
   BMLP_ARM_PRODUCT_GATHER = 10, /* (in arm traces) a squaring of a sparse R done as row gathers: row i of
                                   R | R.R = R[i] | OR of the rows k over the set bits k of R[i] */
-  BMLP_ARM_PRODUCT_SEMINAIVE = 11 /* (in arm traces) a squaring done from the bits D new in the last one:
-                                  R | R.R = R | D.R | R.D (D.R by row gathers, R.D over the nonempty
-                                  rows of D) */
+  BMLP_ARM_PRODUCT_SEMINAIVE = 11, /* (in arm traces) a squaring done from the bits D new in the last one:
+                                  R | R.R = R | D.R | R.D (D.R by row gathers, R.D by a product over the
+                                  nonempty rows of D) */
+  BMLP_ARM_PRODUCT_SEMINAIVE_T = 12 /* (in arm traces) the same squaring with R.D = (D^T . R^T)^T, a second
+                                  row gather over the bits of D between transposes (D's bits spread over
+                                  many rows) */
 } bmlp_arm;
 
 typedef enum {

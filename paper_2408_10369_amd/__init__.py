@@ -30,6 +30,7 @@ ARM_SMP_SPARSE_ROUNDS, ARM_SMP_ADAPTIVE = 7, 8
 ARM_COMPOSE_ROWWISE = 9
 ARM_PRODUCT_GATHER = 10
 ARM_PRODUCT_SEMINAIVE = 11
+ARM_PRODUCT_SEMINAIVE_T = 12
 DISPATCH_PLAIN, DISPATCH_LEARNED, DISPATCH_FORCED = 0, 1, 2
 N_FEATURES, N_OUTPUTS, N_PARAMS = 16, 4, 5508
 

@@ -47,12 +47,17 @@ void hip_check(hipError_t e, const char* what) {
 
 struct bmlp_ctx {
   int device = 0;
-  static constexpr int kSlots = 17;
+  static constexpr int kSlots = 18;
   void* slot[kSlots] = {};
   size_t slot_bytes[kSlots] = {};
   u32* d_flags = nullptr;  // device flags / counters
   u32* h_flags = nullptr;  // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evp0 = nullptr, evp1 = nullptr;
+  // timed products awaiting their readback (statistics): event pairs and matrix-core work counters
+  static constexpr int kPend = 64;
+  hipEvent_t pe0[kPend] = {}, pe1[kPend] = {};
+  unsigned long long* d_exec = nullptr;  // kPend counters on the device
+  unsigned long long* h_exec = nullptr;  // pinned mirror
   // batched launch: the captured kernel chain, reused while the batch is unchanged
   hipStream_t capture_stream = nullptr;
   hipGraph_t bgraph = nullptr;
@@ -81,11 +86,15 @@ enum FlagSlot {
   F_GSTATS = 32,   // 3 x 64-bit graph statistics
   F_EXEC = 40,     // 64-bit count of matrix-core ops issued by a timed product
   F_LIST = 44,     // length of a device row list
+  F_QUEUE = 46,    // 64-bit piece counter of the gathers' overflow queue
   F_WORDS = 128
 };
 
-// S_RD .. S_RL: the semi-naive squarings of rms_core (delta, its row-list, the column gather and the rows)
-enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH, S_RD, S_RA, S_RX, S_RL };
+// S_RD .. S_RL: the semi-naive squarings of rms_core (delta, its row-list, the column gather and the rows;
+// the transposed route also takes S_RA, S_RX and S_BT for D^T, R^T and the gathered product); S_GQ: the
+// overflow queue of the row gathers
+enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH, S_RD, S_RA, S_RX, S_RL,
+            S_GQ };
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -129,6 +138,30 @@ void* ws(bmlp_ctx* c, int s, size_t bytes, const bmlp_opts& o) {
 
 u64* ws_bits(bmlp_ctx* c, int s, i64 rows, i64 ld, const bmlp_opts& o) {
   return (u64*)ws(c, s, (size_t)std::max<i64>(rows * ld, 1) * sizeof(u64), o);
+}
+
+// The overflow queue for a gather of k rows of n bits (heavy rows split over waves), or none when it
+// would take the workspace past the caller's limit.
+GatherQueue gather_queue(bmlp_ctx* c, i64 k, i64 n, const bmlp_opts& o) {
+  GatherQueue q{nullptr, nullptr, 0};
+  const i64 cap = gather_queue_capacity(k, n);
+  const size_t bytes = ((size_t)std::max<i64>(cap, 1) * sizeof(int2) + 255) & ~(size_t)255;
+  if (c->slot_bytes[S_GQ] < bytes && o.workspace_limit > 0 &&
+      ws_total(c) - c->slot_bytes[S_GQ] + bytes > (size_t)o.workspace_limit)
+    return q;
+  q.e = (int2*)ws(c, S_GQ, bytes, o);
+  q.n = (unsigned long long*)(c->d_flags + F_QUEUE);
+  q.cap = cap;
+  q.piece = 64;
+  return q;
+}
+
+// The queue for a gather whose query rows hold `bits` set bits over `rows` rows: only rows beyond twice
+// the mean are split (splitting rows of about the mean size buys no balance and costs the atomics).
+GatherQueue sized(GatherQueue q, i64 bits, i64 rows) {
+  const i64 mean = bits / std::max<i64>(rows, 1);
+  q.piece = (int)std::min<i64>(std::max<i64>(64, 2 * mean), 1 << 24);
+  return q;
 }
 
 bmlp_opts opts_or_default(const bmlp_opts* o) {
@@ -192,42 +225,70 @@ struct StatsRec {
   void trace(int round, int arm) {
     if (st && round >= 0 && round < 64) st->arm_trace[round] = arm;
   }
+  // The timed products of a call are read back together (at the end of the call, or when kPend of them
+  // are waiting), so that timing a product adds no host synchronisation of its own.
+  struct Pending {
+    i64 m, k, n;
+    int arm;
+  };
+  Pending pend[bmlp_ctx::kPend];
+  int npend = 0;
+  void pool() {
+    if (c->d_exec) return;
+    for (int i = 0; i < bmlp_ctx::kPend; ++i) {
+      hip_check(hipEventCreate(&c->pe0[i]), "hipEventCreate");
+      hip_check(hipEventCreate(&c->pe1[i]), "hipEventCreate");
+    }
+    hip_check(hipHostMalloc((void**)&c->h_exec, bmlp_ctx::kPend * sizeof(unsigned long long), hipHostMallocDefault),
+              "hipHostMalloc");
+    hip_check(hipMalloc((void**)&c->d_exec, bmlp_ctx::kPend * sizeof(unsigned long long)), "hipMalloc");
+  }
   // counter of matrix-core work for the next timed product (null when no statistics are kept)
-  unsigned long long* exec_counter() const {
-    return st ? (unsigned long long*)(c->d_flags + F_EXEC) : nullptr;
+  unsigned long long* exec_counter() {
+    if (!st) return nullptr;
+    pool();
+    return c->d_exec + npend;
   }
   void product_begin() {
     if (!st) return;
-    hip_check(hipMemsetAsync(c->d_flags + F_EXEC, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
-    hip_check(hipEventRecord(c->evp0, s), "hipEventRecord");
+    pool();
+    hip_check(hipMemsetAsync(c->d_exec + npend, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+    hip_check(hipEventRecord(c->pe0[npend], s), "hipEventRecord");
   }
   void product(i64 m, i64 k, i64 n, int arm) {
     if (!st) return;
-    hip_check(hipEventRecord(c->evp1, s), "hipEventRecord");
-    hip_check(hipMemcpyAsync(c->h_flags + F_EXEC, c->d_flags + F_EXEC, sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, s),
+    hip_check(hipEventRecord(c->pe1[npend], s), "hipEventRecord");
+    hip_check(hipMemcpyAsync(c->h_exec + npend, c->d_exec + npend, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             s),
               "hipMemcpyAsync");
-    hip_check(hipEventSynchronize(c->evp1), "hipEventSynchronize");
+    pend[npend++] = Pending{m, k, n, arm};
+    if (npend == bmlp_ctx::kPend) flush();
+  }
+  void flush() {
+    if (!st || npend == 0) return;
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    float ms = 0.f;
-    hip_check(hipEventElapsedTime(&ms, c->evp0, c->evp1), "hipEventElapsedTime");
-    unsigned long long issued = 0;
-    std::memcpy(&issued, c->h_flags + F_EXEC, sizeof issued);
-    const uint64_t ops = (uint64_t)2 * (uint64_t)m * (uint64_t)k * (uint64_t)n;
-    st->products += 1;
-    st->bool_ops += ops;
-    st->product_bool_ops += ops;
-    st->product_ms += ms;
-    if (arm == BMLP_ARM_PRODUCT_MFMA) {
-      st->products_mfma += 1;
-      st->product_bool_ops_mfma += ops;
-      st->product_ms_mfma += ms;
-      st->mfma_ops_issued += issued;
+    for (int i = 0; i < npend; ++i) {
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, c->pe0[i], c->pe1[i]), "hipEventElapsedTime");
+      const Pending& p = pend[i];
+      const uint64_t ops = (uint64_t)2 * (uint64_t)p.m * (uint64_t)p.k * (uint64_t)p.n;
+      st->products += 1;
+      st->bool_ops += ops;
+      st->product_bool_ops += ops;
+      st->product_ms += ms;
+      if (p.arm == BMLP_ARM_PRODUCT_MFMA) {
+        st->products_mfma += 1;
+        st->product_bool_ops_mfma += ops;
+        st->product_ms_mfma += ms;
+        st->mfma_ops_issued += c->h_exec[i];
+      }
+      st->bytes_moved += (uint64_t)(p.m * words_for(p.k) + p.k * words_for(p.n) + 2 * p.m * words_for(p.n)) * 8u;
     }
-    st->bytes_moved += (uint64_t)(m * words_for(k) + k * words_for(n) + 2 * m * words_for(n)) * 8u;
+    npend = 0;
   }
   void finish() {
     if (!st) return;
+    flush();
     hip_check(hipEventRecord(c->ev1, s), "hipEventRecord");
     hip_check(hipEventSynchronize(c->ev1), "hipEventSynchronize");
     float ms = 0.f;
@@ -318,19 +379,30 @@ bool rms_gather_pays(i64 n, i64 bits, int arm) {
 }
 
 // A squaring from the bits D new in the last one: with R_t = R_{t-1} | D and R_{t-1}.R_{t-1} inside R_t,
-//   R_t.R_t = R_t | R_t.D | D.R_t,
-// so it costs a row gather over the bits of D (D.R_t), a column gather of R_t at the nonempty rows of
-// D and a product with K = that number of rows (R_t.D), instead of a dense n^3 product.
-bool rms_semi_pays(i64 n, i64 dbits, i64 drows, int arm) {
-  if (n > gather_rows_max_n() || n > gather_cols_max_n()) return false;
-  const double nn = (double)n, row_bytes = 8.0 * (double)words_for(n);
-  const double t_gather = ((double)dbits + 3.0 * nn) * row_bytes / kGatherBytesPerSec;  // D.R and the copy of R
-  const double t_cols = 2.0 * nn * row_bytes / 4.0e12;
-  const double t_prod = 2.0 * nn * nn * (double)drows / (drows >= 512 ? 3.0e15 : 1.2e15);
-  const double t_dense =
-      2.0 * nn * nn * nn / (arm == BMLP_ARM_PRODUCT_MFMA ? kMfmaSquareOpsPerSec : kValuSquareOpsPerSec);
-  return t_gather + t_cols + t_prod + 50.0e-6 < t_dense;
+//   R_t.R_t = R_t | R_t.D | D.R_t.
+// D.R_t is a row gather over the bits of D.  R_t.D is found one of two ways:
+//   columns: a column gather of R_t at the nonempty rows of D and a product with K = that number of rows;
+//   transposed: (D^T . R_t^T)^T, a second row gather over the bits of D between three transposes.
+// The transposed route costs about the bits of D; the column route about n^2 per nonempty row of D, so it
+// only pays when D's bits crowd into few rows.  Seconds of each part at the rates measured at n = 16,384
+// (transposes 3.2e12 bytes/s, moving the matrix in and out):
+struct SemiCost {
+  double common, cols_fixed, per_row, transposed, dense;
+};
+SemiCost rms_semi_cost(i64 n, i64 dbits, int arm) {
+  const double nn = (double)n, rb = 8.0 * (double)words_for(n), db = (double)dbits;
+  SemiCost c;
+  c.common = (db + 3.0 * nn) * rb / kGatherBytesPerSec;  // D.R_t and the copy of R_t
+  c.cols_fixed = 2.0 * nn * rb / 4.0e12;
+  c.per_row = 2.0 * nn * nn;  // Boolean operations of the product per nonempty row of D
+  c.transposed = db * rb / kGatherBytesPerSec + 3.0 * 2.0 * nn * rb / 3.2e12 + 2.0 * nn * rb / kGatherBytesPerSec;
+  c.dense = 2.0 * nn * nn * nn / (arm == BMLP_ARM_PRODUCT_MFMA ? kMfmaSquareOpsPerSec : kValuSquareOpsPerSec);
+  return c;
 }
+double rms_semi_cols_s(const SemiCost& c, i64 drows) {
+  return c.cols_fixed + c.per_row * (double)drows / (drows >= 512 ? 3.0e15 : 1.2e15);
+}
+constexpr double kSemiOverheadS = 50.0e-6;  // launches and the readbacks of the semi-naive route
 
 // R1+ into `out` (n x ldo) -- the RMS fixpoint driver shared by rms, the closure arm of smp and the RMS
 // route of compose.  `R1` has leading dimension ld1.  With the product arm left to the library, each
@@ -353,6 +425,7 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   bool have_prev = false;
   i64 dbits = 0;
   unsigned long long* nb = (unsigned long long*)(c->d_flags + F_NEW);
+  const GatherQueue gq = may_gather ? gather_queue(c, n, n, o) : GatherQueue{nullptr, nullptr, 0};
   const int cap = ceil_log2(std::max<i64>(n, 2)) + 2;
   int it = 0;
   for (;;) {
@@ -361,38 +434,69 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
     // once gathers stop paying they never pay again and the bit count is no longer needed.
     may_gather = may_gather && rms_gather_pays(n, bits, arm);
     const bool gather = may_gather;  // the gathers count the new bits, which keeps `bits` exact
-    bool semi = false;
-    i64 drows = 0;
+    // semi-naive squaring: 0 none, 1 columns route, 2 transposed route
+    int semi = 0;
     u64* dl = nullptr;
     int32_t* list = nullptr;
-    if (!gather && may_semi && have_prev && rms_semi_pays(n, dbits, std::min(n, dbits), arm)) {
-      dl = ws_bits(c, S_RD, n, ldi, o);
-      list = (int32_t*)ws(c, S_RL, (size_t)n * sizeof(int32_t), o);
-      hip_check(launch_ewise(2, cur, ldi, nxt, ldi, dl, ldi, n, n, s), "andnot");
-      hip_check(hipMemsetAsync(c->d_flags + F_LIST, 0, sizeof(u32), s), "hipMemsetAsync");
-      hip_check(launch_nonempty_rows(dl, n, n, ldi, list, c->d_flags + F_LIST, s), "nonempty_rows");
-      drows = (i64)read_flag(c, s, F_LIST);
-      semi = drows > 0 && rms_semi_pays(n, dbits, drows, arm);
+    i64 drows = 0;
+    if (!gather && may_semi && have_prev && dbits > 0) {
+      const SemiCost sc = rms_semi_cost(n, dbits, arm);
+      // D has at least ceil(dbits / n) nonempty rows
+      const double cols_lb = rms_semi_cols_s(sc, (dbits + n - 1) / n);
+      if (sc.common + std::min(sc.transposed, cols_lb) + kSemiOverheadS < sc.dense) {
+        dl = ws_bits(c, S_RD, n, ldi, o);
+        hip_check(launch_ewise(2, cur, ldi, nxt, ldi, dl, ldi, n, n, s), "andnot");
+        semi = 2;
+        if (cols_lb < sc.transposed) {
+          list = (int32_t*)ws(c, S_RL, (size_t)n * sizeof(int32_t), o);
+          hip_check(hipMemsetAsync(c->d_flags + F_LIST, 0, sizeof(u32), s), "hipMemsetAsync");
+          hip_check(launch_nonempty_rows(dl, n, n, ldi, list, c->d_flags + F_LIST, s), "nonempty_rows");
+          drows = (i64)read_flag(c, s, F_LIST);
+          const double tc = rms_semi_cols_s(sc, drows);
+          if (drows > 0 && tc < sc.transposed) semi = 1;
+          if (sc.common + std::min(tc, sc.transposed) + kSemiOverheadS >= sc.dense) semi = 0;
+        }
+      }
     }
     int tarm = arm;
+    bool count_after = false;  // new bits = popcount of the result - bits of cur
     if (gather) {
-      hip_check(launch_gather_rows(cur, ldi, n, cur, ldi, n, 1, nxt, ldi, s, nullptr, nb), "gather_rows");
+      const GatherQueue q = sized(gq, bits, n);
+      hip_check(launch_gather_rows(cur, ldi, n, cur, ldi, n, 1, nxt, ldi, s, nullptr, nb, &q), "gather_rows");
       if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
       tarm = BMLP_ARM_PRODUCT_GATHER;
-    } else if (semi) {
+    } else if (semi == 1) {
       // nxt = cur | D.cur (rows of cur gathered over the bits of D), then nxt |= cur.D over the rows of D
       // with a bit: A = those columns of cur, X = those rows of D
       const i64 kw = words_for(drows);
       u64* am = ws_bits(c, S_RA, n, kw, o);
       u64* xm = ws_bits(c, S_RX, drows, ldi, o);
       hip_check(launch_ewise(4, cur, ldi, nullptr, 0, nxt, ldi, n, n, s), "copy");
-      hip_check(launch_gather_rows(dl, ldi, n, cur, ldi, n, 2, nxt, ldi, s, nullptr, nb), "gather_rows");
+      const GatherQueue q = sized(gq, dbits, n);
+      hip_check(launch_gather_rows(dl, ldi, n, cur, ldi, n, 2, nxt, ldi, s, nullptr, nb, &q), "gather_rows");
       hip_check(launch_gather_cols(cur, ldi, n, n, list, drows, 0, am, kw, s), "gather_cols");
       hip_check(launch_copy_rows(dl, ldi, list, drows, n, xm, ldi, s), "copy_rows");
       product(c, am, kw, xm, ldi, nxt, ldi, nxt, ldi, nullptr, 0, n, drows, n, nullptr, product_arm(o, n, n, drows), s,
               sr, nullptr, 0, nb);
       if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
       tarm = BMLP_ARM_PRODUCT_SEMINAIVE;
+    } else if (semi == 2) {
+      // cur.D = (D^T . cur^T)^T: rows of cur^T gathered over the bits of D^T and transposed back; then
+      // nxt (R_{t-1} is no longer needed once D is formed) = cur | cur.D, and nxt |= D.cur
+      u64* dt = ws_bits(c, S_RX, n, ldi, o);
+      u64* ct = ws_bits(c, S_BT, n, ldi, o);
+      u64* yt = ws_bits(c, S_RA, n, ldi, o);
+      hip_check(launch_transpose(dl, n, n, ldi, dt, ldi, s), "transpose");
+      hip_check(launch_transpose(cur, n, n, ldi, ct, ldi, s), "transpose");
+      const GatherQueue q = sized(gq, dbits, n);
+      hip_check(launch_gather_rows(dt, ldi, n, ct, ldi, n, 0, yt, ldi, s, nullptr, nullptr, &q), "gather_rows");
+      hip_check(launch_transpose(yt, n, n, ldi, dt, ldi, s), "transpose");  // dt now holds cur.D
+      hip_check(launch_ewise(0, dt, ldi, cur, ldi, nxt, ldi, n, n, s), "or");
+      hip_check(launch_gather_rows(dl, ldi, n, cur, ldi, n, 2, nxt, ldi, s, nullptr, nullptr, &q), "gather_rows");
+      hip_check(launch_popcount_total(nxt, n, n, ldi, nb, s), "popcount_total");
+      count_after = true;
+      if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
+      tarm = BMLP_ARM_PRODUCT_SEMINAIVE_T;
     } else {
       product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, c->d_flags, arm, s, sr, nullptr, 0,
               nb);
@@ -403,6 +507,10 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
     hip_check(hipStreamSynchronize(s), "sync");
     unsigned long long added = 0;
     std::memcpy(&added, c->h_flags + F_NEW, sizeof added);
+    if (count_after) {
+      need((i64)added >= bits, BMLP_EDEVICE, "RMS bit count went down");
+      added -= (unsigned long long)bits;
+    }
     bits += (i64)added;
     dbits = (i64)added;
     have_prev = true;
@@ -648,7 +756,9 @@ void smp_rounds(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vs
 void read_off_closure(bmlp_ctx* c, const u64* V, i64 ldv, i64 k, const u64* clo, i64 ldc, i64 n, int reflexive,
                       u64* Vstar, const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
   if (n <= gather_rows_max_n()) {
-    hip_check(launch_gather_rows(V, ldv, k, clo, ldc, n, reflexive, Vstar, ldv, s), "gather_rows");
+    const GatherQueue gq = gather_queue(c, k, n, o);
+    hip_check(launch_gather_rows(V, ldv, k, clo, ldc, n, reflexive, Vstar, ldv, s, nullptr, nullptr, &gq),
+              "gather_rows");
     return;
   }
   product(c, V, ldv, clo, ldc, reflexive ? V : nullptr, ldv, Vstar, ldv, nullptr, 0, k, n, n, nullptr,
@@ -805,6 +915,12 @@ bmlp_status bmlp_destroy(bmlp_handle h) {
       if (h->ev1) (void)hipEventDestroy(h->ev1);
       if (h->evp0) (void)hipEventDestroy(h->evp0);
       if (h->evp1) (void)hipEventDestroy(h->evp1);
+      for (int i = 0; i < bmlp_ctx::kPend; ++i) {
+        if (h->pe0[i]) (void)hipEventDestroy(h->pe0[i]);
+        if (h->pe1[i]) (void)hipEventDestroy(h->pe1[i]);
+      }
+      if (h->d_exec) (void)hipFree(h->d_exec);
+      if (h->h_exec) (void)hipHostFree(h->h_exec);
       if (h->d_model) (void)hipFree(h->d_model);
       if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
       if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
@@ -1155,19 +1271,23 @@ bmlp_status bmlp_compose_two_sided(bmlp_handle h, const uint64_t* Rbase, const u
       i64 dbits = count_bits(h, dl, n, n, nw, s);
       const i64 lbits = may_gather ? count_bits(h, Rleft, n, n, ld, s) : 0;
       unsigned long long* nb = (unsigned long long*)(h->d_flags + F_NEW);
+      const GatherQueue gq = may_gather ? gather_queue(h, n, n, o) : GatherQueue{nullptr, nullptr, 0};
       const i64 cap = n * n + 1;  // every round but the last adds a fact
       while (dbits > 0) {
         need(rounds < cap, BMLP_EITER, "two-sided recursion exceeded %lld rounds", (long long)cap);
         hip_check(hipMemsetAsync(h->d_flags, 0, 8 * sizeof(u32), s), "hipMemsetAsync");
         // W = D . R
-        if (may_gather && rms_gather_pays(n, dbits, arm))
-          hip_check(launch_gather_rows(dl, nw, n, Rright, ld, n, 0, wm, nw, s), "gather_rows");
-        else
+        if (may_gather && rms_gather_pays(n, dbits, arm)) {
+          const GatherQueue q = sized(gq, dbits, n);
+          hip_check(launch_gather_rows(dl, nw, n, Rright, ld, n, 0, wm, nw, s, nullptr, nullptr, &q), "gather_rows");
+        } else {
           product(h, dl, nw, Rright, ld, nullptr, 0, wm, nw, nullptr, 0, n, n, n, nullptr, arm, s, sr);
+        }
         // P |= L . W, D = the bits new to P
         if (may_gather && rms_gather_pays(n, lbits, arm)) {
           hip_check(launch_ewise(4, P, ld, nullptr, 0, aux, nw, n, n, s), "copy");
-          hip_check(launch_gather_rows(Rleft, ld, n, wm, nw, n, 2, P, ld, s, nullptr, nb), "gather_rows");
+          const GatherQueue q = sized(gq, lbits, n);
+          hip_check(launch_gather_rows(Rleft, ld, n, wm, nw, n, 2, P, ld, s, nullptr, nb, &q), "gather_rows");
           hip_check(launch_ewise(2, P, ld, aux, nw, dl, nw, n, n, s), "andnot");
         } else {
           product(h, Rleft, ld, wm, nw, P, ld, P, ld, aux, nw, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb);
@@ -1281,7 +1401,8 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
           hip_check(launch_set_onehot(v1, nw, drows, kr, n, nullptr, s), "set_onehot");
           if (sarm == BMLP_ARM_AUTO || sarm == BMLP_ARM_SMP_ADAPTIVE) sarm = smp_plain_arm(n, kr, gs.m);
           smp_core(h, Rstep, ld, n, v1, sel, kr, nw, 0, sarm, gs, 1, Csr{rp, ci}, o, s, sr);
-          hip_check(launch_gather_rows(sel, nw, kr, Rbase, ld, n, 2, P, ld, s, drows), "gather_rows");
+          const GatherQueue gq = gather_queue(h, kr, n, o);
+          hip_check(launch_gather_rows(sel, nw, kr, Rbase, ld, n, 2, P, ld, s, drows, nullptr, &gq), "gather_rows");
           // the host list is read by the upload above; wait before it goes out of scope
           hip_check(hipStreamSynchronize(s), "sync");
         }

@@ -98,12 +98,22 @@ i64 smp_rows_max_n();
 hipError_t launch_smp_round(const u64* fr, u64* fr_out, i64 ldf, u64* vis, i64 ldvis, i64 k, const i64* rp,
                             const int32_t* ci, const u64* R, i64 ldr, i64 n, u32* changed, unsigned long long* newbits,
                             const u32* pred, u32 pred_val, hipStream_t s);
+// Overflow queue of the gathers: room for gather_queue_capacity(k, n) pieces, a 64-bit counter, and the
+// bits per piece (at least 64; rows with more set bits than that are split).
+struct GatherQueue {
+  int2* e;
+  unsigned long long* n;
+  i64 cap;
+  int piece;
+};
+i64 gather_queue_capacity(i64 k, i64 n);
 // out[map(r)] = init | OR of Cl[u, :] over the set bits u of V[r], with init = 0 (0), V[r] (1) or the
-// current out[map(r)] (2); map(r) = row_map[r], or r without a map; n <= gather_rows_max_n().
-// *newbits (optional) += bits of the answers not in init.  out must not overlap V or Cl.
+// current out[map(r)] (2); map(r) = row_map[r], or r without a map (a map must not repeat a row);
+// n <= gather_rows_max_n().  *newbits (optional) += bits of the answers not in init.  out must not
+// overlap V or Cl.  With a queue (n <= 16,384), rows with more set bits than q->piece are split over waves.
 hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 ldc, i64 n, int init, u64* out,
                               i64 ldo, hipStream_t s, const int32_t* row_map = nullptr,
-                              unsigned long long* newbits = nullptr);
+                              unsigned long long* newbits = nullptr, const GatherQueue* q = nullptr);
 i64 gather_rows_max_n();
 // out[0] += set bits, out[1] = max(out[1], largest row count), out[2] += rows with a set bit
 // (out must be zeroed)

@@ -316,11 +316,19 @@ k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__
 // The same gather with one wave per row, for n <= 16,384 (lane l owns words l + 64 j, j < WPL): no
 // workgroup scan, and the set bits of the row are walked in batches of eight (across its words), so
 // that eight source-row loads per word are in flight at a time.
+//
+// A wave walks a source row in about 170 ns, so one row with thousands of set bits would hold the whole
+// launch up.  With an overflow queue (qe != nullptr) a row with more than `piece` set bits walks only
+// its first `piece` and queues the rest as pieces (row, j) of `piece` bits each (a multiple of 8), for
+// k_gather_rows_q, launched after this kernel, to OR into the row with 64-bit atomics.
+constexpr int kMinPiece = 64;
+
 template <int WPL>
 __global__ void __launch_bounds__(256)
 k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__ Cl, i64 ldc, i64 n, int init,
                 u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map,
-                unsigned long long* __restrict__ newbits) {
+                unsigned long long* __restrict__ newbits, int2* __restrict__ qe, unsigned long long* __restrict__ qn,
+                i64 qcap, int piece) {
   const int lane = threadIdx.x & 63;
   const i64 wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const i64 nwaves = (i64)gridDim.x * 4;
@@ -341,11 +349,30 @@ k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict
       start[j] = a;
       nz[j] = __ballot(vr[j] != 0ull);  // words of the row with set bits (wave-uniform)
     }
+    int limit = 1 << 30;  // sources this wave walks
+    if (qe) {
+      u32 c = 0;
+#pragma unroll
+      for (int j = 0; j < WPL; ++j) c += (u32)__popcll(vr[j]);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+      if (c > (u32)piece) {
+        const u32 extra = (c - 1) / (u32)piece;  // pieces after the first
+        unsigned long long base = 0ull;
+        if (lane == 0) base = atomicAdd(qn, (unsigned long long)extra);
+        base = uniform64(base);
+        for (u32 i = lane; i < extra; i += 64) {
+          const unsigned long long slot = base + i;
+          if ((i64)slot < qcap) qe[slot] = make_int2((int)row, (int)(i + 1));
+        }
+        limit = piece;
+      }
+    }
     // The walk over the row's set bits is wave-uniform: its state (word, remaining bits, sources)
     // lives in scalar registers, so the sources address their rows from scalar bases.
     int w = 0;
     u64 x = 0ull;
-    for (;;) {
+    for (int walked = 0; walked < limit; walked += 8) {
       int src[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -404,29 +431,156 @@ k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict
   wave_count(added, newbits);
 }
 
+// The queued pieces of the heavy rows: piece (row, j) walks the set bits numbered [p j, p j + p) of
+// V[row] in word order and ORs the gathered rows into out[map(row)] with 64-bit atomics; the value each
+// atomic returns tells which of its bits are new, so *newbits stays exact.  The rows already hold their
+// starting value and first piece (k_gather_rows_w, launched before).
+template <int WPL>
+__global__ void __launch_bounds__(256)
+k_gather_rows_q(const u64* __restrict__ V, i64 ldv, const u64* __restrict__ Cl, i64 ldc, i64 n,
+                u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map, const int2* __restrict__ qe,
+                const unsigned long long* __restrict__ qn, i64 qcap, int piece, unsigned long long* __restrict__ newbits) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const i64 nwaves = (i64)gridDim.x * 4;
+  const i64 nw = (n + 63) >> 6;
+  const u64 last_mask = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
+  const i64 queued = (i64)*qn;
+  const i64 cnt = queued < qcap ? queued : qcap;
+  u32 added = 0;
+  for (i64 e = wave; e < cnt; e += nwaves) {
+    const int2 pc = qe[e];
+    const i64 row = pc.x;
+    const i64 orow = row_map ? (i64)row_map[row] : row;
+    const i64 skip = (i64)pc.y * piece;
+    u64 vr[WPL], acc[WPL], nz[WPL];
+    i64 before = 0;  // set bits of the row in the blocks before j
+#pragma unroll
+    for (int j = 0; j < WPL; ++j) {
+      const i64 w = lane + 64 * j;
+      u64 v = w < nw ? V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull) : 0ull;
+      // drop the set bits numbered below skip: inclusive scan of the popcounts across the lanes
+      const u32 c = (u32)__popcll(v);
+      u32 incl = c;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const u32 y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      const i64 drop = skip - (before + (i64)(incl - c));
+      if (drop >= (i64)c) v = 0ull;
+      else
+        for (i64 d = 0; d < drop; ++d) v &= v - 1;
+      before += (i64)__shfl(incl, 63, 64);
+      vr[j] = v;
+      acc[j] = 0ull;
+      nz[j] = __ballot(v != 0ull);
+    }
+    int w = 0;
+    u64 x = 0ull;
+    for (int walked = 0; walked < piece; walked += 8) {
+      int src[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+#pragma unroll
+        for (int j = 0; j < WPL; ++j) {
+          if (!x && nz[j]) {
+            const int b = __ffsll((unsigned long long)nz[j]) - 1;
+            nz[j] &= nz[j] - 1;
+            w = 64 * j + b;
+            x = uniform64(__shfl(vr[j], b, 64));
+          }
+        }
+        src[q] = -1;
+        if (x) {
+          src[q] = 64 * w + (__ffsll((unsigned long long)x) - 1);
+          x &= x - 1;
+        }
+      }
+      if (src[0] < 0) break;
+      const u64* rowp[8];
+      u64 keep[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        keep[q] = src[q] >= 0 ? ~0ull : 0ull;
+        rowp[q] = Cl + (i64)(src[q] >= 0 ? src[q] : src[0]) * ldc;
+      }
+      u64 t[WPL][8];
+#pragma unroll
+      for (int j = 0; j < WPL; ++j) {
+        const int ww = lane + 64 * j;
+        const int wc = ww < nw ? ww : (int)nw - 1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[j][q] = rowp[q][wc];
+      }
+#pragma unroll
+      for (int j = 0; j < WPL; ++j) {
+        u64 v = 0ull;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v |= t[j][q] & keep[q];
+        if (lane + 64 * j < nw) acc[j] |= v;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < WPL; ++j) {
+      const i64 ww = lane + 64 * j;
+      if (ww < nw && acc[j]) {
+        const u64 old = atomicOr((unsigned long long*)&out[orow * ldo + ww], (unsigned long long)acc[j]);
+        added += (u32)__popcll(acc[j] & ~old);
+      }
+    }
+  }
+  wave_count(added, newbits);
+}
+
 }  // namespace
 
 i64 smp_rows_max_n() { return (kMaxLdsWords / 3) * 64; }
 
 i64 gather_rows_max_n() { return (i64)kGatherWords * 64; }
 
+i64 gather_queue_capacity(i64 k, i64 n) { return k * ((n + kMinPiece - 1) / kMinPiece); }
+
 hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 ldc, i64 n, int init, u64* out,
-                              i64 ldo, hipStream_t s, const int32_t* row_map, unsigned long long* newbits) {
+                              i64 ldo, hipStream_t s, const int32_t* row_map, unsigned long long* newbits,
+                              const GatherQueue* q) {
   if (k <= 0) return hipSuccess;
   const i64 nw = words_for(n);
   if (nw > kGatherWords) return hipErrorInvalidValue;
   if (nw <= 256) {
+    const bool queued = q && q->e && q->n && q->cap >= gather_queue_capacity(k, n);
+    int2* qe = queued ? q->e : nullptr;
+    unsigned long long* qn = queued ? q->n : nullptr;
+    const i64 qcap = queued ? q->cap : 0;
+    const int piece = queued ? (std::max(q->piece, kMinPiece) + 7) / 8 * 8 : kMinPiece;
+    if (queued) {
+      const hipError_t e = launch_fill_zero((u64*)qn, 1, s);
+      if (e != hipSuccess) return e;
+    }
     const i64 blocks = (k + 3) / 4;
     const unsigned grid = (unsigned)(blocks < 16384 ? blocks : 16384);
     if (nw <= 64)
       hipLaunchKernelGGL(k_gather_rows_w<1>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits);
+                         row_map, newbits, qe, qn, qcap, piece);
     else if (nw <= 128)
       hipLaunchKernelGGL(k_gather_rows_w<2>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits);
+                         row_map, newbits, qe, qn, qcap, piece);
     else
       hipLaunchKernelGGL(k_gather_rows_w<4>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits);
+                         row_map, newbits, qe, qn, qcap, piece);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !queued) return e;
+    // the pieces: their number is known on the device only, so a fixed grid strides over them
+    const unsigned qgrid = grid < 2048 ? grid : 2048;
+    if (nw <= 64)
+      hipLaunchKernelGGL(k_gather_rows_q<1>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
+                         qn, qcap, piece, newbits);
+    else if (nw <= 128)
+      hipLaunchKernelGGL(k_gather_rows_q<2>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
+                         qn, qcap, piece, newbits);
+    else
+      hipLaunchKernelGGL(k_gather_rows_q<4>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
+                         qn, qcap, piece, newbits);
     return hipGetLastError();
   }
   const unsigned grid = (unsigned)(k < 65535 ? k : 65535);

@@ -154,28 +154,28 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
 #pragma unroll
     for (int q = 0; q < kMChunk; ++q) sr[q] = (vr && kb + q < kwords) ? pr[kb + q] : 0ull;
   };
-  auto stage = [&](const u64 (&sr)[kMChunk], int buf) {
+  auto stage_word = [&](const u64 (&sr)[kMChunk], int buf, int q) -> u32 {
     uint4 (*X)[kMT][kMChunk] = isa ? Ax[buf] : Bx[buf];
+    const u32 lo = (u32)sr[q], hi = (u32)(sr[q] >> 32), rlo = rotr2(lo), rhi = rotr2(hi);
+    const int slot = q ^ ssw;
+    X[0][tt][slot] = make_uint4(lo & 0x22222222u, hi & 0x22222222u, lo & 0x44444444u, hi & 0x44444444u);
+    X[1][tt][slot] = make_uint4(rlo & 0x22222222u, rhi & 0x22222222u, rlo & 0x44444444u, rhi & 0x44444444u);
+    return __ballot(sr[q] != 0ull) != 0ull ? (1u << q) : 0u;
+  };
+  auto stage = [&](const u64 (&sr)[kMChunk], int buf) {
+    u32 zm = 0;
 #pragma unroll
-    for (int q = 0; q < kMChunk; ++q) {
-      const u32 lo = (u32)sr[q], hi = (u32)(sr[q] >> 32), rlo = rotr2(lo), rhi = rotr2(hi);
-      const int slot = q ^ ssw;
-      X[0][tt][slot] = make_uint4(lo & 0x22222222u, hi & 0x22222222u, lo & 0x44444444u, hi & 0x44444444u);
-      X[1][tt][slot] = make_uint4(rlo & 0x22222222u, rhi & 0x22222222u, rlo & 0x44444444u, rhi & 0x44444444u);
-    }
-    if (isa) {
-      u32 zm = 0;
-#pragma unroll
-      for (int q = 0; q < kMChunk; ++q) zm |= (__ballot(sr[q] != 0ull) != 0ull ? 1u : 0u) << q;
-      if (lane == 0) zmask[buf][wave] = zm;
-    }
+    for (int q = 0; q < kMChunk; ++q) zm |= stage_word(sr, buf, q);
+    if (isa && lane == 0) zmask[buf][wave] = zm;
   };
   u32 done_words = 0;  // words of k this wave ran the matrix cores on
   const int csw = (l32 >> 2) & 3;  // word-slot swizzle of every row this lane reads
-  auto compute = [&](int buf, uint4 (&av)[4], uint4 (&bv)[2], u32 mask) {
+  // the staging of the next chunk (sn into stage buf ^ 1) is interleaved word by word with the MFMA groups
+  auto compute = [&](int buf, uint4 (&av)[4], uint4 (&bv)[2], u32 mask, const u64 (&sn)[kMChunk], bool next) {
     const uint4* as = &Ax[buf][h][wr * 128 + l32][0];
     const uint4* bs = &Bx[buf][h][wc * 64 + l32][0];
     done_words += __builtin_popcount(mask);
+    u32 zm = 0;
     // operands of word q + 1 are read while word q is consumed
 #pragma unroll
     for (int q = 0; q < kMChunk; ++q) {
@@ -197,6 +197,7 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
           }
         }
       }
+      if (next) zm |= stage_word(sn, buf ^ 1, q);
       if (q + 1 < kMChunk) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) av[i] = an[i];
@@ -204,6 +205,7 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
         for (int j = 0; j < 2; ++j) bv[j] = bn[j];
       }
     }
+    if (next && isa && lane == 0) zmask[buf ^ 1][wave] = zm;
   };
   // Saturation: the sums only grow, so once every accumulator of a wave is positive its 128 x 64 outputs
   // are final (all ones), and the wave stops issuing matrix-core work.  The waves vote now and then (see
@@ -231,11 +233,9 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
     for (int j = 0; j < 2; ++j) bv[j] = Bx[buf][h][wc * 64 + l32 + 32 * j][0 ^ csw];
     // rows of this wave with a nonzero word q of k (wave-uniform)
     const u32 mask = wsat ? 0u : __builtin_amdgcn_readfirstlane(zmask[buf][2 * wr] | zmask[buf][2 * wr + 1]);
-    if (c + 1 < nchunks) {
-      stage(sn, buf ^ 1);
-      if (c + 3 < nchunks) load(sn, c + 3);
-    }
-    compute(buf, av, bv, mask);
+    const bool next = c + 1 < nchunks;
+    compute(buf, av, bv, mask, sn, next);
+    if (next && c + 3 < nchunks) load(sn, c + 3);
     return false;
   };
   load(s0, 0);

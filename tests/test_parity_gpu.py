@@ -247,19 +247,43 @@ def test_rms_path_graph_loop_counts(ctx, n):
 
 
 def test_rms_seminaive_squaring(ctx):
-    """A sparse random digraph at n = 8,192 (mean degree 1.6): its last squaring adds few bits, so the
-    next is done from them (R | D.R | R.D) rather than as a dense product.  Whole closure checked."""
+    """A sparse random digraph at n = 8,192 (mean degree 1.6): its last squaring adds 3,684 bits spread
+    over 159 rows, so the next is done from them (R | D.R | R.D) with R.D = (D^T . R^T)^T by a second
+    gather, rather than as a dense product.  Whole closure checked."""
     n = 8192
     s, d = gen.er_digraph(n, 2e-4, 5)
     R = gpu_pack(ctx, n, s, d)
     st = {}
     got = host(ctx.rms(R, n, stats=st))
-    assert B.ARM_PRODUCT_SEMINAIVE in st["arm_trace"], st["arm_trace"]
-    assert st["products"] + st["arm_trace"].count(B.ARM_PRODUCT_GATHER) == st["iterations"]
+    tr = st["arm_trace"]
+    assert B.ARM_PRODUCT_SEMINAIVE_T in tr, tr
+    assert st["products"] + tr.count(B.ARM_PRODUCT_GATHER) + tr.count(B.ARM_PRODUCT_SEMINAIVE_T) == st["iterations"]
     assert np.array_equal(got, oracle.closure_rows(n, s, d))
     # the same closure with every squaring a dense product
     got2 = host(ctx.rms(R, n, opts=B.make_opts(product_arm=B.ARM_PRODUCT_MFMA)))
     assert np.array_equal(got, got2)
+
+
+def test_rms_seminaive_both_routes(ctx):
+    """A chain of 200 nodes into a strongly connected core of 3,000 (n = 8,192): late squarings add the
+    whole core to a few chain rows, so R.D goes through the nonempty rows of D (a product with K = those
+    rows), while an earlier squaring whose new bits are spread thin takes the transposed gather.  Whole
+    closure checked against the oracle and against all-dense squarings."""
+    n = 8192
+    s, d = gen.tail_core(n, 3000, 200, 3.0, 11)
+    R = gpu_pack(ctx, n, s, d)
+    st = {}
+    got = host(ctx.rms(R, n, stats=st))
+    tr = st["arm_trace"]
+    print("tail_core arm trace", tr, flush=True)
+    assert B.ARM_PRODUCT_SEMINAIVE in tr and B.ARM_PRODUCT_SEMINAIVE_T in tr, tr
+    assert np.array_equal(got, oracle.closure_rows(n, s, d))
+    assert np.array_equal(got, host(ctx.rms(R, n, opts=B.make_opts(product_arm=B.ARM_PRODUCT_MFMA))))
+    # with a leading dimension beyond the words of a row (padding words must stay zero)
+    ld = boolops.words(n) + 3
+    R2 = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n, ld)
+    got2 = host(ctx.rms(R2, n))
+    assert np.array_equal(got2[:, :boolops.words(n)], got) and not got2[:, boolops.words(n):].any()
 
 
 def test_rms_special_graphs(ctx):
@@ -310,6 +334,25 @@ def test_smp_random(ctx, n, arm, reflexive, parm):
         want = oracle.smp(n, s, d, Vb, reflexive=bool(reflexive))
         assert np.array_equal(got, want), (n, p, arm, reflexive)
         assert st["arm"] == arm
+
+
+@pytest.mark.parametrize("reflexive", [0, 1])
+@pytest.mark.parametrize("n", [700, 3000, 16384])
+def test_smp_closure_heavy_query_rows(ctx, n, reflexive):
+    """Query rows from empty to full read off the closure: rows with more than 64 set bits are split over
+    several waves (the first 64 bits in place, the rest queued and ORed in with atomics)."""
+    rng = np.random.default_rng(77 + n)
+    s, d = gen.er_digraph(n, 2.5 / n, n)
+    dens = [0.0, 1.0 / n, 0.01, 0.05, 0.3, 0.9, 1.0]
+    k = 3 * len(dens)
+    V = np.zeros((k, n), np.uint8)
+    for i in range(k):
+        V[i] = rng.random(n) < dens[i % len(dens)]
+    Vb = boolops.to_bits(V)
+    R = gpu_pack(ctx, n, s, d)
+    got = host(ctx.smp(R, n, dev(Vb), opts=forced(smp_arm=B.ARM_SMP_CLOSURE, smp_reflexive=reflexive)))
+    want = oracle.smp(n, s, d, Vb, reflexive=bool(reflexive))
+    assert np.array_equal(got, want), (n, reflexive)
 
 
 def test_smp_first_config(ctx):
