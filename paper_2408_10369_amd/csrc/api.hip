@@ -47,7 +47,7 @@ void hip_check(hipError_t e, const char* what) {
 
 struct bmlp_ctx {
   int device = 0;
-  static constexpr int kSlots = 18;
+  static constexpr int kSlots = 20;
   void* slot[kSlots] = {};
   size_t slot_bytes[kSlots] = {};
   u32* d_flags = nullptr;  // device flags / counters
@@ -92,9 +92,10 @@ enum FlagSlot {
 
 // S_RD .. S_RL: the semi-naive squarings of rms_core (delta, its row-list, the column gather and the rows;
 // the transposed route also takes S_RA, S_RX and S_BT for D^T, R^T and the gathered product); S_GQ: the
-// overflow queue of the row gathers
+// overflow queue of the row gathers; S_RPT, S_CIT: the CSC (in-edges) of the one-launch selection (through
+// R^T in S_BT for a dense relation)
 enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH, S_RD, S_RA, S_RX, S_RL,
-            S_GQ };
+            S_GQ, S_RPT, S_CIT };
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -531,7 +532,7 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
 
 // CSR of the bit matrix R (n x n, ld) in workspace slots S_DEG/S_RP/S_CI.
 void build_csr(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const bmlp_opts& o, hipStream_t s, i64** rp_out,
-               int32_t** ci_out) {
+               int32_t** ci_out, i64* m_out = nullptr) {
   int32_t* deg = (int32_t*)ws(c, S_DEG, (size_t)n * sizeof(int32_t), o);
   i64* rp = (i64*)ws(c, S_RP, (size_t)(n + 1) * sizeof(i64), o);
   hip_check(launch_row_popcount(R, n, n, ld, deg, nullptr, s), "row_popcount");
@@ -545,7 +546,36 @@ void build_csr(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const bmlp_opts& o, hip
   hip_check(launch_bits_to_csr(R, n, n, ld, rp, ci, s), "bits_to_csr");
   *rp_out = rp;
   *ci_out = ci;
+  if (m_out) *m_out = m;
 }
+
+// CSC of R (the in-edges) in S_RPT/S_CIT, R given as bits (R, ld) and as its CSR (rp, ci; m edges).  A
+// sparse R is inverted from its CSR in O(n + m) with atomics; a denser one through R^T (formed in S_BT),
+// whose passes over n^2 bits beat m contended atomics once m passes about n^2 / 480 (n = 16,384: 45 us
+// against some 200 us at 2.7 M edges; n = 65,536 with 262,144 edges: 20 us against 0.7 ms).
+void build_csc(bmlp_ctx* c, const u64* R, i64 ld, const i64* rp, const int32_t* ci, i64 n, i64 m,
+               const bmlp_opts& o, hipStream_t s, i64** rpt_out, int32_t** cit_out) {
+  int32_t* degt = (int32_t*)ws(c, S_DEG, (size_t)(n + 1) * sizeof(int32_t), o);
+  i64* rpt = (i64*)ws(c, S_RPT, (size_t)(n + 1) * sizeof(i64), o);
+  int32_t* cit = (int32_t*)ws(c, S_CIT, (size_t)std::max<i64>(m, 1) * sizeof(int32_t), o);
+  if ((double)m * 480.0 < (double)n * (double)n) {
+    int32_t* cursor = (int32_t*)ws(c, S_RL, (size_t)(n + 1) * sizeof(int32_t), o);
+    hip_check(launch_csc_from_csr(rp, ci, n, m, degt, cursor, rpt, cit, s), "csc_from_csr");
+  } else {
+    const i64 nw = words_for(n);
+    u64* rt = ws_bits(c, S_BT, n, nw, o);
+    hip_check(launch_transpose(R, n, n, ld, rt, nw, s), "transpose");
+    hip_check(launch_row_popcount(rt, n, n, nw, degt, nullptr, s), "row_popcount");
+    hip_check(launch_scan_rowptr(degt, n, rpt, s), "scan");
+    hip_check(launch_bits_to_csr(rt, n, n, nw, rpt, cit, s), "bits_to_csr");
+  }
+  *rpt_out = rpt;
+  *cit_out = cit;
+}
+
+// The one-launch selection turns bottom-up in rounds whose frontier is large next to the unvisited set;
+// below this mean out-degree such rounds are too rare to pay for the in-edge index.
+constexpr double kBottomUpMinDegree = 4.0;
 
 // number of set bits of a bit matrix (device popcount, one readback)
 i64 count_bits(bmlp_ctx* c, const u64* R, i64 rows, i64 n, i64 ld, hipStream_t s) {
@@ -559,20 +589,22 @@ i64 count_bits(bmlp_ctx* c, const u64* R, i64 rows, i64 n, i64 ld, hipStream_t s
   return (i64)m;
 }
 
-// Plain schedule for the selection, from a timing sweep of the arms on
-// n = 4,096 and 16,384 random digraphs (mean out-degree 1.6 .. 164, k = 1 .. 1024):
-// the sparse-frontier arm wins while the mean out-degree is low (its work grows
-// with the edges it visits); the dense semi-naive arm wins on dense relations (its
-// work is independent of the degree).  Between degree 12 and 30 the sparse arm
-// still wins once 16 or more rows share the launch (degree 16, n = 16,384: k = 1
-// 0.42 ms dense vs 0.62 sparse, k = 64 0.75 vs 0.43); at degree 40 the dense arm
-// wins at every k (k = 1,024: 0.95 vs 2.75 ms).
+// Plain schedule for the selection, from a timing sweep of the two arms on random digraphs with
+// n = 4,096, 16,384 and 65,536, mean out-degree 1.6 .. 164 and k = 1 .. 1,024 query rows.  The
+// one-launch sparse arm turns bottom-up once the frontier is large, so its time hardly grows with the
+// degree; what it pays up front is the edge index (CSR, and CSC from degree 4), which grows with n.
+// It wins whenever 64 or more rows share the launch (n = 65,536, degree 40, k = 1,024: 1.6 ms against
+// 8.2 dense; n = 16,384, degree 164: 0.30 against 0.61) and at every k while the degree is low.  A few
+// rows of a dense relation are served faster by the dense rounds: at n = 16,384 from degree 12 below
+// k = 16 (degree 82, k = 1: 0.26 ms dense, 0.39 sparse), and above that size from degree 6 below k = 16
+// and from degree 12 below k = 64 (n = 65,536, degree 16, k = 16: 1.15 against 1.23).  At n = 4,096 the
+// sparse arm wins nearly everywhere.
 int smp_plain_arm(i64 n, i64 k, i64 m) {
   if (n > smp_rows_max_n()) return BMLP_ARM_SMP_DENSE;
   const double deg = n > 0 ? (double)m / (double)n : 0.0;
-  if (deg < 12.0) return BMLP_ARM_SMP_SPARSE;
-  if (deg < 30.0 && k >= 16) return BMLP_ARM_SMP_SPARSE;
-  return BMLP_ARM_SMP_DENSE;
+  if (k >= 64 || n <= 4096) return BMLP_ARM_SMP_SPARSE;
+  if (n <= 16384) return (deg < 12.0 || k >= 16) ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_DENSE;
+  return (deg < 6.0 || (deg < 12.0 && k >= 16)) ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_DENSE;
 }
 
 // ------------------------------------------------------------ dispatcher features
@@ -631,6 +663,8 @@ void make_features(float* f, const GraphInfo& g, i64 k, int compose, int call_le
 struct Csr {
   const i64* rp = nullptr;
   const int32_t* ci = nullptr;
+  const i64* rpt = nullptr;  // CSC (in-edges), optional
+  const int32_t* cit = nullptr;
 };
 
 // model inference for one feature vector on the device; returns the chosen output index
@@ -774,15 +808,26 @@ void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vsta
   if (c->trace) c->trace->call_arm = arm;
   if (arm == BMLP_ARM_SMP_SPARSE) {
     need(n <= smp_rows_max_n(), BMLP_EINVAL, "sparse SMP arm supports n <= %lld", (long long)smp_rows_max_n());
+    i64 m = gi.m;
     if (!csr.rp) {
       i64* rp;
       int32_t* ci;
-      build_csr(c, R1, ld, n, o, s, &rp, &ci);
+      build_csr(c, R1, ld, n, o, s, &rp, &ci, &m);
       csr.rp = rp;
       csr.ci = ci;
     }
+    const i64* rpt = csr.rpt;
+    const int32_t* cit = csr.cit;
+    if (!rpt && m > 0 && (double)m >= kBottomUpMinDegree * (double)n) {
+      i64* t;
+      int32_t* ct;
+      build_csc(c, R1, ld, csr.rp, csr.ci, n, m, o, s, &t, &ct);
+      rpt = t;
+      cit = ct;
+    }
     hip_check(hipMemsetAsync(c->d_flags + F_ROUNDS, 0, sizeof(u32), s), "hipMemsetAsync");
-    hip_check(launch_smp_rows(V, ldv, k, csr.rp, csr.ci, R1, ld, n, reflexive, Vstar, ldv, c->d_flags + F_ROUNDS, s),
+    hip_check(launch_smp_rows(V, ldv, k, csr.rp, csr.ci, rpt, cit, R1, ld, n, reflexive, Vstar, ldv,
+                              c->d_flags + F_ROUNDS, s),
               "smp_rows");
     const u32 rounds = read_flag(c, s, F_ROUNDS);
     need((i64)rounds <= n + 2, BMLP_EITER, "SMP exceeded the round cap");
@@ -1593,6 +1638,8 @@ struct bmlp_graph_s {
   GraphInfo gi;
   i64* rp = nullptr;        // owned CSR of R1
   int32_t* ci = nullptr;
+  i64* rpt = nullptr;       // owned CSC of R1 (when the mean degree makes bottom-up rounds pay)
+  int32_t* cit = nullptr;
   u64* closure = nullptr;   // owned R1+ (n x ceil(n/64)) once computed
   double spent_ms = 0.0;    // device time spent answering queries without the closure
 };
@@ -1891,10 +1938,25 @@ bmlp_status bmlp_graph_open(bmlp_handle h, const uint64_t* R1, int64_t n, int64_
         G->rp = (i64*)b1.p;
         G->ci = (int32_t*)b2.p;
         b1.p = b2.p = nullptr;
+        if (n <= smp_rows_max_n() && (double)G->gi.m >= kBottomUpMinDegree * (double)n) {
+          i64* rpt;
+          int32_t* cit;
+          build_csc(h, R1, ld, G->rp, G->ci, n, G->gi.m, o, s, &rpt, &cit);
+          DevBuf b3((size_t)(n + 1) * sizeof(i64)), b4((size_t)std::max<i64>(G->gi.m, 1) * sizeof(int32_t));
+          hip_check(hipMemcpyAsync(b3.p, rpt, (size_t)(n + 1) * sizeof(i64), hipMemcpyDeviceToDevice, s), "memcpy");
+          hip_check(hipMemcpyAsync(b4.p, cit, (size_t)G->gi.m * sizeof(int32_t), hipMemcpyDeviceToDevice, s),
+                    "memcpy");
+          hip_check(hipStreamSynchronize(s), "sync");
+          G->rpt = (i64*)b3.p;
+          G->cit = (int32_t*)b4.p;
+          b3.p = b4.p = nullptr;
+        }
       }
     } catch (...) {
       if (G->rp) (void)hipFree(G->rp);
       if (G->ci) (void)hipFree(G->ci);
+      if (G->rpt) (void)hipFree(G->rpt);
+      if (G->cit) (void)hipFree(G->cit);
       delete G;
       throw;
     }
@@ -1911,6 +1973,8 @@ bmlp_status bmlp_graph_close(bmlp_graph g) {
     (void)hipDeviceSynchronize();
     if (g->rp) (void)hipFree(g->rp);
     if (g->ci) (void)hipFree(g->ci);
+    if (g->rpt) (void)hipFree(g->rpt);
+    if (g->cit) (void)hipFree(g->cit);
     if (g->closure) (void)hipFree(g->closure);
     delete g;
   });
@@ -1966,7 +2030,7 @@ bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t* V, uint64_t* Vstar, i
         } else {
           hip_check(hipEventRecord(h->ev1, s), "hipEventRecord");
           if (h->trace) h->trace->call_arm = arm;
-          smp_core(h, g->R1, g->ld, n, V, Vstar, k, ldv, refl, arm, g->gi, 0, Csr{g->rp, g->ci}, o, s, sr);
+          smp_core(h, g->R1, g->ld, n, V, Vstar, k, ldv, refl, arm, g->gi, 0, Csr{g->rp, g->ci, g->rpt, g->cit}, o, s, sr);
           hip_check(hipEventRecord(h->evp1, s), "hipEventRecord");
           hip_check(hipEventSynchronize(h->evp1), "hipEventSynchronize");
           float ms = 0.f;

@@ -56,6 +56,10 @@ hipError_t launch_row_popcount(const u64* a, i64 rows, i64 n, i64 ld, int32_t* d
 hipError_t launch_popcount_total(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* total, hipStream_t s);
 // exclusive scan of deg[0..n) into rp[0..n] (int64); single-workgroup
 hipError_t launch_scan_rowptr(const int32_t* deg, i64 n, i64* rp, hipStream_t s);
+// CSC (rpt, cit: in-edges) of an n-node CSR (rp, ci) with m edges; degt and cursor are n int32 of
+// workspace (8-byte aligned).  The order inside each CSC segment is unspecified.
+hipError_t launch_csc_from_csr(const i64* rp, const int32_t* ci, i64 n, i64 m, int32_t* degt, int32_t* cursor,
+                               i64* rpt, int32_t* cit, hipStream_t s);
 // CSR column indices of the set bits of each row (rp from launch_scan_rowptr)
 hipError_t launch_bits_to_csr(const u64* a, i64 rows, i64 n, i64 ld, const i64* rp, int32_t* ci, hipStream_t s);
 
@@ -89,9 +93,11 @@ i64 gemm_mfma_max_kwords();
 // ---------------------------------------------------------------- selection
 // Per-row fixpoint of the semi-naive selection in one launch (one workgroup
 // per query row, bitmaps in LDS): out[r] = V[r] R+ (reflexive: V[r] R*).
-// Needs CSR (rp, ci) of R and the bit rows of R (for dense frontier nodes).
-hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const u64* R, i64 ldr,
-                           i64 n, int reflexive, u64* out, i64 ldo, u32* iters_max, hipStream_t s);
+// Needs CSR (rp, ci) of R and the bit rows of R (for dense frontier nodes); with the CSC (rpt, cit: the
+// in-edges, optional) rounds with a large frontier run bottom-up.
+hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const i64* rpt,
+                           const int32_t* cit, const u64* R, i64 ldr, i64 n, int reflexive, u64* out, i64 ldo,
+                           u32* iters_max, hipStream_t s);
 i64 smp_rows_max_n();
 // One semi-naive round for k rows with the state in global memory: nxt = fr . R1 (CSR),
 // fr_out = nxt & ~vis, vis |= fr_out.  Runs only when *pred == pred_val (pred optional).

@@ -491,6 +491,28 @@ __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict_
 }
 
 // one wave per row; lanes own consecutive words
+// CSC (in-edges) from a CSR: in-degrees counted with atomics, then each edge (u, v) placed in v's
+// segment at a slot taken from v's cursor.  The order inside a segment is whichever the atomics give.
+__global__ void k_csc_count(const int32_t* __restrict__ ci, i64 m, int32_t* __restrict__ degt) {
+  for (i64 e = blockIdx.x * (i64)blockDim.x + threadIdx.x; e < m; e += (i64)gridDim.x * blockDim.x)
+    atomicAdd(&degt[ci[e]], 1);
+}
+
+__global__ void k_csc_fill(const i64* __restrict__ rp, const int32_t* __restrict__ ci, i64 n, i64 m,
+                           const i64* __restrict__ rpt, int32_t* __restrict__ cursor, int32_t* __restrict__ cit) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 u = wave; u < n; u += nwaves) {
+    const i64 e1 = rp[u + 1];
+    for (i64 e = rp[u] + lane; e < e1; e += 64) {
+      const int32_t v = ci[e];
+      const i64 pos = rpt[v] + atomicAdd(&cursor[v], 1);
+      if (pos < m) cit[pos] = (int32_t)u;  // always: the CSR holds m edges
+    }
+  }
+}
+
 __global__ void k_bits_to_csr(const u64* __restrict__ a, i64 rows, i64 n, i64 ld, const i64* __restrict__ rp,
                               int32_t* __restrict__ ci) {
   const int lane = threadIdx.x & 63;
@@ -666,6 +688,25 @@ hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned lo
 hipError_t launch_scan_rowptr(const int32_t* deg, i64 n, i64* rp, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_rowptr, dim3(1), dim3(1024), 0, s, deg, n, rp);
   return hipGetLastError();
+}
+
+hipError_t launch_csc_from_csr(const i64* rp, const int32_t* ci, i64 n, i64 m, int32_t* degt, int32_t* cursor,
+                               i64* rpt, int32_t* cit, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = launch_fill_zero((u64*)degt, (n + 1) / 2, s);
+  if (e == hipSuccess) e = launch_fill_zero((u64*)cursor, (n + 1) / 2, s);
+  if (e != hipSuccess) return e;
+  if (m > 0) {
+    hipLaunchKernelGGL(k_csc_count, dim3(grid_for(m, kBlock, 16384)), dim3(kBlock), 0, s, ci, m, degt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = launch_scan_rowptr(degt, n, rpt, s)) != hipSuccess) return e;
+  if (m > 0) {
+    hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(n * 64, kBlock, 16384)), dim3(kBlock), 0, s, rp, ci, n, m, rpt,
+                       cursor, cit);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_bits_to_csr(const u64* a, i64 rows, i64 n, i64 ld, const i64* rp, int32_t* ci, hipStream_t s) {

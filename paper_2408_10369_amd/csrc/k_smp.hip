@@ -31,81 +31,133 @@ constexpr i64 kMaxLdsWords = 6144;  // 3 bitmaps x 2048 words = 48 KiB (n <= 131
 
 __global__ void __launch_bounds__(kSmpThreads)
 k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp, const int32_t* __restrict__ ci,
-           const u64* __restrict__ R, i64 ldr, i64 n, int reflexive, u64* __restrict__ out, i64 ldo,
-           u32* __restrict__ iters_max) {
+           const i64* __restrict__ rpt, const int32_t* __restrict__ cit, const u64* __restrict__ R, i64 ldr, i64 n,
+           int reflexive, u64* __restrict__ out, i64 ldo, u32* __restrict__ iters_max) {
   extern __shared__ u64 smem[];
   __shared__ int32_t hubs[kHubCap];
   __shared__ int nhubs;
+  __shared__ u32 cnt[2][2];  // by round parity: frontier size, visited size
   const i64 nw = (n + 63) >> 6;
   u64* vis = smem;
   u64* fr = smem + nw;
   u64* nxt = smem + 2 * nw;
   u32* nxt32 = (u32*)nxt;
   const int t = threadIdx.x;
+  const int lane = t & 63;
   // columns >= n never enter a bitmap, whatever the padding bits of the inputs hold
   const u64 last_mask = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
+  const double davg = (double)rp[n] / (double)(n > 0 ? n : 1);  // mean out-degree
 
   for (i64 row = blockIdx.x; row < k; row += gridDim.x) {
+    if (t < 4) cnt[t >> 1][t & 1] = 0u;
+    if (t == 0) nhubs = 0;
+    __syncthreads();
+    u32 nf0 = 0;
     for (i64 w = t; w < nw; w += kSmpThreads) {
       vis[w] = 0ull;
-      fr[w] = V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
+      const u64 f = V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
+      fr[w] = f;
       nxt[w] = 0ull;
+      nf0 += (u32)__popcll(f);
     }
-    if (t == 0) nhubs = 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nf0 += __shfl_xor(nf0, off, 64);
+    if (lane == 0 && nf0) atomicAdd(&cnt[0][0], nf0);
     __syncthreads();
     u32 rounds = 0;
     for (;;) {
+      const int par = (int)(rounds & 1u);
       ++rounds;
-      // expand the frontier
-      for (i64 w = t; w < nw; w += kSmpThreads) {
-        u64 x = fr[w];
-        while (x) {
-          const int b = __ffsll((unsigned long long)x) - 1;
-          x &= x - 1;
-          const i64 u = w * 64 + b;
+      // direction of this round (the same in every thread): top-down visits the out-edges of the
+      // frontier, bottom-up the in-edges of the unvisited nodes until one comes from the frontier
+      const double nf = (double)cnt[par][0], nu = (double)n - (double)cnt[par][1];
+      const bool bottom_up = rpt && nf * davg > nu * fmin(davg, (double)n / fmax(nf, 1.0));
+      if (t < 2) cnt[par ^ 1][t] = 0u;  // read above; the syncs below order it before the next counts
+      if (bottom_up) {
+        for (i64 w = t; w < nw; w += kSmpThreads) {
+          u64 cand = ~vis[w] & (w == nw - 1 ? last_mask : ~0ull);
+          u64 found = 0ull;
+          while (cand) {
+            const int b = __ffsll((unsigned long long)cand) - 1;
+            cand &= cand - 1;
+            const i64 v = w * 64 + b;
+            const i64 e1 = rpt[v + 1];
+            for (i64 e = rpt[v]; e < e1; ++e) {
+              const int32_t u = cit[e];
+              if ((fr[u >> 6] >> (u & 63)) & 1ull) {
+                found |= 1ull << b;
+                break;
+              }
+            }
+          }
+          nxt[w] = found;
+        }
+        __syncthreads();
+      } else {
+        // expand the frontier
+        for (i64 w = t; w < nw; w += kSmpThreads) {
+          u64 x = fr[w];
+          while (x) {
+            const int b = __ffsll((unsigned long long)x) - 1;
+            x &= x - 1;
+            const i64 u = w * 64 + b;
+            const i64 e0 = rp[u], e1 = rp[u + 1];
+            if (e1 - e0 > kHubDeg) {
+              const int slot = atomicAdd(&nhubs, 1);
+              if (slot < kHubCap) {
+                hubs[slot] = (int32_t)u;
+                continue;
+              }
+            }
+            for (i64 e = e0; e < e1; ++e) {
+              const int32_t v = ci[e];
+              atomicOr(&nxt32[v >> 5], 1u << (v & 31));
+            }
+          }
+        }
+        __syncthreads();
+        const int nh = nhubs < kHubCap ? nhubs : kHubCap;
+        for (int h = 0; h < nh; ++h) {
+          const i64 u = hubs[h];
           const i64 e0 = rp[u], e1 = rp[u + 1];
-          if (e1 - e0 > kHubDeg) {
-            const int slot = atomicAdd(&nhubs, 1);
-            if (slot < kHubCap) {
-              hubs[slot] = (int32_t)u;
-              continue;
+          if (R && (e1 - e0) * 2 > nw) {
+            for (i64 w = t; w < nw; w += kSmpThreads) {
+              const u64 x = R[u * ldr + w];
+              if (x) {
+                atomicOr(&nxt32[2 * w], (u32)x);
+                atomicOr(&nxt32[2 * w + 1], (u32)(x >> 32));
+              }
+            }
+          } else {
+            for (i64 e = e0 + t; e < e1; e += kSmpThreads) {
+              const int32_t v = ci[e];
+              atomicOr(&nxt32[v >> 5], 1u << (v & 31));
             }
           }
-          for (i64 e = e0; e < e1; ++e) {
-            const int32_t v = ci[e];
-            atomicOr(&nxt32[v >> 5], 1u << (v & 31));
-          }
         }
+        __syncthreads();
       }
-      __syncthreads();
-      const int nh = nhubs < kHubCap ? nhubs : kHubCap;
-      for (int h = 0; h < nh; ++h) {
-        const i64 u = hubs[h];
-        const i64 e0 = rp[u], e1 = rp[u + 1];
-        if (R && (e1 - e0) * 2 > nw) {
-          for (i64 w = t; w < nw; w += kSmpThreads) {
-            const u64 x = R[u * ldr + w];
-            if (x) {
-              atomicOr(&nxt32[2 * w], (u32)x);
-              atomicOr(&nxt32[2 * w + 1], (u32)(x >> 32));
-            }
-          }
-        } else {
-          for (i64 e = e0 + t; e < e1; e += kSmpThreads) {
-            const int32_t v = ci[e];
-            atomicOr(&nxt32[v >> 5], 1u << (v & 31));
-          }
-        }
-      }
-      __syncthreads();
       // fr = nxt & ~vis ; vis |= fr ; nxt = 0
       int any = 0;
+      u32 lf = 0, lv = 0;
       for (i64 w = t; w < nw; w += kSmpThreads) {
         const u64 nv = nxt[w] & ~vis[w] & (w == nw - 1 ? last_mask : ~0ull);
-        vis[w] |= nv;
+        const u64 vv = vis[w] | nv;
+        vis[w] = vv;
         fr[w] = nv;
         nxt[w] = 0ull;
         any |= (nv != 0ull);
+        lf += (u32)__popcll(nv);
+        lv += (u32)__popcll(vv);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        lf += __shfl_xor(lf, off, 64);
+        lv += __shfl_xor(lv, off, 64);
+      }
+      if (lane == 0) {
+        if (lf) atomicAdd(&cnt[par ^ 1][0], lf);
+        if (lv) atomicAdd(&cnt[par ^ 1][1], lv);
       }
       if (t == 0) nhubs = 0;
       if (!__syncthreads_or(any)) break;
@@ -601,15 +653,16 @@ hipError_t launch_smp_round(const u64* fr, u64* fr_out, i64 ldf, u64* vis, i64 l
   return hipGetLastError();
 }
 
-hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const u64* R, i64 ldr,
-                           i64 n, int reflexive, u64* out, i64 ldo, u32* iters_max, hipStream_t s) {
+hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const i64* rpt,
+                           const int32_t* cit, const u64* R, i64 ldr, i64 n, int reflexive, u64* out, i64 ldo,
+                           u32* iters_max, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   const i64 nw = words_for(n);
   if (3 * nw > kMaxLdsWords) return hipErrorInvalidValue;
   const size_t lds = (size_t)(3 * nw) * sizeof(u64);
   const unsigned grid = (unsigned)(k < 65535 ? k : 65535);
-  hipLaunchKernelGGL(k_smp_rows, dim3(grid), dim3(kSmpThreads), lds, s, V, ldv, k, rp, ci, R, ldr, n, reflexive, out,
-                     ldo, iters_max);
+  hipLaunchKernelGGL(k_smp_rows, dim3(grid), dim3(kSmpThreads), lds, s, V, ldv, k, rp, ci, rpt, cit, R, ldr, n,
+                     reflexive, out, ldo, iters_max);
   return hipGetLastError();
 }
 

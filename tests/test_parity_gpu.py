@@ -355,6 +355,31 @@ def test_smp_closure_heavy_query_rows(ctx, n, reflexive):
     assert np.array_equal(got, want), (n, reflexive)
 
 
+@pytest.mark.parametrize("n,deg", [(4096, 5.0), (4096, 12.0), (9000, 40.0), (16384, 82.0)])
+def test_smp_bottom_up_rounds(ctx, n, deg):
+    """The one-launch arm turns bottom-up (in-edges of the unvisited nodes) once the frontier is large;
+    its in-edge index is built from the CSR with atomics for a sparse relation (n = 4,096, degree 5) and
+    through R^T otherwise.  Single sources, hubs of a skewed degree sequence and a reflexive call."""
+    rng = np.random.default_rng(int(n + deg))
+    s, d = gen.er_digraph(n, deg / n, int(deg * 100) + n)
+    # a few hubs with a quarter of the nodes as successors
+    hubs = rng.choice(n, 3, replace=False)
+    hs = np.repeat(hubs, n // 4).astype(np.int32)
+    hd = rng.integers(0, n, hs.size).astype(np.int32)
+    s, d = np.r_[s, hs].astype(np.int32), np.r_[d, hd].astype(np.int32)
+    k = 40
+    V = np.zeros((k, n), np.uint8)
+    V[np.arange(k), rng.integers(0, n, k)] = 1
+    V[-5:] |= (rng.random((5, n)) < 0.01).astype(np.uint8)
+    Vb = boolops.to_bits(V)
+    R = gpu_pack(ctx, n, s, d)
+    for refl in (0, 1):
+        st = {}
+        got = host(ctx.smp(R, n, dev(Vb), opts=forced(smp_arm=B.ARM_SMP_SPARSE, smp_reflexive=refl), stats=st))
+        want = oracle.smp(n, s, d, Vb, reflexive=bool(refl))
+        assert np.array_equal(got, want), (n, deg, refl, st.get("iterations"))
+
+
 def test_smp_first_config(ctx):
     n, s, d, srcs = gen.c1()
     R = gpu_pack(ctx, n, s, d)
