@@ -42,7 +42,7 @@ KERNELS = {0: ("k_gemm_valu", "bit-packed Boolean product on the VALU", "alu", V
 GEMM_TRAFFIC = {"k_gemm_mfma": {"sources": ["paper_2408_10369_amd/csrc/k_gemm.hip",
                                             "paper_2408_10369_amd/csrc/mfma_tile.h"],
                                 "sha256": "896c2ac62096b80e7cbd9e687a083aa9d941384d52e7cfdd26658ba46d585f0c",
-                                "bytes_per_launch": 306.5e6}}
+                                "bytes_per_launch": 438.0e6}}
 
 
 def measured_traffic(kernel):
