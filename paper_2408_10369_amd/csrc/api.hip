@@ -47,7 +47,7 @@ void hip_check(hipError_t e, const char* what) {
 
 struct bmlp_ctx {
   int device = 0;
-  static constexpr int kSlots = 20;
+  static constexpr int kSlots = 21;
   void* slot[kSlots] = {};
   size_t slot_bytes[kSlots] = {};
   u32* d_flags = nullptr;  // device flags / counters
@@ -93,9 +93,9 @@ enum FlagSlot {
 // S_RD .. S_RL: the semi-naive squarings of rms_core (delta, its row-list, the column gather and the rows;
 // the transposed route also takes S_RA, S_RX and S_BT for D^T, R^T and the gathered product); S_GQ: the
 // overflow queue of the row gathers; S_RPT, S_CIT: the CSC (in-edges) of the one-launch selection (through
-// R^T in S_BT for a dense relation)
+// R^T in S_BT for a dense relation); S_PERM: a relabelling of the nodes and its inverse (rms_core)
 enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH, S_RD, S_RA, S_RX, S_RL,
-            S_GQ, S_RPT, S_CIT };
+            S_GQ, S_RPT, S_CIT, S_PERM };
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -405,6 +405,77 @@ double rms_semi_cols_s(const SemiCost& c, i64 drows) {
 }
 constexpr double kSemiOverheadS = 50.0e-6;  // launches and the readbacks of the semi-naive route
 
+struct GraphInfo {
+  i64 n = 0, m = 0, maxdeg = 0, nonempty = 0;
+};
+
+GraphInfo graph_info(bmlp_ctx* c, const u64* R, i64 ld, i64 n, hipStream_t s) {
+  GraphInfo g;
+  g.n = n;
+  if (n <= 0) return g;
+  unsigned long long* out = (unsigned long long*)(c->d_flags + F_GSTATS);
+  hip_check(hipMemsetAsync(out, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
+  hip_check(launch_graph_stats(R, n, n, ld, out, s), "graph_stats");
+  hip_check(hipMemcpyAsync(c->h_flags + F_GSTATS, out, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+            "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");
+  unsigned long long v[3];
+  std::memcpy(v, c->h_flags + F_GSTATS, sizeof v);
+  g.m = (i64)v[0];
+  g.maxdeg = (i64)v[1];
+  g.nonempty = (i64)v[2];
+  return g;
+}
+
+// Relabelling before the dense squarings.  Where a relation's closure is one big block -- the rows that
+// reach a giant strongly connected part times the columns it reaches, the sparse random digraphs just
+// above the percolation threshold -- the block is spread over every 256 x 256 output tile in the given
+// node order, so no tile is all ones (copied), saturates early or has all-zero rows (skipped).  With the
+// nodes ordered by class (heavy row and light column, heavy both, light row and heavy column, light
+// both; heavy = at least a quarter of the largest popcount) the block becomes a few contiguous
+// rectangles.  The squarings are the same up to the relabelling, (P R P^T)^2 = P R^2 P^T, and the
+// closure is mapped back at the end.  Returns false (nothing to gain) unless the rows or the columns
+// split into the two classes with at least 2% heavy and 10% light.
+bool rms_relabel(bmlp_ctx* c, const u64* cur, i64 ld, i64 n, const bmlp_opts& o, hipStream_t s, int32_t** perm_out,
+                 int32_t** inv_out) {
+  const i64 nw = words_for(n);
+  int32_t* rowpop = (int32_t*)ws(c, S_DEG, (size_t)n * sizeof(int32_t), o);
+  int32_t* colpop = (int32_t*)ws(c, S_RL, (size_t)n * sizeof(int32_t), o);
+  u64* ct = ws_bits(c, S_BT, n, nw, o);
+  hip_check(launch_row_popcount(cur, n, n, ld, rowpop, nullptr, s), "row_popcount");
+  hip_check(launch_transpose(cur, n, n, ld, ct, nw, s), "transpose");
+  hip_check(launch_row_popcount(ct, n, n, nw, colpop, nullptr, s), "row_popcount");
+  std::vector<int32_t> rp((size_t)n), cp((size_t)n);
+  hip_check(hipMemcpyAsync(rp.data(), rowpop, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
+  hip_check(hipMemcpyAsync(cp.data(), colpop, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");
+  const int32_t rmax = *std::max_element(rp.begin(), rp.end());
+  const int32_t cmax = *std::max_element(cp.begin(), cp.end());
+  if (rmax <= 0 || cmax <= 0) return false;
+  std::vector<int> cls((size_t)n);
+  i64 hin = 0, hout = 0;
+  for (i64 v = 0; v < n; ++v) {
+    const bool in = 4 * (i64)rp[v] >= rmax, out = 4 * (i64)cp[v] >= cmax;
+    hin += in;
+    hout += out;
+    cls[v] = in ? (out ? 1 : 0) : (out ? 2 : 3);
+  }
+  auto splits = [&](i64 h) { return h * 50 >= n && h * 10 <= 9 * n; };  // a light class of at least 10%
+  if (!splits(hin) && !splits(hout)) return false;
+  std::vector<int32_t> perm((size_t)(2 * n));
+  i64 at = 0;
+  for (int k = 0; k < 4; ++k)
+    for (i64 v = 0; v < n; ++v)
+      if (cls[v] == k) perm[at++] = (int32_t)v;
+  for (i64 i = 0; i < n; ++i) perm[n + perm[i]] = (int32_t)i;
+  int32_t* d = (int32_t*)ws(c, S_PERM, (size_t)(2 * n) * sizeof(int32_t), o);
+  hip_check(hipMemcpyAsync(d, perm.data(), (size_t)(2 * n) * sizeof(int32_t), hipMemcpyHostToDevice, s), "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");  // the host vector goes out of scope
+  *perm_out = d;
+  *inv_out = d + n;
+  return true;
+}
+
 // R1+ into `out` (n x ldo) -- the RMS fixpoint driver shared by rms, the closure arm of smp and the RMS
 // route of compose.  `R1` has leading dimension ld1.  With the product arm left to the library, each
 // squaring of a still sparse R is done by row gathers (the bit count of R is kept from the kernels'
@@ -419,7 +490,8 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   hip_check(launch_ewise(4, R1, ld1, nullptr, 0, cur, ldi, n, n, s), "copy");
   if (o.rms_variant == 1) hip_check(launch_set_diag(cur, ldi, n, n, s), "set_diag");
   bool may_gather = o.product_arm == BMLP_ARM_AUTO && n <= gather_rows_max_n();
-  i64 bits = may_gather ? count_bits(c, cur, n, n, ldi, s) : 0;
+  const GraphInfo g0 = may_gather ? graph_info(c, cur, ldi, n, s) : GraphInfo{};
+  i64 bits = g0.m;
   // Semi-naive squarings need D = R_t & ~R_{t-1}: it is formed at the start of a squaring (the other
   // buffer still holds R_{t-1}) when the new-bit count of the last squaring says it may pay.
   const bool may_semi = o.product_arm == BMLP_ARM_AUTO && n <= gather_rows_max_n() && n <= gather_cols_max_n();
@@ -427,6 +499,12 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   i64 dbits = 0;
   unsigned long long* nb = (unsigned long long*)(c->d_flags + F_NEW);
   const GatherQueue gq = may_gather ? gather_queue(c, n, n, o) : GatherQueue{nullptr, nullptr, 0};
+  // relabel (once) before the first dense squaring on the matrix cores, when a tenth or more of the rows
+  // are empty (a light class is certain) and the squarings are large enough to repay the passes over the
+  // matrix (at n = 8,192 they do not); inv maps the closure back
+  bool may_relabel = may_gather && o.rms_variant == 0 && arm == BMLP_ARM_PRODUCT_MFMA && n >= 16384 &&
+                     (n - g0.nonempty) * 10 >= n;
+  const int32_t* inv = nullptr;
   const int cap = ceil_log2(std::max<i64>(n, 2)) + 2;
   int it = 0;
   for (;;) {
@@ -499,6 +577,17 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
       if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
       tarm = BMLP_ARM_PRODUCT_SEMINAIVE_T;
     } else {
+      if (may_relabel) {
+        may_relabel = false;
+        int32_t* perm;
+        int32_t* pinv;
+        if (rms_relabel(c, cur, ldi, n, o, s, &perm, &pinv)) {
+          // R_{t-1} in nxt is not needed by a dense squaring; the next one finds both in the new labels
+          hip_check(launch_permute(cur, ldi, perm, n, nxt, ldi, s), "permute");
+          std::swap(cur, nxt);
+          inv = pinv;
+        }
+      }
       product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, c->d_flags, arm, s, sr, nullptr, 0,
               nb);
     }
@@ -524,6 +613,8 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   if (o.rms_variant == 1) {
     // Algorithm 1, last line: R2* = R2* R1
     product(c, cur, ldi, R1, ld1, nullptr, 0, out, ldo, nullptr, 0, n, n, n, nullptr, arm, s, sr);
+  } else if (inv) {
+    hip_check(launch_permute(cur, ldi, inv, n, out, ldo, s), "permute");
   } else {
     hip_check(launch_ewise(4, cur, ldi, nullptr, 0, out, ldo, n, n, s), "copy");
   }
@@ -531,17 +622,20 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
 }
 
 // CSR of the bit matrix R (n x n, ld) in workspace slots S_DEG/S_RP/S_CI.
+// With m_known >= 0 (the number of set bits of R, counted by the caller) the size needs no readback.
 void build_csr(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const bmlp_opts& o, hipStream_t s, i64** rp_out,
-               int32_t** ci_out, i64* m_out = nullptr) {
+               int32_t** ci_out, i64* m_out = nullptr, i64 m_known = -1) {
   int32_t* deg = (int32_t*)ws(c, S_DEG, (size_t)n * sizeof(int32_t), o);
   i64* rp = (i64*)ws(c, S_RP, (size_t)(n + 1) * sizeof(i64), o);
   hip_check(launch_row_popcount(R, n, n, ld, deg, nullptr, s), "row_popcount");
   hip_check(launch_scan_rowptr(deg, n, rp, s), "scan");
-  // the scan's last entry is the number of set bits
-  hip_check(hipMemcpyAsync(c->h_flags + 4, rp + n, sizeof(i64), hipMemcpyDeviceToHost, s), "memcpy");
-  hip_check(hipStreamSynchronize(s), "sync");
-  i64 m = 0;
-  std::memcpy(&m, c->h_flags + 4, sizeof m);
+  i64 m = m_known;
+  if (m < 0) {
+    // the scan's last entry is the number of set bits
+    hip_check(hipMemcpyAsync(c->h_flags + 4, rp + n, sizeof(i64), hipMemcpyDeviceToHost, s), "memcpy");
+    hip_check(hipStreamSynchronize(s), "sync");
+    std::memcpy(&m, c->h_flags + 4, sizeof m);
+  }
   int32_t* ci = (int32_t*)ws(c, S_CI, (size_t)std::max<i64>(m, 1) * sizeof(int32_t), o);
   hip_check(launch_bits_to_csr(R, n, n, ld, rp, ci, s), "bits_to_csr");
   *rp_out = rp;
@@ -608,27 +702,6 @@ int smp_plain_arm(i64 n, i64 k, i64 m) {
 }
 
 // ------------------------------------------------------------ dispatcher features
-struct GraphInfo {
-  i64 n = 0, m = 0, maxdeg = 0, nonempty = 0;
-};
-
-GraphInfo graph_info(bmlp_ctx* c, const u64* R, i64 ld, i64 n, hipStream_t s) {
-  GraphInfo g;
-  g.n = n;
-  if (n <= 0) return g;
-  unsigned long long* out = (unsigned long long*)(c->d_flags + F_GSTATS);
-  hip_check(hipMemsetAsync(out, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
-  hip_check(launch_graph_stats(R, n, n, ld, out, s), "graph_stats");
-  hip_check(hipMemcpyAsync(c->h_flags + F_GSTATS, out, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
-            "memcpy");
-  hip_check(hipStreamSynchronize(s), "sync");
-  unsigned long long v[3];
-  std::memcpy(v, c->h_flags + F_GSTATS, sizeof v);
-  g.m = (i64)v[0];
-  g.maxdeg = (i64)v[1];
-  g.nonempty = (i64)v[2];
-  return g;
-}
 
 // The 16 dispatcher features (all O(1) to compute from counters the drivers keep):
 //  0 log2(1+n)/16            1 log2(1+m)/24             2 log2(1+m/n)/8 (mean degree)
@@ -812,7 +885,8 @@ void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vsta
     if (!csr.rp) {
       i64* rp;
       int32_t* ci;
-      build_csr(c, R1, ld, n, o, s, &rp, &ci, &m);
+      // gi describes R1 when it was counted (gi.n == n); its bit count then sizes the CSR
+      build_csr(c, R1, ld, n, o, s, &rp, &ci, &m, gi.n == n && gi.m > 0 ? gi.m : -1);
       csr.rp = rp;
       csr.ci = ci;
     }

@@ -491,6 +491,42 @@ __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict_
 }
 
 // one wave per row; lanes own consecutive words
+// Relabelling of the nodes: dst[i][j] = src[perm[i]][perm[j]] for i, j < n (padding words of dst zero).
+// One workgroup per output row with the source row staged in LDS; each output word is one wave's
+// ballot over its 64 columns (lane b reads perm[64 w + b], so the perm reads are whole lines).
+__global__ void __launch_bounds__(256)
+k_permute(const u64* __restrict__ src, i64 lds_, const int32_t* __restrict__ perm, i64 n, u64* __restrict__ dst,
+          i64 ldd) {
+  extern __shared__ u64 srow[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const i64 nw = (n + 63) >> 6;
+  for (i64 i = blockIdx.x; i < n; i += gridDim.x) {
+    const i64 pi = perm[i];
+    const bool ok = pi >= 0 && pi < n;
+    for (i64 w = threadIdx.x; w < nw; w += 256) srow[w] = ok ? src[pi * lds_ + w] : 0ull;
+    __syncthreads();
+    // eight words per pass, their perm loads issued together
+    for (i64 w0 = wv * 8; w0 < ldd; w0 += 32) {
+      int32_t cs[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const i64 j = (w0 + q) * 64 + lane;
+        cs[q] = (w0 + q < nw && j < n) ? perm[j] : -1;
+      }
+      u64 keep = 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t c = cs[q];
+        const bool bit = c >= 0 && c < n && ((srow[c >> 6] >> (c & 63)) & 1ull);
+        const u64 v = __ballot(bit);
+        if (lane == q) keep = v;
+      }
+      if (lane < 8 && w0 + lane < ldd) dst[i * ldd + w0 + lane] = keep;
+    }
+    __syncthreads();
+  }
+}
+
 // CSC (in-edges) from a CSR: in-degrees counted with atomics, then each edge (u, v) placed in v's
 // segment at a slot taken from v's cursor.  The order inside a segment is whichever the atomics give.
 __global__ void k_csc_count(const int32_t* __restrict__ ci, i64 m, int32_t* __restrict__ degt) {
@@ -687,6 +723,15 @@ hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned lo
 
 hipError_t launch_scan_rowptr(const int32_t* deg, i64 n, i64* rp, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_rowptr, dim3(1), dim3(1024), 0, s, deg, n, rp);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const u64* src, i64 lds_, const int32_t* perm, i64 n, u64* dst, i64 ldd, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t lds = (size_t)words_for(n) * sizeof(u64);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)(n < 65535 ? n : 65535)), dim3(256), lds, s, src, lds_, perm, n, dst,
+                     ldd);
   return hipGetLastError();
 }
 

@@ -150,14 +150,16 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
         lf += (u32)__popcll(nv);
         lv += (u32)__popcll(vv);
       }
+      if (rpt) {  // the counts only steer the direction
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        lf += __shfl_xor(lf, off, 64);
-        lv += __shfl_xor(lv, off, 64);
-      }
-      if (lane == 0) {
-        if (lf) atomicAdd(&cnt[par ^ 1][0], lf);
-        if (lv) atomicAdd(&cnt[par ^ 1][1], lv);
+        for (int off = 32; off > 0; off >>= 1) {
+          lf += __shfl_xor(lf, off, 64);
+          lv += __shfl_xor(lv, off, 64);
+        }
+        if (lane == 0) {
+          if (lf) atomicAdd(&cnt[par ^ 1][0], lf);
+          if (lv) atomicAdd(&cnt[par ^ 1][1], lv);
+        }
       }
       if (t == 0) nhubs = 0;
       if (!__syncthreads_or(any)) break;

@@ -59,7 +59,7 @@ struct MfmaLds {
   uint4 Ax[2][2][kMT][kMChunk];  // per stage, lane half h, row and word slot: the dwords half h feeds in
   uint4 Bx[2][2][kMT][kMChunk];
   u64 bal[8][2][16];
-  u32 zmask[2][4];  // per stage and A-staging wave: bit q = some row has a nonzero word q
+  u32 zmask[2][8];  // per stage and staging wave (A: 0..3, B^T: 4..7): bit q = some row has a nonzero word q
   u32 satf[2][8];   // per vote (alternating) and wave: every output of the wave's 128 x 64 block is set
 };
 
@@ -166,7 +166,7 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
     u32 zm = 0;
 #pragma unroll
     for (int q = 0; q < kMChunk; ++q) zm |= stage_word(sr, buf, q);
-    if (isa && lane == 0) zmask[buf][wave] = zm;
+    if (lane == 0) zmask[buf][wave] = zm;
   };
   u32 done_words = 0;  // words of k this wave ran the matrix cores on
   const int csw = (l32 >> 2) & 3;  // word-slot swizzle of every row this lane reads
@@ -205,7 +205,7 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
         for (int j = 0; j < 2; ++j) bv[j] = bn[j];
       }
     }
-    if (next && isa && lane == 0) zmask[buf ^ 1][wave] = zm;
+    if (next && lane == 0) zmask[buf ^ 1][wave] = zm;
   };
   // Saturation: the sums only grow, so once every accumulator of a wave is positive its 128 x 64 outputs
   // are final (all ones), and the wave stops issuing matrix-core work.  The waves vote now and then (see
@@ -231,8 +231,11 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
     for (int i = 0; i < 4; ++i) av[i] = Ax[buf][h][wr * 128 + l32 + 32 * i][0 ^ csw];
 #pragma unroll
     for (int j = 0; j < 2; ++j) bv[j] = Bx[buf][h][wc * 64 + l32 + 32 * j][0 ^ csw];
-    // rows of this wave with a nonzero word q of k (wave-uniform)
-    const u32 mask = wsat ? 0u : __builtin_amdgcn_readfirstlane(zmask[buf][2 * wr] | zmask[buf][2 * wr + 1]);
+    // words q of k with a nonzero word in some row of this wave's A rows and in some of its B^T rows
+    // (wave-uniform): a word that is zero on either side adds nothing to any of the wave's sums
+    const u32 mask = wsat ? 0u
+                          : __builtin_amdgcn_readfirstlane((zmask[buf][2 * wr] | zmask[buf][2 * wr + 1]) &
+                                                           zmask[buf][4 + wc]);
     const bool next = c + 1 < nchunks;
     compute(buf, av, bv, mask, sn, next);
     if (next && c + 3 < nchunks) load(sn, c + 3);

@@ -523,6 +523,25 @@ def test_density_sweep_rms_sampled_rows(ctx, pi, parm):
     assert not np.any(r1 & ~got)
 
 
+@pytest.mark.parametrize("case", ["sweep_p1e-4", "tail_core"])
+def test_rms_relabelled_closure_whole(ctx, case):
+    """Relations with a tenth or more empty rows at n >= 16,384 are relabelled (nodes grouped by heavy /
+    light row and column classes) before their dense squarings and mapped back at the end: the whole
+    closure must equal the one squared in the given order (every squaring forced onto the matrix cores,
+    which never relabels) and, on sampled rows, the oracle's."""
+    if case == "tail_core":
+        n = 16384
+        s, d = gen.tail_core(n, 5000, 300, 2.5, 13)
+    else:
+        n, s, d = gen.c2(0)
+    R = gpu_pack(ctx, n, s, d)
+    got = host(ctx.rms(R, n))
+    plain = host(ctx.rms(R, n, opts=B.make_opts(product_arm=B.ARM_PRODUCT_MFMA)))
+    assert np.array_equal(got, plain)
+    rows = np.sort(np.random.default_rng(5).choice(n, 64, replace=False))
+    assert np.array_equal(got[rows], oracle.closure_rows(n, s, d, rows=rows))
+
+
 @pytest.mark.parametrize("pi", [0, 2, 4])
 def test_density_sweep_smp(ctx, pi):
     n, s, d = gen.c2(pi)
