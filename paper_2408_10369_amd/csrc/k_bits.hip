@@ -7,6 +7,9 @@
 // (Section 3.2), with the code split into 64-bit words.
 #include "bmlp_internal.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace bmlp {
 
 namespace {
@@ -492,36 +495,57 @@ __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict_
 
 // one wave per row; lanes own consecutive words
 // Relabelling of the nodes: dst[i][j] = src[perm[i]][perm[j]] for i, j < n (padding words of dst zero).
-// One workgroup per output row with the source row staged in LDS; each output word is one wave's
-// ballot over its 64 columns (lane b reads perm[64 w + b], so the perm reads are whole lines).
+// A workgroup takes RPB output rows at a time with their source rows staged in LDS; a wave assembles
+// the rows' words w0 .. w0 + 7 together: lane b reads perm[64 w + b] once (whole lines) and tests that
+// column in every staged row, one ballot per (row, word), so the permutation is read once per RPB rows.
+// The row loops are unrolled so that the loads and LDS reads of a pass are all in flight together.
+template <int RPB>
 __global__ void __launch_bounds__(256)
 k_permute(const u64* __restrict__ src, i64 lds_, const int32_t* __restrict__ perm, i64 n, u64* __restrict__ dst,
           i64 ldd) {
-  extern __shared__ u64 srow[];
+  extern __shared__ u64 srow[];  // RPB x nw
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const i64 nw = (n + 63) >> 6;
-  for (i64 i = blockIdx.x; i < n; i += gridDim.x) {
-    const i64 pi = perm[i];
-    const bool ok = pi >= 0 && pi < n;
-    for (i64 w = threadIdx.x; w < nw; w += 256) srow[w] = ok ? src[pi * lds_ + w] : 0ull;
+  for (i64 i0 = blockIdx.x * (i64)RPB; i0 < n; i0 += (i64)gridDim.x * RPB) {
+    const int rows = (int)(n - i0 < RPB ? n - i0 : RPB);
+    i64 pis[RPB];
+#pragma unroll
+    for (int r = 0; r < RPB; ++r) {
+      const i64 pi = r < rows ? (i64)perm[i0 + r] : -1;
+      pis[r] = (pi >= 0 && pi < n) ? pi : -1;
+    }
+    for (i64 w = threadIdx.x; w < nw; w += 256) {
+      u64 v[RPB];
+#pragma unroll
+      for (int r = 0; r < RPB; ++r) v[r] = pis[r] >= 0 ? src[pis[r] * lds_ + w] : 0ull;
+#pragma unroll
+      for (int r = 0; r < RPB; ++r) srow[(i64)r * nw + w] = v[r];
+    }
     __syncthreads();
-    // eight words per pass, their perm loads issued together
     for (i64 w0 = wv * 8; w0 < ldd; w0 += 32) {
       int32_t cs[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const i64 j = (w0 + q) * 64 + lane;
-        cs[q] = (w0 + q < nw && j < n) ? perm[j] : -1;
+        const int32_t c = (w0 + q < nw && j < n) ? perm[j] : -1;
+        cs[q] = (c >= 0 && c < n) ? c : -1;
       }
-      u64 keep = 0ull;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int32_t c = cs[q];
-        const bool bit = c >= 0 && c < n && ((srow[c >> 6] >> (c & 63)) & 1ull);
-        const u64 v = __ballot(bit);
-        if (lane == q) keep = v;
+        const i64 cw = c >= 0 ? (c >> 6) : 0;
+        const int cb = c & 63;
+        u64 x[RPB];
+#pragma unroll
+        for (int r = 0; r < RPB; ++r) x[r] = srow[(i64)r * nw + cw];  // rows past `rows` hold stale data
+        u64 keep = 0ull;  // lane r keeps row r's word
+#pragma unroll
+        for (int r = 0; r < RPB; ++r) {
+          const u64 v = __ballot(c >= 0 && ((x[r] >> cb) & 1ull));
+          if (lane == r) keep = v;
+        }
+        if (lane < rows && w0 + q < ldd) dst[(i0 + lane) * ldd + w0 + q] = keep;
       }
-      if (lane < 8 && w0 + lane < ldd) dst[i * ldd + w0 + lane] = keep;
     }
     __syncthreads();
   }
@@ -728,10 +752,19 @@ hipError_t launch_scan_rowptr(const int32_t* deg, i64 n, i64* rp, hipStream_t s)
 
 hipError_t launch_permute(const u64* src, i64 lds_, const int32_t* perm, i64 n, u64* dst, i64 ldd, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = (size_t)words_for(n) * sizeof(u64);
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)(n < 65535 ? n : 65535)), dim3(256), lds, s, src, lds_, perm, n, dst,
-                     ldd);
+  const i64 nw = words_for(n);
+  const size_t row_bytes = (size_t)nw * sizeof(u64);
+  if (row_bytes > 64 * 1024) return hipErrorInvalidValue;
+  // staged rows: 16 while they fit in 32 KB of LDS, else 4 (n <= 65,536), else 1
+  auto go = [&](auto rpb_tag) {
+    constexpr int RPB = decltype(rpb_tag)::value;
+    const i64 blocks = (n + RPB - 1) / RPB;
+    hipLaunchKernelGGL(k_permute<RPB>, dim3((unsigned)(blocks < 65535 ? blocks : 65535)), dim3(256), row_bytes * RPB,
+                       s, src, lds_, perm, n, dst, ldd);
+  };
+  if (row_bytes * 16 <= 32 * 1024) go(std::integral_constant<int, 16>{});
+  else if (row_bytes * 4 <= 32 * 1024) go(std::integral_constant<int, 4>{});
+  else go(std::integral_constant<int, 1>{});
   return hipGetLastError();
 }
 

@@ -523,7 +523,7 @@ def test_density_sweep_rms_sampled_rows(ctx, pi, parm):
     assert not np.any(r1 & ~got)
 
 
-@pytest.mark.parametrize("case", ["sweep_p1e-4", "tail_core"])
+@pytest.mark.parametrize("case", ["sweep_p1e-4", "tail_core", "n20000"])
 def test_rms_relabelled_closure_whole(ctx, case):
     """Relations with a tenth or more empty rows at n >= 16,384 are relabelled (nodes grouped by heavy /
     light row and column classes) before their dense squarings and mapped back at the end: the whole
@@ -532,6 +532,9 @@ def test_rms_relabelled_closure_whole(ctx, case):
     if case == "tail_core":
         n = 16384
         s, d = gen.tail_core(n, 5000, 300, 2.5, 13)
+    elif case == "n20000":  # rows of 313 words: the relabelling stages four rows per workgroup
+        n = 20000
+        s, d = gen.er_digraph(n, 1.7 / n, 20000)
     else:
         n, s, d = gen.c2(0)
     R = gpu_pack(ctx, n, s, d)
