@@ -87,6 +87,7 @@ enum FlagSlot {
   F_EXEC = 40,     // 64-bit count of matrix-core ops issued by a timed product
   F_LIST = 44,     // length of a device row list
   F_QUEUE = 46,    // 64-bit piece counter of the gathers' overflow queue
+  F_ROUNDS_OUT = 48,  // host side only: a one-launch selection's round count, read at the end of the call
   F_WORDS = 128
 };
 
@@ -287,6 +288,17 @@ struct StatsRec {
     }
     npend = 0;
   }
+  // a one-launch selection's round count, copied back with the end-of-call readback
+  i64 rounds_n = -1;
+  int rounds_arm = 0;
+  void defer_rounds(i64 n, int arm) {
+    if (!st) return;
+    hip_check(hipMemcpyAsync(c->h_flags + F_ROUNDS_OUT, c->d_flags + F_ROUNDS, sizeof(u32), hipMemcpyDeviceToHost,
+                             s),
+              "hipMemcpyAsync");
+    rounds_n = n;
+    rounds_arm = arm;
+  }
   void finish() {
     if (!st) return;
     flush();
@@ -295,6 +307,13 @@ struct StatsRec {
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, c->ev0, c->ev1), "hipEventElapsedTime");
     st->device_ms = ms;
+    if (rounds_n >= 0) {
+      const u32 rounds = c->h_flags[F_ROUNDS_OUT];
+      need((i64)rounds <= rounds_n + 2, BMLP_EITER, "SMP exceeded the round cap");
+      st->iterations = (int32_t)rounds;
+      for (u32 r = 0; r < rounds && r < 64; ++r) trace((int)r, rounds_arm);
+      rounds_n = -1;
+    }
   }
 };
 
@@ -903,12 +922,9 @@ void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vsta
     hip_check(launch_smp_rows(V, ldv, k, csr.rp, csr.ci, rpt, cit, R1, ld, n, reflexive, Vstar, ldv,
                               c->d_flags + F_ROUNDS, s),
               "smp_rows");
-    const u32 rounds = read_flag(c, s, F_ROUNDS);
-    need((i64)rounds <= n + 2, BMLP_EITER, "SMP exceeded the round cap");
-    if (sr.st) {
-      sr.st->iterations = (int32_t)rounds;
-      for (u32 r = 0; r < rounds && r < 64; ++r) sr.trace((int)r, arm);
-    }
+    // the round count only feeds the statistics: it is read with them at the end of the call (the kernel
+    // stops by itself after n + 1 rounds)
+    if (sr.st) sr.defer_rounds(n, arm);
     return;
   }
   if (arm == BMLP_ARM_SMP_CLOSURE) {
