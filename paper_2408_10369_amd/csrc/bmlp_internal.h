@@ -54,7 +54,7 @@ hipError_t launch_row_popcount(const u64* a, i64 rows, i64 n, i64 ld, int32_t* d
                                hipStream_t s);
 // number of set bits of the matrix added into *total (must be zeroed)
 hipError_t launch_popcount_total(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* total, hipStream_t s);
-// exclusive scan of deg[0..n) into rp[0..n] (int64); single-workgroup
+// exclusive scan of deg[0..n) into rp[0..n] (int64); single-workgroup; deg and rp 16-byte aligned
 hipError_t launch_scan_rowptr(const int32_t* deg, i64 n, i64* rp, hipStream_t s);
 // dst[i][j] = src[perm[i]][perm[j]] for a permutation perm of [0, n) (n <= 524,288); dst must not overlap src
 hipError_t launch_permute(const u64* src, i64 lds_, const int32_t* perm, i64 n, u64* dst, i64 ldd, hipStream_t s);

@@ -452,10 +452,17 @@ __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict_
   i64 carry = 0;
   for (i64 base = 0; base < n; base += 1024 * kScanPer) {
     int v[kScanPer];
+    const i64 i0 = base + (i64)t * kScanPer;
+    if (i0 + kScanPer <= n) {
+      // eight consecutive degrees as two 16-byte loads (deg is 16-byte aligned, i0 a multiple of 8)
+      const int4 a = *(const int4*)(deg + i0), b = *(const int4*)(deg + i0 + 4);
+      v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    } else {
 #pragma unroll
-    for (int j = 0; j < kScanPer; ++j) {
-      const i64 i = base + (i64)t * kScanPer + j;
-      v[j] = deg[i < n ? i : n - 1];
+      for (int j = 0; j < kScanPer; ++j) {
+        const i64 i = i0 + j;
+        v[j] = deg[i < n ? i : n - 1];
+      }
     }
     i64 sum = 0;
 #pragma unroll
@@ -481,11 +488,20 @@ __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict_
     }
     __syncthreads();
     i64 run = carry + wpre[wave] + x - sum;
+    i64 out[kScanPer];
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-      const i64 i = base + (i64)t * kScanPer + j;
-      if (i < n) rp[i] = run;
+      out[j] = run;
       run += v[j];
+    }
+    if (i0 + kScanPer <= n) {
+      // rp is 16-byte aligned and i0 a multiple of 8: four 16-byte stores
+#pragma unroll
+      for (int j = 0; j < kScanPer; j += 2) *(longlong2*)(rp + i0 + j) = make_longlong2(out[j], out[j + 1]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kScanPer; ++j)
+        if (i0 + j < n) rp[i0 + j] = out[j];
     }
     carry += wpre[16];
     __syncthreads();  // wsum and wpre are rewritten by the next segment
@@ -493,7 +509,6 @@ __global__ void __launch_bounds__(1024) k_scan_rowptr(const int32_t* __restrict_
   if (t == 0) rp[n] = carry;
 }
 
-// one wave per row; lanes own consecutive words
 // Relabelling of the nodes: dst[i][j] = src[perm[i]][perm[j]] for i, j < n (padding words of dst zero).
 // A workgroup takes RPB output rows at a time with their source rows staged in LDS; a wave assembles
 // the rows' words w0 .. w0 + 7 together: lane b reads perm[64 w + b] once (whole lines) and tests that
@@ -573,6 +588,7 @@ __global__ void k_csc_fill(const i64* __restrict__ rp, const int32_t* __restrict
   }
 }
 
+// one wave per row; lanes own consecutive words
 __global__ void k_bits_to_csr(const u64* __restrict__ a, i64 rows, i64 n, i64 ld, const i64* __restrict__ rp,
                               int32_t* __restrict__ ci) {
   const int lane = threadIdx.x & 63;

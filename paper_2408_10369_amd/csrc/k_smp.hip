@@ -116,7 +116,7 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
           }
         }
         __syncthreads();
-        const int nh = nhubs < kHubCap ? nhubs : kHubCap;
+        const int nh = nhubs < kHubCap ? nhubs : kHubCap;  // the same in every thread after the barrier
         for (int h = 0; h < nh; ++h) {
           const i64 u = hubs[h];
           const i64 e0 = rp[u], e1 = rp[u + 1];
@@ -135,7 +135,7 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
             }
           }
         }
-        __syncthreads();
+        if (nh > 0) __syncthreads();
       }
       // fr = nxt & ~vis ; vis |= fr ; nxt = 0
       int any = 0;
