@@ -254,20 +254,22 @@ struct StatsRec {
   void product_begin() {
     if (!st) return;
     pool();
-    hip_check(hipMemsetAsync(c->d_exec + npend, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+    // the counters of a batch are cleared together before its first product and copied back together
+    if (npend == 0)
+      hip_check(hipMemsetAsync(c->d_exec, 0, bmlp_ctx::kPend * sizeof(unsigned long long), s), "hipMemsetAsync");
     hip_check(hipEventRecord(c->pe0[npend], s), "hipEventRecord");
   }
   void product(i64 m, i64 k, i64 n, int arm) {
     if (!st) return;
     hip_check(hipEventRecord(c->pe1[npend], s), "hipEventRecord");
-    hip_check(hipMemcpyAsync(c->h_exec + npend, c->d_exec + npend, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                             s),
-              "hipMemcpyAsync");
     pend[npend++] = Pending{m, k, n, arm};
     if (npend == bmlp_ctx::kPend) flush();
   }
   void flush() {
     if (!st || npend == 0) return;
+    hip_check(hipMemcpyAsync(c->h_exec, c->d_exec, (size_t)npend * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             s),
+              "hipMemcpyAsync");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     for (int i = 0; i < npend; ++i) {
       float ms = 0.f;
