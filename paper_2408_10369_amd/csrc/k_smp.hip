@@ -117,19 +117,36 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
         }
         __syncthreads();
         const int nh = nhubs < kHubCap ? nhubs : kHubCap;  // the same in every thread after the barrier
-        for (int h = 0; h < nh; ++h) {
-          const i64 u = hubs[h];
-          const i64 e0 = rp[u], e1 = rp[u + 1];
-          if (R && (e1 - e0) * 2 > nw) {
-            for (i64 w = t; w < nw; w += kSmpThreads) {
-              const u64 x = R[u * ldr + w];
-              if (x) {
-                atomicOr(&nxt32[2 * w], (u32)x);
-                atomicOr(&nxt32[2 * w + 1], (u32)(x >> 32));
-              }
+        // hubs whose bit row is denser than their successor list (out-degree > nw / 2) are ORed from R, eight
+        // rows per pass with their loads in flight together; the others are expanded through CSR, a wave each
+        for (int h0 = 0; h0 < nh; h0 += 8) {
+          i64 dense[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            dense[q] = -1;
+            if (h0 + q < nh) {
+              const i64 u = hubs[h0 + q];
+              if (R && (rp[u + 1] - rp[u]) * 2 > nw) dense[q] = u;
             }
-          } else {
-            for (i64 e = e0 + t; e < e1; e += kSmpThreads) {
+          }
+          for (i64 w = t; w < nw; w += kSmpThreads) {
+            u64 x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = dense[q] >= 0 ? R[dense[q] * ldr + w] : 0ull;
+            u64 acc = 0ull;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc |= x[q];
+            if (acc) {
+              atomicOr(&nxt32[2 * w], (u32)acc);
+              atomicOr(&nxt32[2 * w + 1], (u32)(acc >> 32));
+            }
+          }
+          // each wave expands two of the batch's CSR hubs, its lanes over the successor list
+          for (int q = t >> 6; q < 8; q += kSmpThreads / 64) {
+            if (h0 + q >= nh || dense[q] >= 0) continue;
+            const i64 u = hubs[h0 + q];
+            const i64 e1 = rp[u + 1];
+            for (i64 e = rp[u] + lane; e < e1; e += 64) {
               const int32_t v = ci[e];
               atomicOr(&nxt32[v >> 5], 1u << (v & 31));
             }
