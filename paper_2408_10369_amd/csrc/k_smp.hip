@@ -77,18 +77,49 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
         for (i64 w = t; w < nw; w += kSmpThreads) {
           u64 cand = ~vis[w] & (w == nw - 1 ? last_mask : ~0ull);
           u64 found = 0ull;
-          while (cand) {
-            const int b = __ffsll((unsigned long long)cand) - 1;
-            cand &= cand - 1;
-            const i64 v = w * 64 + b;
-            const i64 e1 = rpt[v + 1];
-            for (i64 e = rpt[v]; e < e1; ++e) {
-              const int32_t u = cit[e];
-              if ((fr[u >> 6] >> (u & 63)) & 1ull) {
-                found |= 1ull << b;
-                break;
-              }
+          // eight candidates in flight: slot q scans the in-edges [se, sx) of node 64 w + sb until one
+          // comes from the frontier or the list ends, then takes the next candidate, so that the
+          // thread's in-edge loads overlap instead of forming one chain
+          int sb[8];
+          i64 se[8], sx[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            sb[q] = -1;
+            se[q] = sx[q] = 0;
+            if (cand) {
+              const int b = __ffsll((unsigned long long)cand) - 1;
+              cand &= cand - 1;
+              sb[q] = b;
+              se[q] = rpt[w * 64 + b];
+              sx[q] = rpt[w * 64 + b + 1];
             }
+          }
+          for (;;) {
+            int32_t u[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] = (sb[q] >= 0 && se[q] < sx[q]) ? cit[se[q]] : -1;
+            bool busy = false;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              if (sb[q] < 0) continue;
+              bool done = true;  // a node without (more) in-edges is not reached this round
+              if (u[q] >= 0) {
+                if ((fr[u[q] >> 6] >> (u[q] & 63)) & 1ull) found |= 1ull << sb[q];
+                else done = ++se[q] >= sx[q];
+              }
+              if (done) {
+                sb[q] = -1;
+                if (cand) {
+                  const int b = __ffsll((unsigned long long)cand) - 1;
+                  cand &= cand - 1;
+                  sb[q] = b;
+                  se[q] = rpt[w * 64 + b];
+                  sx[q] = rpt[w * 64 + b + 1];
+                }
+              }
+              busy |= sb[q] >= 0;
+            }
+            if (!busy) break;
           }
           nxt[w] = found;
         }
