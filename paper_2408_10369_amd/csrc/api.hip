@@ -708,18 +708,19 @@ i64 count_bits(bmlp_ctx* c, const u64* R, i64 rows, i64 n, i64 ld, hipStream_t s
 // n = 4,096, 16,384 and 65,536, mean out-degree 1.6 .. 164 and k = 1 .. 1,024 query rows.  The
 // one-launch sparse arm turns bottom-up once the frontier is large, so its time hardly grows with the
 // degree; what it pays up front is the edge index (CSR, and CSC from degree 4), which grows with n.
-// It wins whenever 64 or more rows share the launch (n = 65,536, degree 40, k = 1,024: 1.6 ms against
-// 8.2 dense; n = 16,384, degree 164: 0.30 against 0.61) and at every k while the degree is low.  A few
-// rows of a dense relation are served faster by the dense rounds: at n = 16,384 from degree 12 below
-// k = 16 (degree 82, k = 1: 0.26 ms dense, 0.39 sparse), and above that size from degree 6 below k = 16
-// and from degree 12 below k = 64 (n = 65,536, degree 16, k = 16: 1.15 against 1.23).  At n = 4,096 the
+// It wins whenever 64 or more rows share the launch (n = 65,536, degree 40, k = 1,024: 1.3 ms against
+// 7.9 dense; n = 16,384, degree 164: 0.22 against 0.60) and at every k while the degree is low.  A few
+// rows of a moderately dense relation are served faster by the dense rounds: at n = 16,384 for degree
+// 30 .. 128 below k = 16 (degree 82, k = 1: 0.23 ms dense, 0.28 sparse; at degree 164 the hubs' bit rows
+// make the sparse arm faster again, 0.19 against 0.23), and above that size from degree 12 below k = 16
+// and from degree 30 below k = 64 (n = 65,536, degree 40, k = 16: 0.88 against 1.09).  At n = 4,096 the
 // sparse arm wins nearly everywhere.
 int smp_plain_arm(i64 n, i64 k, i64 m) {
   if (n > smp_rows_max_n()) return BMLP_ARM_SMP_DENSE;
   const double deg = n > 0 ? (double)m / (double)n : 0.0;
   if (k >= 64 || n <= 4096) return BMLP_ARM_SMP_SPARSE;
-  if (n <= 16384) return (deg < 12.0 || k >= 16) ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_DENSE;
-  return (deg < 6.0 || (deg < 12.0 && k >= 16)) ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_DENSE;
+  if (n <= 16384) return (k >= 16 || deg < 30.0 || deg >= 128.0) ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_DENSE;
+  return (deg < 12.0 || (deg < 30.0 && k >= 16)) ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_DENSE;
 }
 
 // ------------------------------------------------------------ dispatcher features

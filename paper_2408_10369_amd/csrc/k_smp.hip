@@ -29,6 +29,10 @@ constexpr int kHubDeg = 48;       // expand cooperatively above this out-degree
 constexpr int kHubCap = 512;      // LDS queue of cooperative nodes per round
 constexpr i64 kMaxLdsWords = 6144;  // 3 bitmaps x 2048 words = 48 KiB (n <= 131072)
 
+// SLOTS: unvisited nodes a thread checks at once in a bottom-up round.  Eight hide the latency of the
+// in-edge loads when few rows share the launch; with many rows the registers they take would cut the
+// workgroups a CU holds (97 against 54 VGPRs), so one is used there.
+template <int SLOTS>
 __global__ void __launch_bounds__(kSmpThreads)
 k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp, const int32_t* __restrict__ ci,
            const i64* __restrict__ rpt, const int32_t* __restrict__ cit, const u64* __restrict__ R, i64 ldr, i64 n,
@@ -77,13 +81,13 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
         for (i64 w = t; w < nw; w += kSmpThreads) {
           u64 cand = ~vis[w] & (w == nw - 1 ? last_mask : ~0ull);
           u64 found = 0ull;
-          // eight candidates in flight: slot q scans the in-edges [se, sx) of node 64 w + sb until one
+          // SLOTS candidates in flight: slot q scans the in-edges [se, sx) of node 64 w + sb until one
           // comes from the frontier or the list ends, then takes the next candidate, so that the
           // thread's in-edge loads overlap instead of forming one chain
-          int sb[8];
-          i64 se[8], sx[8];
+          int sb[SLOTS];
+          i64 se[SLOTS], sx[SLOTS];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
+          for (int q = 0; q < SLOTS; ++q) {
             sb[q] = -1;
             se[q] = sx[q] = 0;
             if (cand) {
@@ -95,12 +99,12 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
             }
           }
           for (;;) {
-            int32_t u[8];
+            int32_t u[SLOTS];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) u[q] = (sb[q] >= 0 && se[q] < sx[q]) ? cit[se[q]] : -1;
+            for (int q = 0; q < SLOTS; ++q) u[q] = (sb[q] >= 0 && se[q] < sx[q]) ? cit[se[q]] : -1;
             bool busy = false;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < SLOTS; ++q) {
               if (sb[q] < 0) continue;
               bool done = true;  // a node without (more) in-edges is not reached this round
               if (u[q] >= 0) {
@@ -711,8 +715,12 @@ hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const in
   if (3 * nw > kMaxLdsWords) return hipErrorInvalidValue;
   const size_t lds = (size_t)(3 * nw) * sizeof(u64);
   const unsigned grid = (unsigned)(k < 65535 ? k : 65535);
-  hipLaunchKernelGGL(k_smp_rows, dim3(grid), dim3(kSmpThreads), lds, s, V, ldv, k, rp, ci, rpt, cit, R, ldr, n,
-                     reflexive, out, ldo, iters_max);
+  if (k <= 2048)
+    hipLaunchKernelGGL(k_smp_rows<8>, dim3(grid), dim3(kSmpThreads), lds, s, V, ldv, k, rp, ci, rpt, cit, R, ldr, n,
+                       reflexive, out, ldo, iters_max);
+  else
+    hipLaunchKernelGGL(k_smp_rows<1>, dim3(grid), dim3(kSmpThreads), lds, s, V, ldv, k, rp, ci, rpt, cit, R, ldr, n,
+                       reflexive, out, ldo, iters_max);
   return hipGetLastError();
 }
 
