@@ -523,7 +523,7 @@ def test_density_sweep_rms_sampled_rows(ctx, pi, parm):
     assert not np.any(r1 & ~got)
 
 
-@pytest.mark.parametrize("case", ["sweep_p1e-4", "tail_core", "n20000"])
+@pytest.mark.parametrize("case", ["sweep_p1e-4", "tail_core", "n20000", "n66000"])
 def test_rms_relabelled_closure_whole(ctx, case):
     """Relations with a tenth or more empty rows at n >= 16,384 are relabelled (nodes grouped by heavy /
     light row and column classes) before their dense squarings and mapped back at the end: the whole
@@ -535,6 +535,9 @@ def test_rms_relabelled_closure_whole(ctx, case):
     elif case == "n20000":  # rows of 313 words: the relabelling stages four rows per workgroup
         n = 20000
         s, d = gen.er_digraph(n, 1.7 / n, 20000)
+    elif case == "n66000":  # rows of 1,032 words: one staged row per workgroup
+        n = 66000
+        s, d = gen.er_digraph(n, 1.7 / n, 66000)
     else:
         n, s, d = gen.c2(0)
     R = gpu_pack(ctx, n, s, d)
