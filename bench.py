@@ -606,21 +606,29 @@ def cpu_baseline(graphs, n, sample_rows):
     t_total = 0.0
     rows_total = 0
     threads = 0
+    # the oracle's rows are compared with the last timed step's outputs (closures and answers), bit for bit
+    compared, mismatched = 0, 0
     for g in graphs:
         s = g["s"].cpu().numpy()
         d = g["d"].cpu().numpy()
         rows = None if sample_rows <= 0 else np.sort(rng.choice(n, sample_rows, replace=False))
         t0 = time.perf_counter()
-        oracle.closure_rows(n, s, d, rows=rows)
+        want = oracle.closure_rows(n, s, d, rows=rows)
         t_total += time.perf_counter() - t0
         rows_total += n if rows is None else len(rows)
         threads = oracle.last_threads
-        for V in g["V"]:
+        got = g["Rstar"].cpu().numpy().view(np.uint64)
+        got = got if rows is None else got[rows]
+        compared += want.shape[0]
+        mismatched += int((got != want).any(axis=1).sum())
+        for V, Vs in zip(g["V"], g["Vs"]):
             Vh = V.cpu().numpy().view(np.uint64)
             t0 = time.perf_counter()
-            oracle.smp(n, s, d, Vh)
+            want = oracle.smp(n, s, d, Vh)
             t_total += time.perf_counter() - t0
             rows_total += Vh.shape[0]
+            compared += want.shape[0]
+            mismatched += int((Vs.cpu().numpy().view(np.uint64) != want).any(axis=1).sum())
     # the same oracle on one thread, on 64 random closure rows per graph
     t1, rows1 = 0.0, 0
     for g in graphs:
@@ -635,6 +643,8 @@ def cpu_baseline(graphs, n, sample_rows):
     return {"value": round(rows_total / t_total, 1), "unit": "query rows/s", "cores": threads, "kind": "oracle",
             "sample": "%s of each of the %d graphs plus every SMP query row (k=1,64,1024), per-source BFS; "
                       "%d rows in %.2f s" % (what, len(graphs), rows_total, t_total),
+            "oracle_parity": {"rows_compared": compared, "rows_differing": mismatched,
+                              "bit_exact": mismatched == 0},
             "value_1_thread": round(rows1 / t1, 1),
             "sample_1_thread": "64 random closure rows of each graph on one thread; %d rows in %.2f s" % (rows1, t1)}
 
