@@ -68,7 +68,7 @@ typedef enum {
   BMLP_ENOMEM = -5,  /* workspace allocation failed or would exceed opts->workspace_limit */
   BMLP_EDEVICE = -6, /* HIP runtime error or device fault */
   BMLP_EITER = -7,   /* iteration cap exceeded (Appendix C, Propositions 1-2); indicates a bug */
-  BMLP_EMODEL = -8   /* dispatcher model file missing, corrupt or incompatible */
+  BMLP_EMODEL = -8   /* dispatcher model or tuning cache file missing, corrupt or incompatible */
 } bmlp_status;
 
 /* Kernel families ("arms").  Every arm returns identical bits. */
@@ -276,6 +276,44 @@ bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t *V, uint64_t *Vstar, i
 /* Whether the session holds the closure (1) or not (0). */
 int32_t bmlp_graph_has_closure(bmlp_graph g);
 bmlp_status bmlp_graph_close(bmlp_graph g);
+
+/* ------------------------------------------------------------ autotuned tile code */
+/* Several kernels come in candidate versions ("tile code": tile shapes, words of k per LDS stage, the
+   order of output tiles over the XCDs, rows per wave); every candidate returns identical bits, they
+   differ in speed only.  A handle keeps, per tuned kernel and size/density bucket, the candidate to
+   use (-1: the built-in default).  Tuned kernels:
+     BMLP_TUNE_MFMA_PRODUCT  the matrix-core product (BMLP_ARM_PRODUCT_MFMA)
+     BMLP_TUNE_VALU_PRODUCT  the bit-packed VALU product (BMLP_ARM_PRODUCT_VALU)
+   Buckets of a product (m x kdim).(kdim x n): 4 * size + class, size 0..3 by the dense operation
+   count 2 m kdim n (below about 2 x 2048^3, 2 x 4096^3, 2 x 8192^3, beyond), class 0..3 by the left
+   operand: set bits below 1/4096, below 1/64, denser or unknown, block-structured (the squarings of a
+   relabelled relation).  bmlp_create loads $BMLP_AUTOTUNE_CACHE, else autotune_cache.json beside the
+   library, when it exists and was written on the same kind of device. */
+typedef enum { BMLP_TUNE_MFMA_PRODUCT = 0, BMLP_TUNE_VALU_PRODUCT = 1 } bmlp_tune_kernel;
+#define BMLP_TUNE_MAX_CANDIDATES 8
+/* Number of candidates / buckets of a tuned kernel (0 for an unknown kernel). */
+int32_t bmlp_tune_candidates(int32_t kernel);
+int32_t bmlp_tune_buckets(int32_t kernel);
+/* The bucket of a product of the given shape and left-operand density (density < 0: unknown;
+   structured nonzero: block-structured), or -1. */
+int32_t bmlp_tune_bucket_of(int32_t kernel, int64_t m, int64_t kdim, int64_t n, double density, int32_t structured);
+/* The handle's candidate for (kernel, bucket) (-1: default) and the device time it was chosen with
+   (ms; 0 when set by hand or not measured); ms may be NULL. */
+bmlp_status bmlp_tune_get(bmlp_handle h, int32_t kernel, int32_t bucket, int32_t *variant, float *ms);
+/* Pin a candidate (-1: back to the default) for one bucket, or for every bucket with bucket = -1. */
+bmlp_status bmlp_tune_set(bmlp_handle h, int32_t kernel, int32_t bucket, int32_t variant);
+/* Run the autotuner on the handle's device: for every kernel in kernel_mask (bit k = tuned kernel k) and
+   every bucket, time each candidate `reps` times (after one warm-up launch; the median counts) on seeded
+   synthetic squarings C = A | A.A at the bucket's representative size (n = 2048, 4096, 8192, 16384) and
+   class, and keep the fastest.  Takes a few seconds and up to 3 x 32 MiB of workspace.  With cache_out
+   non-NULL the result is written there (JSON, see bmlp_tune_save).  report (nullable, host) receives
+   kernels x buckets x BMLP_TUNE_MAX_CANDIDATES median times in ms (-1 where not measured). */
+bmlp_status bmlp_autotune(bmlp_handle h, int32_t kernel_mask, int32_t reps, const char *cache_out, float *report);
+/* Write the handle's choices to / read them from a JSON tuning cache keyed by the device's architecture
+   name and compute-unit count.  A cache of another kind of device, or a malformed one, gives
+   BMLP_EMODEL and leaves the handle unchanged. */
+bmlp_status bmlp_tune_save(bmlp_handle h, const char *path);
+bmlp_status bmlp_tune_load(bmlp_handle h, const char *path);
 
 /* ------------------------------------------------------------ the learned dispatcher */
 /* The dispatcher is a small FP32 network (16 features -> 64 -> 64 -> 4 outputs, ReLU) predicting

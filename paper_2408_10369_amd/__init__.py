@@ -42,7 +42,11 @@ EXPORTS = [
     "bmlp_graph_open", "bmlp_graph_query", "bmlp_graph_has_closure", "bmlp_graph_close",
     "bmlp_set_trace", "bmlp_dispatcher_load", "bmlp_dispatcher_save", "bmlp_dispatcher_loaded",
     "bmlp_dispatcher_train", "bmlp_dispatcher_forward", "bmlp_mlp_loss_grad",
+    "bmlp_tune_candidates", "bmlp_tune_buckets", "bmlp_tune_bucket_of", "bmlp_tune_get", "bmlp_tune_set",
+    "bmlp_autotune", "bmlp_tune_save", "bmlp_tune_load",
 ]
+TUNE_MAX_CANDIDATES = 8
+TUNE_MFMA_PRODUCT, TUNE_VALU_PRODUCT = 0, 1
 
 
 class Trace(ctypes.Structure):
@@ -149,9 +153,18 @@ def lib():
     L.bmlp_dispatcher_train.argtypes = [vp, fp, fp, fp, i64, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, fp]
     L.bmlp_dispatcher_forward.argtypes = [vp, fp, i64, fp]
     L.bmlp_mlp_loss_grad.argtypes = [vp, fp, fp, fp, fp, fp, fp, i64, fp, fp]
+    L.bmlp_tune_candidates.argtypes = [ctypes.c_int32]
+    L.bmlp_tune_buckets.argtypes = [ctypes.c_int32]
+    L.bmlp_tune_bucket_of.argtypes = [ctypes.c_int32, i64, i64, i64, ctypes.c_double, ctypes.c_int32]
+    L.bmlp_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p, fp]
+    L.bmlp_tune_save.argtypes = [vp, ctypes.c_char_p]
+    L.bmlp_tune_load.argtypes = [vp, ctypes.c_char_p]
+    L.bmlp_tune_get.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32), fp]
+    L.bmlp_tune_set.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name in ("bmlp_graph_has_closure", "bmlp_dispatcher_loaded"):
+        if name in ("bmlp_graph_has_closure", "bmlp_dispatcher_loaded", "bmlp_tune_candidates", "bmlp_tune_buckets",
+                    "bmlp_tune_bucket_of"):
             f.restype = ctypes.c_int32
         elif name not in ("bmlp_last_error", "bmlp_opts_init", "bmlp_version"):
             f.restype = ctypes.c_int
@@ -477,6 +490,46 @@ class Context:
         return float(loss.value), G
 
     # -------------------------------------------------------------- sessions
+    # -------------------------------------------------------------- autotuned tile code
+    @staticmethod
+    def tune_candidates(kernel: int) -> int:
+        return int(lib().bmlp_tune_candidates(int(kernel)))
+
+    @staticmethod
+    def tune_buckets(kernel: int) -> int:
+        return int(lib().bmlp_tune_buckets(int(kernel)))
+
+    @staticmethod
+    def tune_bucket_of(kernel: int, m: int, kdim: int, n: int, density: float = -1.0, structured: bool = False) -> int:
+        return int(lib().bmlp_tune_bucket_of(int(kernel), int(m), int(kdim), int(n), float(density),
+                                             1 if structured else 0))
+
+    def autotune(self, kernel_mask: int = 3, reps: int = 3, cache_out: str | None = None):
+        """Time every candidate on every bucket and keep the fastest; returns the report as a nested list
+        [kernel][bucket][candidate] of median ms (-1 where not measured)."""
+        nk = 2
+        nb = self.tune_buckets(0)
+        rep = (ctypes.c_float * (nk * nb * TUNE_MAX_CANDIDATES))()
+        _check(lib().bmlp_autotune(self._h, int(kernel_mask), int(reps),
+                                   cache_out.encode() if cache_out else None, rep))
+        return [[[rep[(k * nb + b) * TUNE_MAX_CANDIDATES + v] for v in range(TUNE_MAX_CANDIDATES)]
+                 for b in range(nb)] for k in range(nk)]
+
+    def tune_save(self, path: str):
+        _check(lib().bmlp_tune_save(self._h, path.encode()))
+
+    def tune_load(self, path: str):
+        _check(lib().bmlp_tune_load(self._h, path.encode()))
+
+    def tune_get(self, kernel: int, bucket: int):
+        v = ctypes.c_int32()
+        ms = ctypes.c_float()
+        _check(lib().bmlp_tune_get(self._h, int(kernel), int(bucket), ctypes.byref(v), ctypes.byref(ms)))
+        return v.value, ms.value
+
+    def tune_set(self, kernel: int, bucket: int, variant: int):
+        _check(lib().bmlp_tune_set(self._h, int(kernel), int(bucket), int(variant)))
+
     def graph(self, R1, n: int, stream=None):
         return Session(self, R1, n, stream)
 

@@ -68,9 +68,16 @@ struct bmlp_ctx {
   bool model = false;
   std::vector<float> h_model;
   bmlp_trace* trace = nullptr;
+  // autotuned tile code per (tuned kernel, bucket): a candidate index, or -1 for the built-in default
+  static constexpr int kTuneKernels = 2, kTuneBuckets = 16;
+  int32_t tune[kTuneKernels][kTuneBuckets];
+  float tune_ms[kTuneKernels][kTuneBuckets];
 };
 
 namespace {
+
+// Kernels with autotuned tile code (bmlp_ctx::tune): the matrix-core product, the VALU product.
+enum TuneKernel { TK_MFMA = 0, TK_VALU = 1 };
 
 // Slots of the handle's small device flag buffer (and its pinned host mirror), in 32-bit words.
 enum FlagSlot {
@@ -334,16 +341,39 @@ u32 read_flag(bmlp_ctx* c, hipStream_t s, int idx = 0) {
 const u64* transpose_b(bmlp_ctx* c, const u64* B, i64 ldb, i64 K, i64 N, const bmlp_opts& o, hipStream_t s,
                        i64* ldbt) {
   *ldbt = std::max<i64>(words_for(K), 1);
+  *ldbt += *ldbt & 1;  // even, so that rows are 16-byte aligned (the tile codes that load 16-byte pieces)
   u64* bt = ws_bits(c, S_BT, N, *ldbt, o);
   hip_check(launch_transpose(B, K, N, ldb, bt, *ldbt, s), "transpose");
   return bt;
 }
 
+// ------------------------------------------------------------ autotuned tile code
+// Buckets of a product (M x K).(K x N): four sizes by the dense operation count 2 M K N (up to about
+// 2 x 2,048^3, 2 x 4,096^3, 2 x 8,192^3, beyond) times four classes of the left operand: bits below
+// 1/4,096 (words of k often zero across a whole row block, skipped), below 1/64, denser or not known,
+// and block-structured (the squarings of a relabelled relation, whose bits crowd into one corner).
+int tune_bucket(i64 M, i64 K, i64 N, double density, bool structured = false) {
+  const double ops = 2.0 * (double)M * (double)K * (double)N;
+  const int sb = ops < 3.4e10 ? 0 : ops < 2.7e11 ? 1 : ops < 2.2e12 ? 2 : 3;
+  const int db = structured ? 3 : density < 0.0 ? 2 : density < 1.0 / 4096.0 ? 0 : density < 1.0 / 64.0 ? 1 : 2;
+  return 4 * sb + db;
+}
+// Candidates the autotuner chooses among, and the built-in defaults (measured on MI355X at n = 16,384)
+constexpr int kTuneCandidates[bmlp_ctx::kTuneKernels] = {kMfmaVariants, kValuVariants};
+constexpr int kTuneDefault[bmlp_ctx::kTuneKernels] = {0, 0};
+int tuned_variant(const bmlp_ctx* c, int kernel, i64 M, i64 K, i64 N, double density, bool structured = false) {
+  const int v = c->tune[kernel][tune_bucket(M, K, N, density, structured)];
+  return v >= 0 ? v : kTuneDefault[kernel];
+}
+
 // One Boolean product C = Cold | A.B (D, changed optional) with the chosen arm.  The MFMA arm reads B
 // transposed: pass BT when the caller has it, else B is transposed into workspace first.
+// `density`: the fraction of set bits of A when the caller knows it (else -1); with `structured` (A is a
+// relabelled, block-structured relation) it picks the tuned tile code.
 void product(bmlp_ctx* c, const u64* A, i64 lda, const u64* B, i64 ldb, const u64* Cold, i64 ldco, u64* C, i64 ldc,
              u64* D, i64 ldd, i64 M, i64 K, i64 N, u32* changed, int arm, hipStream_t s, StatsRec& sr,
-             const u64* BT = nullptr, i64 ldbt = 0, unsigned long long* newbits = nullptr) {
+             const u64* BT = nullptr, i64 ldbt = 0, unsigned long long* newbits = nullptr, double density = -1.0,
+             bool structured = false) {
   GemmArgs g{A, lda, B, ldb, Cold, ldco, C, ldc, D, ldd, M, K, N, changed};
   g.executed = sr.exec_counter();
   g.newbits = newbits;
@@ -352,10 +382,10 @@ void product(bmlp_ctx* c, const u64* A, i64 lda, const u64* B, i64 ldb, const u6
     bmlp_opts_init(&dflt);
     if (!BT) BT = transpose_b(c, B, ldb, K, N, sr.o ? *sr.o : dflt, s, &ldbt);
     sr.product_begin();
-    hip_check(launch_gemm_mfma(g, BT, ldbt, s), "gemm_mfma");
+    hip_check(launch_gemm_mfma(g, BT, ldbt, s, tuned_variant(c, TK_MFMA, M, K, N, density, structured)), "gemm_mfma");
   } else {
     sr.product_begin();
-    hip_check(launch_gemm_valu(g, s), "gemm_valu");
+    hip_check(launch_gemm_valu(g, s, tuned_variant(c, TK_VALU, M, K, N, density, structured)), "gemm_valu");
   }
   sr.product(M, K, N, arm);
 }
@@ -610,7 +640,8 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
         }
       }
       product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, c->d_flags, arm, s, sr, nullptr, 0,
-              nb);
+              nb, g0.n == n ? (double)bits / ((double)n * (double)n) : -1.0,  // the bit count is kept once counted
+              inv != nullptr);
     }
     sr.trace(it, tarm);
     ++it;
@@ -840,8 +871,10 @@ void smp_rounds(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vs
       g.pred_val = 0;
       if (timed) g.executed = sr.exec_counter();
       if (timed) sr.product_begin();
-      if (parm == BMLP_ARM_PRODUCT_MFMA) hip_check(launch_gemm_mfma(g, r1t, ldr1t, s), "gemm_mfma");
-      else hip_check(launch_gemm_valu(g, s), "gemm_valu");
+      if (parm == BMLP_ARM_PRODUCT_MFMA)
+        hip_check(launch_gemm_mfma(g, r1t, ldr1t, s, tuned_variant(c, TK_MFMA, k, n, n, -1.0)), "gemm_mfma");
+      else
+        hip_check(launch_gemm_valu(g, s, tuned_variant(c, TK_VALU, k, n, n, -1.0)), "gemm_valu");
       if (timed) sr.product(k, n, n, parm);
     }
     if (mode != RM_DENSE)
@@ -1012,6 +1045,11 @@ bmlp_status bmlp_create(bmlp_handle* h, int device) {
     DeviceGuard dg(device);
     bmlp_ctx* c = new bmlp_ctx;
     c->device = device;
+    for (int k = 0; k < bmlp_ctx::kTuneKernels; ++k)
+      for (int b = 0; b < bmlp_ctx::kTuneBuckets; ++b) {
+        c->tune[k][b] = -1;
+        c->tune_ms[k][b] = 0.f;
+      }
     if (hipMalloc((void**)&c->d_flags, F_WORDS * sizeof(u32)) != hipSuccess ||
         hipHostMalloc((void**)&c->h_flags, F_WORDS * sizeof(u32), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
@@ -1036,6 +1074,20 @@ bmlp_status bmlp_create(bmlp_handle* h, int device) {
       }
     }
     if (!path.empty() && bmlp_dispatcher_load(c, path.c_str()) != BMLP_OK) g_last_error.clear();
+    // tuning cache: $BMLP_AUTOTUNE_CACHE, else autotune_cache.json beside the library (an empty variable
+    // disables it); a missing, bad or foreign cache leaves the built-in defaults
+    std::string tpath;
+    if (const char* env = std::getenv("BMLP_AUTOTUNE_CACHE")) {
+      tpath = env;
+    } else {
+      Dl_info info;
+      if (dladdr((const void*)&bmlp_create, &info) && info.dli_fname) {
+        tpath = info.dli_fname;
+        const size_t slash = tpath.find_last_of('/');
+        tpath = (slash == std::string::npos ? std::string(".") : tpath.substr(0, slash)) + "/autotune_cache.json";
+      }
+    }
+    if (!tpath.empty() && bmlp_tune_load(c, tpath.c_str()) != BMLP_OK) g_last_error.clear();
   });
 }
 
@@ -1065,6 +1117,234 @@ bmlp_status bmlp_destroy(bmlp_handle h) {
       if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     }
     delete h;
+  });
+}
+
+int32_t bmlp_tune_candidates(int32_t kernel) {
+  return (kernel >= 0 && kernel < bmlp_ctx::kTuneKernels) ? kTuneCandidates[kernel] : 0;
+}
+
+int32_t bmlp_tune_buckets(int32_t kernel) {
+  return (kernel >= 0 && kernel < bmlp_ctx::kTuneKernels) ? bmlp_ctx::kTuneBuckets : 0;
+}
+
+int32_t bmlp_tune_bucket_of(int32_t kernel, int64_t m, int64_t kdim, int64_t n, double density, int32_t structured) {
+  if (kernel < 0 || kernel >= bmlp_ctx::kTuneKernels || m < 0 || kdim < 0 || n < 0) return -1;
+  return tune_bucket(m, kdim, n, density, structured != 0);
+}
+
+bmlp_status bmlp_tune_get(bmlp_handle h, int32_t kernel, int32_t bucket, int32_t* variant, float* ms) {
+  return guarded([&] {
+    need_handle(h);
+    need(kernel >= 0 && kernel < bmlp_ctx::kTuneKernels, BMLP_EINVAL, "unknown tuned kernel %d", kernel);
+    need(bucket >= 0 && bucket < bmlp_ctx::kTuneBuckets, BMLP_EINVAL, "bucket %d out of range", bucket);
+    need(variant != nullptr, BMLP_EINVAL, "variant: null pointer");
+    *variant = h->tune[kernel][bucket];
+    if (ms) *ms = h->tune_ms[kernel][bucket];
+  });
+}
+
+bmlp_status bmlp_tune_set(bmlp_handle h, int32_t kernel, int32_t bucket, int32_t variant) {
+  return guarded([&] {
+    need_handle(h);
+    need(kernel >= 0 && kernel < bmlp_ctx::kTuneKernels, BMLP_EINVAL, "unknown tuned kernel %d", kernel);
+    need(bucket >= -1 && bucket < bmlp_ctx::kTuneBuckets, BMLP_EINVAL, "bucket %d out of range", bucket);
+    need(variant >= -1 && variant < kTuneCandidates[kernel], BMLP_EINVAL, "candidate %d out of range", variant);
+    for (int b = 0; b < bmlp_ctx::kTuneBuckets; ++b)
+      if (bucket == -1 || b == bucket) {
+        h->tune[kernel][b] = variant;
+        h->tune_ms[kernel][b] = 0.f;
+      }
+  });
+}
+
+// The autotuner: every candidate of the selected kernels is timed on synthetic operands of every bucket
+// (seeded random squarings C = A | A.A of the bucket's representative size and class, generated on the
+// device), and the fastest is kept for that bucket.  Candidates return identical bits (checked by the
+// tests), so the choice changes speed only.
+bmlp_status bmlp_autotune(bmlp_handle h, int32_t kernel_mask, int32_t reps, const char* cache_out, float* report) {
+  return guarded([&] {
+    need_handle(h);
+    need(reps >= 1 && reps <= 100, BMLP_EINVAL, "reps must be 1..100");
+    need((kernel_mask & ~((1 << bmlp_ctx::kTuneKernels) - 1)) == 0, BMLP_EINVAL, "unknown kernel in mask");
+    DeviceGuard dg(h->device);
+    hipStream_t s = nullptr;
+    bmlp_opts o;
+    bmlp_opts_init(&o);
+    if (report)
+      for (int i = 0; i < bmlp_ctx::kTuneKernels * bmlp_ctx::kTuneBuckets * BMLP_TUNE_MAX_CANDIDATES; ++i)
+        report[i] = -1.f;
+    hipEvent_t e0 = h->evp0, e1 = h->evp1;
+    for (int sb = 0; sb < 4; ++sb) {
+      const i64 n = (i64)2048 << sb, nw = words_for(n);
+      u64* A = ws_bits(h, S_T0, n, nw, o);
+      u64* C = ws_bits(h, S_T1, n, nw, o);
+      u64* AT = ws_bits(h, S_BT, n, nw, o);
+      for (int db = 0; db < 4; ++db) {
+        // classes: sparse 2^-13; 2^-8; dense with about 2 expected paths of length 2 per pair (the
+        // squarings of a closure on its way to saturation); a dense 40% corner block in a sparse rest
+        const int sdense = sb < 2 ? 5 : 6;
+        const int s_in = db == 0 ? 13 : db == 1 ? 8 : db == 2 ? sdense : 4;
+        const int s_out = db == 3 ? 13 : s_in;
+        const i64 brows = db == 3 ? (2 * n) / 5 : n, bwords = db == 3 ? (2 * nw) / 5 : nw;
+        hip_check(launch_fill_random(A, n, n, nw, 0x5EEDull * (u64)(16 * sb + db + 1), s_in, s_out, brows, bwords, s),
+                  "fill_random");
+        hip_check(launch_transpose(A, n, n, nw, AT, nw, s), "transpose");
+        const int bucket = 4 * sb + db;
+        for (int k = 0; k < bmlp_ctx::kTuneKernels; ++k) {
+          if (!((kernel_mask >> k) & 1)) continue;
+          float best = 0.f;
+          int bestv = -1;
+          for (int v = 0; v < kTuneCandidates[k]; ++v) {
+            GemmArgs g{A, nw, A, nw, A, nw, C, nw, nullptr, 0, n, n, n, nullptr};
+            std::vector<float> ts;
+            for (int r = 0; r <= reps; ++r) {
+              hip_check(hipEventRecord(e0, s), "hipEventRecord");
+              if (k == TK_MFMA) hip_check(launch_gemm_mfma(g, AT, nw, s, v), "gemm_mfma");
+              else hip_check(launch_gemm_valu(g, s, v), "gemm_valu");
+              hip_check(hipEventRecord(e1, s), "hipEventRecord");
+              hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+              float ms = 0.f;
+              hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+              if (r > 0) ts.push_back(ms);  // the first launch warms up
+            }
+            std::sort(ts.begin(), ts.end());
+            const float med = ts[ts.size() / 2];
+            if (report) report[(k * bmlp_ctx::kTuneBuckets + bucket) * BMLP_TUNE_MAX_CANDIDATES + v] = med;
+            if (bestv < 0 || med < best) {
+              best = med;
+              bestv = v;
+            }
+          }
+          h->tune[k][bucket] = bestv;
+          h->tune_ms[k][bucket] = best;
+        }
+      }
+    }
+    if (cache_out) {
+      const bmlp_status st = bmlp_tune_save(h, cache_out);
+      need(st == BMLP_OK, st, "%s", g_last_error.c_str());
+    }
+  });
+}
+
+// The tuning cache: JSON with the device's architecture name and compute-unit count (a cache is used only
+// on the same kind of device) and, per tuned kernel, the candidate and its time for every bucket.
+namespace {
+const char* kTuneNames[bmlp_ctx::kTuneKernels] = {"mfma_product", "valu_product"};
+void device_key(int device, std::string* arch, int* cus) {
+  hipDeviceProp_t prop;
+  hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+  *arch = prop.gcnArchName;
+  *cus = prop.multiProcessorCount;
+}
+}  // namespace
+
+bmlp_status bmlp_tune_save(bmlp_handle h, const char* path) {
+  return guarded([&] {
+    need_handle(h);
+    need(path != nullptr, BMLP_EINVAL, "path: null pointer");
+    std::string arch;
+    int cus = 0;
+    device_key(h->device, &arch, &cus);
+    FILE* fp = std::fopen(path, "w");
+    need(fp != nullptr, BMLP_EINVAL, "cannot write %s", path);
+    std::fprintf(fp, "{\n  \"format\": \"bmlp-autotune\",\n  \"version\": 1,\n  \"arch\": \"%s\",\n  \"cus\": %d,\n",
+                 arch.c_str(), cus);
+    std::fprintf(fp, "  \"buckets\": \"4 * size + class; size by 2 m k n below 3.4e10, 2.7e11, 2.2e12, beyond; class: "
+                     "left operand bits below 1/4096, below 1/64, denser or unknown, block-structured\",\n");
+    std::fprintf(fp, "  \"kernels\": [\n");
+    for (int k = 0; k < bmlp_ctx::kTuneKernels; ++k) {
+      std::fprintf(fp, "    {\"kernel\": %d, \"name\": \"%s\", \"candidates\": %d,\n     \"choice\": [", k, kTuneNames[k],
+                   kTuneCandidates[k]);
+      for (int b = 0; b < bmlp_ctx::kTuneBuckets; ++b) std::fprintf(fp, "%s%d", b ? ", " : "", h->tune[k][b]);
+      std::fprintf(fp, "],\n     \"ms\": [");
+      for (int b = 0; b < bmlp_ctx::kTuneBuckets; ++b) std::fprintf(fp, "%s%.4f", b ? ", " : "", h->tune_ms[k][b]);
+      std::fprintf(fp, "]}%s\n", k + 1 < bmlp_ctx::kTuneKernels ? "," : "");
+    }
+    std::fprintf(fp, "  ]\n}\n");
+    const bool ok = std::ferror(fp) == 0;
+    std::fclose(fp);
+    need(ok, BMLP_EINVAL, "short write to %s", path);
+  });
+}
+
+bmlp_status bmlp_tune_load(bmlp_handle h, const char* path) {
+  return guarded([&] {
+    need_handle(h);
+    need(path != nullptr, BMLP_EINVAL, "path: null pointer");
+    FILE* fp = std::fopen(path, "r");
+    need(fp != nullptr, BMLP_EMODEL, "cannot open tuning cache %s", path);
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, fp)) > 0) text.append(buf, got);
+    std::fclose(fp);
+    // a small reader for the format bmlp_tune_save writes
+    auto str_after = [&](const char* key, size_t from, std::string* out) -> size_t {
+      const size_t k = text.find(key, from);
+      if (k == std::string::npos) return k;
+      const size_t a = text.find('"', text.find(':', k) + 1);
+      const size_t b = a == std::string::npos ? a : text.find('"', a + 1);
+      if (b == std::string::npos) return b;
+      *out = text.substr(a + 1, b - a - 1);
+      return b;
+    };
+    auto int_after = [&](const char* key, size_t from, long* out) -> size_t {
+      const size_t k = text.find(key, from);
+      if (k == std::string::npos) return k;
+      const size_t c = text.find(':', k);
+      if (c == std::string::npos) return c;
+      char* end = nullptr;
+      *out = std::strtol(text.c_str() + c + 1, &end, 10);
+      return end == text.c_str() + c + 1 ? std::string::npos : (size_t)(end - text.c_str());
+    };
+    std::string fmt, arch;
+    long version = 0, cus = 0;
+    need(str_after("\"format\"", 0, &fmt) != std::string::npos && fmt == "bmlp-autotune" &&
+             int_after("\"version\"", 0, &version) != std::string::npos && version == 1,
+         BMLP_EMODEL, "%s is not a tuning cache of this format", path);
+    need(str_after("\"arch\"", 0, &arch) != std::string::npos && int_after("\"cus\"", 0, &cus) != std::string::npos,
+         BMLP_EMODEL, "%s: no device key", path);
+    std::string my_arch;
+    int my_cus = 0;
+    DeviceGuard dg(h->device);
+    device_key(h->device, &my_arch, &my_cus);
+    need(arch == my_arch && cus == my_cus, BMLP_EMODEL, "%s was tuned on %s with %ld CUs, this device is %s with %d",
+         path, arch.c_str(), cus, my_arch.c_str(), my_cus);
+    int32_t tune[bmlp_ctx::kTuneKernels][bmlp_ctx::kTuneBuckets];
+    float ms[bmlp_ctx::kTuneKernels][bmlp_ctx::kTuneBuckets];
+    size_t at = 0;
+    for (int k = 0; k < bmlp_ctx::kTuneKernels; ++k) {
+      long kk = -1;
+      at = int_after("\"kernel\"", at, &kk);
+      need(at != std::string::npos && kk == k, BMLP_EMODEL, "%s: kernel %d missing", path, k);
+      size_t c = text.find("\"choice\"", at);
+      need(c != std::string::npos, BMLP_EMODEL, "%s: kernel %d has no choice", path, k);
+      c = text.find('[', c);
+      const char* q = text.c_str() + c + 1;
+      for (int b = 0; b < bmlp_ctx::kTuneBuckets; ++b) {
+        char* end = nullptr;
+        const long v = std::strtol(q, &end, 10);
+        need(end != q && v >= -1 && v < kTuneCandidates[k], BMLP_EMODEL, "%s: bad choice for kernel %d", path, k);
+        tune[k][b] = (int32_t)v;
+        q = end;
+        while (*q == ',' || *q == ' ') ++q;
+      }
+      size_t m = text.find("\"ms\"", at);
+      need(m != std::string::npos, BMLP_EMODEL, "%s: kernel %d has no times", path, k);
+      q = text.c_str() + text.find('[', m) + 1;
+      for (int b = 0; b < bmlp_ctx::kTuneBuckets; ++b) {
+        char* end = nullptr;
+        ms[k][b] = std::strtof(q, &end);
+        need(end != q, BMLP_EMODEL, "%s: bad time for kernel %d", path, k);
+        q = end;
+        while (*q == ',' || *q == ' ') ++q;
+      }
+      at = (size_t)(q - text.c_str());
+    }
+    std::memcpy(h->tune, tune, sizeof tune);
+    std::memcpy(h->tune_ms, ms, sizeof ms);
   });
 }
 

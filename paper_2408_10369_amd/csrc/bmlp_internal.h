@@ -17,6 +17,9 @@ static inline i64 words_for(i64 n) { return (n + 63) >> 6; }
 // All bit matrices: row-major, LSB-first uint64 words, leading dimension in
 // words.  `nw` = ceil(cols/64) words carry data; words in [nw, ld) are padding.
 hipError_t launch_fill_zero(u64* p, i64 nwords, hipStream_t s);
+// seeded random bits, each 1 with probability 2^-s_in inside rows < brows and words < bwords, 2^-s_out elsewhere
+hipError_t launch_fill_random(u64* a, i64 rows, i64 n, i64 ld, u64 seed, int s_in, int s_out, i64 brows, i64 bwords,
+                              hipStream_t s);
 hipError_t launch_pack_u8(const uint8_t* d, i64 rows, i64 n, i64 ldd, u64* bits, i64 ld, hipStream_t s);
 hipError_t launch_unpack_u8(const u64* bits, i64 rows, i64 n, i64 ld, uint8_t* d, i64 ldd, hipStream_t s);
 // bits must be zeroed beforehand; out-of-range pairs set *bad = 1.
@@ -86,10 +89,21 @@ struct GemmArgs {
   unsigned long long* executed = nullptr;  // += matrix-core ops actually issued (MFMA arm, optional)
 };
 enum ProductKernel { PK_VALU = 0, PK_MFMA = 1 };
-hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s);
+// variant (autotuner candidates, identical bits): rows per wave of the tile for M > 64: 0 -> 16, 1 -> 8,
+// 2 -> 4 (thin products, M <= 64, always take 4)
+constexpr int kValuVariants = 3;
+hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s, int variant = 0);
 // MFMA int8 arm: needs B transposed (BT: N x K bits, ldbt) instead of B; K <= 64 * gemm_mfma_max_kwords()
 // (the int32 sums stay exact).
-hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s);
+// variant: the tile code (autotuner candidates, identical bits):
+//   0, 1, 2  256 x 256 tile, operands expanded into e2m1 nibbles while staging (4 words of k per LDS
+//            stage); output tiles in row-major, XCD-contiguous or XCD-interleaved order
+//   3, 4, 5  raw words in LDS, operands formed in registers (8 words per stage); the same three orders
+// A variant whose alignment needs (16-byte rows for 3..5) are not met runs as 0.
+constexpr int kMfmaVariants = 6;
+hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s, int variant = 0);
+bool gemm_mfma_variant_ok(int variant, const GemmArgs& g, const u64* BT, i64 ldbt);
+int gemm_mfma_variants();
 i64 gemm_mfma_max_kwords();
 
 // ---------------------------------------------------------------- selection

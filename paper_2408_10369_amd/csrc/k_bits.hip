@@ -32,6 +32,31 @@ __global__ void k_fill_zero(u64* __restrict__ p, i64 nwords) {
   for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < nwords; i += (i64)gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// Seeded random bits for the autotuner's synthetic operands: every bit of word (row, w) is 1 with
+// probability 2^-s (the AND of s words of a counter-based hash, splitmix64's finaliser), s = s_in inside
+// the block rows < brows, words < bwords and s_out elsewhere; padding bits stay 0.
+__device__ __forceinline__ u64 mix64(u64 z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void k_fill_random(u64* __restrict__ a, i64 rows, i64 n, i64 ld, u64 seed, int s_in, int s_out, i64 brows,
+                              i64 bwords) {
+  const i64 nw = (n + 63) >> 6;
+  const i64 total = rows * ld;
+  for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < total; i += (i64)gridDim.x * blockDim.x) {
+    const i64 row = i / ld, w = i - row * ld;
+    u64 v = 0;
+    if (w < nw) {
+      const int sh = (row < brows && w < bwords) ? s_in : s_out;
+      v = ~0ull;
+      for (int k = 0; k < sh; ++k) v &= mix64(seed + 0x9E3779B97F4A7C15ull * (u64)(i * 16 + k + 1));
+      if (w == nw - 1) v &= last_word_mask(n);
+    }
+    a[i] = v;
+  }
+}
+
 // one wave per output word: lane l looks at byte (row, 64w + l); the wave
 // ballot is the packed word.
 __global__ void k_pack_u8(const uint8_t* __restrict__ d, i64 rows, i64 n, i64 ldd, u64* __restrict__ bits, i64 ld) {
@@ -615,6 +640,14 @@ __global__ void k_bits_to_csr(const u64* __restrict__ a, i64 rows, i64 n, i64 ld
 }
 
 }  // namespace
+
+hipError_t launch_fill_random(u64* a, i64 rows, i64 n, i64 ld, u64 seed, int s_in, int s_out, i64 brows, i64 bwords,
+                              hipStream_t s) {
+  if (rows <= 0 || ld <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_random, dim3(grid_for(rows * ld, kBlock, 16384)), dim3(kBlock), 0, s, a, rows, n, ld, seed,
+                     s_in, s_out, brows, bwords);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_zero(u64* p, i64 nwords, hipStream_t s) {
   if (nwords <= 0) return hipSuccess;

@@ -20,6 +20,7 @@
 #include "bmlp_internal.h"
 #include "valu_tile.h"
 #include "mfma_tile.h"
+#include "mfma_tile2.h"
 
 namespace bmlp {
 
@@ -131,33 +132,104 @@ hipError_t launch_rpw(const GemmArgs& g, hipStream_t s, i64 target_blocks) {
   return hipGetLastError();
 }
 
+// Output tile of workgroup b.  Workgroups are dealt to the 8 XCDs round-robin (b mod 8), and each XCD
+// has its own L2.  Orders:
+//   0  row-major over the tiles: an XCD gets every row tile and an eighth of the column tiles;
+//   1  contiguous: the workgroups of one XCD get a contiguous range of an order that walks groups of
+//      ceil(rtiles / 2) row tiles column by column, so each XCD works on half of A's row tiles and a
+//      quarter of B's column tiles (a 2 x 4 partition of the output);
+//   2  interleaved: XCD x gets the tiles (tr, tc) with tr = x / 4 (mod 2) and tc = x (mod 4), walked in
+//      groups of 8 of its row tiles, column by column: the same halving of each XCD's operand footprint,
+//      while a block-structured product (its work in one corner) still spreads over all XCDs.  It needs
+//      an even number of row tiles and a multiple of 4 column tiles, else order 1 is used.
+__device__ __forceinline__ void grouped(i64 li, i64 rows, i64 cols, i64 gmax, i64* i, i64* j) {
+  const i64 gsz = rows < gmax ? rows : gmax;
+  const i64 group = li / (gsz * cols), first = group * gsz;
+  const i64 rin = rows - first < gsz ? rows - first : gsz;
+  const i64 in = li - group * gsz * cols;
+  *i = first + in % rin;
+  *j = in / rin;
+}
+__device__ __forceinline__ void tile_of_block(i64 b, i64 rtiles, i64 ctiles, int order, i64* tr, i64* tc) {
+  if (order == 2 && (rtiles & 1) == 0 && (ctiles & 3) == 0) {
+    const i64 x = b & 7, li = b >> 3;
+    i64 i, j;
+    grouped(li, rtiles / 2, ctiles / 4, 8, &i, &j);
+    *tr = 2 * i + (x >> 2);
+    *tc = 4 * j + (x & 3);
+    return;
+  }
+  if (order == 0) {
+    *tr = b / ctiles;
+    *tc = b % ctiles;
+    return;
+  }
+  const i64 nb = rtiles * ctiles, per = nb / 8;
+  const i64 bb = b < 8 * per ? (b % 8) * per + b / 8 : b;
+  grouped(bb, rtiles, ctiles, (rtiles + 1) / 2, tr, tc);
+}
+
+template <int ORDER>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_gemm_mfma(MfmaTile g, const u32* __restrict__ pred, u32 pred_val) {
   __shared__ MfmaLds L;
   if (pred && *pred != pred_val) return;  // another arm serves this round
-  const i64 ctiles = (g.N + kMT - 1) / kMT;
-  mfma_tile(L, g, blockIdx.x / ctiles, blockIdx.x % ctiles);
+  const i64 rtiles = (g.M + kMT - 1) / kMT, ctiles = (g.N + kMT - 1) / kMT;
+  i64 tr, tc;
+  tile_of_block(blockIdx.x, rtiles, ctiles, ORDER, &tr, &tc);
+  mfma_tile(L, g, tr, tc);
+}
+
+template <int KC, int SUB, int ORDER>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_gemm_mfma2(MfmaTile g, const u32* __restrict__ pred, u32 pred_val) {
+  __shared__ Mfma2Lds<KC> L;
+  if (pred && *pred != pred_val) return;  // another arm serves this round
+  const i64 rtiles = (g.M + kMT - 1) / kMT, ctiles = (g.N + kMT - 1) / kMT;
+  i64 tr, tc;
+  tile_of_block(blockIdx.x, rtiles, ctiles, ORDER, &tr, &tc);
+  mfma_tile2<KC, SUB>(L, g, tr, tc);
 }
 
 }  // namespace
 
 i64 gemm_mfma_max_kwords() { return kMaxKWords; }
 
-hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s) {
+int gemm_mfma_variants() { return kMfmaVariants; }
+
+bool gemm_mfma_variant_ok(int variant, const GemmArgs& g, const u64* BT, i64 ldbt) {
+  if (variant < 0 || variant >= kMfmaVariants) return false;
+  if (variant <= 2) return true;
+  // the second layout loads rows of A and B^T in 16-byte pieces
+  return ((uintptr_t)g.A & 15u) == 0 && ((uintptr_t)BT & 15u) == 0 && (g.lda & 1) == 0 && (ldbt & 1) == 0;
+}
+
+hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s, int variant) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (words_for(g.K) > kMaxKWords) return hipErrorInvalidValue;
+  if (!gemm_mfma_variant_ok(variant, g, BT, ldbt)) variant = 0;
   const i64 tiles = ((g.M + kMT - 1) / kMT) * ((g.N + kMT - 1) / kMT);
   const MfmaTile t{g.A, g.lda, BT, ldbt, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N,
                     g.changed, g.newbits, g.executed, nullptr};
-  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)tiles), dim3(512), 0, s, t, g.pred, g.pred_val);
+  const dim3 grid((unsigned)tiles), block(512);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((k_gemm_mfma<1>), grid, block, 0, s, t, g.pred, g.pred_val); break;
+    case 2: hipLaunchKernelGGL((k_gemm_mfma<2>), grid, block, 0, s, t, g.pred, g.pred_val); break;
+    case 3: hipLaunchKernelGGL((k_gemm_mfma2<8, 1, 0>), grid, block, 0, s, t, g.pred, g.pred_val); break;
+    case 4: hipLaunchKernelGGL((k_gemm_mfma2<8, 1, 1>), grid, block, 0, s, t, g.pred, g.pred_val); break;
+    case 5: hipLaunchKernelGGL((k_gemm_mfma2<8, 1, 2>), grid, block, 0, s, t, g.pred, g.pred_val); break;
+    default: hipLaunchKernelGGL((k_gemm_mfma<0>), grid, block, 0, s, t, g.pred, g.pred_val); break;
+  }
   return hipGetLastError();
 }
 
 
-hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s) {
+hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s, int variant) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   constexpr i64 kTargetBlocks = 1024;  // 4 workgroups per CU on 256 CUs
   if (g.M <= 64) return launch_rpw<4>(g, s, kTargetBlocks);
+  if (variant == 1) return launch_rpw<8>(g, s, kTargetBlocks);
+  if (variant == 2) return launch_rpw<4>(g, s, kTargetBlocks);
   return launch_rpw<16>(g, s, kTargetBlocks);
 }
 

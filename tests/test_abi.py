@@ -64,3 +64,20 @@ def test_create_without_device_fails_cleanly(L):
     rc = L.bmlp_create(ctypes.byref(h), 0)
     assert rc in (P.EDEVICE, P.EINVAL)
     assert not h.value
+
+
+def test_tune_buckets_host_only(L):
+    """Buckets of the autotuned tile code: 4 sizes by the dense operation count, 4 operand classes."""
+    import paper_2408_10369_amd as P
+    C = P.Context
+    assert C.tune_candidates(P.TUNE_MFMA_PRODUCT) >= 2 and C.tune_candidates(P.TUNE_VALU_PRODUCT) >= 2
+    assert C.tune_candidates(7) == 0 and C.tune_buckets(7) == 0
+    assert C.tune_buckets(P.TUNE_MFMA_PRODUCT) == 16
+    k = P.TUNE_MFMA_PRODUCT
+    assert C.tune_bucket_of(k, 2048, 2048, 2048) == 4 * 0 + 2          # unknown density counts as dense
+    assert C.tune_bucket_of(k, 4096, 4096, 4096, 1e-5) == 4 * 1 + 0
+    assert C.tune_bucket_of(k, 8192, 8192, 8192, 1e-3) == 4 * 2 + 1
+    assert C.tune_bucket_of(k, 16384, 16384, 16384, 0.3) == 4 * 3 + 2
+    assert C.tune_bucket_of(k, 16384, 16384, 16384, 0.3, structured=True) == 4 * 3 + 3
+    assert C.tune_bucket_of(k, 65536, 65536, 65536, -1.0) == 4 * 3 + 2
+    assert C.tune_bucket_of(k, -1, 1, 1) == -1 and C.tune_bucket_of(9, 1, 1, 1) == -1
