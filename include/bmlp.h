@@ -205,6 +205,19 @@ bmlp_status bmlp_rms(bmlp_handle h, const uint64_t *R1, uint64_t *Rstar, int64_t
 bmlp_status bmlp_smp(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, const uint64_t *V,
                      uint64_t *Vstar, int64_t k, int64_t ldv, const bmlp_opts *opts, void *stream,
                      bmlp_stats *stats);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc): the selection of bmlp_smp, Vstar = V x R1+ (V x R1* when reflexive
+   is nonzero), always by the one-launch sparse-frontier kernel, with the relation's edge index (CSR,
+   and from mean out-degree 4 the in-edges too) built in a fixed 64 MiB device array of the library
+   instead of the handle's workspace.  It calls no hipMalloc, hipFree or allocating routine.  Limits:
+   n <= 131072, and the index must fit: about 28 (n + 1) bytes plus 4 bytes per edge (8 per edge from
+   mean degree 4); larger inputs give BMLP_ENOMEM with nothing written.  Synchronises the stream once (the
+   edge count, read back into the handle's pinned words, sizes the index); the selection itself is
+   asynchronous on the stream.  Every call on one device shares that device's array, and its contents
+   are those of the last call: calls that overlap on one device (other streams, other threads or other
+   handles) race and must not be issued.  Same arguments and errors as bmlp_smp otherwise. */
+bmlp_status bmlp_smp_noalloc(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, const uint64_t *V,
+                             uint64_t *Vstar, int64_t k, int64_t ldv, int32_t reflexive, void *stream);
 /* General linear recursion over binary predicates (Theorem 1): the least model of
        p(X,Y) <- b(X,Y).    p(X,Y) <- s(X,Z), p(Z,Y).
    as P = Rs* x Rb, the least P with P = Rb + Rs x P.  Rbase, Rstep, P: n x n (ld).  P must not

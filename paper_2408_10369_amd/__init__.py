@@ -43,7 +43,7 @@ EXPORTS = [
     "bmlp_set_trace", "bmlp_dispatcher_load", "bmlp_dispatcher_save", "bmlp_dispatcher_loaded",
     "bmlp_dispatcher_train", "bmlp_dispatcher_forward", "bmlp_mlp_loss_grad",
     "bmlp_tune_candidates", "bmlp_tune_buckets", "bmlp_tune_bucket_of", "bmlp_tune_get", "bmlp_tune_set",
-    "bmlp_autotune", "bmlp_tune_save", "bmlp_tune_load",
+    "bmlp_autotune", "bmlp_tune_save", "bmlp_tune_load", "bmlp_smp_noalloc",
 ]
 TUNE_MAX_CANDIDATES = 8
 TUNE_MFMA_PRODUCT, TUNE_VALU_PRODUCT = 0, 1
@@ -137,6 +137,7 @@ def lib():
     L.bmlp_product.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, i64, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_rms.argtypes = [vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_smp.argtypes = [vp, vp, i64, i64, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
+    L.bmlp_smp_noalloc.argtypes = [vp, vp, i64, i64, vp, vp, i64, i64, ctypes.c_int32, vp]
     L.bmlp_compose_linear.argtypes = [vp, vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_compose_two_sided.argtypes = [vp, vp, vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_closure_insert.argtypes = [vp, vp, i64, i64, vp, vp, i64, P(Opts), vp, P(Stats)]
@@ -358,6 +359,16 @@ class Context:
                               ctypes.byref(st) if st is not None else None))
         if st is not None:
             stats.update(st.as_dict())
+        return out
+
+    def smp_noalloc(self, R1, n: int, V, out, reflexive: bool = False, stream=None):
+        """bmlp_smp_noalloc: the selection with the edge index in the library's fixed device array; the
+        caller provides every buffer (``out`` included)."""
+        _, ld = _bits_shape(R1, n)
+        k, ldv = _bits_shape(V)
+        _bits_shape(out, k)
+        _check(lib().bmlp_smp_noalloc(self._h, _ptr(R1), n, ld, _ptr(V), _ptr(out), k, ldv,
+                                      1 if reflexive else 0, _stream(stream)))
         return out
 
     def compose_linear(self, Rbase, Rstep, n: int, out=None, opts=None, stream=None, stats=None):

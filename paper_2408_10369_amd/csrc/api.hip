@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -51,6 +52,7 @@ struct bmlp_ctx {
   void* slot[kSlots] = {};
   size_t slot_bytes[kSlots] = {};
   u32* d_flags = nullptr;  // device flags / counters
+  unsigned char* scratch = nullptr;  // this device's address of the file-scope scratch array (bmlp_smp_noalloc)
   u32* h_flags = nullptr;  // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evp0 = nullptr, evp1 = nullptr;
   // timed products awaiting their readback (statistics): event pairs and matrix-core work counters
@@ -75,6 +77,32 @@ struct bmlp_ctx {
 };
 
 namespace {
+
+// ------------------------------------------------------------ allocation-free selection
+// bmlp_smp_noalloc builds the relation's edge index in this file-scope device array instead of the
+// handle's workspace.  Each device the library runs on holds its own copy until the process ends; host
+// code never uses the array's name as an address (it is a host-side stand-in): bmlp_create looks up the
+// device address once per device with hipGetSymbolAddress and keeps it.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxScratchDevices] = {};
+
+// The scratch array's address on `device`, which must be the current device.  Null if it cannot be found.
+unsigned char* scratch_address(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_dev[device] = (unsigned char*)p;
+  }
+  return g_scratch_dev[device];
+}
 
 // Kernels with autotuned tile code (bmlp_ctx::tune): the matrix-core product, the VALU product.
 enum TuneKernel { TK_MFMA = 0, TK_VALU = 1 };
@@ -1059,6 +1087,7 @@ bmlp_status bmlp_create(bmlp_handle* h, int device) {
       fail(BMLP_ENOMEM, "handle allocation failed");
     }
     hip_check(hipMemset(c->d_flags, 0, F_WORDS * sizeof(u32)), "hipMemset");
+    c->scratch = scratch_address(device);
     *h = c;
     // default dispatcher model: $BMLP_DISPATCHER_MODEL, else dispatcher_model.bin beside the library
     // (an empty variable disables it); a missing or bad file leaves the plain schedule in force
@@ -1569,6 +1598,68 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, c
     if (stats) stats->arm = arm;
     sr.finish();
     if (h->trace && stats) h->trace->total_ms = (float)stats->device_ms;
+  });
+}
+
+// The selection of bmlp_smp by its one-launch sparse kernel with the relation's CSR (and, from mean degree
+// 4, its CSC) built in the file-scope scratch array: no allocation of any kind.  Layout of the scratch
+// (256-byte aligned parts): the round counter, out-degrees, row offsets, in-degrees, fill cursors,
+// in-edge offsets, then the column indices of the CSR and the CSC.
+bmlp_status bmlp_smp_noalloc(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, const uint64_t* V,
+                             uint64_t* Vstar, int64_t k, int64_t ldv, int32_t reflexive, void* stream) {
+  return guarded([&] {
+    need_handle(h);
+    need(n <= smp_rows_max_n(), BMLP_EINVAL, "bmlp_smp_noalloc supports n <= %lld", (long long)smp_rows_max_n());
+    check_bits_arg(R1, "R1", n, n, ld);
+    check_bits_arg(V, "V", k, n, ldv);
+    check_bits_arg(Vstar, "Vstar", k, n, ldv);
+    const Range rv = range_of(Vstar, k, ldv);
+    need(!overlap(rv, range_of(V, k, ldv)), BMLP_EALIAS, "Vstar overlaps V");
+    need(!overlap(rv, range_of(R1, n, ld)), BMLP_EALIAS, "Vstar overlaps R1");
+    if (k == 0) return;
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+      hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
+      return;
+    }
+    need(h->scratch != nullptr, BMLP_EDEVICE, "the scratch array has no address on device %d", h->device);
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t n1 = (size_t)n + 1;
+    const size_t o_deg = 256, o_rp = o_deg + up(4 * n1), o_degt = o_rp + up(8 * n1), o_cur = o_degt + up(4 * n1),
+                 o_rpt = o_cur + up(4 * n1), o_ci = o_rpt + up(8 * n1);
+    need(o_ci <= kScratchBytes, BMLP_ENOMEM, "scratch (%zu bytes) too small for n = %lld", kScratchBytes, (long long)n);
+    unsigned char* sp = h->scratch;
+    u32* rounds = (u32*)sp;
+    int32_t* deg = (int32_t*)(sp + o_deg);
+    i64* rp = (i64*)(sp + o_rp);
+    hip_check(launch_row_popcount(R1, n, n, ld, deg, nullptr, s), "row_popcount");
+    hip_check(launch_scan_rowptr(deg, n, rp, s), "scan");
+    // the edge count sizes the index: one readback into the handle's pinned flag words
+    hip_check(hipMemcpyAsync(h->h_flags + F_CNT, rp + n, sizeof(i64), hipMemcpyDeviceToHost, s), "memcpy");
+    hip_check(hipStreamSynchronize(s), "sync");
+    i64 m = 0;
+    std::memcpy(&m, h->h_flags + F_CNT, sizeof m);
+    const bool csc = m > 0 && (double)m >= kBottomUpMinDegree * (double)n;
+    const size_t o_cit = o_ci + up(4 * (size_t)std::max<i64>(m, 1));
+    const size_t end = csc ? o_cit + up(4 * (size_t)m) : o_cit;
+    need(end <= kScratchBytes, BMLP_ENOMEM, "scratch (%zu bytes) too small for n = %lld with %lld edges (%zu bytes)",
+         kScratchBytes, (long long)n, (long long)m, end);
+    int32_t* ci = (int32_t*)(sp + o_ci);
+    hip_check(launch_bits_to_csr(R1, n, n, ld, rp, ci, s), "bits_to_csr");
+    const i64* rpt = nullptr;
+    const int32_t* cit = nullptr;
+    if (csc) {
+      i64* t_rp = (i64*)(sp + o_rpt);
+      int32_t* t_ci = (int32_t*)(sp + o_cit);
+      hip_check(launch_csc_from_csr(rp, ci, n, m, (int32_t*)(sp + o_degt), (int32_t*)(sp + o_cur), t_rp, t_ci, s),
+                "csc_from_csr");
+      rpt = t_rp;
+      cit = t_ci;
+    }
+    hip_check(launch_fill_zero((u64*)rounds, 1, s), "fill_zero");  // a kernel, not a memset node
+    hip_check(launch_smp_rows(V, ldv, k, rp, ci, rpt, cit, R1, ld, n, reflexive ? 1 : 0, Vstar, ldv, rounds, s),
+              "smp_rows");
   });
 }
 
