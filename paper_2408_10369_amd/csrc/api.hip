@@ -19,6 +19,7 @@
 #include "bmlp_batch.h"
 #include "bmlp_mlp.h"
 #include "bmlp_internal.h"
+#include "rms_cost.h"
 
 using namespace bmlp;
 
@@ -123,8 +124,11 @@ enum FlagSlot {
   F_LIST = 44,     // length of a device row list
   F_QUEUE = 46,    // 64-bit piece counter of the gathers' overflow queue
   F_ROUNDS_OUT = 48,  // host side only: a one-launch selection's round count, read at the end of the call
-  F_WORDS = 128
+  F_TOT0 = 50,        // host side only: the first running bit count of an RMS chain, uploaded from here
+  F_CHAIN = 128,      // BMLP-RMS: one record of kRmsRecWords words per squaring (rms_core)
+  F_WORDS = 512
 };
+constexpr int kChainRecords = (F_WORDS - F_CHAIN) / kRmsRecWords;
 
 // S_RD .. S_RL: the semi-naive squarings of rms_core (delta, its row-list, the column gather and the rows;
 // the transposed route also takes S_RA, S_RX and S_BT for D^T, R^T and the gathered product); S_GQ: the
@@ -181,6 +185,7 @@ u64* ws_bits(bmlp_ctx* c, int s, i64 rows, i64 ld, const bmlp_opts& o) {
 // would take the workspace past the caller's limit.
 GatherQueue gather_queue(bmlp_ctx* c, i64 k, i64 n, const bmlp_opts& o) {
   GatherQueue q{nullptr, nullptr, 0};
+  if (words_for(n) > 256) return q;  // the wide-row gather kernel takes no queue
   const i64 cap = gather_queue_capacity(k, n);
   const size_t bytes = ((size_t)std::max<i64>(cap, 1) * sizeof(int2) + 255) & ~(size_t)255;
   if (c->slot_bytes[S_GQ] < bytes && o.workspace_limit > 0 &&
@@ -289,6 +294,7 @@ struct StatsRec {
   void product_begin() {
     if (!st) return;
     pool();
+    if (npend == bmlp_ctx::kPend) flush();  // a full batch is read back before the next product is timed
     // the counters of a batch are cleared together before its first product and copied back together
     if (npend == 0)
       hip_check(hipMemsetAsync(c->d_exec, 0, bmlp_ctx::kPend * sizeof(unsigned long long), s), "hipMemsetAsync");
@@ -298,7 +304,12 @@ struct StatsRec {
     if (!st) return;
     hip_check(hipEventRecord(c->pe1[npend], s), "hipEventRecord");
     pend[npend++] = Pending{m, k, n, arm};
-    if (npend == bmlp_ctx::kPend) flush();
+  }
+  // forget the last timed product: it was enqueued ahead under a device-side condition that did not hold,
+  // so it ran no work (its events and counter are reused by the next product).  Batches are read back
+  // before the next product, so the last one is always still pending.
+  void cancel_last() {
+    if (st && npend > 0) --npend;
   }
   void flush() {
     if (!st || npend == 0) return;
@@ -367,11 +378,11 @@ u32 read_flag(bmlp_ctx* c, hipStream_t s, int idx = 0) {
 
 // transpose of B (K x N) into the S_BT workspace, for the MFMA arm
 const u64* transpose_b(bmlp_ctx* c, const u64* B, i64 ldb, i64 K, i64 N, const bmlp_opts& o, hipStream_t s,
-                       i64* ldbt) {
+                       i64* ldbt, const u32* pred = nullptr, u32 pred_val = 0) {
   *ldbt = std::max<i64>(words_for(K), 1);
   *ldbt += *ldbt & 1;  // even, so that rows are 16-byte aligned (the tile codes that load 16-byte pieces)
   u64* bt = ws_bits(c, S_BT, N, *ldbt, o);
-  hip_check(launch_transpose(B, K, N, ldb, bt, *ldbt, s), "transpose");
+  hip_check(launch_transpose(B, K, N, ldb, bt, *ldbt, s, pred, pred_val), "transpose");
   return bt;
 }
 
@@ -401,14 +412,16 @@ int tuned_variant(const bmlp_ctx* c, int kernel, i64 M, i64 K, i64 N, double den
 void product(bmlp_ctx* c, const u64* A, i64 lda, const u64* B, i64 ldb, const u64* Cold, i64 ldco, u64* C, i64 ldc,
              u64* D, i64 ldd, i64 M, i64 K, i64 N, u32* changed, int arm, hipStream_t s, StatsRec& sr,
              const u64* BT = nullptr, i64 ldbt = 0, unsigned long long* newbits = nullptr, double density = -1.0,
-             bool structured = false) {
+             bool structured = false, const u32* pred = nullptr, u32 pred_val = 0) {
   GemmArgs g{A, lda, B, ldb, Cold, ldco, C, ldc, D, ldd, M, K, N, changed};
   g.executed = sr.exec_counter();
   g.newbits = newbits;
+  g.pred = pred;  // with pred, the product (and the transpose it needs) runs only when *pred == pred_val
+  g.pred_val = pred_val;
   if (arm == BMLP_ARM_PRODUCT_MFMA) {
     bmlp_opts dflt;
     bmlp_opts_init(&dflt);
-    if (!BT) BT = transpose_b(c, B, ldb, K, N, sr.o ? *sr.o : dflt, s, &ldbt);
+    if (!BT) BT = transpose_b(c, B, ldb, K, N, sr.o ? *sr.o : dflt, s, &ldbt, pred, pred_val);
     sr.product_begin();
     hip_check(launch_gemm_mfma(g, BT, ldbt, s, tuned_variant(c, TK_MFMA, M, K, N, density, structured)), "gemm_mfma");
   } else {
@@ -441,48 +454,11 @@ int product_arm(const bmlp_opts& o, i64 M, i64 N, i64 K) {
 
 i64 count_bits(bmlp_ctx* c, const u64* R, i64 rows, i64 n, i64 ld, hipStream_t s);
 
-// A squaring R.R of a sparse R is cheaper as row gathers (row i of R | R.R = R[i] | OR of the rows k
-// over the set bits k of R[i], the rows read whole) than as a dense product: the gathers move about
-// (bits + 3 n) rows of n bits, the dense product does 2 n^3 operations.  The rates are measured on
-// MI355X at n = 16,384: dense squarings on the matrix cores (4.5e15 on a product that skips nothing),
-// gathers of rows from L2 / Infinity Cache (888 MB in 222 us with all of a wave's loads in flight).
-constexpr double kMfmaSquareOpsPerSec = 4.5e15;
-constexpr double kValuSquareOpsPerSec = 1.7e15;
-constexpr double kGatherBytesPerSec = 4.0e12;
+// The cost model of the squarings (rms_cost.h) with the gather kernel's size limit
 bool rms_gather_pays(i64 n, i64 bits, int arm) {
-  if (n > gather_rows_max_n()) return false;
-  const double nn = (double)n, row_bytes = 8.0 * (double)words_for(n);
-  const double t_gather = ((double)bits + 3.0 * nn) * row_bytes / kGatherBytesPerSec;
-  const double t_dense =
-      2.0 * nn * nn * nn / (arm == BMLP_ARM_PRODUCT_MFMA ? kMfmaSquareOpsPerSec : kValuSquareOpsPerSec);
-  return t_gather < t_dense;
+  return bmlp::rms_gather_pays(n, bits, arm == BMLP_ARM_PRODUCT_MFMA, gather_rows_max_n());
 }
-
-// A squaring from the bits D new in the last one: with R_t = R_{t-1} | D and R_{t-1}.R_{t-1} inside R_t,
-//   R_t.R_t = R_t | R_t.D | D.R_t.
-// D.R_t is a row gather over the bits of D.  R_t.D is found one of two ways:
-//   columns: a column gather of R_t at the nonempty rows of D and a product with K = that number of rows;
-//   transposed: (D^T . R_t^T)^T, a second row gather over the bits of D between three transposes.
-// The transposed route costs about the bits of D; the column route about n^2 per nonempty row of D, so it
-// only pays when D's bits crowd into few rows.  Seconds of each part at the rates measured at n = 16,384
-// (transposes 3.2e12 bytes/s, moving the matrix in and out):
-struct SemiCost {
-  double common, cols_fixed, per_row, transposed, dense;
-};
-SemiCost rms_semi_cost(i64 n, i64 dbits, int arm) {
-  const double nn = (double)n, rb = 8.0 * (double)words_for(n), db = (double)dbits;
-  SemiCost c;
-  c.common = (db + 3.0 * nn) * rb / kGatherBytesPerSec;  // D.R_t and the copy of R_t
-  c.cols_fixed = 2.0 * nn * rb / 4.0e12;
-  c.per_row = 2.0 * nn * nn;  // Boolean operations of the product per nonempty row of D
-  c.transposed = db * rb / kGatherBytesPerSec + 3.0 * 2.0 * nn * rb / 3.2e12 + 2.0 * nn * rb / kGatherBytesPerSec;
-  c.dense = 2.0 * nn * nn * nn / (arm == BMLP_ARM_PRODUCT_MFMA ? kMfmaSquareOpsPerSec : kValuSquareOpsPerSec);
-  return c;
-}
-double rms_semi_cols_s(const SemiCost& c, i64 drows) {
-  return c.cols_fixed + c.per_row * (double)drows / (drows >= 512 ? 3.0e15 : 1.2e15);
-}
-constexpr double kSemiOverheadS = 50.0e-6;  // launches and the readbacks of the semi-naive route
+SemiCost rms_semi_cost(i64 n, i64 dbits, int arm) { return bmlp::rms_semi_cost(n, dbits, arm == BMLP_ARM_PRODUCT_MFMA); }
 
 struct GraphInfo {
   i64 n = 0, m = 0, maxdeg = 0, nonempty = 0;
@@ -576,7 +552,6 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   const bool may_semi = o.product_arm == BMLP_ARM_AUTO && n <= gather_rows_max_n() && n <= gather_cols_max_n();
   bool have_prev = false;
   i64 dbits = 0;
-  unsigned long long* nb = (unsigned long long*)(c->d_flags + F_NEW);
   const GatherQueue gq = may_gather ? gather_queue(c, n, n, o) : GatherQueue{nullptr, nullptr, 0};
   // relabel (once) before the first dense squaring on the matrix cores, when a tenth or more of the rows
   // are empty (a light class is certain) and the squarings are large enough to repay the passes over the
@@ -585,98 +560,142 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
                      (n - g0.nonempty) * 10 >= n;
   const int32_t* inv = nullptr;
   const int cap = ceil_log2(std::max<i64>(n, 2)) + 2;
+  // Squaring t records its new-bit count (and the device's running bit count and route) in record t of the
+  // chain.  While the host reads squaring t's count back, squaring t + 1 is already queued: a one-thread
+  // kernel picks its route from that count on the device (the rules below, rms_cost.h), and its row
+  // gathers and its dense product are both enqueued, each running only when the route names it.  The
+  // device thus never waits for the host between squarings that stay on those two routes; the semi-naive
+  // form and the relabelling are left to the host (route "host"), which then runs the squaring itself.
+  need(cap + 1 < kChainRecords, BMLP_EINVAL, "n too large for the squaring chain");
+  u32* recs = c->d_flags + F_CHAIN;
+  auto rec_nb = [&](int t) { return (unsigned long long*)(recs + (i64)t * kRmsRecWords); };
+  hip_check(launch_fill_zero((u64*)recs, (i64)(F_WORDS - F_CHAIN) / 2, s), "fill_zero");
+  if (g0.n == n) {
+    // the running count starts from the bits of R1 (counted above)
+    const unsigned long long m0 = (unsigned long long)g0.m;
+    std::memcpy(c->h_flags + F_TOT0, &m0, sizeof m0);
+    hip_check(hipMemcpyAsync(recs + 2, c->h_flags + F_TOT0, sizeof m0, hipMemcpyHostToDevice, s), "memcpy");
+  }
+  const bool mfma = arm == BMLP_ARM_PRODUCT_MFMA;
   int it = 0;
+  u32 queued = RR_HOST;  // route of squaring `it` when it was enqueued ahead (gathers or dense), else RR_HOST
   for (;;) {
-    hip_check(hipMemsetAsync(c->d_flags, 0, 8 * sizeof(u32), s), "hipMemsetAsync");
-    // variant 0: R <- R | R.R ; variant 1: R' = R.R (I is in R, so R | R.R = R.R).  R only grows, so
-    // once gathers stop paying they never pay again and the bit count is no longer needed.
-    may_gather = may_gather && rms_gather_pays(n, bits, arm);
-    const bool gather = may_gather;  // the gathers count the new bits, which keeps `bits` exact
-    // semi-naive squaring: 0 none, 1 columns route, 2 transposed route
-    int semi = 0;
-    u64* dl = nullptr;
-    int32_t* list = nullptr;
-    i64 drows = 0;
-    if (!gather && may_semi && have_prev && dbits > 0) {
-      const SemiCost sc = rms_semi_cost(n, dbits, arm);
-      // D has at least ceil(dbits / n) nonempty rows
-      const double cols_lb = rms_semi_cols_s(sc, (dbits + n - 1) / n);
-      if (sc.common + std::min(sc.transposed, cols_lb) + kSemiOverheadS < sc.dense) {
-        dl = ws_bits(c, S_RD, n, ldi, o);
-        hip_check(launch_ewise(2, cur, ldi, nxt, ldi, dl, ldi, n, n, s), "andnot");
-        semi = 2;
-        if (cols_lb < sc.transposed) {
-          list = (int32_t*)ws(c, S_RL, (size_t)n * sizeof(int32_t), o);
-          hip_check(hipMemsetAsync(c->d_flags + F_LIST, 0, sizeof(u32), s), "hipMemsetAsync");
-          hip_check(launch_nonempty_rows(dl, n, n, ldi, list, c->d_flags + F_LIST, s), "nonempty_rows");
-          drows = (i64)read_flag(c, s, F_LIST);
-          const double tc = rms_semi_cols_s(sc, drows);
-          if (drows > 0 && tc < sc.transposed) semi = 1;
-          if (sc.common + std::min(tc, sc.transposed) + kSemiOverheadS >= sc.dense) semi = 0;
-        }
-      }
-    }
+    unsigned long long* nb = rec_nb(it);
     int tarm = arm;
     bool count_after = false;  // new bits = popcount of the result - bits of cur
-    if (gather) {
-      const GatherQueue q = sized(gq, bits, n);
-      hip_check(launch_gather_rows(cur, ldi, n, cur, ldi, n, 1, nxt, ldi, s, nullptr, nb, &q), "gather_rows");
+    int semi = 0;              // semi-naive squaring: 0 none, 1 columns route, 2 transposed route
+    if (queued == RR_GATHER) {
       if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
       tarm = BMLP_ARM_PRODUCT_GATHER;
-    } else if (semi == 1) {
-      // nxt = cur | D.cur (rows of cur gathered over the bits of D), then nxt |= cur.D over the rows of D
-      // with a bit: A = those columns of cur, X = those rows of D
-      const i64 kw = words_for(drows);
-      u64* am = ws_bits(c, S_RA, n, kw, o);
-      u64* xm = ws_bits(c, S_RX, drows, ldi, o);
-      hip_check(launch_ewise(4, cur, ldi, nullptr, 0, nxt, ldi, n, n, s), "copy");
-      const GatherQueue q = sized(gq, dbits, n);
-      hip_check(launch_gather_rows(dl, ldi, n, cur, ldi, n, 2, nxt, ldi, s, nullptr, nb, &q), "gather_rows");
-      hip_check(launch_gather_cols(cur, ldi, n, n, list, drows, 0, am, kw, s), "gather_cols");
-      hip_check(launch_copy_rows(dl, ldi, list, drows, n, xm, ldi, s), "copy_rows");
-      product(c, am, kw, xm, ldi, nxt, ldi, nxt, ldi, nullptr, 0, n, drows, n, nullptr, product_arm(o, n, n, drows), s,
-              sr, nullptr, 0, nb);
-      if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
-      tarm = BMLP_ARM_PRODUCT_SEMINAIVE;
-    } else if (semi == 2) {
-      // cur.D = (D^T . cur^T)^T: rows of cur^T gathered over the bits of D^T and transposed back; then
-      // nxt (R_{t-1} is no longer needed once D is formed) = cur | cur.D, and nxt |= D.cur
-      u64* dt = ws_bits(c, S_RX, n, ldi, o);
-      u64* ct = ws_bits(c, S_BT, n, ldi, o);
-      u64* yt = ws_bits(c, S_RA, n, ldi, o);
-      hip_check(launch_transpose(dl, n, n, ldi, dt, ldi, s), "transpose");
-      hip_check(launch_transpose(cur, n, n, ldi, ct, ldi, s), "transpose");
-      const GatherQueue q = sized(gq, dbits, n);
-      hip_check(launch_gather_rows(dt, ldi, n, ct, ldi, n, 0, yt, ldi, s, nullptr, nullptr, &q), "gather_rows");
-      hip_check(launch_transpose(yt, n, n, ldi, dt, ldi, s), "transpose");  // dt now holds cur.D
-      hip_check(launch_ewise(0, dt, ldi, cur, ldi, nxt, ldi, n, n, s), "or");
-      hip_check(launch_gather_rows(dl, ldi, n, cur, ldi, n, 2, nxt, ldi, s, nullptr, nullptr, &q), "gather_rows");
-      hip_check(launch_popcount_total(nxt, n, n, ldi, nb, s), "popcount_total");
-      count_after = true;
-      if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
-      tarm = BMLP_ARM_PRODUCT_SEMINAIVE_T;
-    } else {
-      if (may_relabel) {
-        may_relabel = false;
-        int32_t* perm;
-        int32_t* pinv;
-        if (rms_relabel(c, cur, ldi, n, o, s, &perm, &pinv)) {
-          // R_{t-1} in nxt is not needed by a dense squaring; the next one finds both in the new labels
-          hip_check(launch_permute(cur, ldi, perm, n, nxt, ldi, s), "permute");
-          std::swap(cur, nxt);
-          inv = pinv;
+    } else if (queued != RR_DENSE) {
+      // the host runs this squaring.  variant 0: R <- R | R.R ; variant 1: R' = R.R (I is in R, so
+      // R | R.R = R.R).  R only grows, so once gathers stop paying they never pay again and the bit
+      // count is no longer needed.
+      may_gather = may_gather && rms_gather_pays(n, bits, arm);
+      const bool gather = may_gather;  // the gathers count the new bits, which keeps `bits` exact
+      u64* dl = nullptr;
+      int32_t* list = nullptr;
+      i64 drows = 0;
+      if (!gather && may_semi && have_prev && dbits > 0) {
+        const SemiCost sc = rms_semi_cost(n, dbits, arm);
+        // D has at least ceil(dbits / n) nonempty rows
+        const double cols_lb = rms_semi_cols_s(sc, (dbits + n - 1) / n);
+        if (sc.common + std::min(sc.transposed, cols_lb) + kSemiOverheadS < sc.dense) {
+          dl = ws_bits(c, S_RD, n, ldi, o);
+          hip_check(launch_ewise(2, cur, ldi, nxt, ldi, dl, ldi, n, n, s), "andnot");
+          semi = 2;
+          if (cols_lb < sc.transposed) {
+            list = (int32_t*)ws(c, S_RL, (size_t)n * sizeof(int32_t), o);
+            hip_check(launch_fill_zero((u64*)(c->d_flags + F_LIST), 1, s), "fill_zero");
+            hip_check(launch_nonempty_rows(dl, n, n, ldi, list, c->d_flags + F_LIST, s), "nonempty_rows");
+            drows = (i64)read_flag(c, s, F_LIST);
+            const double tc = rms_semi_cols_s(sc, drows);
+            if (drows > 0 && tc < sc.transposed) semi = 1;
+            if (sc.common + std::min(tc, sc.transposed) + kSemiOverheadS >= sc.dense) semi = 0;
+          }
         }
       }
-      product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, c->d_flags, arm, s, sr, nullptr, 0,
-              nb, g0.n == n ? (double)bits / ((double)n * (double)n) : -1.0,  // the bit count is kept once counted
-              inv != nullptr);
+      if (gather) {
+        const GatherQueue q = sized(gq, bits, n);
+        hip_check(launch_gather_rows(cur, ldi, n, cur, ldi, n, 1, nxt, ldi, s, nullptr, nb, &q), "gather_rows");
+        if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
+        tarm = BMLP_ARM_PRODUCT_GATHER;
+      } else if (semi == 1) {
+        // nxt = cur | D.cur (rows of cur gathered over the bits of D), then nxt |= cur.D over the rows of D
+        // with a bit: A = those columns of cur, X = those rows of D
+        const i64 kw = words_for(drows);
+        u64* am = ws_bits(c, S_RA, n, kw, o);
+        u64* xm = ws_bits(c, S_RX, drows, ldi, o);
+        hip_check(launch_ewise(4, cur, ldi, nullptr, 0, nxt, ldi, n, n, s), "copy");
+        const GatherQueue q = sized(gq, dbits, n);
+        hip_check(launch_gather_rows(dl, ldi, n, cur, ldi, n, 2, nxt, ldi, s, nullptr, nb, &q), "gather_rows");
+        hip_check(launch_gather_cols(cur, ldi, n, n, list, drows, 0, am, kw, s), "gather_cols");
+        hip_check(launch_copy_rows(dl, ldi, list, drows, n, xm, ldi, s), "copy_rows");
+        product(c, am, kw, xm, ldi, nxt, ldi, nxt, ldi, nullptr, 0, n, drows, n, nullptr, product_arm(o, n, n, drows),
+                s, sr, nullptr, 0, nb);
+        if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
+        tarm = BMLP_ARM_PRODUCT_SEMINAIVE;
+      } else if (semi == 2) {
+        // cur.D = (D^T . cur^T)^T: rows of cur^T gathered over the bits of D^T and transposed back; then
+        // nxt (R_{t-1} is no longer needed once D is formed) = cur | cur.D, and nxt |= D.cur
+        u64* dt = ws_bits(c, S_RX, n, ldi, o);
+        u64* ct = ws_bits(c, S_BT, n, ldi, o);
+        u64* yt = ws_bits(c, S_RA, n, ldi, o);
+        hip_check(launch_transpose(dl, n, n, ldi, dt, ldi, s), "transpose");
+        hip_check(launch_transpose(cur, n, n, ldi, ct, ldi, s), "transpose");
+        const GatherQueue q = sized(gq, dbits, n);
+        hip_check(launch_gather_rows(dt, ldi, n, ct, ldi, n, 0, yt, ldi, s, nullptr, nullptr, &q), "gather_rows");
+        hip_check(launch_transpose(yt, n, n, ldi, dt, ldi, s), "transpose");  // dt now holds cur.D
+        hip_check(launch_ewise(0, dt, ldi, cur, ldi, nxt, ldi, n, n, s), "or");
+        hip_check(launch_gather_rows(dl, ldi, n, cur, ldi, n, 2, nxt, ldi, s, nullptr, nullptr, &q), "gather_rows");
+        hip_check(launch_popcount_total(nxt, n, n, ldi, nb, s), "popcount_total");
+        count_after = true;
+        if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
+        tarm = BMLP_ARM_PRODUCT_SEMINAIVE_T;
+      } else {
+        if (may_relabel) {
+          may_relabel = false;
+          int32_t* perm;
+          int32_t* pinv;
+          if (rms_relabel(c, cur, ldi, n, o, s, &perm, &pinv)) {
+            // R_{t-1} in nxt is not needed by a dense squaring; the next one finds both in the new labels
+            hip_check(launch_permute(cur, ldi, perm, n, nxt, ldi, s), "permute");
+            std::swap(cur, nxt);
+            inv = pinv;
+          }
+        }
+        product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb,
+                g0.n == n ? (double)bits / ((double)n * (double)n) : -1.0,  // the bit count is kept once counted
+                inv != nullptr);
+      }
     }
     sr.trace(it, tarm);
     ++it;
-    hip_check(hipMemcpyAsync(c->h_flags, c->d_flags, 8 * sizeof(u32), hipMemcpyDeviceToHost, s), "memcpy");
+    // enqueue squaring `it` ahead (it reads nxt and writes cur), unless this one was semi-naive (its count
+    // is a total, not the new bits) or the cap is reached
+    const bool ahead = semi == 0 && it < cap;
+    if (ahead) {
+      hip_check(launch_rms_decide(recs, it, n, mfma ? 1 : 0, may_gather ? 1 : 0, (may_semi && dbits >= 0) ? 1 : 0,
+                                  may_relabel ? 0 : 1, gather_rows_max_n(), s),
+                "rms_decide");
+      const u32* route = recs + (i64)it * kRmsRecWords + 4;
+      unsigned long long* nb2 = rec_nb(it);
+      if (may_gather) {
+        const GatherQueue q = sized(gq, bits, n);
+        hip_check(launch_gather_rows(nxt, ldi, n, nxt, ldi, n, 1, cur, ldi, s, nullptr, nb2, &q, route, RR_GATHER),
+                  "gather_rows");
+      }
+      product(c, nxt, ldi, nxt, ldi, nxt, ldi, cur, ldi, nullptr, 0, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb2,
+              g0.n == n ? (double)bits / ((double)n * (double)n) : -1.0, inv != nullptr, route, RR_DENSE);
+    }
+    // read back this squaring's count and, when the next one was enqueued, its route (one contiguous copy)
+    const size_t words = ahead ? (size_t)kRmsRecWords + 5 : 2;
+    hip_check(hipMemcpyAsync(c->h_flags + F_CHAIN + (i64)(it - 1) * kRmsRecWords, recs + (i64)(it - 1) * kRmsRecWords,
+                             words * sizeof(u32), hipMemcpyDeviceToHost, s),
+              "memcpy");
     hip_check(hipStreamSynchronize(s), "sync");
     unsigned long long added = 0;
-    std::memcpy(&added, c->h_flags + F_NEW, sizeof added);
+    std::memcpy(&added, c->h_flags + F_CHAIN + (i64)(it - 1) * kRmsRecWords, sizeof added);
     if (count_after) {
       need((i64)added >= bits, BMLP_EDEVICE, "RMS bit count went down");
       added -= (unsigned long long)bits;
@@ -686,7 +705,11 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
     have_prev = true;
     const bool changed = added != 0;
     std::swap(cur, nxt);
+    queued = ahead ? c->h_flags[F_CHAIN + (i64)it * kRmsRecWords + 4] : (u32)RR_HOST;
+    if (ahead && queued != RR_DENSE) sr.cancel_last();  // the product enqueued ahead did not run
     if (!changed) break;
+    need(queued != RR_STOP, BMLP_EDEVICE, "RMS: the device saw no new bits");
+    if (ahead && queued != RR_GATHER) may_gather = false;  // the device found that gathers no longer pay
     need(it < cap, BMLP_EITER, "RMS exceeded %d products (n=%lld)", cap, (long long)n);
   }
   if (sr.st) sr.st->iterations = it;

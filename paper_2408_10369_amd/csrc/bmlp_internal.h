@@ -25,9 +25,10 @@ hipError_t launch_unpack_u8(const u64* bits, i64 rows, i64 n, i64 ld, uint8_t* d
 // bits must be zeroed beforehand; out-of-range pairs set *bad = 1.
 hipError_t launch_pack_coo(const int32_t* r, const int32_t* c, i64 m, i64 rows, i64 n, u64* bits, i64 ld,
                            u32* bad, hipStream_t s);
-// elementwise: op 0 = or, 1 = and, 2 = andnot (a & ~b), 3 = not a (padding kept 0), 4 = copy a
+// elementwise: op 0 = or, 1 = and, 2 = andnot (a & ~b), 3 = not a (padding kept 0), 4 = copy a; with
+// pred, only when *pred == pred_val
 hipError_t launch_ewise(int op, const u64* a, i64 lda, const u64* b, i64 ldb, u64* c, i64 ldc, i64 rows,
-                        i64 n, hipStream_t s);
+                        i64 n, hipStream_t s, const u32* pred = nullptr, u32 pred_val = 0);
 // zero the padding words [nw, ld) of every row (nw = ceil(n/64))
 hipError_t launch_zero_pad(u64* a, i64 rows, i64 n, i64 ld, hipStream_t s);
 // set the diagonal bits (i, i) for i < min(rows, n)
@@ -48,8 +49,10 @@ hipError_t launch_closure64(const u64* M, i64 ldm, i64 b, u64* out, i64 ldo, hip
 hipError_t launch_gather_cols(const u64* T, i64 ldt, i64 rows, i64 n, const int32_t* cols, i64 b, int diag, u64* A,
                               i64 lda, hipStream_t s);
 i64 gather_cols_max_n();
-// out (cols x rows) = transpose of in (rows x cols)
-hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out, i64 ldo, hipStream_t s);
+// out (cols x rows) = transpose of in (rows x cols); with pred, only when *pred == pred_val (the padding
+// words of out beyond ceil(rows/64) are then left as they are: the products never read them)
+hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out, i64 ldo, hipStream_t s,
+                            const u32* pred = nullptr, u32 pred_val = 0);
 // nonzero padding bits (columns >= n) in any row -> *bad = 1
 hipError_t launch_check_pad(const u64* a, i64 rows, i64 n, i64 ld, u32* bad, hipStream_t s);
 // per-row popcount into deg (int32), plus total into *total (u64, must be zeroed)
@@ -133,10 +136,18 @@ i64 gather_queue_capacity(i64 k, i64 n);
 // current out[map(r)] (2); map(r) = row_map[r], or r without a map (a map must not repeat a row);
 // n <= gather_rows_max_n().  *newbits (optional) += bits of the answers not in init.  out must not
 // overlap V or Cl.  With a queue (n <= 16,384), rows with more set bits than q->piece are split over waves.
+// With pred, the gather runs only when *pred == pred_val.
 hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 ldc, i64 n, int init, u64* out,
                               i64 ldo, hipStream_t s, const int32_t* row_map = nullptr,
-                              unsigned long long* newbits = nullptr, const GatherQueue* q = nullptr);
+                              unsigned long long* newbits = nullptr, const GatherQueue* q = nullptr,
+                              const u32* pred = nullptr, u32 pred_val = 0);
 i64 gather_rows_max_n();
+// The route of BMLP-RMS squaring t, decided on the device from the bits squaring t - 1 added: recs holds
+// kRmsRecWords-word records {new bits u64, running count u64, route u32} per squaring; reads record t - 1,
+// writes record t's running count and route (stop / row gathers / dense product / back to the host for
+// the semi-naive form or the relabelling).  One thread.
+hipError_t launch_rms_decide(u32* recs, int t, i64 n, int mfma, int may_gather, int may_semi, int dense_ok,
+                             i64 gather_max_n, hipStream_t s);
 // out[0] += set bits, out[1] = max(out[1], largest row count), out[2] += rows with a set bit
 // (out must be zeroed)
 hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* out, hipStream_t s);

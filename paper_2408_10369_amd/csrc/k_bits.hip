@@ -95,7 +95,8 @@ __global__ void k_pack_coo(const int32_t* __restrict__ r, const int32_t* __restr
 }
 
 __global__ void k_ewise(int op, const u64* __restrict__ a, i64 lda, const u64* __restrict__ b, i64 ldb,
-                        u64* __restrict__ c, i64 ldc, i64 rows, i64 n) {
+                        u64* __restrict__ c, i64 ldc, i64 rows, i64 n, const u32* __restrict__ pred, u32 pred_val) {
+  if (pred && *pred != pred_val) return;
   const i64 nw = (n + 63) >> 6;
   const i64 total = rows * ldc;
   const u64 lm = last_word_mask(n);
@@ -262,8 +263,10 @@ __device__ __forceinline__ u64 transpose_block64(u64 x) {
 }
 
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))  // two workgroups per CU
-k_transpose(const u64* __restrict__ in, i64 rows, i64 cols, i64 ldi, u64* __restrict__ out, i64 ldo) {
+k_transpose(const u64* __restrict__ in, i64 rows, i64 cols, i64 ldi, u64* __restrict__ out, i64 ldo,
+            const u32* __restrict__ pred, u32 pred_val) {
   __shared__ u64 buf[kTpLds];
+  if (pred && *pred != pred_val) return;  // the product this transpose feeds does not run
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -678,10 +681,10 @@ hipError_t launch_pack_coo(const int32_t* r, const int32_t* c, i64 m, i64 rows, 
 }
 
 hipError_t launch_ewise(int op, const u64* a, i64 lda, const u64* b, i64 ldb, u64* c, i64 ldc, i64 rows, i64 n,
-                        hipStream_t s) {
+                        hipStream_t s, const u32* pred, u32 pred_val) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ewise, dim3(grid_for(rows * ldc, kBlock, 16384)), dim3(kBlock), 0, s, op, a, lda, b, ldb, c,
-                     ldc, rows, n);
+                     ldc, rows, n, pred, pred_val);
   return hipGetLastError();
 }
 
@@ -751,10 +754,11 @@ hipError_t launch_gather_cols(const u64* T, i64 ldt, i64 rows, i64 n, const int3
   return hipGetLastError();
 }
 
-hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out, i64 ldo, hipStream_t s) {
+hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out, i64 ldo, hipStream_t s,
+                            const u32* pred, u32 pred_val) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   const i64 nwo = words_for(rows);
-  if (ldo > nwo) {
+  if (ldo > nwo && !pred) {
     hipError_t e = launch_fill_zero(out, cols * ldo, s);
     if (e != hipSuccess) return e;
   }
@@ -762,7 +766,8 @@ hipError_t launch_transpose(const u64* in, i64 rows, i64 cols, i64 ldi, u64* out
   if ((i64)kTpRows * ldi >= (1ll << 32) || (i64)64 * kTpWords * ldo >= (1ll << 32)) return hipErrorInvalidValue;
   const i64 tiles = ((rows + kTpRows - 1) / kTpRows) * ((words_for(cols) + kTpWords - 1) / kTpWords);
   if (tiles >= (1ll << 31)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_transpose, dim3((unsigned)tiles), dim3(512), 0, s, in, rows, cols, ldi, out, ldo);
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)tiles), dim3(512), 0, s, in, rows, cols, ldi, out, ldo, pred,
+                     pred_val);
   return hipGetLastError();
 }
 

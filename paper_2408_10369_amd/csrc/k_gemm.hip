@@ -21,6 +21,7 @@
 #include "valu_tile.h"
 #include "mfma_tile.h"
 #include "mfma_tile2.h"
+#include "rms_cost.h"
 
 namespace bmlp {
 
@@ -113,16 +114,16 @@ hipError_t launch_rpw(const GemmArgs& g, hipStream_t s, i64 target_blocks) {
   ksplit = (kwords + cps - 1) / cps;
   if (ksplit < 1) ksplit = 1;
   if (ksplit > 1) {
-    // C := Cold (unless C is Cold), D := 0
+    // C := Cold (unless C is Cold), D := 0 -- under the product's own condition
     if (g.Cold && g.Cold != g.C) {
-      hipError_t e = launch_ewise(4, g.Cold, g.ldco, nullptr, 0, g.C, g.ldc, g.M, g.N, s);
+      hipError_t e = launch_ewise(4, g.Cold, g.ldco, nullptr, 0, g.C, g.ldc, g.M, g.N, s, g.pred, g.pred_val);
       if (e != hipSuccess) return e;
     } else if (!g.Cold) {
-      hipError_t e = launch_ewise(4, g.C, g.ldc, nullptr, 0, g.C, g.ldc, g.M, 0, s);  // zero C rows
+      hipError_t e = launch_ewise(4, g.C, g.ldc, nullptr, 0, g.C, g.ldc, g.M, 0, s, g.pred, g.pred_val);  // zero C rows
       if (e != hipSuccess) return e;
     }
     if (g.D) {
-      hipError_t e = launch_ewise(4, g.D, g.ldd, nullptr, 0, g.D, g.ldd, g.M, 0, s);  // zero D rows
+      hipError_t e = launch_ewise(4, g.D, g.ldd, nullptr, 0, g.D, g.ldd, g.M, 0, s, g.pred, g.pred_val);  // zero D rows
       if (e != hipSuccess) return e;
     }
   }
@@ -191,7 +192,33 @@ k_gemm_mfma2(MfmaTile g, const u32* __restrict__ pred, u32 pred_val) {
   mfma_tile2<KC, SUB>(L, g, tr, tc);
 }
 
+// The device-side choice of the next RMS squaring's route (see launch_rms_decide), the same rules the host
+// driver applies: stop when the last squaring added nothing; row gathers while they pay; the semi-naive
+// form (driven by the host) when it may pay; else the dense product, unless the relabelling is still due.
+__global__ void k_rms_decide(u32* __restrict__ recs, int t, i64 n, int mfma, int may_gather, int may_semi,
+                             int dense_ok, i64 gather_max_n) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const unsigned long long* prev = (const unsigned long long*)(recs + (i64)(t - 1) * kRmsRecWords);
+  unsigned long long* cur = (unsigned long long*)(recs + (i64)t * kRmsRecWords);
+  const unsigned long long added = prev[0];
+  const unsigned long long bits = prev[1] + added;
+  cur[1] = bits;
+  u32 route;
+  if (added == 0) route = RR_STOP;
+  else if (may_gather && rms_gather_pays(n, (i64)bits, mfma != 0, gather_max_n)) route = RR_GATHER;
+  else if (may_semi && rms_semi_may_pay(n, (i64)added, mfma != 0)) route = RR_HOST;
+  else route = dense_ok ? RR_DENSE : RR_HOST;
+  recs[(i64)t * kRmsRecWords + 4] = route;
+}
+
 }  // namespace
+
+hipError_t launch_rms_decide(u32* recs, int t, i64 n, int mfma, int may_gather, int may_semi, int dense_ok,
+                             i64 gather_max_n, hipStream_t s) {
+  hipLaunchKernelGGL(k_rms_decide, dim3(1), dim3(64), 0, s, recs, t, n, mfma, may_gather, may_semi, dense_ok,
+                     gather_max_n);
+  return hipGetLastError();
+}
 
 i64 gemm_mfma_max_kwords() { return kMaxKWords; }
 

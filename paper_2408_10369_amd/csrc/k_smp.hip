@@ -331,9 +331,10 @@ constexpr int kGatherWords = 2048;
 __global__ void __launch_bounds__(256)
 k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__ Cl, i64 ldc, i64 n, int init,
               u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map,
-              unsigned long long* __restrict__ newbits) {
+              unsigned long long* __restrict__ newbits, const u32* __restrict__ pred, u32 pred_val) {
   __shared__ int32_t srcs[1024];
   __shared__ int scan[256];
+  if (pred && *pred != pred_val) return;
   const i64 nw = (n + 63) >> 6;
   const u64 last_mask = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
   const int t = threadIdx.x;
@@ -434,7 +435,8 @@ __global__ void __launch_bounds__(256)
 k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__ Cl, i64 ldc, i64 n, int init,
                 u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map,
                 unsigned long long* __restrict__ newbits, int2* __restrict__ qe, unsigned long long* __restrict__ qn,
-                i64 qcap, int piece) {
+                i64 qcap, int piece, const u32* __restrict__ pred, u32 pred_val) {
+  if (pred && *pred != pred_val) return;  // another kernel serves this squaring
   const int lane = threadIdx.x & 63;
   const i64 wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const i64 nwaves = (i64)gridDim.x * 4;
@@ -545,7 +547,9 @@ template <int WPL>
 __global__ void __launch_bounds__(256)
 k_gather_rows_q(const u64* __restrict__ V, i64 ldv, const u64* __restrict__ Cl, i64 ldc, i64 n,
                 u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map, const int2* __restrict__ qe,
-                const unsigned long long* __restrict__ qn, i64 qcap, int piece, unsigned long long* __restrict__ newbits) {
+                const unsigned long long* __restrict__ qn, i64 qcap, int piece, unsigned long long* __restrict__ newbits,
+                const u32* __restrict__ pred, u32 pred_val) {
+  if (pred && *pred != pred_val) return;
   const int lane = threadIdx.x & 63;
   const i64 wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const i64 nwaves = (i64)gridDim.x * 4;
@@ -649,7 +653,7 @@ i64 gather_queue_capacity(i64 k, i64 n) { return k * ((n + kMinPiece - 1) / kMin
 
 hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 ldc, i64 n, int init, u64* out,
                               i64 ldo, hipStream_t s, const int32_t* row_map, unsigned long long* newbits,
-                              const GatherQueue* q) {
+                              const GatherQueue* q, const u32* pred, u32 pred_val) {
   if (k <= 0) return hipSuccess;
   const i64 nw = words_for(n);
   if (nw > kGatherWords) return hipErrorInvalidValue;
@@ -667,31 +671,31 @@ hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 l
     const unsigned grid = (unsigned)(blocks < 16384 ? blocks : 16384);
     if (nw <= 64)
       hipLaunchKernelGGL(k_gather_rows_w<1>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits, qe, qn, qcap, piece);
+                         row_map, newbits, qe, qn, qcap, piece, pred, pred_val);
     else if (nw <= 128)
       hipLaunchKernelGGL(k_gather_rows_w<2>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits, qe, qn, qcap, piece);
+                         row_map, newbits, qe, qn, qcap, piece, pred, pred_val);
     else
       hipLaunchKernelGGL(k_gather_rows_w<4>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits, qe, qn, qcap, piece);
+                         row_map, newbits, qe, qn, qcap, piece, pred, pred_val);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !queued) return e;
     // the pieces: their number is known on the device only, so a fixed grid strides over them
     const unsigned qgrid = grid < 2048 ? grid : 2048;
     if (nw <= 64)
       hipLaunchKernelGGL(k_gather_rows_q<1>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
-                         qn, qcap, piece, newbits);
+                         qn, qcap, piece, newbits, pred, pred_val);
     else if (nw <= 128)
       hipLaunchKernelGGL(k_gather_rows_q<2>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
-                         qn, qcap, piece, newbits);
+                         qn, qcap, piece, newbits, pred, pred_val);
     else
       hipLaunchKernelGGL(k_gather_rows_q<4>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
-                         qn, qcap, piece, newbits);
+                         qn, qcap, piece, newbits, pred, pred_val);
     return hipGetLastError();
   }
   const unsigned grid = (unsigned)(k < 65535 ? k : 65535);
   hipLaunchKernelGGL(k_gather_rows, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo, row_map,
-                     newbits);
+                     newbits, pred, pred_val);
   return hipGetLastError();
 }
 hipError_t launch_smp_round(const u64* fr, u64* fr_out, i64 ldf, u64* vis, i64 ldvis, i64 k, const i64* rp,
