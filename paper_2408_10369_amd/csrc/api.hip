@@ -685,8 +685,10 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
         hip_check(launch_gather_rows(nxt, ldi, n, nxt, ldi, n, 1, cur, ldi, s, nullptr, nb2, &q, route, RR_GATHER),
                   "gather_rows");
       }
-      product(c, nxt, ldi, nxt, ldi, nxt, ldi, cur, ldi, nullptr, 0, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb2,
-              g0.n == n ? (double)bits / ((double)n * (double)n) : -1.0, inv != nullptr, route, RR_DENSE);
+      // the bit count of R_it is not known on the host yet: a squaring that falls to the dense product
+      // counts as dense for the tuned tile code (sparser ones go to the gathers)
+      product(c, nxt, ldi, nxt, ldi, nxt, ldi, cur, ldi, nullptr, 0, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb2, -1.0,
+              inv != nullptr, route, RR_DENSE);
     }
     // read back this squaring's count and, when the next one was enqueued, its route (one contiguous copy)
     const size_t words = ahead ? (size_t)kRmsRecWords + 5 : 2;
@@ -1210,10 +1212,17 @@ bmlp_status bmlp_tune_set(bmlp_handle h, int32_t kernel, int32_t bucket, int32_t
   });
 }
 
-// The autotuner: every candidate of the selected kernels is timed on synthetic operands of every bucket
-// (seeded random squarings C = A | A.A of the bucket's representative size and class, generated on the
-// device), and the fastest is kept for that bucket.  Candidates return identical bits (checked by the
-// tests), so the choice changes speed only.
+// The autotuner.  Every candidate of the selected kernels is timed on the squarings C = R | R.R that a
+// closure goes through, at four sizes (n = 2,048, 4,096, 8,192, 16,384):
+//   * the states of a seeded random digraph of mean out-degree 8 on its way to its closure (they fill
+//     the "below 1/64" and "denser" classes);
+//   * the states of one of mean out-degree 2, just above the percolation threshold, once they are dense
+//     enough for the matrix cores, relabelled as the RMS driver relabels such a relation (the
+//     block-structured class);
+//   * uniform random bits for a class no state fell into (density 2^-13 for the sparsest).
+// The random bits are drawn on the device (k_fill_random).  A candidate's score in a bucket is its median
+// time summed over the bucket's states; the fastest is kept.  Candidates return identical bits (checked
+// by the tests), so the choice changes speed only.
 bmlp_status bmlp_autotune(bmlp_handle h, int32_t kernel_mask, int32_t reps, const char* cache_out, float* report) {
   return guarded([&] {
     need_handle(h);
@@ -1223,36 +1232,31 @@ bmlp_status bmlp_autotune(bmlp_handle h, int32_t kernel_mask, int32_t reps, cons
     hipStream_t s = nullptr;
     bmlp_opts o;
     bmlp_opts_init(&o);
+    constexpr int NK = bmlp_ctx::kTuneKernels, NC = BMLP_TUNE_MAX_CANDIDATES;
     if (report)
-      for (int i = 0; i < bmlp_ctx::kTuneKernels * bmlp_ctx::kTuneBuckets * BMLP_TUNE_MAX_CANDIDATES; ++i)
-        report[i] = -1.f;
+      for (int i = 0; i < NK * bmlp_ctx::kTuneBuckets * NC; ++i) report[i] = -1.f;
     hipEvent_t e0 = h->evp0, e1 = h->evp1;
+    unsigned long long* nbc = (unsigned long long*)(h->d_flags + F_NEW);
+    u64 seed = 0x5EED5EEDull;
     for (int sb = 0; sb < 4; ++sb) {
       const i64 n = (i64)2048 << sb, nw = words_for(n);
-      u64* A = ws_bits(h, S_T0, n, nw, o);
+      const int logn = 11 + sb;
+      u64* R = ws_bits(h, S_T0, n, nw, o);
       u64* C = ws_bits(h, S_T1, n, nw, o);
-      u64* AT = ws_bits(h, S_BT, n, nw, o);
-      for (int db = 0; db < 4; ++db) {
-        // classes: sparse 2^-13; 2^-8; dense with about 2 expected paths of length 2 per pair (the
-        // squarings of a closure on its way to saturation); a dense 40% corner block in a sparse rest
-        const int sdense = sb < 2 ? 5 : 6;
-        const int s_in = db == 0 ? 13 : db == 1 ? 8 : db == 2 ? sdense : 4;
-        const int s_out = db == 3 ? 13 : s_in;
-        const i64 brows = db == 3 ? (2 * n) / 5 : n, bwords = db == 3 ? (2 * nw) / 5 : nw;
-        hip_check(launch_fill_random(A, n, n, nw, 0x5EEDull * (u64)(16 * sb + db + 1), s_in, s_out, brows, bwords, s),
-                  "fill_random");
-        hip_check(launch_transpose(A, n, n, nw, AT, nw, s), "transpose");
-        const int bucket = 4 * sb + db;
-        for (int k = 0; k < bmlp_ctx::kTuneKernels; ++k) {
+      u64* P = ws_bits(h, S_T2, n, nw, o);
+      u64* RT = ws_bits(h, S_BT, n, nw, o);
+      double sum[NK][4][NC] = {};
+      int states[4] = {0, 0, 0, 0};
+      auto time_state = [&](const u64* A, int cls) {
+        hip_check(launch_transpose(A, n, n, nw, RT, nw, s), "transpose");
+        for (int k = 0; k < NK; ++k) {
           if (!((kernel_mask >> k) & 1)) continue;
-          float best = 0.f;
-          int bestv = -1;
           for (int v = 0; v < kTuneCandidates[k]; ++v) {
             GemmArgs g{A, nw, A, nw, A, nw, C, nw, nullptr, 0, n, n, n, nullptr};
             std::vector<float> ts;
             for (int r = 0; r <= reps; ++r) {
               hip_check(hipEventRecord(e0, s), "hipEventRecord");
-              if (k == TK_MFMA) hip_check(launch_gemm_mfma(g, AT, nw, s, v), "gemm_mfma");
+              if (k == TK_MFMA) hip_check(launch_gemm_mfma(g, RT, nw, s, v), "gemm_mfma");
               else hip_check(launch_gemm_valu(g, s, v), "gemm_valu");
               hip_check(hipEventRecord(e1, s), "hipEventRecord");
               hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
@@ -1261,15 +1265,73 @@ bmlp_status bmlp_autotune(bmlp_handle h, int32_t kernel_mask, int32_t reps, cons
               if (r > 0) ts.push_back(ms);  // the first launch warms up
             }
             std::sort(ts.begin(), ts.end());
-            const float med = ts[ts.size() / 2];
-            if (report) report[(k * bmlp_ctx::kTuneBuckets + bucket) * BMLP_TUNE_MAX_CANDIDATES + v] = med;
-            if (bestv < 0 || med < best) {
-              best = med;
-              bestv = v;
-            }
+            sum[k][cls][v] += ts[ts.size() / 2];
+          }
+        }
+        ++states[cls];
+      };
+      // R <- R | R.R (the first matrix-core candidate), returning the bits it added
+      auto square = [&]() -> i64 {
+        hip_check(launch_transpose(R, n, n, nw, RT, nw, s), "transpose");
+        hip_check(launch_fill_zero((u64*)nbc, 1, s), "fill_zero");
+        GemmArgs g{R, nw, R, nw, R, nw, C, nw, nullptr, 0, n, n, n, nullptr};
+        g.newbits = nbc;
+        hip_check(launch_gemm_mfma(g, RT, nw, s, 0), "gemm_mfma");
+        std::swap(R, C);
+        return (i64)read_flag(h, s, F_NEW) | ((i64)read_flag(h, s, F_NEW + 1) << 32);
+      };
+      auto cls_of = [&](i64 bits) {
+        const double d = (double)bits / ((double)n * (double)n);
+        return d < 1.0 / 4096.0 ? 0 : d < 1.0 / 64.0 ? 1 : 2;
+      };
+      // 1. mean out-degree 8, squared to its closure
+      hip_check(launch_fill_random(R, n, n, nw, ++seed, logn - 3, logn - 3, n, nw, s), "fill_random");
+      i64 bits = count_bits(h, R, n, n, nw, s);
+      for (int step = 0; step < 8; ++step) {
+        time_state(R, cls_of(bits));
+        const i64 added = square();
+        if (added == 0) break;
+        bits += added;
+      }
+      // 2. mean out-degree 2: squared until dense, relabelled, then its squarings timed as block-structured
+      hip_check(launch_fill_random(R, n, n, nw, ++seed, logn - 1, logn - 1, n, nw, s), "fill_random");
+      bits = count_bits(h, R, n, n, nw, s);
+      for (int step = 0; step < 8 && cls_of(bits) < 2; ++step) {
+        const i64 added = square();
+        if (added == 0) break;
+        bits += added;
+      }
+      int32_t* perm;
+      int32_t* pinv;
+      if (rms_relabel(h, R, nw, n, o, s, &perm, &pinv)) {
+        hip_check(launch_permute(R, nw, perm, n, P, nw, s), "permute");
+        std::swap(R, P);
+        for (int step = 0; step < 3; ++step) {
+          time_state(R, 3);
+          if (square() == 0) break;
+        }
+      }
+      // 3. uniform random bits for the classes no state fell into: 2^-13, 2^-8, 2^-(logn/2 - 1), and a
+      //    dense corner block of 40% of the rows and columns in a sparse rest
+      for (int cls = 0; cls < 4; ++cls) {
+        if (states[cls] > 0) continue;
+        const int s_in = cls == 0 ? 13 : cls == 1 ? 8 : cls == 2 ? logn / 2 - 1 : 4;
+        const int s_out = cls == 3 ? 13 : s_in;
+        const i64 brows = cls == 3 ? (2 * n) / 5 : n, bwords = cls == 3 ? (2 * nw) / 5 : nw;
+        hip_check(launch_fill_random(R, n, n, nw, ++seed, s_in, s_out, brows, bwords, s), "fill_random");
+        time_state(R, cls);
+      }
+      for (int k = 0; k < NK; ++k) {
+        if (!((kernel_mask >> k) & 1)) continue;
+        for (int cls = 0; cls < 4; ++cls) {
+          const int bucket = 4 * sb + cls;
+          int bestv = 0;
+          for (int v = 0; v < kTuneCandidates[k]; ++v) {
+            if (report) report[(k * bmlp_ctx::kTuneBuckets + bucket) * NC + v] = (float)(sum[k][cls][v] / states[cls]);
+            if (sum[k][cls][v] < sum[k][cls][bestv]) bestv = v;
           }
           h->tune[k][bucket] = bestv;
-          h->tune_ms[k][bucket] = best;
+          h->tune_ms[k][bucket] = (float)(sum[k][cls][bestv] / states[cls]);
         }
       }
     }
