@@ -67,9 +67,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
                     help="bound the oracle's closure rows per graph (0: all rows)")
-    ap.add_argument("--workloads", default="batch,programs,stream,isforeign,dynamic,samegen,io",
+    ap.add_argument("--workloads", default="c1,batch,programs,stream,isforeign,dynamic,samegen,io",
                     help="held-out workloads measured after the main one, plain vs learned schedule "
-                         "(comma list of batch, programs, stream, isforeign, dynamic, samegen, io; empty for none)")
+                         "(comma list of c1, batch, programs, stream, isforeign, dynamic, samegen, io; empty for none)")
     ap.add_argument("--stream-queries", type=int, default=10000,
                     help="queries of the n=65,536 stream to run (a prefix of the 10,000)")
     ap.add_argument("--workloads-only", action="store_true",
@@ -122,6 +122,16 @@ def main():
 
     # product launches of the timed steps, per kernel (0 VALU, 1 MFMA): RMS squarings and dense selection rounds
     prod = {arm: {"ms": 0.0, "ops": 0, "launches": 0, "issued": 0} for arm in KERNELS}
+    # the matrix-core launches of each graph's closure, for the spread of the per-launch rates
+    spread = [{"ms": 0.0, "ops": 0, "launches": 0, "issued": 0} for _ in range(len(graphs))]
+    smp_rec = {"ms": 0.0, "rows": 0}
+
+    def add_spread(gi, st):
+        sp = spread[gi]
+        sp["ms"] += st["product_ms_mfma"]
+        sp["ops"] += st["product_bool_ops_mfma"]
+        sp["launches"] += st["products_mfma"]
+        sp["issued"] += st["mfma_ops_issued"]
 
     def add_products(st):
         mf = prod[1]
@@ -148,8 +158,11 @@ def main():
                 smp_ms.append(st2["device_ms"])
                 if record:
                     add_products(st2)
+                    smp_rec["ms"] += st2["device_ms"]
+                    smp_rec["rows"] += k
             if record:
                 add_products(st)
+                add_spread(gi, st)
                 if len(per_graph) < len(graphs):
                     per_graph.append({"p": g["p"], "edges": g["m"], "rms_squarings": st["iterations"],
                                       "rms_squarings_by_gather": st["arm_trace"].count(B.ARM_PRODUCT_GATHER),
@@ -173,37 +186,62 @@ def main():
     pk = prod[arm]
     avg_launch_ms = pk["ms"] / max(pk["launches"], 1)
     ops_per_launch = pk["ops"] / max(pk["launches"], 1)
-    achieved_tops = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12 if avg_launch_ms > 0 else 0.0
+    dense_tops = ops_per_launch / (avg_launch_ms / 1000.0) / 1e12 if avg_launch_ms > 0 else 0.0
     kname, kdesc, bound, peak = KERNELS[arm]
+    # work done: the matrix-core operations the launches actually issued (saturated output tiles are copied
+    # and all-zero words of k skipped, so a launch issues less than the dense count of its product); the
+    # VALU kernel issues what it counts
+    work_per_launch = (pk["issued"] if arm == 1 else pk["ops"]) / max(pk["launches"], 1)
+    achieved = work_per_launch / (avg_launch_ms / 1000.0) / 1e12 if avg_launch_ms > 0 else 0.0
     roofline = {"bound": bound, "kernel": "%s (%s; every launch of it in the step: RMS squarings and dense "
                                           "selection rounds)" % (kname, kdesc),
-                "achieved": round(achieved_tops, 2), "peak": round(peak, 1), "unit": "Tbool-op/s",
-                "frac": round(achieved_tops / peak, 4), "traffic": measured_traffic(kname),
+                "achieved": round(achieved, 2), "peak": round(peak, 1), "unit": "Tbool-op/s",
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname),
                 "traffic_unit": "HBM bytes per launch",
-                "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": pk["launches"] // args.steps,
+                "work": "operations issued by the launches (not the dense count of the products)",
+                "work_per_launch": round(work_per_launch), "avg_launch_ms": round(avg_launch_ms, 4),
+                "launches_per_step": pk["launches"] // args.steps,
+                "dense_count_rate": round(dense_tops, 2),
+                "frac_dense_count": round(dense_tops / peak, 4),
+                "issued_fraction_of_dense_count": round(work_per_launch / max(ops_per_launch, 1), 4),
                 "other_product_kernel_ms_per_step": round(sum(prod[a]["ms"] for a in prod if a != arm) / args.steps,
                                                           3)}
-    if arm == 1 and pk["ms"] > 0:
-        # what the matrix cores actually ran: saturated output tiles and all-zero words of k are skipped, so
-        # this rate (not the algorithmic one above) is the hardware efficiency of the kernel
-        issued_tops = pk["issued"] / (pk["ms"] / 1000.0) / 1e12
-        roofline["issued_fraction_of_algorithmic"] = round(pk["issued"] / max(pk["ops"], 1), 4)
-        roofline["achieved_issued"] = round(issued_tops, 2)
-        roofline["frac_issued"] = round(issued_tops / peak, 4)
+    if arm == 1:
+        # the per-graph spread of the launches: average launch time and issued rate of each closure's
+        # matrix-core squarings
+        roofline["launch_spread"] = [
+            {"p": graphs[i]["p"], "launches_per_step": sp["launches"] // args.steps,
+             "avg_launch_ms": round(sp["ms"] / max(sp["launches"], 1), 4),
+             "issued_frac": round(sp["issued"] / (sp["ms"] / 1000.0) / 1e12 / peak, 4) if sp["ms"] > 0 else None,
+             "issued_fraction_of_dense_count": round(sp["issued"] / max(sp["ops"], 1), 4)}
+            for i, sp in enumerate(spread)]
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(graphs, n, args.cpu_sample_rows)
 
+    # the selections' data movement against the HBM roofline: query rows read and answer rows written
+    # (n / 8 bytes each; the edge index and the relation's rows read on the way are not counted)
+    smp_bytes = 2 * smp_rec["rows"] * (n // 8)
+    smp_hbm = {"bound": "hbm (latency at few rows)", "rows_per_step": smp_rec["rows"] // args.steps,
+               "device_ms_per_step": round(smp_rec["ms"] / args.steps, 3),
+               "rows_per_s": round(smp_rec["rows"] / (smp_rec["ms"] / 1e3), 1) if smp_rec["ms"] > 0 else None,
+               "achieved_GB_per_s": round(smp_bytes / (smp_rec["ms"] / 1e3) / 1e9, 2) if smp_rec["ms"] > 0 else None,
+               "peak_GB_per_s": 8000.0,
+               "frac": round(smp_bytes / (smp_rec["ms"] / 1e3) / 8e12, 5) if smp_rec["ms"] > 0 else None,
+               "bytes": "query rows read + answer rows written, n/8 bytes each"}
     out = {
         "metric": "closure/SMP queries per sec and Bool-op TOPS vs roofline",
         "value": round(value, 1), "unit": "query rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64 bit-packed (AND/OR)", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 bit-packed AND/OR (VALU kernels); e2m1 (fp4) matrix-core products with fp32 accumulation "
+                 "and a > 0 threshold (the dominant kernel)",
+        "data": "synthetic",
         "config": {"workload": "ER digraph density sweep n=16384, p in {1e-4,5e-4,1e-3,5e-3,1e-2}: "
                                "pack + BMLP-RMS closure + BMLP-SMP from k=1,64,1024 sources per graph",
                    "n": n, "graphs": len(graphs), "query_rows_per_step": rows_per_step},
-        "roofline": roofline, "cpu_baseline": cpu, "per_graph": per_graph,
+        "roofline": roofline, "cpu_baseline": cpu, "smp_hbm": smp_hbm, "per_graph": per_graph,
     }
     wl = [w for w in args.workloads.split(",") if w]
     if wl:
@@ -218,8 +256,8 @@ def main():
 def run_workloads(ctx, args):
     res = {}
     for name in [w for w in args.workloads.split(",") if w]:
-        fn = {"batch": wl_batch, "programs": wl_programs, "stream": wl_stream, "isforeign": wl_isforeign,
-              "dynamic": wl_dynamic, "samegen": wl_samegen, "io": wl_io}[name]
+        fn = {"c1": wl_c1, "batch": wl_batch, "programs": wl_programs, "stream": wl_stream,
+              "isforeign": wl_isforeign, "dynamic": wl_dynamic, "samegen": wl_samegen, "io": wl_io}[name]
         res[name] = fn(ctx, args)
         print(json.dumps({"workload_done": name}), file=sys.stderr, flush=True)
     return res
@@ -343,7 +381,9 @@ def wl_programs(ctx, args):
 
 def wl_stream(ctx, args):
     """A stream of selection queries (k log-uniform in [1, 4096]) over one scale-free digraph,
-    n = 65,536, m = 262,144, answered through a session; plain vs learned schedule."""
+    n = 65,536, m = 262,144, answered through a session; plain vs learned schedule.  The timed pass packs
+    each query asynchronously and asks for no statistics (the arm that served a query is read on the
+    host); the answers are fingerprinted in a second, untimed pass over the first queries."""
     import torch
 
     import gen
@@ -362,8 +402,10 @@ def wl_stream(ctx, args):
     # the plain schedule answers every query of this stream by the one-launch sparse selection; the other
     # static policy builds the closure at the first query and reads every answer off it
     modes["forced_closure"] = B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE)
+    rows_total = sum(len(q) for q in queries)
+    nverify = min(len(queries), 500)
     for mode, o in modes.items():
-        arms, hs = {}, []
+        arms = {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         closure_at = None
@@ -371,26 +413,73 @@ def wl_stream(ctx, args):
             for qi, (r, c) in enumerate(qr):
                 k = len(queries[qi])
                 Vk, Vsk = V[:k], Vs[:k]
-                ctx.pack_coo(r, c, k, n, out=Vk)
-                st = {}
-                g.query(Vk, out=Vsk, opts=o, stats=st)
-                arms[st["arm"]] = arms.get(st["arm"], 0) + 1
+                ctx.pack_coo_async(r, c, k, n, out=Vk)
+                g.query(Vk, out=Vsk, opts=o)
+                a = g.last_arm
+                arms[a] = arms.get(a, 0) + 1
                 if closure_at is None and g.has_closure:
                     closure_at = qi
-                hs.append(_hash_dev(Vsk, W))
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+        ctx.deferred_error()
+        # fingerprints of the answers to the first queries, in a pass of their own
+        hs = []
+        with ctx.graph(R, n) as g:
+            for qi in range(nverify):
+                r, c = qr[qi]
+                k = len(queries[qi])
+                ctx.pack_coo_async(r, c, k, n, out=V[:k])
+                g.query(V[:k], out=Vs[:k], opts=o)
+                hs.append(_hash_dev(Vs[:k], W))
         fp[mode] = [int(h) for h in torch.stack(hs).cpu()]
+        # bytes a query moves at the least: its rows read, one closure row per source read, its answers
+        # written (n / 8 bytes each) -- the rows of a read-off answer
+        hbm_bytes = 3 * rows_total * (n // 8)
         res[mode] = {"ms": round(ms, 1), "queries_per_s": round(len(queries) / (ms / 1e3), 1),
-                     "rows_per_s": round(sum(len(q) for q in queries) / (ms / 1e3), 1),
-                     "arms": {str(k): v for k, v in sorted(arms.items())}, "closure_built_at_query": closure_at}
+                     "rows_per_s": round(rows_total / (ms / 1e3), 1),
+                     "arms": {str(k): v for k, v in sorted(arms.items())}, "closure_built_at_query": closure_at,
+                     "hbm": {"bytes": hbm_bytes, "achieved_GB_per_s": round(hbm_bytes / (ms / 1e3) / 1e9, 1),
+                             "frac": round(hbm_bytes / (ms / 1e3) / 8e12, 4),
+                             "floor_ms_at_8TBps": round(hbm_bytes / 8e12 * 1e3, 2)}}
     return {"workload": "scale-free digraph n=65536 m=262144, %d queries, k log-uniform [1,4096] "
-                        "(%d rows), one session" % (len(queries), sum(len(q) for q in queries)),
+                        "(%d rows), one session" % (len(queries), rows_total),
             "plain": res["plain"], "learned": res["learned"], "forced_closure": res["forced_closure"],
             "speedup_learned_over_plain": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
             "learned_over_best_static_policy": round(
                 res["learned"]["ms"] / min(res["plain"]["ms"], res["forced_closure"]["ms"]), 3),
-            "bit_identical": all(h == fp["plain"] for h in fp.values())}
+            "bit_identical": all(h == fp["plain"] for h in fp.values()),
+            "bit_identical_checked_queries": nverify}
+
+
+def wl_c1(ctx, args):
+    """The smallest configuration as latency: BMLP-RMS on the n = 1,000, p = 0.002 digraph and BMLP-SMP from
+    its 10 sources, one call at a time (median of 50 calls, host wall time around each call)."""
+    import torch
+
+    import gen
+    import paper_2408_10369_amd as B
+
+    n, s, d, srcs = gen.c1()
+    R = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n)
+    r, c = gen.query_lists(srcs)
+    V = ctx.pack_coo(torch.as_tensor(r), torch.as_tensor(c), len(srcs), n)
+    out = {}
+    for name, fn in (("rms", lambda: ctx.rms(R, n)), ("smp_10_sources", lambda: ctx.smp(R, n, V))):
+        ref = fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(50):
+            t0 = time.perf_counter()
+            got = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e6)
+        st = {}
+        (ctx.rms(R, n, stats=st) if name == "rms" else ctx.smp(R, n, V, stats=st))
+        out[name] = {"us_median": round(sorted(ts)[25], 1), "us_min": round(min(ts), 1),
+                     "device_us": round(st["device_ms"] * 1e3, 1), "iterations": st["iterations"],
+                     "bit_identical_across_calls": bool(torch.equal(ref, got))}
+    return {"workload": "ER digraph n=1000, p=0.002 (%d edges): closure and 10-source selection latency" % len(s),
+            **out}
 
 
 def wl_isforeign(ctx, args):

@@ -153,6 +153,14 @@ bmlp_status bmlp_pack_u8(bmlp_handle h, const uint8_t *dense, int64_t rows, int6
    An index outside [0,rows) x [0,n) gives BMLP_EINVAL.  Synchronises the stream (error check). */
 bmlp_status bmlp_pack_coo(bmlp_handle h, const int32_t *row, const int32_t *col, int64_t m, int64_t rows,
                           int64_t n, uint64_t *bits, int64_t ld, void *stream);
+/* bmlp_pack_coo without its synchronisation, for streams of small packings: asynchronous on the stream.
+   A fact outside [0,rows) x [0,n) is skipped (nothing is written outside `bits`) and latched in the handle;
+   bmlp_deferred_error reports it. */
+bmlp_status bmlp_pack_coo_async(bmlp_handle h, const int32_t *row, const int32_t *col, int64_t m, int64_t rows,
+                                int64_t n, uint64_t *bits, int64_t ld, void *stream);
+/* BMLP_EINVAL when a fact given to bmlp_pack_coo_async on this handle since the last check lay outside its
+   matrix (the latch is then cleared), else BMLP_OK.  Synchronises the stream. */
+bmlp_status bmlp_deferred_error(bmlp_handle h, void *stream);
 /* Facts from a bit matrix (decoding, the inverse of bmlp_pack_coo): the set bits of `bits` (rows x n,
    ld) as (row, column) pairs, sorted by row and then column, written to the DEVICE int32 arrays row_out
    and col_out (either may be NULL) of capacity `cap` entries.  *count (HOST) receives the number of
@@ -283,11 +291,14 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc *graphs, int32_t c
    (ski-rental rule).  The session owns its closure buffer (n x ceil(n/64) words). */
 typedef struct bmlp_graph_s *bmlp_graph;
 bmlp_status bmlp_graph_open(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, void *stream, bmlp_graph *g);
-/* Vstar = V x R1+ (Eq. 5), like bmlp_smp; stats->arm tells which arm answered. */
+/* Vstar = V x R1+ (Eq. 5), like bmlp_smp; stats->arm tells which arm answered.  Without stats the query
+   is asynchronous on the stream except where the learned schedule times it (before the closure exists). */
 bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t *V, uint64_t *Vstar, int64_t k, int64_t ldv,
                              const bmlp_opts *opts, void *stream, bmlp_stats *stats);
 /* Whether the session holds the closure (1) or not (0). */
 int32_t bmlp_graph_has_closure(bmlp_graph g);
+/* The arm (bmlp_arm) that served the session's last query, -1 before the first; host-side, no waiting. */
+int32_t bmlp_graph_last_arm(bmlp_graph g);
 bmlp_status bmlp_graph_close(bmlp_graph g);
 
 /* ------------------------------------------------------------ autotuned tile code */

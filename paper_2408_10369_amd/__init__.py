@@ -44,6 +44,7 @@ EXPORTS = [
     "bmlp_dispatcher_train", "bmlp_dispatcher_forward", "bmlp_mlp_loss_grad",
     "bmlp_tune_candidates", "bmlp_tune_buckets", "bmlp_tune_bucket_of", "bmlp_tune_get", "bmlp_tune_set",
     "bmlp_autotune", "bmlp_tune_save", "bmlp_tune_load", "bmlp_smp_noalloc",
+    "bmlp_pack_coo_async", "bmlp_deferred_error", "bmlp_graph_last_arm",
 ]
 TUNE_MAX_CANDIDATES = 8
 TUNE_MFMA_PRODUCT, TUNE_VALU_PRODUCT = 0, 1
@@ -128,6 +129,9 @@ def lib():
     L.bmlp_version.restype = ctypes.c_int32
     L.bmlp_pack_u8.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
     L.bmlp_pack_coo.argtypes = [vp, vp, vp, i64, i64, i64, vp, i64, vp]
+    L.bmlp_pack_coo_async.argtypes = [vp, vp, vp, i64, i64, i64, vp, i64, vp]
+    L.bmlp_deferred_error.argtypes = [vp, vp]
+    L.bmlp_graph_last_arm.argtypes = [vp]
     L.bmlp_unpack_u8.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
     L.bmlp_unpack_coo.argtypes = [vp, vp, i64, i64, i64, vp, vp, i64, P(ctypes.c_int64), vp]
     for f in (L.bmlp_or, L.bmlp_and, L.bmlp_andnot):
@@ -165,7 +169,7 @@ def lib():
     for name in EXPORTS:
         f = getattr(L, name)
         if name in ("bmlp_graph_has_closure", "bmlp_dispatcher_loaded", "bmlp_tune_candidates", "bmlp_tune_buckets",
-                    "bmlp_tune_bucket_of"):
+                    "bmlp_tune_bucket_of", "bmlp_graph_last_arm"):
             f.restype = ctypes.c_int32
         elif name not in ("bmlp_last_error", "bmlp_opts_init", "bmlp_version"):
             f.restype = ctypes.c_int
@@ -259,6 +263,17 @@ class Context:
         _check(lib().bmlp_pack_coo(self._h, _ptr(row), _ptr(col), row.numel(), rows, n, _ptr(out),
                                    out.shape[1], _stream(stream)))
         return out
+
+    def pack_coo_async(self, row, col, rows: int, n: int, out, stream=None):
+        """bmlp_pack_coo_async: no synchronisation; row/col must be int32 device tensors, out a bit matrix.
+        Out-of-range facts are skipped and reported by deferred_error()."""
+        _bits_shape(out, rows)
+        _check(lib().bmlp_pack_coo_async(self._h, _ptr(row), _ptr(col), row.numel(), rows, n, _ptr(out),
+                                         out.shape[1], _stream(stream)))
+        return out
+
+    def deferred_error(self, stream=None):
+        _check(lib().bmlp_deferred_error(self._h, _stream(stream)))
 
     def pack_u8(self, dense, ld: int | None = None, out=None, stream=None):
         rows, n = dense.shape
@@ -570,6 +585,10 @@ class Session:
     @property
     def has_closure(self) -> bool:
         return bool(lib().bmlp_graph_has_closure(self._g))
+
+    @property
+    def last_arm(self) -> int:
+        return int(lib().bmlp_graph_last_arm(self._g))
 
     def close(self):
         if getattr(self, "_g", None):

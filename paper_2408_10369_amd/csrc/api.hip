@@ -125,6 +125,7 @@ enum FlagSlot {
   F_QUEUE = 46,    // 64-bit piece counter of the gathers' overflow queue
   F_ROUNDS_OUT = 48,  // host side only: a one-launch selection's round count, read at the end of the call
   F_TOT0 = 50,        // host side only: the first running bit count of an RMS chain, uploaded from here
+  F_DEFER = 54,       // an out-of-range fact given to bmlp_pack_coo_async (latched until bmlp_deferred_error)
   F_CHAIN = 128,      // BMLP-RMS: one record of kRmsRecWords words per squaring (rms_core)
   F_WORDS = 512
 };
@@ -1495,6 +1496,34 @@ bmlp_status bmlp_pack_coo(bmlp_handle h, const int32_t* row, const int32_t* col,
   });
 }
 
+bmlp_status bmlp_pack_coo_async(bmlp_handle h, const int32_t* row, const int32_t* col, int64_t m, int64_t rows,
+                                int64_t n, uint64_t* bits, int64_t ld, void* stream) {
+  return guarded([&] {
+    need_handle(h);
+    check_bits_arg(bits, "bits", rows, n, ld);
+    need(m >= 0, BMLP_EINVAL, "m < 0");
+    if (m > 0) {
+      need(row && col, BMLP_EINVAL, "row/col: null pointer");
+      need(((uintptr_t)row & 3u) == 0 && ((uintptr_t)col & 3u) == 0, BMLP_EALIGN, "row/col: not 4-byte aligned");
+    }
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    hip_check(launch_fill_zero(bits, rows * ld, s), "fill_zero");
+    hip_check(launch_pack_coo(row, col, m, rows, n, bits, ld, h->d_flags + F_DEFER, s), "pack_coo");
+  });
+}
+
+bmlp_status bmlp_deferred_error(bmlp_handle h, void* stream) {
+  return guarded([&] {
+    need_handle(h);
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    const u32 bad = read_flag(h, s, F_DEFER);
+    if (bad) hip_check(launch_fill_zero((u64*)(h->d_flags + F_DEFER - (F_DEFER & 1)), 1, s), "fill_zero");
+    need(bad == 0, BMLP_EINVAL, "a fact given to bmlp_pack_coo_async lay outside its matrix (it was skipped)");
+  });
+}
+
 bmlp_status bmlp_unpack_coo(bmlp_handle h, const uint64_t* bits, int64_t rows, int64_t n, int64_t ld,
                             int32_t* row_out, int32_t* col_out, int64_t cap, int64_t* count, void* stream) {
   return guarded([&] {
@@ -2191,6 +2220,7 @@ struct bmlp_graph_s {
   int32_t* cit = nullptr;
   u64* closure = nullptr;   // owned R1+ (n x ceil(n/64)) once computed
   double spent_ms = 0.0;    // device time spent answering queries without the closure
+  int32_t last_arm = -1;    // the arm that served the last query
 };
 
 namespace {
@@ -2552,7 +2582,8 @@ bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t* V, uint64_t* Vstar, i
       if (!use_closure) {
         const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
         const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
-        const double delta0 = (double)count_bits(h, V, k, n, ldv, s);
+        // the source count is a feature of the model's choice (and of the trace) only
+        const double delta0 = ((learned && !forced) || h->trace) ? (double)count_bits(h, V, k, n, ldv, s) : 0.0;
         float pred[4] = {0, 0, 0, 0};
         arm = smp_choose_arm(h, o, g->gi, k, 0, refl, delta0, s, learned ? pred : nullptr);
         if (arm == BMLP_ARM_SMP_CLOSURE) use_closure = true;  // and keep it for later queries
@@ -2577,14 +2608,19 @@ bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t* V, uint64_t* Vstar, i
           }
           g->closure = clo;
         } else {
-          hip_check(hipEventRecord(h->ev1, s), "hipEventRecord");
+          // the learned schedule's ski rental needs the device time of the query: only then does the
+          // query wait for its own end
+          const bool rent = learned && !forced;
+          if (rent) hip_check(hipEventRecord(h->ev1, s), "hipEventRecord");
           if (h->trace) h->trace->call_arm = arm;
           smp_core(h, g->R1, g->ld, n, V, Vstar, k, ldv, refl, arm, g->gi, 0, Csr{g->rp, g->ci, g->rpt, g->cit}, o, s, sr);
-          hip_check(hipEventRecord(h->evp1, s), "hipEventRecord");
-          hip_check(hipEventSynchronize(h->evp1), "hipEventSynchronize");
-          float ms = 0.f;
-          hip_check(hipEventElapsedTime(&ms, h->ev1, h->evp1), "hipEventElapsedTime");
-          g->spent_ms += ms;
+          if (rent) {
+            hip_check(hipEventRecord(h->evp1, s), "hipEventRecord");
+            hip_check(hipEventSynchronize(h->evp1), "hipEventSynchronize");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, h->ev1, h->evp1), "hipEventElapsedTime");
+            g->spent_ms += ms;
+          }
         }
       }
       if (use_closure) {
@@ -2592,9 +2628,12 @@ bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t* V, uint64_t* Vstar, i
         read_off_closure(h, V, ldv, k, g->closure, nw, n, refl, Vstar, o, s, sr);
       }
     }
+    g->last_arm = arm;
     if (stats) stats->arm = arm;
     sr.finish();
   });
 }
+
+int32_t bmlp_graph_last_arm(bmlp_graph g) { return g ? g->last_arm : -1; }
 
 }  // extern "C"
