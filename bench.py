@@ -381,9 +381,10 @@ def wl_programs(ctx, args):
 
 def wl_stream(ctx, args):
     """A stream of selection queries (k log-uniform in [1, 4096]) over one scale-free digraph,
-    n = 65,536, m = 262,144, answered through a session; plain vs learned schedule.  The timed pass packs
-    each query asynchronously and asks for no statistics (the arm that served a query is read on the
-    host); the answers are fingerprinted in a second, untimed pass over the first queries."""
+    n = 65,536, m = 262,144, answered through a session; plain vs learned schedule.  The timed pass gives
+    each query as its k source constants and asks for no statistics (the arm that served a query is read
+    on the host); the answers are fingerprinted in a second, untimed pass over the first queries, given
+    as bit rows through the general query entry point."""
     import torch
 
     import gen
@@ -393,7 +394,7 @@ def wl_stream(ctx, args):
     s, d = gen.scalefree_digraph()
     R = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n)
     queries = gen.query_stream(count=args.stream_queries)
-    qr = [tuple(torch.as_tensor(x).cuda() for x in gen.query_lists(q)) for q in queries]
+    qs = [torch.as_tensor(q).cuda() for q in queries]  # each query: its k source constants (int32)
     V = ctx.zeros(4096, n)
     Vs = ctx.zeros(4096, n)
     W = torch.randint(-2**62, 2**62, (Vs.numel(),), dtype=torch.int64, device="cuda")
@@ -410,15 +411,12 @@ def wl_stream(ctx, args):
         t0 = time.perf_counter()
         closure_at = None
         with ctx.graph(R, n) as g:
-            for qi, (r, c) in enumerate(qr):
-                k = len(queries[qi])
-                Vk, Vsk = V[:k], Vs[:k]
-                ctx.pack_coo_async(r, c, k, n, out=Vk)
-                g.query(Vk, out=Vsk, opts=o)
+            for qi, src in enumerate(qs):
+                g.query_sources(src, Vs[:src.numel()], opts=o)
                 a = g.last_arm
                 arms[a] = arms.get(a, 0) + 1
-                if closure_at is None and g.has_closure:
-                    closure_at = qi
+                if closure_at is None and a == B.ARM_SMP_CLOSURE:
+                    closure_at = qi  # the closure is built by the first query it answers
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
         ctx.deferred_error()
@@ -426,8 +424,9 @@ def wl_stream(ctx, args):
         hs = []
         with ctx.graph(R, n) as g:
             for qi in range(nverify):
-                r, c = qr[qi]
+                # the same queries as bit rows through the general entry point
                 k = len(queries[qi])
+                r, c = (torch.as_tensor(x).cuda() for x in gen.query_lists(queries[qi]))
                 ctx.pack_coo_async(r, c, k, n, out=V[:k])
                 g.query(V[:k], out=Vs[:k], opts=o)
                 hs.append(_hash_dev(Vs[:k], W))

@@ -295,6 +295,14 @@ bmlp_status bmlp_graph_open(bmlp_handle h, const uint64_t *R1, int64_t n, int64_
    is asynchronous on the stream except where the learned schedule times it (before the closure exists). */
 bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t *V, uint64_t *Vstar, int64_t k, int64_t ldv,
                              const bmlp_opts *opts, void *stream, bmlp_stats *stats);
+/* The k one-hot queries r(src[i], Y) (Eq. 5 with a single source each): Vstar row i = e_src[i] x R1+
+   (| e_src[i] when opts->smp_reflexive), like bmlp_graph_query with the query rows given by their
+   sources (DEVICE int32 array).  Once the session holds the closure an answer is one closure row, read
+   by index.  An index outside [0, n) gives an all-zero answer row and is latched for
+   bmlp_deferred_error (no synchronisation).  Without stats the query is asynchronous on the stream
+   except where the learned schedule times it (before the closure exists). */
+bmlp_status bmlp_graph_query_sources(bmlp_graph g, const int32_t *src, uint64_t *Vstar, int64_t k, int64_t ldv,
+                                     const bmlp_opts *opts, void *stream, bmlp_stats *stats);
 /* Whether the session holds the closure (1) or not (0). */
 int32_t bmlp_graph_has_closure(bmlp_graph g);
 /* The arm (bmlp_arm) that served the session's last query, -1 before the first; host-side, no waiting. */

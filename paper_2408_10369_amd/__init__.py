@@ -44,7 +44,7 @@ EXPORTS = [
     "bmlp_dispatcher_train", "bmlp_dispatcher_forward", "bmlp_mlp_loss_grad",
     "bmlp_tune_candidates", "bmlp_tune_buckets", "bmlp_tune_bucket_of", "bmlp_tune_get", "bmlp_tune_set",
     "bmlp_autotune", "bmlp_tune_save", "bmlp_tune_load", "bmlp_smp_noalloc",
-    "bmlp_pack_coo_async", "bmlp_deferred_error", "bmlp_graph_last_arm",
+    "bmlp_pack_coo_async", "bmlp_deferred_error", "bmlp_graph_last_arm", "bmlp_graph_query_sources",
 ]
 TUNE_MAX_CANDIDATES = 8
 TUNE_MFMA_PRODUCT, TUNE_VALU_PRODUCT = 0, 1
@@ -132,6 +132,7 @@ def lib():
     L.bmlp_pack_coo_async.argtypes = [vp, vp, vp, i64, i64, i64, vp, i64, vp]
     L.bmlp_deferred_error.argtypes = [vp, vp]
     L.bmlp_graph_last_arm.argtypes = [vp]
+    L.bmlp_graph_query_sources.argtypes = [vp, vp, vp, i64, i64, P(Opts), vp, P(Stats)]
     L.bmlp_unpack_u8.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
     L.bmlp_unpack_coo.argtypes = [vp, vp, i64, i64, i64, vp, vp, i64, P(ctypes.c_int64), vp]
     for f in (L.bmlp_or, L.bmlp_and, L.bmlp_andnot):
@@ -578,6 +579,19 @@ class Session:
         _check(lib().bmlp_graph_query(self._g, _ptr(V), _ptr(out), k, ldv,
                                       ctypes.byref(opts) if opts is not None else None, _stream(stream),
                                       ctypes.byref(st) if st is not None else None))
+        if st is not None:
+            stats.update(st.as_dict())
+        return out
+
+    def query_sources(self, src, out, opts=None, stream=None, stats=None):
+        """bmlp_graph_query_sources: one-hot queries given by their source indices (int32 device tensor)."""
+        k, ldv = _bits_shape(out)
+        if src.numel() != k:
+            raise ValueError("one source per answer row")
+        st = Stats() if stats is not None else None
+        _check(lib().bmlp_graph_query_sources(self._g, _ptr(src), _ptr(out), k, ldv,
+                                              ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                              ctypes.byref(st) if st is not None else None))
         if st is not None:
             stats.update(st.as_dict())
         return out

@@ -49,7 +49,7 @@ void hip_check(hipError_t e, const char* what) {
 
 struct bmlp_ctx {
   int device = 0;
-  static constexpr int kSlots = 21;
+  static constexpr int kSlots = 22;
   void* slot[kSlots] = {};
   size_t slot_bytes[kSlots] = {};
   u32* d_flags = nullptr;  // device flags / counters
@@ -134,9 +134,10 @@ constexpr int kChainRecords = (F_WORDS - F_CHAIN) / kRmsRecWords;
 // S_RD .. S_RL: the semi-naive squarings of rms_core (delta, its row-list, the column gather and the rows;
 // the transposed route also takes S_RA, S_RX and S_BT for D^T, R^T and the gathered product); S_GQ: the
 // overflow queue of the row gathers; S_RPT, S_CIT: the CSC (in-edges) of the one-launch selection (through
-// R^T in S_BT for a dense relation); S_PERM: a relabelling of the nodes and its inverse (rms_core)
+// R^T in S_BT for a dense relation); S_PERM: a relabelling of the nodes and its inverse (rms_core); S_QV: the
+// query rows of a session query given by its source indices
 enum Slot { S_W0 = 0, S_W1, S_W2, S_W3, S_W4, S_DEG, S_RP, S_CI, S_T0, S_T1, S_T2, S_BT, S_BATCH, S_RD, S_RA, S_RX, S_RL,
-            S_GQ, S_RPT, S_CIT, S_PERM };
+            S_GQ, S_RPT, S_CIT, S_PERM, S_QV };
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -2559,6 +2560,92 @@ bmlp_status bmlp_graph_close(bmlp_graph g) {
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// A session query: V (k query rows), or for one-hot queries their source indices src (then V is null and is
+// formed only if the query is not answered from the closure; an index outside [0, n) gives an all-zero
+// answer row and is latched for bmlp_deferred_error).
+void graph_query_core(bmlp_graph g, const uint64_t* V, const int32_t* src, uint64_t* Vstar, int64_t k, int64_t ldv,
+                      const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
+  bmlp_ctx* h = g->c;
+  const i64 n = g->n;
+  const int refl = o.smp_reflexive ? 1 : 0;
+  int arm = BMLP_ARM_SMP_CLOSURE;
+  if (k > 0 && n == 0) hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
+  if (k > 0 && n > 0) {
+    const i64 nw = words_for(n);
+    bool use_closure = g->closure != nullptr;
+    if (!use_closure) {
+      const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
+      const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
+      // the source count is a feature of the model's choice (and of the trace) only
+      const double delta0 = src ? (double)k
+                                : ((learned && !forced) || h->trace) ? (double)count_bits(h, V, k, n, ldv, s) : 0.0;
+      float pred[4] = {0, 0, 0, 0};
+      arm = smp_choose_arm(h, o, g->gi, k, 0, refl, delta0, s, learned ? pred : nullptr);
+      if (arm == BMLP_ARM_SMP_CLOSURE) use_closure = true;  // and keep it for later queries
+      if (learned && !forced) {
+        // ski rental: build the closure once its predicted cost is below the time already spent on
+        // this relation plus this query's predicted cost without it
+        const double p_iter = std::exp(std::min(pred[0], g->gi.n <= smp_rows_max_n() ? pred[3] : pred[0]));
+        const double p_clo = std::exp(pred[2]);
+        if (p_clo <= g->spent_ms + p_iter) use_closure = true;
+      }
+      if (use_closure) {
+        u64* clo = nullptr;
+        if (hipMalloc((void**)&clo, (size_t)std::max<i64>(n * nw, 1) * sizeof(u64)) != hipSuccess) {
+          (void)hipGetLastError();
+          fail(BMLP_ENOMEM, "closure allocation failed");
+        }
+        try {
+          rms_core(h, g->R1, g->ld, clo, nw, n, o, s, sr);
+        } catch (...) {
+          (void)hipFree(clo);
+          throw;
+        }
+        g->closure = clo;
+      } else {
+        if (!V) {
+          // the query rows of the sources
+          u64* qv = ws_bits(h, S_QV, k, ldv, o);
+          hip_check(launch_fill_zero(qv, k * ldv, s), "fill_zero");
+          hip_check(launch_set_onehot(qv, ldv, src, k, n, h->d_flags + F_DEFER, s), "set_onehot");
+          V = qv;
+        }
+        // the learned schedule's ski rental needs the device time of the query: only then does the
+        // query wait for its own end
+        const bool rent = learned && !forced;
+        if (rent) hip_check(hipEventRecord(h->ev1, s), "hipEventRecord");
+        if (h->trace) h->trace->call_arm = arm;
+        smp_core(h, g->R1, g->ld, n, V, Vstar, k, ldv, refl, arm, g->gi, 0, Csr{g->rp, g->ci, g->rpt, g->cit}, o, s, sr);
+        if (rent) {
+          hip_check(hipEventRecord(h->evp1, s), "hipEventRecord");
+          hip_check(hipEventSynchronize(h->evp1), "hipEventSynchronize");
+          float ms = 0.f;
+          hip_check(hipEventElapsedTime(&ms, h->ev1, h->evp1), "hipEventElapsedTime");
+          g->spent_ms += ms;
+        }
+      }
+    }
+    if (use_closure) {
+      arm = BMLP_ARM_SMP_CLOSURE;
+      if (src)
+        hip_check(launch_rows_by_index(g->closure, nw, src, k, n, refl, Vstar, ldv, h->d_flags + F_DEFER, s),
+                  "rows_by_index");
+      else
+        read_off_closure(h, V, ldv, k, g->closure, nw, n, refl, Vstar, o, s, sr);
+    }
+  }
+  g->last_arm = arm;
+  if (sr.st) sr.st->arm = arm;
+}
+
+}  // namespace
+
+extern "C" {
+
 bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t* V, uint64_t* Vstar, int64_t k, int64_t ldv,
                              const bmlp_opts* opts, void* stream, bmlp_stats* stats) {
   return guarded([&] {
@@ -2573,63 +2660,31 @@ bmlp_status bmlp_graph_query(bmlp_graph g, const uint64_t* V, uint64_t* Vstar, i
     DeviceGuard dg(h->device);
     hipStream_t s = (hipStream_t)stream;
     StatsRec sr(stats, h, s, &o);
-    const int refl = o.smp_reflexive ? 1 : 0;
-    int arm = BMLP_ARM_SMP_CLOSURE;
-    if (k > 0 && n == 0) hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
-    if (k > 0 && n > 0) {
-      const i64 nw = words_for(n);
-      bool use_closure = g->closure != nullptr;
-      if (!use_closure) {
-        const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
-        const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
-        // the source count is a feature of the model's choice (and of the trace) only
-        const double delta0 = ((learned && !forced) || h->trace) ? (double)count_bits(h, V, k, n, ldv, s) : 0.0;
-        float pred[4] = {0, 0, 0, 0};
-        arm = smp_choose_arm(h, o, g->gi, k, 0, refl, delta0, s, learned ? pred : nullptr);
-        if (arm == BMLP_ARM_SMP_CLOSURE) use_closure = true;  // and keep it for later queries
-        if (learned && !forced) {
-          // ski rental: build the closure once its predicted cost is below the time already spent on
-          // this relation plus this query's predicted cost without it
-          const double p_iter = std::exp(std::min(pred[0], g->gi.n <= smp_rows_max_n() ? pred[3] : pred[0]));
-          const double p_clo = std::exp(pred[2]);
-          if (p_clo <= g->spent_ms + p_iter) use_closure = true;
-        }
-        if (use_closure) {
-          u64* clo = nullptr;
-          if (hipMalloc((void**)&clo, (size_t)std::max<i64>(n * nw, 1) * sizeof(u64)) != hipSuccess) {
-            (void)hipGetLastError();
-            fail(BMLP_ENOMEM, "closure allocation failed");
-          }
-          try {
-            rms_core(h, g->R1, g->ld, clo, nw, n, o, s, sr);
-          } catch (...) {
-            (void)hipFree(clo);
-            throw;
-          }
-          g->closure = clo;
-        } else {
-          // the learned schedule's ski rental needs the device time of the query: only then does the
-          // query wait for its own end
-          const bool rent = learned && !forced;
-          if (rent) hip_check(hipEventRecord(h->ev1, s), "hipEventRecord");
-          if (h->trace) h->trace->call_arm = arm;
-          smp_core(h, g->R1, g->ld, n, V, Vstar, k, ldv, refl, arm, g->gi, 0, Csr{g->rp, g->ci, g->rpt, g->cit}, o, s, sr);
-          if (rent) {
-            hip_check(hipEventRecord(h->evp1, s), "hipEventRecord");
-            hip_check(hipEventSynchronize(h->evp1), "hipEventSynchronize");
-            float ms = 0.f;
-            hip_check(hipEventElapsedTime(&ms, h->ev1, h->evp1), "hipEventElapsedTime");
-            g->spent_ms += ms;
-          }
-        }
-      }
-      if (use_closure) {
-        arm = BMLP_ARM_SMP_CLOSURE;
-        read_off_closure(h, V, ldv, k, g->closure, nw, n, refl, Vstar, o, s, sr);
-      }
+    graph_query_core(g, V, nullptr, Vstar, k, ldv, o, s, sr);
+    sr.finish();
+  });
+}
+
+bmlp_status bmlp_graph_query_sources(bmlp_graph g, const int32_t* src, uint64_t* Vstar, int64_t k, int64_t ldv,
+                                     const bmlp_opts* opts, void* stream, bmlp_stats* stats) {
+  return guarded([&] {
+    need(g != nullptr, BMLP_EINVAL, "null session");
+    bmlp_ctx* h = g->c;
+    const bmlp_opts o = opts_or_default(opts);
+    const i64 n = g->n;
+    need(k >= 0, BMLP_EINVAL, "k < 0");
+    if (k > 0) {
+      need(src != nullptr, BMLP_EINVAL, "src: null pointer");
+      need(((uintptr_t)src & 3u) == 0, BMLP_EALIGN, "src: not 4-byte aligned");
     }
-    g->last_arm = arm;
-    if (stats) stats->arm = arm;
+    check_bits_arg(Vstar, "Vstar", k, n, ldv);
+    need(!overlap(range_of(Vstar, k, ldv), range_of(g->R1, n, g->ld)), BMLP_EALIAS, "Vstar overlaps R1");
+    need(!overlap(range_of(Vstar, k, ldv), Range{(uintptr_t)src, (uintptr_t)(src + k)}), BMLP_EALIAS,
+         "Vstar overlaps src");
+    DeviceGuard dg(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    StatsRec sr(stats, h, s, &o);
+    graph_query_core(g, nullptr, src, Vstar, k, ldv, o, s, sr);
     sr.finish();
   });
 }

@@ -41,6 +41,10 @@ hipError_t launch_nonempty_rows(const u64* a, i64 rows, i64 n, i64 ld, int32_t* 
 // dst row i = src row list[i] for i < k (n columns; padding words of dst up to ldd zeroed)
 hipError_t launch_copy_rows(const u64* src, i64 lds, const int32_t* list, i64 k, i64 n, u64* dst, i64 ldd,
                             hipStream_t s);
+// out row i = C row idx[i] (| bit idx[i] when reflexive); padding words up to ldo zeroed; an index outside
+// [0, n) gives a zero row and raises *bad
+hipError_t launch_rows_by_index(const u64* C, i64 ldc, const int32_t* idx, i64 k, i64 n, int reflexive, u64* out,
+                               i64 ldo, u32* bad, hipStream_t s);
 // out[rp[r] .. rp[r+1]) = r for r < rows
 hipError_t launch_rows_from_rp(const i64* rp, i64 rows, int32_t* out, hipStream_t s);
 // out = I | M+ for b <= 64 (M, out: b rows of one significant word)

@@ -181,6 +181,26 @@ __global__ void k_copy_rows(const u64* __restrict__ src, i64 lds, const int32_t*
   }
 }
 
+// One-hot queries answered from a closure: out row i = C row idx[i] (| bit idx[i] when reflexive), padding
+// words up to ldo zeroed; an index outside [0, n) gives a zero row and raises *bad.  One wave per row.
+__global__ void k_rows_by_index(const u64* __restrict__ C, i64 ldc, const int32_t* __restrict__ idx, i64 k, i64 n,
+                                int reflexive, u64* __restrict__ out, i64 ldo, u32* __restrict__ bad) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  const i64 nw = (n + 63) >> 6;
+  for (i64 i = wave; i < k; i += nwaves) {
+    const i64 j = idx[i];
+    const bool ok = j >= 0 && j < n;
+    if (!ok && lane == 0 && bad) atomicOr(bad, 1u);
+    for (i64 w = lane; w < ldo; w += 64) {
+      u64 v = (ok && w < nw) ? C[j * ldc + w] : 0ull;
+      if (ok && reflexive && w == (j >> 6)) v |= 1ull << (j & 63);
+      out[i * ldo + w] = v;
+    }
+  }
+}
+
 // raises *bad when an index lies outside [0, n)
 __global__ void k_check_index(const int32_t* __restrict__ idx, i64 k, i64 n, u32* __restrict__ bad) {
   for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < k; i += (i64)gridDim.x * blockDim.x) {
@@ -705,6 +725,14 @@ hipError_t launch_set_diag(u64* a, i64 ld, i64 rows, i64 n, hipStream_t s) {
 hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, i64 n, u32* bad, hipStream_t s) {
   if (k <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_set_onehot, dim3(grid_for(k)), dim3(kBlock), 0, s, a, ld, idx, k, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_by_index(const u64* C, i64 ldc, const int32_t* idx, i64 k, i64 n, int reflexive, u64* out,
+                               i64 ldo, u32* bad, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_by_index, dim3(grid_for(k * 64, kBlock, 16384)), dim3(kBlock), 0, s, C, ldc, idx, k, n,
+                     reflexive, out, ldo, bad);
   return hipGetLastError();
 }
 

@@ -76,3 +76,36 @@ def test_session_without_stats(ctx, mode):
             want = oracle.smp(n, s, d, host(V[:k]))
             assert np.array_equal(host(Vs[:k]), want), (mode, q, k, arm)
     ctx.deferred_error()
+
+
+@pytest.mark.parametrize("mode", ["plain", "learned", "forced_closure"])
+@pytest.mark.parametrize("refl", [0, 1])
+def test_session_query_by_sources(ctx, mode, refl):
+    """One-hot queries given by their source indices equal the same queries given as bit rows; an index out
+    of range gives a zero row and is reported by bmlp_deferred_error."""
+    n = 9000
+    s, d = gen.er_digraph(n, 2.5 / n, 9000)
+    R = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n)
+    base = {"plain": dict(dispatch=B.DISPATCH_PLAIN), "learned": dict(dispatch=B.DISPATCH_LEARNED),
+            "forced_closure": dict(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE)}[mode]
+    opts = B.make_opts(smp_reflexive=refl, **base)
+    rng = np.random.default_rng(9 + refl)
+    out = ctx.zeros(700, n)
+    with ctx.graph(R, n) as g:
+        for q in range(10):
+            k = int(rng.integers(1, 700))
+            srcs = rng.choice(n, k, replace=False).astype(np.int32)
+            out.fill_(-1)
+            g.query_sources(torch.as_tensor(srcs).cuda(), out[:k], opts=opts)
+            V = np.zeros((k, n), np.uint8)
+            V[np.arange(k), srcs] = 1
+            from oracle import boolops
+            want = oracle.smp(n, s, d, boolops.to_bits(V), reflexive=bool(refl))
+            assert np.array_equal(host(out[:k]), want), (mode, refl, q, k, g.last_arm)
+        ctx.deferred_error()
+        bad = np.array([3, n, 5], np.int32)
+        g.query_sources(torch.as_tensor(bad).cuda(), out[:3], opts=opts)
+        got = host(out[:3])
+        assert not got[1].any()
+        with pytest.raises(B.BmlpError):
+            ctx.deferred_error()
