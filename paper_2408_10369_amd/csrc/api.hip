@@ -20,6 +20,7 @@
 #include "bmlp_mlp.h"
 #include "bmlp_internal.h"
 #include "rms_cost.h"
+#include "features.h"
 
 using namespace bmlp;
 
@@ -811,34 +812,11 @@ int smp_plain_arm(i64 n, i64 k, i64 m) {
 
 // ------------------------------------------------------------ dispatcher features
 
-// The 16 dispatcher features (all O(1) to compute from counters the drivers keep):
-//  0 log2(1+n)/16            1 log2(1+m)/24             2 log2(1+m/n)/8 (mean degree)
-//  3 log2(1+maxdeg/(1+m/n))/8 (degree skew)             4 nonempty rows / n
-//  5 log2(1+k)/16            6 min(k/n, 4)              7 composition request (0/1)
-//  8 call-level query (1) or round-level query (0)       9 round / 64
-// 10 |delta| / (k n)         11 |visited| / (k n)        12 log2(1+|delta|)/32
-// 13 min(|delta| / |previous delta|, 16) / 16            14 log2(1 + |delta| m/n)/40 (edges to visit)
-// 15 reflexive answer (0/1)
+// The 16 dispatcher features (features.h), all O(1) from counters the drivers keep
 void make_features(float* f, const GraphInfo& g, i64 k, int compose, int call_level, int round, double delta,
                    double prev_delta, double vis, int reflexive) {
-  const double n = (double)std::max<i64>(g.n, 1), m = (double)g.m, kk = (double)std::max<i64>(k, 1);
-  const double deg = m / n;
-  f[0] = (float)(std::log2(1.0 + n) / 16.0);
-  f[1] = (float)(std::log2(1.0 + m) / 24.0);
-  f[2] = (float)(std::log2(1.0 + deg) / 8.0);
-  f[3] = (float)(std::log2(1.0 + (double)g.maxdeg / (1.0 + deg)) / 8.0);
-  f[4] = (float)((double)g.nonempty / n);
-  f[5] = (float)(std::log2(1.0 + (double)k) / 16.0);
-  f[6] = (float)std::min(4.0, (double)k / n);
-  f[7] = compose ? 1.f : 0.f;
-  f[8] = call_level ? 1.f : 0.f;
-  f[9] = (float)(round / 64.0);
-  f[10] = (float)(delta / (kk * n));
-  f[11] = (float)(vis / (kk * n));
-  f[12] = (float)(std::log2(1.0 + delta) / 32.0);
-  f[13] = (float)(std::min(16.0, delta / std::max(prev_delta, 1.0)) / 16.0);
-  f[14] = (float)(std::log2(1.0 + delta * deg) / 40.0);
-  f[15] = reflexive ? 1.f : 0.f;
+  bmlp::make_features(f, (double)g.n, (double)g.m, (double)g.maxdeg, (double)g.nonempty, (double)k,
+                      compose ? 1.f : 0.f, call_level, round, delta, prev_delta, vis, reflexive);
 }
 
 struct Csr {
@@ -2079,15 +2057,18 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return graphs[a].n > graphs[b].n; });
-    BatchPlan plan{0, 0, 0, 0, 0, false, 0, 0, 0};
+    BatchPlan plan{0, 0, 0, 0, 0, 0, 0, 0, 0};
     // Query answers: the plain schedule takes the paper's mapping of a partially grounded query to
-    // BMLP-SMP (a selection per query row); otherwise the rows are read off the closures the batch
-    // computes anyway (reuse of intermediate results).  Graphs beyond the selection kernel's size
-    // always read the closure.
+    // BMLP-SMP (a selection per query row); forced, all by selection or all off the closures; learned,
+    // per graph as the dispatcher model chooses on the device (answers off the closure -- which is
+    // computed anyway when it is an output -- or by selection; a graph whose closure is neither an
+    // output nor read is not squared at all).  Graphs beyond the selection kernel's size always read
+    // the closure.
     const bool forced_sel = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
-    plan.select_by_bfs = forced_sel ? o.smp_arm != BMLP_ARM_SMP_CLOSURE : o.dispatch == BMLP_DISPATCH_PLAIN;
+    const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
+    plan.qmode = forced_sel ? (o.smp_arm == BMLP_ARM_SMP_CLOSURE ? 0 : 1) : learned ? 2 : 1;
     size_t buf_words = 0;
-    BatchPlan sizes{0, 0, 0, 0, 0, false, 0, 0, 0};  // the totals the flag area depends on
+    BatchPlan sizes{0, 0, 0, 0, 0, 0, 0, 0, 0};  // the totals the flag area depends on
     for (int i = 0; i < count; ++i) {
       const bmlp_graph_desc& d = graphs[i];
       plan.rounds = std::max(plan.rounds, ceil_log2(std::max<int64_t>(d.n, 2)) + 2);
@@ -2112,6 +2093,7 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       BatchGraph& G = tab[j];
       G.n = d.n;
       G.nw = words_for(d.n);
+      G.closure_req = d.closure ? 1 : 0;
       G.R1 = d.R1;
       G.ld = d.ld;
       G.closure = d.closure;
@@ -2154,7 +2136,7 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
     };
     mix(graphs, sizeof(bmlp_graph_desc) * (size_t)count);
     mix(&base, sizeof base);
-    mix(&plan.select_by_bfs, sizeof plan.select_by_bfs);
+    mix(&plan.qmode, sizeof plan.qmode);
     if (!h->bexec || key != h->bkey) {
       if (h->bexec) {
         hip_check(hipGraphExecDestroy(h->bexec), "hipGraphExecDestroy");
@@ -2170,7 +2152,8 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       if (!h->capture_stream)
         hip_check(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
       hip_check(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-      const hipError_t le = launch_batch_chain(d_table, count, plan, d_flags, h->capture_stream);
+      const hipError_t le =
+          launch_batch_chain(d_table, count, plan, d_flags, learned ? h->d_model : nullptr, h->capture_stream);
       hipGraph_t graph = nullptr;
       const hipError_t ce = hipStreamEndCapture(h->capture_stream, &graph);
       hip_check(le, "batch chain");
@@ -2186,21 +2169,28 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       std::vector<u32> fl(nflags);
       hip_check(hipMemcpyAsync(fl.data(), d_flags, nflags * sizeof(u32), hipMemcpyDeviceToHost, s), "memcpy");
       hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-      int max_rounds = 0;
+      int max_rounds = 0, by_closure = 0, by_selection = 0;
+      const u32* qsel = fl.data() + batch_qsel_offset(count, plan);
+      const u32* needc = qsel + count;
       for (int j = 0; j < count; ++j) {
+        const uint64_t nn = (uint64_t)tab[j].n;
+        const bool sel = qsel[j] != 0;
+        if (tab[j].k > 0) ++(sel ? by_selection : by_closure);
+        if (!needc[j]) continue;  // not squared
         int r = 0;
         while (r < plan.rounds && fl[(size_t)j * plan.rounds + r]) ++r;
         need(r < plan.rounds, BMLP_EITER, "batched RMS exceeded %d rounds (graph of n=%lld)", plan.rounds,
              (long long)tab[j].n);
         const int prods = r + 1;  // the rounds that changed plus the one that found the fixpoint
         max_rounds = std::max(max_rounds, prods);
-        const uint64_t nn = (uint64_t)tab[j].n;
-        const bool gathered = tab[j].k > 0 && !(plan.select_by_bfs && tab[j].n <= batch_bfs_max_n());
+        const bool gathered = tab[j].k > 0 && !sel;
         stats->products += prods + (gathered ? 1 : 0);
         stats->bool_ops += (uint64_t)prods * 2u * nn * nn * nn + (gathered ? 2u * (uint64_t)tab[j].k * nn * nn : 0u);
       }
       stats->iterations = max_rounds;
-      stats->arm = plan.select_by_bfs ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_CLOSURE;
+      stats->arm = by_selection == 0 ? BMLP_ARM_SMP_CLOSURE : by_closure == 0 ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_AUTO;
+      stats->arm_trace[0] = by_closure;  // graphs (with queries) answered off their closure
+      stats->arm_trace[1] = by_selection;  // graphs answered by per-row selection
       stats->product_bool_ops = stats->bool_ops;
       stats->product_ms = stats->device_ms;
     }

@@ -6,6 +6,7 @@ namespace bmlp {
 
 struct BatchGraph {
   i64 n, nw;             // nodes, data words per row
+  i64 closure_req;       // the caller asked for the closure (it is an output)
   const u64* R1; i64 ld; // input relation
   u64* closure; i64 ldc; // output R1+ (may be null)
   const u64* V; i64 k; i64 ldv;  // query rows (k may be 0)
@@ -29,7 +30,9 @@ struct BatchPlan {
   int rounds;            // kernels in the chain = largest round cap of the batch
   i64 total_rows, total_tiles, total_select_tiles;
   i64 total_qrows;       // query rows of all graphs
-  bool select_by_bfs;    // answer queries by selection (BMLP-SMP) instead of reading the closure
+  int qmode;             // how query rows are answered: 0 off the closures; 1 by per-row selection (BMLP-SMP)
+                         // where the selection kernel takes the graph (the paper's mapping); 2 per graph
+                         // as the dispatcher model chooses on the device (qsel below)
   i64 total_mfma_tiles;  // matrix-core tiles per round, over all graphs
   i64 total_tblocks;     // transpose blocks per round, over all graphs
   i64 total_mblocks;     // 256-row blocks of the matrix-core graphs
@@ -46,8 +49,13 @@ i64 batch_rtiles(i64 n);
 i64 batch_select_tiles(i64 k, i64 n);
 // words of the flag area of a batch (zeroed by the chain's setup kernel)
 i64 batch_flag_words(int count, const BatchPlan& p);
-// records the kernel chain on stream s (setup, rounds, select, copy); flags must hold
-// batch_flag_words(count, p) words
-hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& p, u32* flags, hipStream_t s);
+// records the kernel chain on stream s (setup, the per-graph modes, rounds, select, copy); flags must hold
+// batch_flag_words(count, p) words.  model: the dispatcher's parameters | mu | sd on the device (qmode 2).
+// Per graph the flag area ends with: qsel (1 = its query rows are answered by per-row selection), need
+// (1 = its closure is computed), and for qmode 2 its statistics, features and the model's outputs.
+hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& p, u32* flags, const float* model,
+                              hipStream_t s);
+// offsets (words) of the per-graph areas in the flag area
+i64 batch_qsel_offset(int count, const BatchPlan& p);
 
 }  // namespace bmlp

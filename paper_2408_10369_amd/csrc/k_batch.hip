@@ -19,6 +19,8 @@
 #include "bmlp_batch.h"
 #include "valu_tile.h"
 #include "mfma_tile.h"
+#include "features.h"
+#include "bmlp_mlp.h"
 
 namespace bmlp {
 
@@ -81,6 +83,82 @@ __global__ void k_batch_setup(BatchGraph* __restrict__ gs, int count, i64 total_
   }
 }
 
+// Per graph: whether its query rows are answered by per-row selection (qsel) and whether its closure is
+// computed (need), for the fixed modes; qmode 2 starts from the plain choice and k_batch_choose decides.
+__global__ void k_batch_modes(const BatchGraph* __restrict__ gs, int count, int qmode, i64 bfs_words,
+                              u32* __restrict__ qsel, u32* __restrict__ need) {
+  const i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  const BatchGraph& G = gs[g];
+  const u32 sel = (qmode != 0 && G.k > 0 && G.nw <= bfs_words) ? 1u : 0u;
+  qsel[g] = sel;
+  need[g] = (G.closure_req || (G.k > 0 && !sel)) ? 1u : 0u;
+}
+
+// Statistics of each graph for the dispatcher's features: set bits of R1, its largest row count, its
+// nonempty rows, and the set bits of its query rows.  One wave per (graph, row) of the batch-wide row
+// numbering; gst holds 4 u64 per graph (zeroed by the setup kernel).
+__global__ void k_batch_stats(const BatchGraph* __restrict__ gs, int count, i64 total_rows,
+                              unsigned long long* __restrict__ gst) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 rr = wave; rr < total_rows; rr += nwaves) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (gs[mid].row_begin <= rr) lo = mid; else hi = mid - 1;
+    }
+    const BatchGraph& G = gs[lo];
+    const i64 row = rr - G.row_begin;
+    u32 pr = 0, pv = 0;
+    for (i64 w = lane; w < G.nw; w += 64) {
+      const u64 lm = (w == G.nw - 1 && (G.n & 63)) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
+      if (row < G.n) pr += (u32)__popcll(G.R1[row * G.ld + w] & lm);
+      if (row < G.k) pv += (u32)__popcll(G.V[row * G.ldv + w] & lm);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      pr += __shfl_xor(pr, off, 64);
+      pv += __shfl_xor(pv, off, 64);
+    }
+    if (lane == 0) {
+      unsigned long long* s = gst + 4 * (i64)lo;
+      if (pr) {
+        atomicAdd(&s[0], (unsigned long long)pr);
+        atomicMax(&s[1], (unsigned long long)pr);
+        atomicAdd(&s[2], 1ull);
+      }
+      if (pv) atomicAdd(&s[3], (unsigned long long)pv);
+    }
+  }
+}
+
+// The call-level features of each graph's queries (as the library computes them for a selection call),
+// with feature 7 = 0.5 where the closure is computed anyway (an output of the batch), 0 where it is not.
+__global__ void k_batch_features(const BatchGraph* __restrict__ gs, int count, const unsigned long long* __restrict__ gst,
+                                 float* __restrict__ X) {
+  const i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  const BatchGraph& G = gs[g];
+  const unsigned long long* s = gst + 4 * g;
+  make_features(X + kIn * g, (double)G.n, (double)s[0], (double)s[1], (double)s[2], (double)G.k,
+                G.closure_req ? 0.5f : 0.f, 1, 0, (double)s[3], (double)s[3], 0.0, 0);
+}
+
+// The model's choice per graph between reading its answers off the closure (output 2) and per-row
+// selection (output 3, the one-launch selection's prediction), where the selection kernel takes the graph.
+__global__ void k_batch_choose(const BatchGraph* __restrict__ gs, int count, i64 bfs_words, const float* __restrict__ Y,
+                               u32* __restrict__ qsel, u32* __restrict__ need) {
+  const i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  const BatchGraph& G = gs[g];
+  const bool can_select = G.k > 0 && G.nw <= bfs_words;
+  const u32 sel = (can_select && Y[kOut * g + 3] < Y[kOut * g + 2]) ? 1u : 0u;  // ties keep the closure
+  qsel[g] = sel;
+  need[g] = (G.closure_req || (G.k > 0 && !sel)) ? 1u : 0u;
+}
+
 // Rows row0 .. row0 + kRPW - 1 of R | R.R by row gathers (row i = R[i] | OR of the rows k over the
 // set bits k of R[i]), one wave, lane l owning word l (nw <= 64).  The set bits of a row are walked in
 // batches of eight (across its words), so that eight row loads are in flight at a time.
@@ -139,14 +217,14 @@ __device__ __forceinline__ int gather_square_rows(const u64* __restrict__ cur, u
 __global__ void __launch_bounds__(256)
 k_batch_decide(const BatchGraph* __restrict__ gs, int count, i64 total_blocks, int round, int rounds,
                const u32* __restrict__ changed, const u32* __restrict__ any_active, u32* __restrict__ bdense,
-               u32* __restrict__ gdense) {
+               u32* __restrict__ gdense, const u32* __restrict__ need) {
   __shared__ u32 bits_w[4];
   if (round > 0 && any_active[round - 1] == 0u) return;  // every graph has converged
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   for (i64 b = blockIdx.x; b < total_blocks; b += gridDim.x) {
     const int g = find_item(gs, count, b, 4);
-    if (round > 0 && !changed[(i64)g * rounds + round - 1]) continue;
+    if (!need[g] || (round > 0 && !changed[(i64)g * rounds + round - 1])) continue;
     const BatchGraph& G = gs[g];
     const i64 blk = b - G.mblock_begin;
     const u64* cur = (round & 1) ? G.buf1 : G.buf0;
@@ -172,7 +250,7 @@ k_batch_decide(const BatchGraph* __restrict__ gs, int count, i64 total_blocks, i
 __global__ void __launch_bounds__(256)
 k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int round, int rounds,
               u32* __restrict__ changed, u32* __restrict__ counters, u32* __restrict__ any_active,
-              const u32* __restrict__ bdense) {
+              const u32* __restrict__ bdense, const u32* __restrict__ need) {
   __shared__ u64 Bs[64][kTileWords];
   __shared__ i64 item;
   __shared__ u32 tile_bits[4];
@@ -186,7 +264,7 @@ k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int
     __syncthreads();
     if (t >= total_tiles) break;
     const int g = find_graph(gs, count, t, false);
-    if (round > 0 && !changed[(i64)g * rounds + round - 1]) continue;
+    if (!need[g] || (round > 0 && !changed[(i64)g * rounds + round - 1])) continue;
     const BatchGraph& G = gs[g];
     const i64 local = t - G.tile_begin;
     const u64* cur = (round & 1) ? G.buf1 : G.buf0;
@@ -246,14 +324,14 @@ k_batch_round(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int
 __global__ void __launch_bounds__(256)
 k_batch_transpose(const BatchGraph* __restrict__ gs, int count, i64 total_blocks, int round, int rounds,
                   const u32* __restrict__ changed, const u32* __restrict__ any_active,
-                  const u32* __restrict__ gdense) {
+                  const u32* __restrict__ gdense, const u32* __restrict__ need) {
   if (round > 0 && any_active[round - 1] == 0u) return;  // every graph has converged
   const int lane = threadIdx.x & 63;
   const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
   const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
   for (i64 bi = wave; bi < total_blocks; bi += nwaves) {
     const int g = find_item(gs, count, bi, 3);
-    if (round > 0 && !changed[(i64)g * rounds + round - 1]) continue;
+    if (!need[g] || (round > 0 && !changed[(i64)g * rounds + round - 1])) continue;
     if (!gdense[(i64)g * rounds + round]) continue;  // every block of the graph is squared by gathers
     const BatchGraph& G = gs[g];
     const i64 local = bi - G.tblock_begin;
@@ -277,12 +355,12 @@ k_batch_transpose(const BatchGraph* __restrict__ gs, int count, i64 total_blocks
 // to the row gathers of k_batch_round.
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_batch_round_mfma(const BatchGraph* __restrict__ gs, int count, int round, int rounds, u32* __restrict__ changed,
-                   u32* __restrict__ any_active, const u32* __restrict__ bdense) {
+                   u32* __restrict__ any_active, const u32* __restrict__ bdense, const u32* __restrict__ need) {
   __shared__ MfmaLds L;
   if (round > 0 && any_active[round - 1] == 0u) return;  // every graph has converged
   const i64 t = blockIdx.x;  // one workgroup per tile; tiles are numbered biggest graphs first
   const int g = find_item(gs, count, t, 2);
-  if (round > 0 && !changed[(i64)g * rounds + round - 1]) return;
+  if (!need[g] || (round > 0 && !changed[(i64)g * rounds + round - 1])) return;
   const BatchGraph& G = gs[g];
   const i64 local = t - G.mfma_tile_begin;
   const i64 tr = local / G.mfma_rtiles, tc = local - tr * G.mfma_rtiles;
@@ -296,7 +374,7 @@ k_batch_round_mfma(const BatchGraph* __restrict__ gs, int count, int round, int 
 
 __global__ void __launch_bounds__(256)
 k_batch_select(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, int rounds,
-               const u32* __restrict__ changed, u32* __restrict__ counter, i64 skip_nw_upto) {
+               const u32* __restrict__ changed, u32* __restrict__ counter, const u32* __restrict__ qsel) {
   __shared__ u64 Bs[64][kTileWords];
   __shared__ i64 item;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -308,7 +386,7 @@ k_batch_select(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, in
     if (t >= total_tiles) break;
     const int g = find_graph(gs, count, t, true);
     const BatchGraph& G = gs[g];
-    if (G.nw <= skip_nw_upto) continue;  // answered by the selection kernel
+    if (qsel[g]) continue;  // answered by the selection kernel
     const int fr = final_round(changed, g, rounds);
     const u64* clo = ((fr + 1) & 1) ? G.buf1 : G.buf0;  // buffer written by the last round
     const i64 local = t - G.smp_tile_begin;
@@ -333,7 +411,8 @@ constexpr int kBfsWords = 256;  // n <= 16,384
 constexpr int kBfsPer = kBfsWords / 64;
 
 __global__ void __launch_bounds__(256)
-k_batch_select_bfs(const BatchGraph* __restrict__ gs, int count, i64 total_qrows, u32* __restrict__ counter) {
+k_batch_select_bfs(const BatchGraph* __restrict__ gs, int count, i64 total_qrows, u32* __restrict__ counter,
+                   const u32* __restrict__ qsel) {
   __shared__ i64 item[4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (;;) {
@@ -349,7 +428,7 @@ k_batch_select_bfs(const BatchGraph* __restrict__ gs, int count, i64 total_qrows
     }
     const BatchGraph& G = gs[lo];
     const i64 row = it - G.qrow_begin;
-    if (row >= G.k || G.nw > kBfsWords) continue;  // larger graphs read their answers off the closure
+    if (row >= G.k || G.nw > kBfsWords || !qsel[lo]) continue;  // answered off the closure
     const u64 lm = (G.n & 63) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
     u64 fr[kBfsPer], vis[kBfsPer], nxt[kBfsPer];
 #pragma unroll
@@ -441,8 +520,14 @@ i64 batch_bfs_max_n() { return (i64)kBfsWords * 64; }
 
 i64 batch_mfma_min_n() { return 1024; }
 
+i64 batch_qsel_offset(int count, const BatchPlan& p) {
+  const i64 w = 2 * (i64)count * p.rounds + 2 * (i64)p.rounds + 2 + p.total_mblocks;
+  return (w + 1) & ~(i64)1;  // 8-byte aligned for the statistics that follow
+}
+
+// per graph after qsel: need (1), statistics (4 u64), features (16 float), model outputs (4 float)
 i64 batch_flag_words(int count, const BatchPlan& p) {
-  return 2 * (i64)count * p.rounds + 2 * (i64)p.rounds + 2 + p.total_mblocks;
+  return batch_qsel_offset(count, p) + (i64)count * (1 + 1 + 8 + kIn + kOut) + 2;
 }
 
 i64 batch_select_tiles(i64 k, i64 n) {
@@ -450,56 +535,84 @@ i64 batch_select_tiles(i64 k, i64 n) {
   return ((k + kTileRows - 1) / kTileRows) * ((nw + kTileWords - 1) / kTileWords);
 }
 
-hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& p, u32* flags, hipStream_t s) {
+hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& p, u32* flags, const float* model,
+                              hipStream_t s) {
   // flags layout: changed[count * rounds] | any_active[rounds] | counters[rounds + 2] |
-  //               gdense[count * rounds] | bdense[total_mblocks]
+  //               gdense[count * rounds] | bdense[total_mblocks] | (aligned) qsel[count] | need[count] |
+  //               (aligned) stats[count][4 u64] | X[count][16] | Y[count][4]
   u32* changed = flags;
   u32* any_active = flags + (i64)count * p.rounds;
   u32* counters = any_active + p.rounds;
   u32* gdense = counters + p.rounds + 2;
   u32* bdense = gdense + (i64)count * p.rounds;
+  u32* qsel = flags + batch_qsel_offset(count, p);
+  u32* need = qsel + count;
+  unsigned long long* gst = (unsigned long long*)(flags + ((batch_qsel_offset(count, p) + 2 * (i64)count + 1) & ~(i64)1));
+  float* X = (float*)(gst + 4 * (i64)count);
+  float* Y = X + (i64)kIn * count;
   const i64 nflags = batch_flag_words(count, p);
   hipLaunchKernelGGL(k_batch_setup, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
                      count, p.total_rows, flags, nflags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const unsigned ggrid = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(k_batch_modes, dim3(ggrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count, p.qmode,
+                     (i64)kBfsWords, qsel, need);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (p.qmode == 2 && model) {
+    // the dispatcher's choice per graph, on the device: statistics, features, the network, the argmin
+    hipLaunchKernelGGL(k_batch_stats, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s,
+                       (const BatchGraph*)d_graphs, count, p.total_rows, gst);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_features, dim3(ggrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count,
+                       (const unsigned long long*)gst, X);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_mlp_forward(model, model + kParams, model + kParams + kIn, X, count, nullptr, nullptr, Y, s)) !=
+        hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_batch_choose, dim3(ggrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count,
+                       (i64)kBfsWords, (const float*)Y, qsel, need);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int pgrid = grid_cap(p.total_tiles, 1024);
   for (int r = 0; r < p.rounds; ++r) {
     if (p.total_mblocks > 0) {
       hipLaunchKernelGGL(k_batch_decide, dim3(grid_cap(p.total_mblocks, 4096)), dim3(256), 0, s,
                          (const BatchGraph*)d_graphs, count, p.total_mblocks, r, p.rounds, (const u32*)changed,
-                         (const u32*)any_active, bdense, gdense);
+                         (const u32*)any_active, bdense, gdense, (const u32*)need);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     if (p.total_tiles > 0) {
       hipLaunchKernelGGL(k_batch_round, dim3(pgrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count,
-                         p.total_tiles, r, p.rounds, changed, counters, any_active, (const u32*)bdense);
+                         p.total_tiles, r, p.rounds, changed, counters, any_active, (const u32*)bdense,
+                         (const u32*)need);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     if (p.total_mfma_tiles > 0) {
       hipLaunchKernelGGL(k_batch_transpose, dim3(grid_cap((p.total_tblocks * 64 + 255) / 256, 8192)), dim3(256), 0, s,
                          (const BatchGraph*)d_graphs, count, p.total_tblocks, r, p.rounds, (const u32*)changed,
-                         (const u32*)any_active, (const u32*)gdense);
+                         (const u32*)any_active, (const u32*)gdense, (const u32*)need);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k_batch_round_mfma, dim3((unsigned)p.total_mfma_tiles), dim3(512), 0, s,
-                         (const BatchGraph*)d_graphs, count, r, p.rounds, changed, any_active, (const u32*)bdense);
+                         (const BatchGraph*)d_graphs, count, r, p.rounds, changed, any_active, (const u32*)bdense,
+                         (const u32*)need);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
   }
-  if (p.select_by_bfs && p.total_qrows > 0) {
+  if (p.qmode != 0 && p.total_qrows > 0) {
     hipLaunchKernelGGL(k_batch_select_bfs, dim3(grid_cap((p.total_qrows + 3) / 4, 2048)), dim3(256), 0, s,
-                       (const BatchGraph*)d_graphs, count, p.total_qrows, counters + p.rounds + 1);
+                       (const BatchGraph*)d_graphs, count, p.total_qrows, counters + p.rounds + 1, (const u32*)qsel);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (p.total_select_tiles > 0) {
     hipLaunchKernelGGL(k_batch_select, dim3(grid_cap(p.total_select_tiles, 1024)), dim3(256), 0, s,
                        (const BatchGraph*)d_graphs, count, p.total_select_tiles, p.rounds, (const u32*)changed,
-                       counters + p.rounds, p.select_by_bfs ? (i64)kBfsWords : (i64)0);
+                       counters + p.rounds, (const u32*)qsel);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

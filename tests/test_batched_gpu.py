@@ -143,3 +143,32 @@ def test_batched_512_graph_workload(ctx, mode):
     ctx.batched(graphs, opts=mode_opts(mode), stats=st)
     check(graphs, refs)
     assert st["iterations"] <= 14
+
+
+@pytest.mark.parametrize("mode", list(MODES) + ["selection"])
+def test_batched_queries_only(ctx, mode):
+    """Graphs whose closure is not an output: the plain schedule answers every query row by per-row
+    selection (and squares nothing), the forced closure squares every graph, and the learned schedule
+    lets the model choose per graph on the device; every answer is the oracle's."""
+    rng = np.random.default_rng(12)
+    specs = []
+    for n in [1, 64, 65, 300, 700, 1100, 2049, 4096, 40]:
+        A = (rng.random((n, n)) < min(3.0 / n, 1.0)).astype(np.uint8)
+        s, d = np.nonzero(A)
+        k = int(rng.integers(1, min(n, 64) + 1))
+        specs.append((n, s, d, rng.choice(n, k, replace=False)))
+    graphs, refs = make_batch(ctx, specs, with_closure=False)
+    opts = mode_opts(mode) if mode != "selection" else B.make_opts(dispatch=B.DISPATCH_FORCED,
+                                                                   smp_arm=B.ARM_SMP_SPARSE)
+    st = {}
+    ctx.batched(graphs, opts=opts, stats=st)
+    check(graphs, refs)
+    by_closure, by_selection = st["arm_trace"][0], st["arm_trace"][1]
+    assert by_closure + by_selection == len(specs)
+    if mode in ("plain", "selection"):
+        assert by_selection == len(specs) and st["products"] == 0  # nothing squared
+    if mode == "closure":
+        assert by_closure == len(specs)
+    # a second call reuses the captured launch and gives the same answers
+    ctx.batched(graphs, opts=opts)
+    check(graphs, refs)
