@@ -1,7 +1,13 @@
 """What the shipped dispatcher model gains over the plain schedule, on small held-out cases shaped like
 the benchmark's: a query stream on one scale-free relation (the session builds the closure once it pays),
 and linear-recursion programs over the multi-relational graph (seeds the training never saw).  Every
-answer is the oracle's; the learned schedule's device time must not exceed the plain one's."""
+answer is the oracle's.
+
+A stream cannot know how many queries are still to come, so the learned session buys the closure by ski
+rental: once the predicted closure cost is below the selection time already spent.  With exact cost
+predictions that keeps every prefix of the stream within twice the better of the two static schedules
+(always select, closure first); the test allows three times for the model's prediction error, and asks
+that over the whole stream the learned schedule spends no more device time than the plain one."""
 import os
 
 import numpy as np
@@ -34,28 +40,33 @@ def host(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-def test_stream_learned_beats_plain(ctx):
+def test_stream_learned_ski_rental(ctx):
     n = 16384
     s, d = gen.scalefree_digraph(n=n, m=4 * n, seed=55)
     R = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n)
-    queries = gen.query_stream(n=n, count=60, kmax=1024, base_seed=88000)
+    queries = gen.query_stream(n=n, count=240, kmax=1024, base_seed=88000)
     out = ctx.zeros(1024, n)
-    total = {}
-    for mode in (B.DISPATCH_PLAIN, B.DISPATCH_LEARNED):
-        o = B.make_opts(dispatch=mode)
-        ms = 0.0
+    modes = {"plain": B.make_opts(dispatch=B.DISPATCH_PLAIN), "learned": B.make_opts(dispatch=B.DISPATCH_LEARNED),
+             "closure": B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE)}
+    cum = {}
+    for name, o in modes.items():
+        ms, c = 0.0, []
         with ctx.graph(R, n) as g:
             for qi, q in enumerate(queries):
                 st = {}
                 src = torch.as_tensor(q).cuda()
                 g.query_sources(src, out[: len(q)], opts=o, stats=st)
                 ms += st["device_ms"]
-                if qi % 15 == 0:
+                c.append(ms)
+                if qi % 60 == 0:
                     V = np.zeros((len(q), (n + 63) // 64), np.uint64)
                     V[np.arange(len(q)), q // 64] = np.uint64(1) << (q % 64).astype(np.uint64)
-                    assert np.array_equal(host(out[: len(q)]), oracle.smp(n, s, d, V)), (mode, qi)
-        total[mode] = ms
-    assert total[B.DISPATCH_LEARNED] <= total[B.DISPATCH_PLAIN], total
+                    assert np.array_equal(host(out[: len(q)]), oracle.smp(n, s, d, V)), (name, qi)
+        cum[name] = np.array(c)
+    best_static = np.minimum(cum["plain"], cum["closure"])
+    worst = float(np.max(cum["learned"] / best_static))
+    assert worst <= 3.0, (worst, cum["learned"][-1], cum["plain"][-1], cum["closure"][-1])
+    assert cum["learned"][-1] <= cum["plain"][-1], (cum["learned"][-1], cum["plain"][-1])
 
 
 def test_programs_learned_regret_not_worse_than_plain(ctx):
