@@ -420,8 +420,10 @@ def wl_stream(ctx, args):
     res, fp = {}, {}
     modes = _modes(B)
     # the plain schedule answers every query of this stream by the one-launch sparse selection; the other
-    # static policy builds the closure at the first query and reads every answer off it
+    # static policies build the closure at the first query (by BMLP-RMS, or by the selection from every
+    # source) and read every answer off it
     modes["forced_closure"] = B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE)
+    modes["forced_closure_select"] = B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE_SELECT)
     rows_total = sum(len(q) for q in queries)
     nverify = min(len(queries), 500)
     for mode, o in modes.items():
@@ -434,7 +436,7 @@ def wl_stream(ctx, args):
                 g.query_sources(src, Vs[:src.numel()], opts=o)
                 a = g.last_arm
                 arms[a] = arms.get(a, 0) + 1
-                if closure_at is None and a == B.ARM_SMP_CLOSURE:
+                if closure_at is None and a in (B.ARM_SMP_CLOSURE, B.ARM_SMP_CLOSURE_SELECT):
                     closure_at = qi  # the closure is built by the first query it answers
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
@@ -462,9 +464,13 @@ def wl_stream(ctx, args):
     return {"workload": "scale-free digraph n=65536 m=262144, %d queries, k log-uniform [1,4096] "
                         "(%d rows), one session" % (len(queries), rows_total),
             "plain": res["plain"], "learned": res["learned"], "forced_closure": res["forced_closure"],
+            "forced_closure_select": res["forced_closure_select"],
+            "arm_codes": {"3": "one-launch selection", "4": "read off the closure (query 0 of forced_closure: "
+                          "built by BMLP-RMS)", "13": "the closure built by the selection from every source"},
             "speedup_learned_over_plain": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
             "learned_over_best_static_policy": round(
-                res["learned"]["ms"] / min(res["plain"]["ms"], res["forced_closure"]["ms"]), 3),
+                res["learned"]["ms"] / min(res[m]["ms"] for m in ("plain", "forced_closure", "forced_closure_select")),
+                3),
             "bit_identical": all(h == fp["plain"] for h in fp.values()),
             "bit_identical_checked_queries": nverify}
 

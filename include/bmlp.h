@@ -90,9 +90,13 @@ typedef enum {
   BMLP_ARM_PRODUCT_SEMINAIVE = 11, /* (in arm traces) a squaring done from the bits D new in the last one:
                                   R | R.R = R | D.R | R.D (D.R by row gathers, R.D by a product over the
                                   nonempty rows of D) */
-  BMLP_ARM_PRODUCT_SEMINAIVE_T = 12 /* (in arm traces) the same squaring with R.D = (D^T . R^T)^T, a second
+  BMLP_ARM_PRODUCT_SEMINAIVE_T = 12, /* (in arm traces) the same squaring with R.D = (D^T . R^T)^T, a second
                                   row gather over the bits of D between transposes (D's bits spread over
                                   many rows) */
+  BMLP_ARM_SMP_CLOSURE_SELECT = 13 /* selection as V . R1+ with R1+ built by the one-launch selection from
+                                  every source (the rows of I . R1+, Eq. 5 with V = I; n <= 131072):
+                                  the same closure as BMLP-RMS, by frontier expansion instead of squarings.
+                                  Not available in bmlp_batched, whose closures are squared. */
 } bmlp_arm;
 
 typedef enum {
@@ -105,7 +109,8 @@ typedef struct {
   uint32_t size;          /* sizeof(bmlp_opts); set by bmlp_opts_init */
   int32_t dispatch;       /* bmlp_dispatch */
   int32_t product_arm;    /* BMLP_ARM_AUTO, _PRODUCT_VALU or _PRODUCT_MFMA */
-  int32_t smp_arm;        /* BMLP_ARM_AUTO, _SMP_DENSE, _SMP_SPARSE or _SMP_CLOSURE */
+  int32_t smp_arm;        /* BMLP_ARM_AUTO, _SMP_DENSE, _SMP_SPARSE, _SMP_CLOSURE, _SMP_SPARSE_ROUNDS,
+                             _SMP_ADAPTIVE or _SMP_CLOSURE_SELECT */
   int32_t compose_arm;    /* BMLP_ARM_AUTO, _COMPOSE_RMS, _COMPOSE_SEMINAIVE or _COMPOSE_ROWWISE */
   int32_t rms_variant;    /* 0: R <- R | R.R to a fixpoint (default);
                              1: Algorithm 1 as printed: R = I + R1, square to a fixpoint, times R1 */
@@ -288,7 +293,10 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc *graphs, int32_t c
    (reuse of intermediate results, Section 4).  Under the plain schedule a session never computes
    the closure; under the learned schedule it does so when the model's predicted cost of the
    closure falls below the time already spent answering this relation's queries iteratively
-   (ski-rental rule).  The session owns its closure buffer (n x ceil(n/64) words). */
+   (ski-rental rule), and builds it by BMLP-RMS or by the selection from every source
+   (BMLP_ARM_SMP_CLOSURE_SELECT), whichever the model predicts cheaper.  Forced with smp_arm
+   BMLP_ARM_SMP_CLOSURE or _SMP_CLOSURE_SELECT, the first query builds the closure that way.  The
+   session owns its closure buffer (n x ceil(n/64) words). */
 typedef struct bmlp_graph_s *bmlp_graph;
 bmlp_status bmlp_graph_open(bmlp_handle h, const uint64_t *R1, int64_t n, int64_t ld, void *stream, bmlp_graph *g);
 /* Vstar = V x R1+ (Eq. 5), like bmlp_smp; stats->arm tells which arm answered.  Without stats the query
@@ -305,7 +313,9 @@ bmlp_status bmlp_graph_query_sources(bmlp_graph g, const int32_t *src, uint64_t 
                                      const bmlp_opts *opts, void *stream, bmlp_stats *stats);
 /* Whether the session holds the closure (1) or not (0). */
 int32_t bmlp_graph_has_closure(bmlp_graph g);
-/* The arm (bmlp_arm) that served the session's last query, -1 before the first; host-side, no waiting. */
+/* The arm (bmlp_arm) that served the session's last query, -1 before the first; host-side, no waiting.
+   The query that built the closure reports the build (BMLP_ARM_SMP_CLOSURE: by BMLP-RMS,
+   _SMP_CLOSURE_SELECT: by selection); later answers read off it report BMLP_ARM_SMP_CLOSURE. */
 int32_t bmlp_graph_last_arm(bmlp_graph g);
 bmlp_status bmlp_graph_close(bmlp_graph g);
 

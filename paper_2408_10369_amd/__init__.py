@@ -27,6 +27,7 @@ ARM_PRODUCT_VALU, ARM_PRODUCT_MFMA = 0, 1
 ARM_SMP_DENSE, ARM_SMP_SPARSE, ARM_SMP_CLOSURE = 2, 3, 4
 ARM_COMPOSE_RMS, ARM_COMPOSE_SEMINAIVE = 5, 6
 ARM_SMP_SPARSE_ROUNDS, ARM_SMP_ADAPTIVE = 7, 8
+ARM_SMP_CLOSURE_SELECT = 13
 ARM_COMPOSE_ROWWISE = 9
 ARM_PRODUCT_GATHER = 10
 ARM_PRODUCT_SEMINAIVE = 11

@@ -961,6 +961,24 @@ void read_off_closure(bmlp_ctx* c, const u64* V, i64 ldv, i64 k, const u64* clo,
   hip_check(launch_zero_pad(Vstar, k, n, ldv, s), "zero_pad");
 }
 
+void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vstar, i64 k, i64 ldv, int reflexive,
+              int arm, const GraphInfo& gi, int compose, Csr csr, const bmlp_opts& o, hipStream_t s, StatsRec& sr);
+
+// R1+ (n x n, leading dimension ldo) by the one-launch selection from every source: row i of R1+ is the
+// selection from the one-hot row e_i (the selection with V = I, whose rows the kernel forms itself).
+// The same closure BMLP-RMS reaches, by per-source frontier expansion instead of squarings, which is
+// cheaper where the closure rows cost less to expand than the squarings of a dense product.
+void closure_by_selection(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, u64* out, i64 ldo, const GraphInfo& gi, Csr csr,
+                          const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
+  need(n <= smp_rows_max_n(), BMLP_EINVAL, "the closure by selection supports n <= %lld",
+       (long long)smp_rows_max_n());
+  const int keep = sr.st ? sr.st->arm : 0;
+  const int keep_trace = c->trace ? c->trace->call_arm : 0;
+  smp_core(c, R1, ld, n, nullptr, out, n, ldo, 0, BMLP_ARM_SMP_SPARSE, gi, 0, csr, o, s, sr);
+  if (sr.st) sr.st->arm = keep;
+  if (c->trace) c->trace->call_arm = keep_trace;
+}
+
 // Vstar = V . R1+ (or V . R1* when reflexive) by the given call-level arm.
 void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vstar, i64 k, i64 ldv, int reflexive,
               int arm, const GraphInfo& gi, int compose, Csr csr, const bmlp_opts& o, hipStream_t s, StatsRec& sr) {
@@ -996,9 +1014,12 @@ void smp_core(bmlp_ctx* c, const u64* R1, i64 ld, i64 n, const u64* V, u64* Vsta
     if (sr.st) sr.defer_rounds(n, arm);
     return;
   }
-  if (arm == BMLP_ARM_SMP_CLOSURE) {
+  if (arm == BMLP_ARM_SMP_CLOSURE || arm == BMLP_ARM_SMP_CLOSURE_SELECT) {
     u64* clo = ws_bits(c, S_W2, n, nw, o);
-    rms_core(c, R1, ld, clo, nw, n, o, s, sr);
+    if (arm == BMLP_ARM_SMP_CLOSURE)
+      rms_core(c, R1, ld, clo, nw, n, o, s, sr);
+    else
+      closure_by_selection(c, R1, ld, n, clo, nw, gi, csr, o, s, sr);
     read_off_closure(c, V, ldv, k, clo, nw, n, reflexive, Vstar, o, s, sr);
     return;
   }
@@ -1665,7 +1686,8 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, c
     const bool forced = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
     if (forced)
       need(o.smp_arm == BMLP_ARM_SMP_DENSE || o.smp_arm == BMLP_ARM_SMP_SPARSE || o.smp_arm == BMLP_ARM_SMP_CLOSURE ||
-               o.smp_arm == BMLP_ARM_SMP_SPARSE_ROUNDS || o.smp_arm == BMLP_ARM_SMP_ADAPTIVE,
+               o.smp_arm == BMLP_ARM_SMP_SPARSE_ROUNDS || o.smp_arm == BMLP_ARM_SMP_ADAPTIVE ||
+               o.smp_arm == BMLP_ARM_SMP_CLOSURE_SELECT,
            BMLP_EINVAL, "smp_arm %d is not a selection arm", o.smp_arm);
     DeviceGuard dg(h->device);
     hipStream_t s = (hipStream_t)stream;
@@ -1931,7 +1953,8 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
     }
     if (o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO)
       need(o.smp_arm == BMLP_ARM_SMP_DENSE || o.smp_arm == BMLP_ARM_SMP_SPARSE || o.smp_arm == BMLP_ARM_SMP_CLOSURE ||
-               o.smp_arm == BMLP_ARM_SMP_SPARSE_ROUNDS || o.smp_arm == BMLP_ARM_SMP_ADAPTIVE,
+               o.smp_arm == BMLP_ARM_SMP_SPARSE_ROUNDS || o.smp_arm == BMLP_ARM_SMP_ADAPTIVE ||
+               o.smp_arm == BMLP_ARM_SMP_CLOSURE_SELECT,
            BMLP_EINVAL, "smp_arm %d is not a selection arm", o.smp_arm);
     DeviceGuard dg(h->device);
     hipStream_t s = (hipStream_t)stream;
@@ -2065,6 +2088,8 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
     // output nor read is not squared at all).  Graphs beyond the selection kernel's size always read
     // the closure.
     const bool forced_sel = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
+    need(!forced_sel || o.smp_arm != BMLP_ARM_SMP_CLOSURE_SELECT, BMLP_EINVAL,
+         "the batched launch squares its closures (smp_arm %d is not available there)", o.smp_arm);
     const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
     plan.qmode = forced_sel ? (o.smp_arm == BMLP_ARM_SMP_CLOSURE ? 0 : 1) : learned ? 2 : 1;
     size_t buf_words = 0;
@@ -2211,6 +2236,8 @@ struct bmlp_graph_s {
   int32_t* cit = nullptr;
   u64* closure = nullptr;   // owned R1+ (n x ceil(n/64)) once computed
   double spent_ms = 0.0;    // device time spent answering queries without the closure
+  double p_sel_all_ms = -1; // the model's predicted time of the closure by selection (learned sessions)
+  int32_t closure_arm = -1; // how the closure was built, until the query that built it has reported it
   int32_t last_arm = -1;    // the arm that served the last query
 };
 
@@ -2575,12 +2602,28 @@ void graph_query_core(bmlp_graph g, const uint64_t* V, const int32_t* src, uint6
                                 : ((learned && !forced) || h->trace) ? (double)count_bits(h, V, k, n, ldv, s) : 0.0;
       float pred[4] = {0, 0, 0, 0};
       arm = smp_choose_arm(h, o, g->gi, k, 0, refl, delta0, s, learned ? pred : nullptr);
-      if (arm == BMLP_ARM_SMP_CLOSURE) use_closure = true;  // and keep it for later queries
+      // how a closure would be built: by squarings (BMLP-RMS), or by the selection from every source
+      int build = arm == BMLP_ARM_SMP_CLOSURE_SELECT ? BMLP_ARM_SMP_CLOSURE_SELECT : BMLP_ARM_SMP_CLOSURE;
+      if (arm == BMLP_ARM_SMP_CLOSURE || arm == BMLP_ARM_SMP_CLOSURE_SELECT) use_closure = true;
       if (learned && !forced) {
+        // the closure's predicted cost: the cheaper of the two builds (the selection from all n sources
+        // predicted once per session, by the model's one-launch output at k = n)
+        double p_clo = std::exp(pred[2]);
+        if (g->gi.n <= smp_rows_max_n()) {
+          if (g->p_sel_all_ms < 0.0) {
+            float f[kIn], pa[4];
+            make_features(f, g->gi, n, 0, 1, 0, (double)n, (double)n, 0.0, 0);
+            (void)model_decide(h, f, 0x8u, s, pa);
+            g->p_sel_all_ms = std::exp(pa[3]);
+          }
+          if (g->p_sel_all_ms < p_clo) {
+            p_clo = g->p_sel_all_ms;
+            build = BMLP_ARM_SMP_CLOSURE_SELECT;
+          }
+        }
         // ski rental: build the closure once its predicted cost is below the time already spent on
         // this relation plus this query's predicted cost without it
         const double p_iter = std::exp(std::min(pred[0], g->gi.n <= smp_rows_max_n() ? pred[3] : pred[0]));
-        const double p_clo = std::exp(pred[2]);
         if (p_clo <= g->spent_ms + p_iter) use_closure = true;
       }
       if (use_closure) {
@@ -2590,12 +2633,16 @@ void graph_query_core(bmlp_graph g, const uint64_t* V, const int32_t* src, uint6
           fail(BMLP_ENOMEM, "closure allocation failed");
         }
         try {
-          rms_core(h, g->R1, g->ld, clo, nw, n, o, s, sr);
+          if (build == BMLP_ARM_SMP_CLOSURE_SELECT)
+            closure_by_selection(h, g->R1, g->ld, n, clo, nw, g->gi, Csr{g->rp, g->ci, g->rpt, g->cit}, o, s, sr);
+          else
+            rms_core(h, g->R1, g->ld, clo, nw, n, o, s, sr);
         } catch (...) {
           (void)hipFree(clo);
           throw;
         }
         g->closure = clo;
+        g->closure_arm = build;
       } else {
         if (!V) {
           // the query rows of the sources
@@ -2620,7 +2667,9 @@ void graph_query_core(bmlp_graph g, const uint64_t* V, const int32_t* src, uint6
       }
     }
     if (use_closure) {
-      arm = BMLP_ARM_SMP_CLOSURE;
+      // the query that builds the closure reports how it was built; later ones read it off
+      arm = g->closure_arm >= 0 ? g->closure_arm : BMLP_ARM_SMP_CLOSURE;
+      g->closure_arm = -1;
       if (src)
         hip_check(launch_rows_by_index(g->closure, nw, src, k, n, refl, Vstar, ldv, h->d_flags + F_DEFER, s),
                   "rows_by_index");

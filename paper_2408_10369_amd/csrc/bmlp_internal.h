@@ -118,7 +118,8 @@ i64 gemm_mfma_max_kwords();
 // Per-row fixpoint of the semi-naive selection in one launch (one workgroup
 // per query row, bitmaps in LDS): out[r] = V[r] R+ (reflexive: V[r] R*).
 // Needs CSR (rp, ci) of R and the bit rows of R (for dense frontier nodes); with the CSC (rpt, cit: the
-// in-edges, optional) rounds with a large frontier run bottom-up.
+// in-edges, optional) rounds with a large frontier run bottom-up.  V null stands for the identity (row r
+// starts from node r; k <= n), so that out holds the rows of R+ (R* when reflexive).
 hipError_t launch_smp_rows(const u64* V, i64 ldv, i64 k, const i64* rp, const int32_t* ci, const i64* rpt,
                            const int32_t* cit, const u64* R, i64 ldr, i64 n, int reflexive, u64* out, i64 ldo,
                            u32* iters_max, hipStream_t s);

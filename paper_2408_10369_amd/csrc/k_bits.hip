@@ -182,21 +182,31 @@ __global__ void k_copy_rows(const u64* __restrict__ src, i64 lds, const int32_t*
 }
 
 // One-hot queries answered from a closure: out row i = C row idx[i] (| bit idx[i] when reflexive), padding
-// words up to ldo zeroed; an index outside [0, n) gives a zero row and raises *bad.  One wave per row.
-__global__ void k_rows_by_index(const u64* __restrict__ C, i64 ldc, const int32_t* __restrict__ idx, i64 k, i64 n,
-                                int reflexive, u64* __restrict__ out, i64 ldo, u32* __restrict__ bad) {
-  const int lane = threadIdx.x & 63;
-  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
-  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+// words up to ldo zeroed; an index outside [0, n) gives a zero row and raises *bad.  A workgroup copies
+// 1,024 words of one row (segment seg of row i), four words per thread with all four loads in flight, so
+// that a query of few rows waits for one memory round trip rather than one per 512 bytes.
+constexpr int kRowSegWords = 4 * kBlock;
+__global__ void __launch_bounds__(kBlock)
+k_rows_by_index(const u64* __restrict__ C, i64 ldc, const int32_t* __restrict__ idx, i64 k, i64 n, int reflexive,
+                u64* __restrict__ out, i64 ldo, u32* __restrict__ bad) {
   const i64 nw = (n + 63) >> 6;
-  for (i64 i = wave; i < k; i += nwaves) {
+  const i64 segs = (ldo + kRowSegWords - 1) / kRowSegWords;
+  for (i64 b = blockIdx.x; b < k * segs; b += gridDim.x) {
+    const i64 i = b / segs, w0 = (b - i * segs) * kRowSegWords;
     const i64 j = idx[i];
     const bool ok = j >= 0 && j < n;
-    if (!ok && lane == 0 && bad) atomicOr(bad, 1u);
-    for (i64 w = lane; w < ldo; w += 64) {
-      u64 v = (ok && w < nw) ? C[j * ldc + w] : 0ull;
-      if (ok && reflexive && w == (j >> 6)) v |= 1ull << (j & 63);
-      out[i * ldo + w] = v;
+    if (!ok && w0 == 0 && threadIdx.x == 0 && bad) atomicOr(bad, 1u);
+    u64 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const i64 w = w0 + q * kBlock + threadIdx.x;
+      v[q] = (ok && w < nw) ? C[j * ldc + w] : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const i64 w = w0 + q * kBlock + threadIdx.x;
+      if (ok && reflexive && w == (j >> 6)) v[q] |= 1ull << (j & 63);
+      if (w < ldo) out[i * ldo + w] = v[q];
     }
   }
 }
@@ -731,8 +741,10 @@ hipError_t launch_set_onehot(u64* a, i64 ld, const int32_t* idx, i64 k, i64 n, u
 hipError_t launch_rows_by_index(const u64* C, i64 ldc, const int32_t* idx, i64 k, i64 n, int reflexive, u64* out,
                                i64 ldo, u32* bad, hipStream_t s) {
   if (k <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_by_index, dim3(grid_for(k * 64, kBlock, 16384)), dim3(kBlock), 0, s, C, ldc, idx, k, n,
-                     reflexive, out, ldo, bad);
+  if (ldo <= 0) return hipSuccess;
+  const i64 blocks = k * ((ldo + kRowSegWords - 1) / kRowSegWords);
+  hipLaunchKernelGGL(k_rows_by_index, dim3((unsigned)std::min<i64>(blocks, 1 << 20)), dim3(kBlock), 0, s, C, ldc, idx,
+                     k, n, reflexive, out, ldo, bad);
   return hipGetLastError();
 }
 

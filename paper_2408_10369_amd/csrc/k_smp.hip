@@ -59,7 +59,9 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
     u32 nf0 = 0;
     for (i64 w = t; w < nw; w += kSmpThreads) {
       vis[w] = 0ull;
-      const u64 f = V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
+      // V null: the rows of the identity (row i starts from node i), so the answers are the rows of R1+
+      const u64 f = V ? V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull)
+                      : (w == (row >> 6) && row < n ? 1ull << (row & 63) : 0ull);
       fr[w] = f;
       nxt[w] = 0ull;
       nf0 += (u32)__popcll(f);
@@ -219,7 +221,8 @@ k_smp_rows(const u64* __restrict__ V, i64 ldv, i64 k, const i64* __restrict__ rp
     }
     for (i64 w = t; w < nw; w += kSmpThreads) {
       u64 v = vis[w];
-      if (reflexive) v |= V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull);
+      if (reflexive)
+        v |= V ? V[row * ldv + w] & (w == nw - 1 ? last_mask : ~0ull) : (w == (row >> 6) ? 1ull << (row & 63) : 0ull);
       out[row * ldo + w] = v;
     }
     for (i64 w = nw + t; w < ldo; w += kSmpThreads) out[row * ldo + w] = 0ull;

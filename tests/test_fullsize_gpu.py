@@ -95,7 +95,22 @@ def test_scalefree_closure_sampled_rows(ctx, scalefree):
 STREAM_QUERIES = 24
 
 
-@pytest.mark.parametrize("mode", ["plain", "learned", "forced_closure"])
+def test_scalefree_closure_by_selection_sampled_rows(ctx, scalefree):
+    """R1+ of the stream's relation by the selection from every source: the same sampled rows as the
+    oracle, and bit for bit the closure BMLP-RMS reaches."""
+    n, s, d = scalefree
+    R = gpu_pack(ctx, n, s, d)
+    eye = ctx.pack_coo(torch.arange(n, dtype=torch.int32), torch.arange(n, dtype=torch.int32), n, n)
+    got = ctx.smp(R, n, eye, opts=B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE_SELECT))
+    rows = np.sort(np.random.default_rng(65537).choice(n, 2048, replace=False))
+    want = oracle.closure_rows(n, s, d, rows=rows)
+    gh = host(got)
+    assert first_diff(gh[rows], want) is None, first_diff(gh[rows], want)
+    del eye
+    assert np.array_equal(gh, host(ctx.rms(R, n)))
+
+
+@pytest.mark.parametrize("mode", ["plain", "learned", "forced_closure", "forced_closure_select"])
 def test_scalefree_stream_every_answer(ctx, scalefree, mode):
     n, s, d = scalefree
     queries = gen.query_stream(count=STREAM_QUERIES)
@@ -103,7 +118,8 @@ def test_scalefree_stream_every_answer(ctx, scalefree, mode):
     assert sum(k > 2048 for k in ks) >= 3  # the one-slot bottom-up kernel serves these under every schedule
     opts = {"plain": B.make_opts(dispatch=B.DISPATCH_PLAIN),
             "learned": B.make_opts(dispatch=B.DISPATCH_LEARNED),
-            "forced_closure": B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE)}[mode]
+            "forced_closure": B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE),
+            "forced_closure_select": B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE_SELECT)}[mode]
     R = gpu_pack(ctx, n, s, d)
     arms = []
     with ctx.graph(R, n) as g:
@@ -120,6 +136,9 @@ def test_scalefree_stream_every_answer(ctx, scalefree, mode):
         assert all(a == B.ARM_SMP_SPARSE for a, k in zip(arms, ks) if k >= 64)
     if mode == "forced_closure":
         assert all(a == B.ARM_SMP_CLOSURE for a in arms)
+    if mode == "forced_closure_select":
+        # the first query builds the closure by selection, the others read it off
+        assert arms[0] == B.ARM_SMP_CLOSURE_SELECT and all(a == B.ARM_SMP_CLOSURE for a in arms[1:]), arms
 
 
 @pytest.mark.parametrize("n,deg,k", [(4096, 4.4, 2100), (9000, 6.0, 2500), (16384, 4.6, 3000)])

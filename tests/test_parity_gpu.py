@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2408_10369_amd as B  # noqa: E402
 
-ARMS_SMP = [B.ARM_SMP_DENSE, B.ARM_SMP_SPARSE, B.ARM_SMP_CLOSURE]
+ARMS_SMP = [B.ARM_SMP_DENSE, B.ARM_SMP_SPARSE, B.ARM_SMP_CLOSURE, B.ARM_SMP_CLOSURE_SELECT]
 
 
 @pytest.fixture(scope="module")
@@ -317,8 +317,8 @@ def test_rms_padding_words_zeroed(ctx):
 @pytest.mark.parametrize("arm", ARMS_SMP)
 @pytest.mark.parametrize("n", [1, 2, 63, 65, 129, 700, 2000])
 def test_smp_random(ctx, n, arm, reflexive, parm):
-    if parm == B.ARM_PRODUCT_MFMA and arm == B.ARM_SMP_SPARSE:
-        pytest.skip("the sparse arm launches no product")
+    if parm == B.ARM_PRODUCT_MFMA and arm in (B.ARM_SMP_SPARSE, B.ARM_SMP_CLOSURE_SELECT):
+        pytest.skip("the arm launches no product")
     rng = np.random.default_rng(2000 + n)
     for p in (1.2 / n, 5.0 / n):
         A, s, d = rand_graph(rng, n, min(p, 1.0))
@@ -334,6 +334,23 @@ def test_smp_random(ctx, n, arm, reflexive, parm):
         want = oracle.smp(n, s, d, Vb, reflexive=bool(reflexive))
         assert np.array_equal(got, want), (n, p, arm, reflexive)
         assert st["arm"] == arm
+
+
+@pytest.mark.parametrize("n", [1, 64, 65, 1000, 5000])
+def test_closure_by_selection_is_the_closure(ctx, n):
+    """The selection from every source (V = I) under the closure-by-selection arm returns R1+ itself,
+    and the read-off of I, R1+ and R1* rows agrees with the oracle's closure."""
+    rng = np.random.default_rng(4242 + n)
+    for p in (1.5 / max(n, 1), 4.0 / max(n, 1)):
+        A, s, d = rand_graph(rng, n, min(p, 1.0))
+        R = gpu_pack(ctx, n, s, d)
+        eye_bits = boolops.to_bits(boolops.identity(n))
+        eye = dev(eye_bits)
+        want = oracle.closure_rows(n, s, d)
+        for refl in (0, 1):
+            got = host(ctx.smp(R, n, eye, opts=forced(smp_arm=B.ARM_SMP_CLOSURE_SELECT, smp_reflexive=refl)))
+            w = want | eye_bits if refl else want
+            assert np.array_equal(got, w), (n, p, refl)
 
 
 @pytest.mark.parametrize("reflexive", [0, 1])

@@ -51,13 +51,15 @@ def test_pack_coo_async_and_deferred_error(ctx):
     ctx.deferred_error()
 
 
-@pytest.mark.parametrize("mode", ["plain", "learned", "forced_closure"])
+@pytest.mark.parametrize("mode", ["plain", "learned", "forced_closure", "forced_closure_select"])
 def test_session_without_stats(ctx, mode):
     n = 20000
     s, d = gen.er_digraph(n, 3.0 / n, 20000)
     R = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n)
     opts = {"plain": B.make_opts(dispatch=B.DISPATCH_PLAIN), "learned": B.make_opts(dispatch=B.DISPATCH_LEARNED),
-            "forced_closure": B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE)}[mode]
+            "forced_closure": B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE),
+            "forced_closure_select": B.make_opts(dispatch=B.DISPATCH_FORCED,
+                                                 smp_arm=B.ARM_SMP_CLOSURE_SELECT)}[mode]
     rng = np.random.default_rng(77)
     V = ctx.zeros(600, n)
     Vs = ctx.zeros(600, n)
@@ -70,9 +72,14 @@ def test_session_without_stats(ctx, mode):
             ctx.pack_coo_async(torch.as_tensor(rr).cuda(), torch.as_tensor(cc).cuda(), k, n, out=V[:k])
             g.query(V[:k], out=Vs[:k], opts=opts)
             arm = g.last_arm
-            assert arm in (B.ARM_SMP_SPARSE, B.ARM_SMP_CLOSURE, B.ARM_SMP_DENSE, B.ARM_SMP_ADAPTIVE)
+            assert arm in (B.ARM_SMP_SPARSE, B.ARM_SMP_CLOSURE, B.ARM_SMP_DENSE, B.ARM_SMP_ADAPTIVE,
+                           B.ARM_SMP_CLOSURE_SELECT)
             if mode == "forced_closure":
                 assert arm == B.ARM_SMP_CLOSURE
+            if mode == "forced_closure_select":
+                assert arm == (B.ARM_SMP_CLOSURE_SELECT if q == 0 else B.ARM_SMP_CLOSURE), (q, arm)
+            if arm == B.ARM_SMP_CLOSURE_SELECT:
+                assert g.has_closure
             want = oracle.smp(n, s, d, host(V[:k]))
             assert np.array_equal(host(Vs[:k]), want), (mode, q, k, arm)
     ctx.deferred_error()
@@ -109,3 +116,14 @@ def test_session_query_by_sources(ctx, mode, refl):
         assert not got[1].any()
         with pytest.raises(B.BmlpError):
             ctx.deferred_error()
+
+
+def test_batched_rejects_closure_by_selection(ctx):
+    n = 100
+    s, d = gen.er_digraph(n, 0.03, 3)
+    R = ctx.pack_coo(torch.as_tensor(s), torch.as_tensor(d), n, n)
+    V = ctx.zeros(4, n)
+    desc = [{"n": n, "R1": R, "V": V, "Vstar": ctx.zeros(4, n), "closure": None}]
+    with pytest.raises(B.BmlpError) as e:
+        ctx.batched(desc, opts=B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_CLOSURE_SELECT))
+    assert e.value.status == B.EINVAL
