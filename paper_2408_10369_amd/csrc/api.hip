@@ -2151,6 +2151,10 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       plan.total_tiles += mfma ? 4 * G.mfma_rtiles : batch_tiles(d.n);  // 64-row tiles of an MFMA graph
       plan.total_select_tiles += d.k > 0 ? batch_select_tiles(d.k, d.n) : 0;
       plan.total_qrows += d.k;
+      if (d.k > 0 && d.n > 0 && d.n <= batch_ms_max_n()) {
+        plan.ms_max_n = std::max<i64>(plan.ms_max_n, d.n);
+        plan.ms_qrows += d.k;
+      }
     }
     need((size_t)batch_flag_words(count, plan) == nflags, BMLP_EDEVICE, "batched plan: flag area mismatch");
     // the captured chain is reused while the batch (and its workspace) is unchanged

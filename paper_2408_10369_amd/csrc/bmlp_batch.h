@@ -36,7 +36,13 @@ struct BatchPlan {
   i64 total_mfma_tiles;  // matrix-core tiles per round, over all graphs
   i64 total_tblocks;     // transpose blocks per round, over all graphs
   i64 total_mblocks;     // 256-row blocks of the matrix-core graphs
+  i64 ms_max_n;          // largest n of the graphs with query rows whose selection runs 64 rows at a time
+                         // (n <= batch_ms_max_n(); 0: none)
+  i64 ms_qrows;          // query rows of those graphs
 };
+
+// largest n whose query rows the batch selects 64 at a time (masks per node in LDS)
+i64 batch_ms_max_n();
 
 // smallest n whose squarings run on the matrix cores in a batch
 i64 batch_mfma_min_n();

@@ -96,41 +96,65 @@ __global__ void k_batch_modes(const BatchGraph* __restrict__ gs, int count, int 
 }
 
 // Statistics of each graph for the dispatcher's features: set bits of R1, its largest row count, its
-// nonempty rows, and the set bits of its query rows.  One wave per (graph, row) of the batch-wide row
-// numbering; gst holds 4 u64 per graph (zeroed by the setup kernel).
-__global__ void k_batch_stats(const BatchGraph* __restrict__ gs, int count, i64 total_rows,
-                              unsigned long long* __restrict__ gst) {
-  const int lane = threadIdx.x & 63;
-  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
-  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
-  for (i64 rr = wave; rr < total_rows; rr += nwaves) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (gs[mid].row_begin <= rr) lo = mid; else hi = mid - 1;
-    }
-    const BatchGraph& G = gs[lo];
-    const i64 row = rr - G.row_begin;
-    u32 pr = 0, pv = 0;
-    for (i64 w = lane; w < G.nw; w += 64) {
-      const u64 lm = (w == G.nw - 1 && (G.n & 63)) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
-      if (row < G.n) pr += (u32)__popcll(G.R1[row * G.ld + w] & lm);
-      if (row < G.k) pv += (u32)__popcll(G.V[row * G.ldv + w] & lm);
-    }
+// nonempty rows, and the set bits of its query rows.  One workgroup of eight waves per graph; a wave takes
+// eight rows at a time with all their loads in flight (lanes over the words of a row); the sums stay in
+// registers and LDS, and gst (4 u64 per graph) is written once per graph, with no atomics.
+constexpr int kStatsRows = 8;
+__global__ void __launch_bounds__(512)
+k_batch_stats(const BatchGraph* __restrict__ gs, int count, unsigned long long* __restrict__ gst) {
+  __shared__ unsigned long long part[8][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (i64 g = blockIdx.x; g < count; g += gridDim.x) {
+    const BatchGraph& G = gs[g];
+    const u64 lm = (G.n & 63) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
+    unsigned long long bits = 0, mx = 0, nonempty = 0, vbits = 0;  // wave-uniform after the reductions
+    const i64 rows = G.n > G.k ? G.n : G.k;
+    for (i64 row0 = (i64)wave * kStatsRows; row0 < rows; row0 += 8 * kStatsRows) {
+      u32 pr[kStatsRows], pv[kStatsRows];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      pr += __shfl_xor(pr, off, 64);
-      pv += __shfl_xor(pv, off, 64);
+      for (int r = 0; r < kStatsRows; ++r) pr[r] = pv[r] = 0u;
+      for (i64 w = lane; w < G.nw; w += 64) {
+        const u64 m = w == G.nw - 1 ? lm : ~0ull;
+        u64 xr[kStatsRows], xv[kStatsRows];
+#pragma unroll
+        for (int r = 0; r < kStatsRows; ++r) {
+          const i64 row = row0 + r;
+          xr[r] = row < G.n ? G.R1[row * G.ld + w] : 0ull;
+          xv[r] = row < G.k ? G.V[row * G.ldv + w] : 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < kStatsRows; ++r) {
+          pr[r] += (u32)__popcll(xr[r] & m);
+          pv[r] += (u32)__popcll(xv[r] & m);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kStatsRows; ++r) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          pr[r] += __shfl_xor(pr[r], off, 64);
+          pv[r] += __shfl_xor(pv[r], off, 64);
+        }
+        bits += pr[r];
+        mx = pr[r] > mx ? pr[r] : mx;
+        nonempty += pr[r] ? 1u : 0u;
+        vbits += pv[r];
+      }
     }
     if (lane == 0) {
-      unsigned long long* s = gst + 4 * (i64)lo;
-      if (pr) {
-        atomicAdd(&s[0], (unsigned long long)pr);
-        atomicMax(&s[1], (unsigned long long)pr);
-        atomicAdd(&s[2], 1ull);
-      }
-      if (pv) atomicAdd(&s[3], (unsigned long long)pv);
+      part[wave][0] = bits;
+      part[wave][1] = mx;
+      part[wave][2] = nonempty;
+      part[wave][3] = vbits;
     }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int q = threadIdx.x;
+      unsigned long long v = part[0][q];
+      for (int w = 1; w < 8; ++w) v = q == 1 ? (part[w][q] > v ? part[w][q] : v) : v + part[w][q];
+      gst[4 * g + q] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -402,6 +426,105 @@ k_batch_select(const BatchGraph* __restrict__ gs, int count, i64 total_tiles, in
   }
 }
 
+// Selection without the closure for the graphs of n <= 64 kMsWords: the semi-naive fixpoint of Eq. 5 for 64
+// query rows at once, transposed.  One workgroup per graph keeps, per node u, the 64-bit masks vis[u]
+// (which of the chunk's query rows have reached u) and fr[u] (rows that reached u and are not yet pushed
+// along u's edges) in LDS.  A wave takes the nodes of a 64-node block whose fr is nonzero, clears it, loads
+// their bit rows of R1 (eight rows in flight) and pushes the mask along every edge u -> v:
+//   old = vis[v] |= f; fr[v] |= f & ~old
+// so each (query row, node) pair enters fr once per time it enters vis, and the fixpoint is the
+// selection's: vis = V_chunk R1+ (transposed), in whatever order the pushes happen.  A pass over all nodes
+// that finds no nonzero fr ends the fixpoint.  One 512-byte row load serves 64 query rows, where the
+// per-row kernel below loads it once per row.
+constexpr int kMsWords = 64;  // n <= 4,096
+constexpr int kMsThreads = 512;
+
+__global__ void __launch_bounds__(kMsThreads)
+k_batch_select_ms(const BatchGraph* __restrict__ gs, int count, i64 nmax, const u32* __restrict__ qsel) {
+  extern __shared__ u64 msh[];
+  u64* fr = msh;
+  u64* vis = msh + nmax;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  constexpr int kWaves = kMsThreads / 64;
+  for (i64 g = blockIdx.x; g < count; g += gridDim.x) {
+    const BatchGraph& G = gs[g];
+    if (!qsel[g] || G.k == 0 || G.n == 0 || G.nw > kMsWords || G.n > nmax) continue;  // uniform per workgroup
+    const i64 n = G.n, nw = G.nw;
+    const u64 lm = (n & 63) ? ((1ull << (n & 63)) - 1ull) : ~0ull;
+    for (i64 c0 = 0; c0 < G.k; c0 += 64) {
+      const int kc = (int)(G.k - c0 < 64 ? G.k - c0 : 64);
+      // fr[u] = the query rows of the chunk with bit u set (a 64 x 64 bit transpose per node block)
+      for (i64 i = wave; i < nw; i += kWaves) {
+        u64 x = lane < kc ? G.V[(c0 + lane) * G.ldv + i] : 0ull;
+        if (i == nw - 1) x &= lm;
+        u64 mine = 0ull;
+        for (int b = 0; b < 64; ++b) {
+          const u64 bal = __ballot((x >> b) & 1ull);
+          if (lane == b) mine = bal;
+        }
+        if (64 * i + lane < n) {
+          fr[64 * i + lane] = mine;
+          vis[64 * i + lane] = 0ull;
+        }
+      }
+      __syncthreads();
+      for (;;) {
+        int did = 0;
+        for (i64 i = wave; i < nw; i += kWaves) {
+          const i64 u = 64 * i + lane;
+          const u64 f = u < n ? atomicExch((unsigned long long*)&fr[u], 0ull) : 0ull;
+          u64 m = __ballot(f != 0ull);
+          did |= m != 0ull;
+          while (m) {
+            int ln[8];
+            int cnt = 0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+              ln[c] = 0;
+              if (m) {
+                ln[c] = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                ++cnt;
+              }
+            }
+            u64 row[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              row[c] = (c < cnt && lane < nw) ? G.R1[(64 * i + ln[c]) * G.ld + lane] & (lane == nw - 1 ? lm : ~0ull)
+                                              : 0ull;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+              if (c >= cnt) break;
+              const u64 fu = __shfl(f, ln[c], 64);
+              u64 x = row[c];
+              while (x) {
+                const int b = __ffsll((unsigned long long)x) - 1;
+                x &= x - 1;
+                const i64 v = 64 * (i64)lane + b;
+                const u64 old = atomicOr((unsigned long long*)&vis[v], fu);
+                const u64 nb = fu & ~old;
+                if (nb) atomicOr((unsigned long long*)&fr[v], nb);
+              }
+            }
+          }
+        }
+        if (!__syncthreads_or(did)) break;
+      }
+      // answer rows c0 .. c0 + kc - 1, word i: the transpose of vis over node block i
+      for (i64 i = wave; i < nw; i += kWaves) {
+        const u64 v = 64 * i + lane < n ? vis[64 * i + lane] : 0ull;
+        u64 mine = 0ull;
+        for (int q = 0; q < kc; ++q) {
+          const u64 bal = __ballot((v >> q) & 1ull);
+          if (lane == q) mine = bal;
+        }
+        if (lane < kc) G.Vstar[(c0 + lane) * G.ldv + i] = mine;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Selection without the closure (the plain schedule's reading of a partially grounded query as
 // BMLP-SMP): one wave per query row runs the semi-naive fixpoint of Eq. 5 with its frontier,
 // visited and successor bitmaps in registers (lane l owns words l, l + 64, ...; up to kBfsWords
@@ -428,7 +551,8 @@ k_batch_select_bfs(const BatchGraph* __restrict__ gs, int count, i64 total_qrows
     }
     const BatchGraph& G = gs[lo];
     const i64 row = it - G.qrow_begin;
-    if (row >= G.k || G.nw > kBfsWords || !qsel[lo]) continue;  // answered off the closure
+    // answered off the closure, or by the multi-row kernel above
+    if (row >= G.k || G.nw > kBfsWords || G.nw <= kMsWords || !qsel[lo]) continue;
     const u64 lm = (G.n & 63) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
     u64 fr[kBfsPer], vis[kBfsPer], nxt[kBfsPer];
 #pragma unroll
@@ -518,6 +642,8 @@ i64 batch_rtiles(i64 n) { return (n + kTileRows - 1) / kTileRows; }
 
 i64 batch_bfs_max_n() { return (i64)kBfsWords * 64; }
 
+i64 batch_ms_max_n() { return (i64)kMsWords * 64; }
+
 i64 batch_mfma_min_n() { return 1024; }
 
 i64 batch_qsel_offset(int count, const BatchPlan& p) {
@@ -561,8 +687,8 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (p.qmode == 2 && model) {
     // the dispatcher's choice per graph, on the device: statistics, features, the network, the argmin
-    hipLaunchKernelGGL(k_batch_stats, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s,
-                       (const BatchGraph*)d_graphs, count, p.total_rows, gst);
+    hipLaunchKernelGGL(k_batch_stats, dim3((unsigned)count), dim3(512), 0, s, (const BatchGraph*)d_graphs, count,
+                       gst);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_features, dim3(ggrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count,
                        (const unsigned long long*)gst, X);
@@ -603,7 +729,14 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
       if (e != hipSuccess) return e;
     }
   }
-  if (p.qmode != 0 && p.total_qrows > 0) {
+  if (p.qmode != 0 && p.ms_max_n > 0) {
+    hipLaunchKernelGGL(k_batch_select_ms, dim3((unsigned)count), dim3(kMsThreads),
+                       (size_t)(2 * p.ms_max_n) * sizeof(u64), s, (const BatchGraph*)d_graphs, count, p.ms_max_n,
+                       (const u32*)qsel);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (p.qmode != 0 && p.total_qrows > p.ms_qrows) {
     hipLaunchKernelGGL(k_batch_select_bfs, dim3(grid_cap((p.total_qrows + 3) / 4, 2048)), dim3(256), 0, s,
                        (const BatchGraph*)d_graphs, count, p.total_qrows, counters + p.rounds + 1, (const u32*)qsel);
     e = hipGetLastError();

@@ -172,3 +172,30 @@ def test_batched_queries_only(ctx, mode):
     # a second call reuses the captured launch and gives the same answers
     ctx.batched(graphs, opts=opts)
     check(graphs, refs)
+
+
+@pytest.mark.parametrize("mode", ["plain", "selection"])
+def test_batched_selection_chunks_and_sizes(ctx, mode):
+    """Per-row selection inside the batch: 64 query rows at a time for n <= 4,096 (k = 1, 64, 65, 130 and
+    200 rows, multi-source rows, a hub, self-loops), one row at a time above that (n = 4,097 and 5,000)."""
+    rng = np.random.default_rng(31)
+    specs = []
+    for n, k, deg in ((64, 64, 2.0), (65, 65, 3.0), (700, 130, 1.5), (4096, 200, 4.0), (1000, 1, 6.0),
+                      (257, 64, 40.0), (4097, 70, 3.0), (5000, 20, 2.5)):
+        A = (rng.random((n, n)) < min(deg / n, 1.0)).astype(np.uint8)
+        A[n // 2, :] = rng.random(n) < 0.5  # a hub row
+        A[np.arange(0, n, 7), np.arange(0, n, 7)] = 1  # self-loops
+        s, d = np.nonzero(A)
+        specs.append((n, s, d, rng.choice(n, k, replace=k > n)))
+    graphs, refs = make_batch(ctx, specs, with_closure=False)
+    # a few query rows with several sources
+    for g, (n, s, d) in zip(graphs, refs):
+        Vh = host(g["V"]).copy()
+        extra = rng.integers(0, n, (min(5, Vh.shape[0]), 3))
+        for i, cols in enumerate(extra):
+            for c in cols:
+                Vh[i, c // 64] |= np.uint64(1) << np.uint64(c % 64)
+        g["V"].copy_(torch.from_numpy(Vh.view(np.int64)))
+    opts = None if mode == "plain" else B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_SPARSE)
+    ctx.batched(graphs, opts=opts)
+    check(graphs, refs)
