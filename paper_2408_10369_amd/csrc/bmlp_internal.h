@@ -106,8 +106,8 @@ hipError_t launch_gemm_valu(const GemmArgs& g, hipStream_t s, int variant = 0);
 //   0, 1, 2  256 x 256 tile, operands expanded into e2m1 nibbles while staging (4 words of k per LDS
 //            stage); output tiles in row-major, XCD-contiguous or XCD-interleaved order
 //   3, 4, 5  raw words in LDS, operands formed in registers (8 words per stage); the same three orders
-//   6, 7     as 0, 1 with one workgroup per compute unit walking the tiles (no launch per tile)
-// A variant whose alignment needs (16-byte rows for 3..5) are not met runs as 0.
+//   6, 7     the two tile codes with the output tiles in column strips per XCD
+// A variant whose alignment needs (16-byte rows for 3, 4, 5 and 7) are not met runs as 0.
 constexpr int kMfmaVariants = 8;
 hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStream_t s, int variant = 0);
 bool gemm_mfma_variant_ok(int variant, const GemmArgs& g, const u64* BT, i64 ldbt);

@@ -142,7 +142,11 @@ hipError_t launch_rpw(const GemmArgs& g, hipStream_t s, i64 target_blocks) {
 //   2  interleaved: XCD x gets the tiles (tr, tc) with tr = x / 4 (mod 2) and tc = x (mod 4), walked in
 //      groups of 8 of its row tiles, column by column: the same halving of each XCD's operand footprint,
 //      while a block-structured product (its work in one corner) still spreads over all XCDs.  It needs
-//      an even number of row tiles and a multiple of 4 column tiles, else order 1 is used.
+//      an even number of row tiles and a multiple of 4 column tiles, else order 1 is used;
+//   3  column strips: XCD x gets the column tiles [x c/8, (x + 1) c/8) (c = ctiles) and walks them in
+//      sub-strips of 8 columns, row by row, so the workgroups an XCD holds at once (8 rows of 8 columns
+//      at two per CU) share 8 panels of A and 8 of B^T, and the 8 B^T panels of a sub-strip stay in its
+//      L2 while the rows go by.  It needs multiples of 8 row tiles and of 64 column tiles, else order 1.
 __device__ __forceinline__ void grouped(i64 li, i64 rows, i64 cols, i64 gmax, i64* i, i64* j) {
   const i64 gsz = rows < gmax ? rows : gmax;
   const i64 group = li / (gsz * cols), first = group * gsz;
@@ -152,6 +156,13 @@ __device__ __forceinline__ void grouped(i64 li, i64 rows, i64 cols, i64 gmax, i6
   *j = in / rin;
 }
 __device__ __forceinline__ void tile_of_block(i64 b, i64 rtiles, i64 ctiles, int order, i64* tr, i64* tc) {
+  if (order == 3 && (rtiles & 7) == 0 && (ctiles & 63) == 0) {
+    const i64 x = b & 7, li = b >> 3, cw = ctiles >> 3;
+    const i64 sub = li / (rtiles * 8), rem = li - sub * rtiles * 8;
+    *tr = rem >> 3;
+    *tc = x * cw + sub * 8 + (rem & 7);
+    return;
+  }
   if (order == 2 && (rtiles & 1) == 0 && (ctiles & 3) == 0) {
     const i64 x = b & 7, li = b >> 3;
     i64 i, j;
@@ -179,24 +190,6 @@ k_gemm_mfma(MfmaTile g, const u32* __restrict__ pred, u32 pred_val) {
   i64 tr, tc;
   tile_of_block(blockIdx.x, rtiles, ctiles, ORDER, &tr, &tc);
   mfma_tile(L, g, tr, tc);
-}
-
-// The same tile code with a grid of one workgroup per compute unit that walks the tiles (t, t + grid, ...):
-// no workgroup launch per tile, which is most of the time of a product whose tiles are mostly copied
-// (saturated) or stop early.  The grid is a multiple of 8, so tile t keeps the XCD of its order.
-template <int ORDER>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_gemm_mfma_persistent(MfmaTile g, const u32* __restrict__ pred, u32 pred_val) {
-  __shared__ MfmaLds L;
-  if (pred && *pred != pred_val) return;  // another arm serves this round
-  const i64 rtiles = (g.M + kMT - 1) / kMT, ctiles = (g.N + kMT - 1) / kMT;
-  const i64 tiles = rtiles * ctiles;
-  for (i64 t = blockIdx.x; t < tiles; t += gridDim.x) {
-    if (t != (i64)blockIdx.x) __syncthreads();  // the last tile's LDS is read no more
-    i64 tr, tc;
-    tile_of_block(t, rtiles, ctiles, ORDER, &tr, &tc);
-    mfma_tile(L, g, tr, tc);
-  }
 }
 
 template <int KC, int SUB, int ORDER>
@@ -244,7 +237,7 @@ int gemm_mfma_variants() { return kMfmaVariants; }
 
 bool gemm_mfma_variant_ok(int variant, const GemmArgs& g, const u64* BT, i64 ldbt) {
   if (variant < 0 || variant >= kMfmaVariants) return false;
-  if (variant <= 2 || variant >= 6) return true;
+  if (variant <= 2 || variant == 6) return true;
   // the second layout loads rows of A and B^T in 16-byte pieces
   return ((uintptr_t)g.A & 15u) == 0 && ((uintptr_t)BT & 15u) == 0 && (g.lda & 1) == 0 && (ldbt & 1) == 0;
 }
@@ -257,19 +250,9 @@ hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStrea
   const MfmaTile t{g.A, g.lda, BT, ldbt, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N,
                     g.changed, g.newbits, g.executed, nullptr};
   const dim3 grid((unsigned)tiles), block(512);
-  // the persistent candidates: one workgroup per compute unit (a multiple of 8), at most one per tile
-  static int cus[64] = {};
-  int dev = 0;
-  if (variant >= 6) {
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return hipErrorInvalidDevice;
-  }
-  const i64 pgrid_full = ((i64)(cus[dev] > 0 ? cus[dev] : 256) + 7) / 8 * 8;
-  const dim3 pgrid((unsigned)(tiles < pgrid_full ? tiles : pgrid_full));
   switch (variant) {
-    case 6: hipLaunchKernelGGL((k_gemm_mfma_persistent<0>), pgrid, block, 0, s, t, g.pred, g.pred_val); break;
-    case 7: hipLaunchKernelGGL((k_gemm_mfma_persistent<1>), pgrid, block, 0, s, t, g.pred, g.pred_val); break;
+    case 6: hipLaunchKernelGGL((k_gemm_mfma<3>), grid, block, 0, s, t, g.pred, g.pred_val); break;
+    case 7: hipLaunchKernelGGL((k_gemm_mfma2<8, 1, 3>), grid, block, 0, s, t, g.pred, g.pred_val); break;
     case 1: hipLaunchKernelGGL((k_gemm_mfma<1>), grid, block, 0, s, t, g.pred, g.pred_val); break;
     case 2: hipLaunchKernelGGL((k_gemm_mfma<2>), grid, block, 0, s, t, g.pred, g.pred_val); break;
     case 3: hipLaunchKernelGGL((k_gemm_mfma2<8, 1, 0>), grid, block, 0, s, t, g.pred, g.pred_val); break;
