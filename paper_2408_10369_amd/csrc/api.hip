@@ -2082,16 +2082,24 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return graphs[a].n > graphs[b].n; });
     BatchPlan plan{0, 0, 0, 0, 0, 0, 0, 0, 0};
     // Query answers: the plain schedule takes the paper's mapping of a partially grounded query to
-    // BMLP-SMP (a selection per query row); forced, all by selection or all off the closures; learned,
-    // per graph as the dispatcher model chooses on the device (answers off the closure -- which is
-    // computed anyway when it is an output -- or by selection; a graph whose closure is neither an
-    // output nor read is not squared at all).  Graphs beyond the selection kernel's size always read
-    // the closure.
+    // BMLP-SMP (a selection per query row); forced, all by selection or all off the closures; learned, a
+    // graph whose closure is an output reads its answers off it (the closure is computed anyway), and
+    // for the others the dispatcher model chooses on the device between the closure and selection (a
+    // graph whose closure is neither an output nor read is not squared at all).  Graphs beyond the
+    // selection kernel's size always read the closure.
     const bool forced_sel = o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO;
     need(!forced_sel || o.smp_arm != BMLP_ARM_SMP_CLOSURE_SELECT, BMLP_EINVAL,
          "the batched launch squares its closures (smp_arm %d is not available there)", o.smp_arm);
     const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
     plan.qmode = forced_sel ? (o.smp_arm == BMLP_ARM_SMP_CLOSURE ? 0 : 1) : learned ? 2 : 1;
+    if (plan.qmode == 2) {
+      // the model has a choice only for graphs with query rows, no closure output and a size the selection
+      // kernels take; without one, every graph reads its answers off its closure and the model is not run
+      bool choice = false;
+      for (int i = 0; i < count; ++i)
+        choice |= graphs[i].k > 0 && graphs[i].closure == nullptr && graphs[i].n <= batch_bfs_max_n();
+      if (!choice) plan.qmode = 0;
+    }
     size_t buf_words = 0;
     BatchPlan sizes{0, 0, 0, 0, 0, 0, 0, 0, 0};  // the totals the flag area depends on
     for (int i = 0; i < count; ++i) {
@@ -2138,6 +2146,8 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       G.mfma_tile_begin = plan.total_mfma_tiles;
       G.tblock_begin = plan.total_tblocks;
       G.mblock_begin = plan.total_mblocks;
+      G.sgroup_begin = plan.total_sgroups;
+      plan.total_sgroups += (std::max<int64_t>(d.n, d.k) + 63) / 64;
       const bool mfma = d.n >= batch_mfma_min_n();
       G.bt = mfma ? bufs + off : nullptr;
       G.mfma_rtiles = mfma ? (d.n + 255) / 256 : 0;
@@ -2147,7 +2157,7 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
         plan.total_tblocks += G.nw * G.nw;
         plan.total_mblocks += G.mfma_rtiles;
       }
-      plan.total_rows += std::max<int64_t>(d.n, d.k);
+      plan.total_rows += (std::max<int64_t>(d.n, d.k) + 7) / 8 * 8;  // groups of 8 rows never span two graphs
       plan.total_tiles += mfma ? 4 * G.mfma_rtiles : batch_tiles(d.n);  // 64-row tiles of an MFMA graph
       plan.total_select_tiles += d.k > 0 ? batch_select_tiles(d.k, d.n) : 0;
       plan.total_qrows += d.k;

@@ -12,7 +12,8 @@ struct BatchGraph {
   const u64* V; i64 k; i64 ldv;  // query rows (k may be 0)
   u64* Vstar;            // output V R1+
   u64* buf0; u64* buf1;  // ping-pong workspace, n x nw each
-  i64 row_begin;         // first row of this graph in the batch-wide row numbering (max(n, k) rows each)
+  i64 row_begin;         // first row of this graph in the batch-wide row numbering (max(n, k) rows each,
+                         // rounded up to a multiple of 8)
   i64 tile_begin;        // first product tile of this graph (tiles per round = batch_tiles(n))
   i64 rtiles;            // row tiles of the graph
   i64 smp_tile_begin;    // first selection tile of this graph
@@ -24,6 +25,7 @@ struct BatchGraph {
   i64 mfma_tile_begin;   // first matrix-core tile of this graph (mfma_rtiles^2 per round)
   i64 tblock_begin;      // first 64 x 64 transpose block of this graph (nw^2 per round)
   i64 mblock_begin;      // first 256-row block of this graph (mfma_rtiles)
+  i64 sgroup_begin;      // first 64-row group of this graph's statistics pass (max(n, k) rows)
 };
 
 struct BatchPlan {
@@ -39,6 +41,7 @@ struct BatchPlan {
   i64 ms_max_n;          // largest n of the graphs with query rows whose selection runs 64 rows at a time
                          // (n <= batch_ms_max_n(); 0: none)
   i64 ms_qrows;          // query rows of those graphs
+  i64 total_sgroups;     // 64-row groups of the statistics pass, over all graphs
 };
 
 // largest n whose query rows the batch selects 64 at a time (masks per node in LDS)

@@ -65,20 +65,29 @@ __global__ void k_batch_setup(BatchGraph* __restrict__ gs, int count, i64 total_
   const i64 tid = blockIdx.x * (i64)blockDim.x + threadIdx.x;
   const i64 nth = (i64)gridDim.x * blockDim.x;
   for (i64 i = tid; i < nflags; i += nth) flags[i] = 0u;
-  // one thread per (graph row, word): rows are numbered across graphs by row_begin
-  for (i64 rr = tid / 64; rr < total_rows; rr += nth / 64) {
+  // rows are numbered across graphs by row_begin, each graph's rows padded to a multiple of 8, so a group
+  // of 8 rows lies in one graph: a wave takes a group (one search for its graph), lanes the words, all
+  // eight rows' loads in flight
+  const int lane = threadIdx.x & 63;
+  const i64 wave = tid >> 6, nwaves = nth >> 6;
+  for (i64 grp = wave; grp < total_rows / 8; grp += nwaves) {
+    const i64 rr = grp * 8;
     int lo = 0, hi = count - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (gs[mid].row_begin <= rr) lo = mid; else hi = mid - 1;
     }
     const BatchGraph& G = gs[lo];
-    const i64 row = rr - G.row_begin;
-    if (row >= G.n) continue;
-    for (i64 w = tid & 63; w < G.nw; w += 64) {
-      u64 x = G.R1[row * G.ld + w];
-      if (w == G.nw - 1 && (G.n & 63)) x &= (1ull << (G.n & 63)) - 1ull;
-      G.buf0[row * G.nw + w] = x;
+    const i64 row0 = rr - G.row_begin;
+    if (row0 >= G.n) continue;
+    const u64 lm = (G.n & 63) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
+    for (i64 w = lane; w < G.nw; w += 64) {
+      u64 x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = row0 + r < G.n ? G.R1[(row0 + r) * G.ld + w] : 0ull;
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        if (row0 + r < G.n) G.buf0[(row0 + r) * G.nw + w] = w == G.nw - 1 ? x[r] & lm : x[r];
     }
   }
 }
@@ -96,20 +105,29 @@ __global__ void k_batch_modes(const BatchGraph* __restrict__ gs, int count, int 
 }
 
 // Statistics of each graph for the dispatcher's features: set bits of R1, its largest row count, its
-// nonempty rows, and the set bits of its query rows.  One workgroup of eight waves per graph; a wave takes
-// eight rows at a time with all their loads in flight (lanes over the words of a row); the sums stay in
-// registers and LDS, and gst (4 u64 per graph) is written once per graph, with no atomics.
+// nonempty rows, and the set bits of its query rows.  One wave per group of 64 rows of a graph (max(n, k)
+// rows, groups numbered batch-wide from sgroup_begin), eight rows at a time with all their loads in flight
+// (lanes over the words of a row); four atomics per wave into gst (4 u64 per graph, zeroed by the setup
+// kernel), so a large graph's rows spread over many waves.
 constexpr int kStatsRows = 8;
-__global__ void __launch_bounds__(512)
-k_batch_stats(const BatchGraph* __restrict__ gs, int count, unsigned long long* __restrict__ gst) {
-  __shared__ unsigned long long part[8][4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (i64 g = blockIdx.x; g < count; g += gridDim.x) {
-    const BatchGraph& G = gs[g];
+__global__ void __launch_bounds__(256)
+k_batch_stats(const BatchGraph* __restrict__ gs, int count, i64 total_groups, unsigned long long* __restrict__ gst) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 grp = wave; grp < total_groups; grp += nwaves) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (gs[mid].sgroup_begin <= grp) lo = mid; else hi = mid - 1;
+    }
+    const BatchGraph& G = gs[lo];
     const u64 lm = (G.n & 63) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
-    unsigned long long bits = 0, mx = 0, nonempty = 0, vbits = 0;  // wave-uniform after the reductions
     const i64 rows = G.n > G.k ? G.n : G.k;
-    for (i64 row0 = (i64)wave * kStatsRows; row0 < rows; row0 += 8 * kStatsRows) {
+    const i64 first = (grp - G.sgroup_begin) * 64;
+    const i64 last = first + 64 < rows ? first + 64 : rows;
+    unsigned long long bits = 0, mx = 0, nonempty = 0, vbits = 0;  // wave-uniform after the reductions
+    for (i64 row0 = first; row0 < last; row0 += kStatsRows) {
       u32 pr[kStatsRows], pv[kStatsRows];
 #pragma unroll
       for (int r = 0; r < kStatsRows; ++r) pr[r] = pv[r] = 0u;
@@ -119,8 +137,8 @@ k_batch_stats(const BatchGraph* __restrict__ gs, int count, unsigned long long* 
 #pragma unroll
         for (int r = 0; r < kStatsRows; ++r) {
           const i64 row = row0 + r;
-          xr[r] = row < G.n ? G.R1[row * G.ld + w] : 0ull;
-          xv[r] = row < G.k ? G.V[row * G.ldv + w] : 0ull;
+          xr[r] = row < last && row < G.n ? G.R1[row * G.ld + w] : 0ull;
+          xv[r] = row < last && row < G.k ? G.V[row * G.ldv + w] : 0ull;
         }
 #pragma unroll
         for (int r = 0; r < kStatsRows; ++r) {
@@ -142,19 +160,14 @@ k_batch_stats(const BatchGraph* __restrict__ gs, int count, unsigned long long* 
       }
     }
     if (lane == 0) {
-      part[wave][0] = bits;
-      part[wave][1] = mx;
-      part[wave][2] = nonempty;
-      part[wave][3] = vbits;
+      unsigned long long* st = gst + 4 * (i64)lo;
+      if (bits) {
+        atomicAdd(&st[0], bits);
+        atomicMax(&st[1], mx);
+        atomicAdd(&st[2], nonempty);
+      }
+      if (vbits) atomicAdd(&st[3], vbits);
     }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-      const int q = threadIdx.x;
-      unsigned long long v = part[0][q];
-      for (int w = 1; w < 8; ++w) v = q == 1 ? (part[w][q] > v ? part[w][q] : v) : v + part[w][q];
-      gst[4 * g + q] = v;
-    }
-    __syncthreads();
   }
 }
 
@@ -177,7 +190,10 @@ __global__ void k_batch_choose(const BatchGraph* __restrict__ gs, int count, i64
   const i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x;
   if (g >= count) return;
   const BatchGraph& G = gs[g];
-  const bool can_select = G.k > 0 && G.nw <= bfs_words;
+  // a closure that is an output is computed anyway, and reading the answers off it (the closure rows of
+  // each query row's sources) costs less than expanding them by selection: the model is asked only where
+  // the closure would be computed for the queries alone
+  const bool can_select = G.k > 0 && G.nw <= bfs_words && !G.closure_req;
   const u32 sel = (can_select && Y[kOut * g + 3] < Y[kOut * g + 2]) ? 1u : 0u;  // ties keep the closure
   qsel[g] = sel;
   need[g] = (G.closure_req || (G.k > 0 && !sel)) ? 1u : 0u;
@@ -608,21 +624,33 @@ __global__ void k_batch_copy(const BatchGraph* __restrict__ gs, int count, i64 t
                              const u32* __restrict__ changed) {
   const i64 tid = blockIdx.x * (i64)blockDim.x + threadIdx.x;
   const i64 nth = (i64)gridDim.x * blockDim.x;
-  for (i64 rr = tid / 64; rr < total_rows; rr += nth / 64) {
+  const int lane = threadIdx.x & 63;
+  const i64 wave = tid >> 6, nwaves = nth >> 6;
+  // groups of 8 rows of one graph, as in k_batch_setup
+  for (i64 grp = wave; grp < total_rows / 8; grp += nwaves) {
+    const i64 rr = grp * 8;
     int lo = 0, hi = count - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (gs[mid].row_begin <= rr) lo = mid; else hi = mid - 1;
     }
     const BatchGraph& G = gs[lo];
-    const i64 row = rr - G.row_begin;
-    if (G.closure && row < G.n) {
+    const i64 row0 = rr - G.row_begin;
+    if (G.closure && row0 < G.n) {
       const int fr = final_round(changed, lo, rounds);
       const u64* clo = ((fr + 1) & 1) ? G.buf1 : G.buf0;
-      for (i64 w = tid & 63; w < G.ldc; w += 64) G.closure[row * G.ldc + w] = (w < G.nw) ? clo[row * G.nw + w] : 0ull;
+      for (i64 w = lane; w < G.ldc; w += 64) {
+        u64 x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[r] = (row0 + r < G.n && w < G.nw) ? clo[(row0 + r) * G.nw + w] : 0ull;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          if (row0 + r < G.n) G.closure[(row0 + r) * G.ldc + w] = x[r];
+      }
     }
-    if (row < G.k)
-      for (i64 w = G.nw + (tid & 63); w < G.ldv; w += 64) G.Vstar[row * G.ldv + w] = 0ull;
+    for (int r = 0; r < 8; ++r)
+      if (row0 + r < G.k)
+        for (i64 w = G.nw + lane; w < G.ldv; w += 64) G.Vstar[(row0 + r) * G.ldv + w] = 0ull;
   }
 }
 
@@ -677,7 +705,7 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
   float* X = (float*)(gst + 4 * (i64)count);
   float* Y = X + (i64)kIn * count;
   const i64 nflags = batch_flag_words(count, p);
-  hipLaunchKernelGGL(k_batch_setup, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
+  hipLaunchKernelGGL(k_batch_setup, dim3(grid_cap((p.total_rows / 8 * 64 + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
                      count, p.total_rows, flags, nflags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -687,8 +715,8 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (p.qmode == 2 && model) {
     // the dispatcher's choice per graph, on the device: statistics, features, the network, the argmin
-    hipLaunchKernelGGL(k_batch_stats, dim3((unsigned)count), dim3(512), 0, s, (const BatchGraph*)d_graphs, count,
-                       gst);
+    hipLaunchKernelGGL(k_batch_stats, dim3(grid_cap((p.total_sgroups * 64 + 255) / 256, 8192)), dim3(256), 0, s,
+                       (const BatchGraph*)d_graphs, count, p.total_sgroups, gst);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_features, dim3(ggrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count,
                        (const unsigned long long*)gst, X);
@@ -749,7 +777,7 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_batch_copy, dim3(grid_cap((p.total_rows * 64 + 255) / 256, 8192)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_batch_copy, dim3(grid_cap((p.total_rows / 8 * 64 + 255) / 256, 8192)), dim3(256), 0, s,
                      (const BatchGraph*)d_graphs, count, p.total_rows, p.rounds, (const u32*)changed);
   return hipGetLastError();
 }

@@ -143,6 +143,9 @@ def test_batched_512_graph_workload(ctx, mode):
     ctx.batched(graphs, opts=mode_opts(mode), stats=st)
     check(graphs, refs)
     assert st["iterations"] <= 14
+    if mode == "learned":
+        # every closure is an output, so every graph reads its answers off it
+        assert st["arm_trace"][0] == len(bg) and st["arm_trace"][1] == 0, st["arm_trace"][:2]
 
 
 @pytest.mark.parametrize("mode", list(MODES) + ["selection"])
