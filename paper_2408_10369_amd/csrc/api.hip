@@ -1972,27 +1972,52 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
       //        transposed step relation (n query rows);
       //  (iii) rows: P[X] = Rb[X] | OR of Rb[Z] over Z in e_X . Rs+, a strict selection from each
       //        row X that has a step edge, then the rows of Rb gathered; other rows are Rb's.
-      const GraphInfo gs = graph_info(h, Rstep, ld, n, s);
+      GraphInfo gs;
+      gs.n = n;
       const bool learned = o.dispatch == BMLP_DISPATCH_LEARNED && h->model && !forced;
       const bool rowwise_ok = n <= gather_rows_max_n();
       int sarm = (o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO) ? o.smp_arm : BMLP_ARM_AUTO;
       if (learned || h->trace) {
-        const double delta0 = (double)count_bits(h, Rbase, n, n, ld, s);
-        float f[kIn];
-        make_features(f, gs, n, 1, 1, 0, delta0, delta0, delta0, 1);
-        if (h->trace) std::memcpy(h->trace->call_features, f, sizeof f);
+        // the step relation's statistics, the base relation's bits, the features and the model's choice are
+        // computed on the device one after another and read back together: one host wait for the call
+        // (outputs: 0 columns by adaptive rounds, 1 rows, 2 closure, 3 columns by the one-launch kernel)
+        u32 allowed = 0x5u;
+        if (rowwise_ok) allowed |= 0x2u;
+        if (n <= smp_rows_max_n()) allowed |= 0x8u;
+        unsigned long long* gst = (unsigned long long*)(h->d_flags + F_GSTATS);
+        unsigned long long* cnt = (unsigned long long*)(h->d_flags + F_CNT);
+        float* feat = (float*)(h->d_flags + F_FEAT);
+        hip_check(hipMemsetAsync(gst, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
+        hip_check(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+        hip_check(launch_graph_stats(Rstep, n, n, ld, gst, s), "graph_stats");
+        hip_check(launch_popcount_total(Rbase, n, n, ld, cnt, s), "popcount_total");
+        hip_check(launch_call_features(gst, cnt, n, n, 1.f, 1, feat, s), "call_features");
+        if (learned)
+          hip_check(launch_mlp_decide(h->d_model, h->d_model + kParams, h->d_model + kParams + kIn, feat,
+                                      (float*)(h->d_flags + F_PRED), h->d_flags + F_DEC, allowed, s),
+                    "mlp_decide");
+        // words F_CNT .. F_GSTATS + 6: the bit count, the decision, the predictions, the features, the stats
+        hip_check(hipMemcpyAsync(h->h_flags + F_CNT, h->d_flags + F_CNT, (F_GSTATS + 6 - F_CNT) * sizeof(u32),
+                                 hipMemcpyDeviceToHost, s),
+                  "memcpy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        unsigned long long v[3];
+        std::memcpy(v, h->h_flags + F_GSTATS, sizeof v);
+        gs.m = (i64)v[0];
+        gs.maxdeg = (i64)v[1];
+        gs.nonempty = (i64)v[2];
+        if (h->trace) std::memcpy(h->trace->call_features, h->h_flags + F_FEAT, kIn * sizeof(float));
         if (learned) {
-          // outputs: 0 columns by adaptive rounds, 1 rows, 2 closure, 3 columns by the one-launch kernel
-          u32 allowed = 0x5u;
-          if (rowwise_ok) allowed |= 0x2u;
-          if (n <= smp_rows_max_n()) allowed |= 0x8u;
           float pred[4];
-          const int d = model_decide(h, f, allowed, s, pred);
+          std::memcpy(pred, h->h_flags + F_PRED, sizeof pred);
+          const int d = (int)h->h_flags[F_DEC];
           if (h->trace) std::memcpy(h->trace->call_pred, pred, sizeof pred);
           arm = d == 1 ? BMLP_ARM_COMPOSE_ROWWISE : d == 2 ? BMLP_ARM_COMPOSE_RMS : BMLP_ARM_COMPOSE_SEMINAIVE;
           if (d == 0) sarm = BMLP_ARM_SMP_ADAPTIVE;
           if (d == 3) sarm = BMLP_ARM_SMP_SPARSE;
         }
+      } else {
+        gs = graph_info(h, Rstep, ld, n, s);
       }
       if (arm == BMLP_ARM_COMPOSE_SEMINAIVE) {
         u64* rbt = ws_bits(h, S_T0, n, nw, o);

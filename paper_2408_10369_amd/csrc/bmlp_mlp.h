@@ -17,6 +17,10 @@ hipError_t launch_mlp_backward(const float* P, const float* mu, const float* sd,
 // one sample: pred (4) = MLP(feat); *decision = argmin of pred over the outputs set in `allowed`
 hipError_t launch_mlp_decide(const float* P, const float* mu, const float* sd, const float* feat, float* pred,
                              u32* decision, u32 allowed, hipStream_t s);
+// The call-level features (features.h) of a request from device counts: gstats = (bits, largest row, nonempty
+// rows) of the relation, *delta0 = the set bits of the query rows; one thread writes f[16].
+hipError_t launch_call_features(const unsigned long long* gstats, const unsigned long long* delta0, i64 n, i64 k,
+                                float context, int reflexive, float* f, hipStream_t s);
 hipError_t launch_adam(float* P, const float* G, float* M1, float* M2, float lr, float beta1, float beta2, float eps,
                        int step, hipStream_t s);
 

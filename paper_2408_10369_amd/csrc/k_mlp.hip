@@ -13,6 +13,7 @@
 // the Adam step.
 #include "bmlp_internal.h"
 #include "bmlp_mlp.h"
+#include "features.h"
 
 namespace bmlp {
 
@@ -179,6 +180,15 @@ __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float
   P[p] -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
 }
 
+__global__ void k_call_features(const unsigned long long* __restrict__ gstats,
+                                const unsigned long long* __restrict__ delta0, i64 n, i64 k, float context,
+                                int reflexive, float* __restrict__ f) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double d0 = (double)*delta0;
+  make_features(f, (double)n, (double)gstats[0], (double)gstats[1], (double)gstats[2], (double)k, context, 1, 0, d0,
+                d0, reflexive ? d0 : 0.0, reflexive);
+}
+
 }  // namespace
 
 hipError_t launch_mlp_forward(const float* P, const float* mu, const float* sd, const float* X, i64 rows, float* H1,
@@ -204,6 +214,12 @@ hipError_t launch_mlp_backward(const float* P, const float* mu, const float* sd,
 hipError_t launch_mlp_decide(const float* P, const float* mu, const float* sd, const float* feat, float* pred,
                              u32* decision, u32 allowed, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_decide, dim3(1), dim3(64), 0, s, P, mu, sd, feat, pred, decision, allowed);
+  return hipGetLastError();
+}
+
+hipError_t launch_call_features(const unsigned long long* gstats, const unsigned long long* delta0, i64 n, i64 k,
+                                float context, int reflexive, float* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_call_features, dim3(1), dim3(64), 0, s, gstats, delta0, n, k, context, reflexive, f);
   return hipGetLastError();
 }
 
