@@ -1048,6 +1048,43 @@ int smp_choose_arm(bmlp_ctx* c, const bmlp_opts& o, const GraphInfo& gi, i64 k, 
   return smp_plain_arm(gi.n, k, gi.m);
 }
 
+// The call-level inputs of a dispatcher choice, computed on the device and read back together (one host
+// wait): the statistics of R (n x n), the set bits of the query rows Q (qrows x n), the 16 features
+// (features.h) and, with allowed != 0, the model's decision among the allowed outputs.  Returns the
+// decision, or -1 when the model is not asked.
+int call_stats_decide(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const u64* Q, i64 qrows, i64 ldq, i64 k,
+                      float context, int reflexive, u32 allowed, hipStream_t s, GraphInfo* gi, double* delta0) {
+  unsigned long long* gst = (unsigned long long*)(c->d_flags + F_GSTATS);
+  unsigned long long* cnt = (unsigned long long*)(c->d_flags + F_CNT);
+  float* feat = (float*)(c->d_flags + F_FEAT);
+  hip_check(hipMemsetAsync(gst, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
+  hip_check(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+  hip_check(launch_graph_stats(R, n, n, ld, gst, s), "graph_stats");
+  hip_check(launch_popcount_total(Q, qrows, n, ldq, cnt, s), "popcount_total");
+  hip_check(launch_call_features(gst, cnt, n, k, context, reflexive, feat, s), "call_features");
+  if (allowed)
+    hip_check(launch_mlp_decide(c->d_model, c->d_model + kParams, c->d_model + kParams + kIn, feat,
+                                (float*)(c->d_flags + F_PRED), c->d_flags + F_DEC, allowed, s),
+              "mlp_decide");
+  // words F_CNT .. F_GSTATS + 6: the bit count, the decision, the predictions, the features, the statistics
+  hip_check(hipMemcpyAsync(c->h_flags + F_CNT, c->d_flags + F_CNT, (F_GSTATS + 6 - F_CNT) * sizeof(u32),
+                           hipMemcpyDeviceToHost, s),
+            "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");
+  unsigned long long v[3], d0 = 0;
+  std::memcpy(v, c->h_flags + F_GSTATS, sizeof v);
+  std::memcpy(&d0, c->h_flags + F_CNT, sizeof d0);
+  gi->n = n;
+  gi->m = (i64)v[0];
+  gi->maxdeg = (i64)v[1];
+  gi->nonempty = (i64)v[2];
+  *delta0 = (double)d0;
+  if (c->trace) std::memcpy(c->trace->call_features, c->h_flags + F_FEAT, kIn * sizeof(float));
+  if (!allowed) return -1;
+  if (c->trace) std::memcpy(c->trace->call_pred, c->h_flags + F_PRED, 4 * sizeof(float));
+  return (int)c->h_flags[F_DEC];
+}
+
 template <class F>
 bmlp_status guarded(F&& f) {
   try {
@@ -1702,11 +1739,23 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, c
       if (n == 0) {
         hip_check(launch_fill_zero(Vstar, k * ldv, s), "fill_zero");
       } else {
-        const GraphInfo gi = graph_info(h, R1, ld, n, s);
         // the source count is a feature of the model's call-level choice (and of the trace) only
         const bool model_call = !forced && o.dispatch == BMLP_DISPATCH_LEARNED && h->model;
-        const double delta0 = (model_call || h->trace) ? (double)count_bits(h, V, k, n, ldv, s) : 0.0;
-        arm = smp_choose_arm(h, o, gi, k, 0, refl, delta0, s, nullptr);
+        GraphInfo gi;
+        if (model_call || h->trace) {
+          // the statistics, the source bits, the features and the model's choice in one device pass
+          u32 allowed = 0x5u;  // rounds, closure
+          if (n <= smp_rows_max_n()) allowed |= 0x8u;  // one-launch sparse
+          double delta0 = 0.0;
+          const int d = call_stats_decide(h, R1, ld, n, V, k, ldv, k, 0.f, refl, model_call ? allowed : 0u, s, &gi,
+                                          &delta0);
+          if (forced) arm = o.smp_arm;
+          else if (model_call) arm = d == 2 ? BMLP_ARM_SMP_CLOSURE : d == 3 ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_ADAPTIVE;
+          else arm = smp_plain_arm(gi.n, k, gi.m);
+        } else {
+          gi = graph_info(h, R1, ld, n, s);
+          arm = smp_choose_arm(h, o, gi, k, 0, refl, 0.0, s, nullptr);
+        }
         smp_core(h, R1, ld, n, V, Vstar, k, ldv, refl, arm, gi, 0, Csr{}, o, s, sr);
       }
     }
@@ -1978,40 +2027,14 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
       const bool rowwise_ok = n <= gather_rows_max_n();
       int sarm = (o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm != BMLP_ARM_AUTO) ? o.smp_arm : BMLP_ARM_AUTO;
       if (learned || h->trace) {
-        // the step relation's statistics, the base relation's bits, the features and the model's choice are
-        // computed on the device one after another and read back together: one host wait for the call
-        // (outputs: 0 columns by adaptive rounds, 1 rows, 2 closure, 3 columns by the one-launch kernel)
+        // outputs: 0 columns by adaptive rounds, 1 rows, 2 closure, 3 columns by the one-launch kernel
         u32 allowed = 0x5u;
         if (rowwise_ok) allowed |= 0x2u;
         if (n <= smp_rows_max_n()) allowed |= 0x8u;
-        unsigned long long* gst = (unsigned long long*)(h->d_flags + F_GSTATS);
-        unsigned long long* cnt = (unsigned long long*)(h->d_flags + F_CNT);
-        float* feat = (float*)(h->d_flags + F_FEAT);
-        hip_check(hipMemsetAsync(gst, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
-        hip_check(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
-        hip_check(launch_graph_stats(Rstep, n, n, ld, gst, s), "graph_stats");
-        hip_check(launch_popcount_total(Rbase, n, n, ld, cnt, s), "popcount_total");
-        hip_check(launch_call_features(gst, cnt, n, n, 1.f, 1, feat, s), "call_features");
-        if (learned)
-          hip_check(launch_mlp_decide(h->d_model, h->d_model + kParams, h->d_model + kParams + kIn, feat,
-                                      (float*)(h->d_flags + F_PRED), h->d_flags + F_DEC, allowed, s),
-                    "mlp_decide");
-        // words F_CNT .. F_GSTATS + 6: the bit count, the decision, the predictions, the features, the stats
-        hip_check(hipMemcpyAsync(h->h_flags + F_CNT, h->d_flags + F_CNT, (F_GSTATS + 6 - F_CNT) * sizeof(u32),
-                                 hipMemcpyDeviceToHost, s),
-                  "memcpy");
-        hip_check(hipStreamSynchronize(s), "sync");
-        unsigned long long v[3];
-        std::memcpy(v, h->h_flags + F_GSTATS, sizeof v);
-        gs.m = (i64)v[0];
-        gs.maxdeg = (i64)v[1];
-        gs.nonempty = (i64)v[2];
-        if (h->trace) std::memcpy(h->trace->call_features, h->h_flags + F_FEAT, kIn * sizeof(float));
+        double delta0 = 0.0;
+        const int d = call_stats_decide(h, Rstep, ld, n, Rbase, n, ld, n, 1.f, 1, learned ? allowed : 0u, s, &gs,
+                                        &delta0);
         if (learned) {
-          float pred[4];
-          std::memcpy(pred, h->h_flags + F_PRED, sizeof pred);
-          const int d = (int)h->h_flags[F_DEC];
-          if (h->trace) std::memcpy(h->trace->call_pred, pred, sizeof pred);
           arm = d == 1 ? BMLP_ARM_COMPOSE_ROWWISE : d == 2 ? BMLP_ARM_COMPOSE_RMS : BMLP_ARM_COMPOSE_SEMINAIVE;
           if (d == 0) sarm = BMLP_ARM_SMP_ADAPTIVE;
           if (d == 3) sarm = BMLP_ARM_SMP_SPARSE;
