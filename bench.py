@@ -129,6 +129,7 @@ def main():
     # the matrix-core launches of each graph's closure, for the spread of the per-launch rates
     spread = [{"ms": 0.0, "ops": 0, "launches": 0, "issued": 0} for _ in range(len(graphs))]
     smp_rec = {"ms": 0.0, "rows": 0}
+    gather_rec = {"ms": 0.0, "bytes": 0, "launches": 0}
 
     def add_spread(gi, st):
         sp = spread[gi]
@@ -176,6 +177,9 @@ def main():
                 smp_rec["rows"] += k
             add_products(st)
             add_spread(gi, st)
+            gather_rec["ms"] += st["gather_ms"]
+            gather_rec["bytes"] += st["gather_bytes"]
+            gather_rec["launches"] += st["gathers"]
             if len(per_graph) < len(graphs):
                 per_graph.append({"p": g["p"], "edges": g["m"], "rms_squarings": st["iterations"],
                                   "rms_squarings_by_gather": st["arm_trace"].count(B.ARM_PRODUCT_GATHER),
@@ -242,6 +246,18 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(graphs, n, args.cpu_sample_rows)
 
+    # the RMS squarings done by row gathers (k_gather_rows_w, with k_gather_rows_q for the queued pieces of
+    # heavy rows) against the HBM roofline: per squaring of an R with b set bits, the n rows of R and the b
+    # source rows read and the n result rows written, n / 8 bytes each, over the squaring's HIP-event time
+    gather_hbm = None
+    if gather_rec["launches"] and gather_rec["ms"] > 0:
+        gbs = gather_rec["bytes"] / (gather_rec["ms"] / 1e3) / 1e9
+        gather_hbm = {"bound": "hbm", "kernel": "k_gather_rows_w + k_gather_rows_q (RMS squarings of a sparse R)",
+                      "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                      "launches_per_step": gather_rec["launches"] // isteps,
+                      "avg_launch_ms": round(gather_rec["ms"] / gather_rec["launches"], 4),
+                      "bytes_per_launch": round(gather_rec["bytes"] / gather_rec["launches"]),
+                      "bytes": "per squaring of an R with b set bits: (2n + b) rows of n/8 bytes"}
     # the selections' data movement against the HBM roofline: query rows read and answer rows written
     # (n / 8 bytes each; the edge index and the relation's rows read on the way are not counted)
     smp_bytes = 2 * smp_rec["rows"] * (n // 8)
@@ -263,7 +279,8 @@ def main():
         "config": {"workload": "ER digraph density sweep n=16384, p in {1e-4,5e-4,1e-3,5e-3,1e-2}: "
                                "pack + BMLP-RMS closure + BMLP-SMP from k=1,64,1024 sources per graph",
                    "n": n, "graphs": len(graphs), "query_rows_per_step": rows_per_step},
-        "roofline": roofline, "cpu_baseline": cpu, "smp_hbm": smp_hbm, "per_graph": per_graph,
+        "roofline": roofline, "gather_hbm": gather_hbm, "cpu_baseline": cpu, "smp_hbm": smp_hbm,
+        "per_graph": per_graph,
     }
     wl = [w for w in args.workloads.split(",") if w]
     if wl:

@@ -136,6 +136,10 @@ typedef struct {
   uint64_t mfma_ops_issued;  /* matrix-core operations those launches actually issued: less than their
                                 Boolean operations when output tiles are already saturated or words of k
                                 are zero across a row block, more on ragged tile edges */
+  int32_t gathers;           /* BMLP-RMS squarings done by row gathers (events around each) */
+  double gather_ms;          /* device time of those squarings */
+  uint64_t gather_bytes;     /* their algorithmic bytes: per squaring of an R with b set bits, the n rows of R
+                                read, the b source rows read and the n rows written, n / 8 bytes each */
 } bmlp_stats;
 
 /* ------------------------------------------------------------ handles */

@@ -87,7 +87,8 @@ class Stats(ctypes.Structure):
                 ("arm", ctypes.c_int32), ("products_mfma", ctypes.c_int32), ("bool_ops", ctypes.c_uint64),
                 ("bytes_moved", ctypes.c_uint64), ("device_ms", ctypes.c_double), ("product_ms", ctypes.c_double),
                 ("product_bool_ops", ctypes.c_uint64), ("product_ms_mfma", ctypes.c_double),
-                ("product_bool_ops_mfma", ctypes.c_uint64), ("mfma_ops_issued", ctypes.c_uint64)]
+                ("product_bool_ops_mfma", ctypes.c_uint64), ("mfma_ops_issued", ctypes.c_uint64),
+                ("gathers", ctypes.c_int32), ("gather_ms", ctypes.c_double), ("gather_bytes", ctypes.c_uint64)]
 
     def as_dict(self):
         tr = [int(a) for a in self.arm_trace if a != -1]
@@ -97,7 +98,8 @@ class Stats(ctypes.Structure):
                 "product_bool_ops": int(self.product_bool_ops), "products_mfma": int(self.products_mfma),
                 "product_ms_mfma": float(self.product_ms_mfma),
                 "product_bool_ops_mfma": int(self.product_bool_ops_mfma),
-                "mfma_ops_issued": int(self.mfma_ops_issued)}
+                "mfma_ops_issued": int(self.mfma_ops_issued), "gathers": int(self.gathers),
+                "gather_ms": float(self.gather_ms), "gather_bytes": int(self.gather_bytes)}
 
 
 class BmlpError(RuntimeError):

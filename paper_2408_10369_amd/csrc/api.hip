@@ -275,6 +275,9 @@ struct StatsRec {
   struct Pending {
     i64 m, k, n;
     int arm;
+    int kind;   // 0 a product, 1 a squaring by row gathers
+    i64 bytes;  // a gather squaring's algorithmic bytes (-1 until known)
+    bool valid; // false once cancelled: it was enqueued ahead and its predicate was off
   };
   Pending pend[bmlp_ctx::kPend];
   int npend = 0;
@@ -306,13 +309,32 @@ struct StatsRec {
   void product(i64 m, i64 k, i64 n, int arm) {
     if (!st) return;
     hip_check(hipEventRecord(c->pe1[npend], s), "hipEventRecord");
-    pend[npend++] = Pending{m, k, n, arm};
+    pend[npend++] = Pending{m, k, n, arm, 0, 0, true};
+  }
+  // A squaring by row gathers, timed like a product.  gather_begin keeps room for it and the dense product
+  // enqueued beside it, so that both are still pending when the route is read back.  Returns its index
+  // (-1 without statistics).
+  int gather_begin() {
+    if (!st) return -1;
+    if (npend + 2 > bmlp_ctx::kPend) flush();
+    product_begin();
+    return npend;
+  }
+  void gather_end(int idx, i64 bytes) {
+    if (!st || idx < 0) return;
+    hip_check(hipEventRecord(c->pe1[npend], s), "hipEventRecord");
+    pend[npend++] = Pending{0, 0, 0, BMLP_ARM_PRODUCT_GATHER, 1, bytes, true};
+  }
+  void set_bytes(int idx, i64 bytes) {
+    if (st && idx >= 0 && idx < npend) pend[idx].bytes = bytes;
+  }
+  void cancel(int idx) {
+    if (st && idx >= 0 && idx < npend) pend[idx].valid = false;
   }
   // forget the last timed product: it was enqueued ahead under a device-side condition that did not hold,
-  // so it ran no work (its events and counter are reused by the next product).  Batches are read back
-  // before the next product, so the last one is always still pending.
+  // so it ran no work.  Batches are read back before the next timed launch, so it is still pending.
   void cancel_last() {
-    if (st && npend > 0) --npend;
+    if (st && npend > 0) pend[npend - 1].valid = false;
   }
   void flush() {
     if (!st || npend == 0) return;
@@ -321,9 +343,17 @@ struct StatsRec {
               "hipMemcpyAsync");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     for (int i = 0; i < npend; ++i) {
+      const Pending& p = pend[i];
+      if (!p.valid) continue;
       float ms = 0.f;
       hip_check(hipEventElapsedTime(&ms, c->pe0[i], c->pe1[i]), "hipEventElapsedTime");
-      const Pending& p = pend[i];
+      if (p.kind == 1) {
+        if (p.bytes < 0) continue;
+        st->gathers += 1;
+        st->gather_ms += ms;
+        st->gather_bytes += (uint64_t)p.bytes;
+        continue;
+      }
       const uint64_t ops = (uint64_t)2 * (uint64_t)p.m * (uint64_t)p.k * (uint64_t)p.n;
       st->products += 1;
       st->bool_ops += ops;
@@ -467,6 +497,10 @@ struct GraphInfo {
   i64 n = 0, m = 0, maxdeg = 0, nonempty = 0;
 };
 
+// Algorithmic bytes of a squaring of an n x n R with `bits` set bits by row gathers: the n rows of R read as
+// query rows, one source row read per set bit, the n rows of the result written (n / 8 bytes a row).
+i64 gather_bytes(i64 n, i64 bits) { return (2 * n + bits) * ((n + 7) / 8); }
+
 GraphInfo graph_info(bmlp_ctx* c, const u64* R, i64 ld, i64 n, hipStream_t s) {
   GraphInfo g;
   g.n = n;
@@ -582,6 +616,7 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   const bool mfma = arm == BMLP_ARM_PRODUCT_MFMA;
   int it = 0;
   u32 queued = RR_HOST;  // route of squaring `it` when it was enqueued ahead (gathers or dense), else RR_HOST
+  int ahead_gather = -1; // the timing entry of the gathers enqueued ahead, until their route is known
   for (;;) {
     unsigned long long* nb = rec_nb(it);
     int tarm = arm;
@@ -620,7 +655,9 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
       }
       if (gather) {
         const GatherQueue q = sized(gq, bits, n);
+        const int gi = sr.gather_begin();
         hip_check(launch_gather_rows(cur, ldi, n, cur, ldi, n, 1, nxt, ldi, s, nullptr, nb, &q), "gather_rows");
+        sr.gather_end(gi, gather_bytes(n, bits));
         if (sr.st) sr.st->bool_ops += (uint64_t)2 * (uint64_t)n * (uint64_t)n * (uint64_t)n;
         tarm = BMLP_ARM_PRODUCT_GATHER;
       } else if (semi == 1) {
@@ -685,8 +722,10 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
       unsigned long long* nb2 = rec_nb(it);
       if (may_gather) {
         const GatherQueue q = sized(gq, bits, n);
+        ahead_gather = sr.gather_begin();
         hip_check(launch_gather_rows(nxt, ldi, n, nxt, ldi, n, 1, cur, ldi, s, nullptr, nb2, &q, route, RR_GATHER),
                   "gather_rows");
+        sr.gather_end(ahead_gather, -1);  // its bytes are known once this squaring's count is read back
       }
       // the bit count of R_it is not known on the host yet: a squaring that falls to the dense product
       // counts as dense for the tuned tile code (sparser ones go to the gathers)
@@ -712,6 +751,12 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
     std::swap(cur, nxt);
     queued = ahead ? c->h_flags[F_CHAIN + (i64)it * kRmsRecWords + 4] : (u32)RR_HOST;
     if (ahead && queued != RR_DENSE) sr.cancel_last();  // the product enqueued ahead did not run
+    if (ahead_gather >= 0) {
+      // the gathers enqueued ahead square R_it, whose bit count is now known
+      if (queued == RR_GATHER) sr.set_bytes(ahead_gather, gather_bytes(n, bits));
+      else sr.cancel(ahead_gather);
+      ahead_gather = -1;
+    }
     if (!changed) break;
     need(queued != RR_STOP, BMLP_EDEVICE, "RMS: the device saw no new bits");
     if (ahead && queued != RR_GATHER) may_gather = false;  // the device found that gathers no longer pay

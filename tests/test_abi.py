@@ -43,7 +43,8 @@ def test_opts_defaults_and_struct_sizes(L):
     o = P.make_opts()
     assert o.size == ctypes.sizeof(P.Opts) == 40
     assert o.dispatch == P.DISPATCH_PLAIN and o.product_arm == P.ARM_AUTO and o.rms_variant == 0
-    assert ctypes.sizeof(P.Stats) == 4 + 4 + 256 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
+    # ... mfma_ops_issued, then gathers (int32, padded to 8), gather_ms, gather_bytes
+    assert ctypes.sizeof(P.Stats) == 4 + 4 + 256 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert L.bmlp_version() >= 100
 
 
