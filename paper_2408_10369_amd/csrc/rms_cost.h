@@ -7,11 +7,12 @@
 namespace bmlp {
 
 // Rates measured on MI355X at n = 16,384: dense squarings on the matrix cores (4.5e15 on a product that
-// skips nothing) and on the VALU, row gathers from L2 / Infinity Cache (888 MB in 222 us with all of a
-// wave's loads in flight), transposes moving the matrix in and out (3.2e12 bytes/s).
+// skips nothing) and on the VALU, squarings by row gathers (6.1e12 bytes/s of rows read and written over
+// the density sweep's gather squarings, 7.5e12 on the largest), transposes moving the matrix in and out
+// (3.2e12 bytes/s).
 constexpr double kMfmaSquareOpsPerSec = 4.5e15;
 constexpr double kValuSquareOpsPerSec = 1.7e15;
-constexpr double kGatherBytesPerSec = 4.0e12;
+constexpr double kGatherBytesPerSec = 6.0e12;
 constexpr double kSemiOverheadS = 50.0e-6;  // launches and the readbacks of the semi-naive route
 
 // A squaring R.R of a sparse R is cheaper as row gathers (row i of R | R.R = R[i] | OR of the rows k over
