@@ -235,6 +235,13 @@ def test_rms_path_graph_loop_counts(ctx, n):
     # squarings (by the product kernels or, while R is sparse, by row gathers)
     assert st["iterations"] == math.ceil(math.log2(n - 1)) + 1
     assert st["products"] + st["arm_trace"].count(B.ARM_PRODUCT_GATHER) == st["iterations"]
+    # the timed gather squarings and their algorithmic bytes: squaring t reads the n rows of R_t = R + ..
+    # + R^(2^t), whose bits are the paths of length 1 .. 2^t, one source row per bit, and writes n rows
+    bits = [sum(n - j for j in range(1, min(2 ** t, n - 1) + 1)) for t in range(st["iterations"])]
+    want = sum((2 * n + bits[t]) * ((n + 7) // 8) for t, a in enumerate(st["arm_trace"]) if a == B.ARM_PRODUCT_GATHER)
+    assert st["gathers"] == st["arm_trace"].count(B.ARM_PRODUCT_GATHER)
+    assert st["gather_bytes"] == want, (st["gather_bytes"], want)
+    assert (st["gather_ms"] > 0) == (st["gathers"] > 0)
     st1 = {}
     ctx.rms(R, n, opts=B.make_opts(rms_variant=1), stats=st1)
     assert st1["iterations"] == math.ceil(math.log2(n - 1)) + 1
