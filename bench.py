@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-schedule variant of the main step (its launches then stay out of a trace)")
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
                     help="bound the oracle's closure rows per graph (0: all rows)")
     ap.add_argument("--workloads", default="c1,batch,batch_queries,programs,stream,isforeign,dynamic,samegen,io",
@@ -150,15 +152,19 @@ def main():
         va["launches"] += st["products"] - st["products_mfma"]
     per_graph = []
 
-    def step():
+    def step(opts=None):
         # the timed step: the edge lists are packed without a host wait (an out-of-range fact would be
         # latched and reported after the timed region) and no call asks for statistics
         for g in graphs:
             ctx.pack_coo_async(g["s"], g["d"], n, n, out=g["R"])
-            ctx.rms(g["R"], n, out=g["Rstar"])
+            ctx.rms(g["R"], n, out=g["Rstar"], opts=opts)
             for qi, (r, c, k) in enumerate(g["queries"]):
                 ctx.pack_coo_async(r, c, k, n, out=g["V"][qi])
-                ctx.smp(g["R"], n, g["V"][qi], out=g["Vs"][qi])
+                ctx.smp(g["R"], n, g["V"][qi], out=g["Vs"][qi], opts=opts)
+
+    def fingerprint():
+        torch.cuda.synchronize()
+        return [int(_hash_dev(t, W)) for g in graphs for t in [g["Rstar"]] + g["Vs"]]
 
     def instrumented_step():
         # the same calls with statistics (device times, per-launch product timings, arms), untimed
@@ -204,6 +210,31 @@ def main():
     torch.cuda.synchronize()
     rows_per_step = sum(n + sum(k for (_, _, k) in g["queries"]) for g in graphs)
     value = rows_per_step / (ms_per_step / 1000.0)
+    W = torch.randint(-2**62, 2**62, (n * (n // 64),), dtype=torch.int64, device="cuda")
+    fp_plain = fingerprint()
+
+    # the same step under the learned schedule (the dispatcher may build a closure by the selection from
+    # every source, and picks the selections' arms), timed the same way; its answers must be the plain ones
+    learned_opts = B.make_opts(dispatch=B.DISPATCH_LEARNED)
+    for _ in range(0 if args.no_learned else args.warmup):
+        step(learned_opts)
+    torch.cuda.synchronize()
+    learned = None
+    if not args.no_learned:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(learned_opts)
+        torch.cuda.synchronize()
+        ms_learned = (time.perf_counter() - t0) * 1000.0 / args.steps
+        by_selection = 0
+        for g in graphs:
+            st = {}
+            ctx.rms(g["R"], n, out=g["Rstar"], opts=learned_opts, stats=st)
+            by_selection += st["arm"] == B.ARM_SMP_CLOSURE_SELECT
+        learned = {"ms_per_step": round(ms_learned, 3), "value": round(rows_per_step / (ms_learned / 1000.0), 1),
+                   "speedup_over_plain": round(ms_per_step / ms_learned, 3),
+                   "closures_by_selection": by_selection, "closures": len(graphs),
+                   "bit_identical": fingerprint() == fp_plain}
 
     # the dominant kernel: the product kernel with the most device time in the step
     arm = max(prod, key=lambda a: prod[a]["ms"])
@@ -279,6 +310,7 @@ def main():
         "config": {"workload": "ER digraph density sweep n=16384, p in {1e-4,5e-4,1e-3,5e-3,1e-2}: "
                                "pack + BMLP-RMS closure + BMLP-SMP from k=1,64,1024 sources per graph",
                    "n": n, "graphs": len(graphs), "query_rows_per_step": rows_per_step},
+        "learned": learned,
         "roofline": roofline, "gather_hbm": gather_hbm, "cpu_baseline": cpu, "smp_hbm": smp_hbm,
         "per_graph": per_graph,
     }

@@ -212,7 +212,10 @@ bmlp_status bmlp_product(bmlp_handle h, const uint64_t *A, int64_t lda, const ui
 /* BMLP-RMS (Algorithm 1; Eq. 1 fixed point): Rstar = R1+ = sum_{k>=1} R1^k, i.e. Rstar_ij = 1 iff
    a path of length >= 1 leads from i to j.  R1, Rstar: n x n, leading dimension ld.  Rstar must
    not overlap R1.  The default variant iterates R <- R + R x R from R1 (ceil(log2 L)+1 products,
-   L the longest shortest path); variant 1 steps Algorithm 1 as printed.  Same bits either way. */
+   L the longest shortest path); variant 1 steps Algorithm 1 as printed.  Same bits either way.
+   Under the learned schedule (variant 0, n <= 131072) the dispatcher may build the same closure by
+   the one-launch selection from every source (Eq. 5 with V = I) where it predicts that cheaper;
+   forced with smp_arm BMLP_ARM_SMP_CLOSURE_SELECT it always does; stats->arm then says so. */
 bmlp_status bmlp_rms(bmlp_handle h, const uint64_t *R1, uint64_t *Rstar, int64_t n, int64_t ld,
                      const bmlp_opts *opts, void *stream, bmlp_stats *stats);
 /* BMLP-SMP (Eq. 5; Algorithm 2): Vstar = V x R1+ row by row, the answers of the k partially

@@ -1094,18 +1094,25 @@ int smp_choose_arm(bmlp_ctx* c, const bmlp_opts& o, const GraphInfo& gi, i64 k, 
 }
 
 // The call-level inputs of a dispatcher choice, computed on the device and read back together (one host
-// wait): the statistics of R (n x n), the set bits of the query rows Q (qrows x n), the 16 features
-// (features.h) and, with allowed != 0, the model's decision among the allowed outputs.  Returns the
-// decision, or -1 when the model is not asked.
+// wait): the statistics of R (n x n), the set bits of the query rows Q (qrows x n; Q null: *delta0 gives
+// them), the 16 features (features.h) and, with allowed != 0, the model's decision among the allowed
+// outputs.  Returns the decision, or -1 when the model is not asked.
 int call_stats_decide(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const u64* Q, i64 qrows, i64 ldq, i64 k,
                       float context, int reflexive, u32 allowed, hipStream_t s, GraphInfo* gi, double* delta0) {
   unsigned long long* gst = (unsigned long long*)(c->d_flags + F_GSTATS);
   unsigned long long* cnt = (unsigned long long*)(c->d_flags + F_CNT);
   float* feat = (float*)(c->d_flags + F_FEAT);
   hip_check(hipMemsetAsync(gst, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
-  hip_check(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
   hip_check(launch_graph_stats(R, n, n, ld, gst, s), "graph_stats");
-  hip_check(launch_popcount_total(Q, qrows, n, ldq, cnt, s), "popcount_total");
+  if (Q) {
+    hip_check(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+    hip_check(launch_popcount_total(Q, qrows, n, ldq, cnt, s), "popcount_total");
+  } else {
+    // no query rows given: *delta0 holds their bit count (the identity's n for a closure)
+    const unsigned long long d = (unsigned long long)*delta0;
+    std::memcpy(c->h_flags + F_CNT, &d, sizeof d);
+    hip_check(hipMemcpyAsync(cnt, c->h_flags + F_CNT, sizeof d, hipMemcpyHostToDevice, s), "memcpy");
+  }
   hip_check(launch_call_features(gst, cnt, n, k, context, reflexive, feat, s), "call_features");
   if (allowed)
     hip_check(launch_mlp_decide(c->d_model, c->d_model + kParams, c->d_model + kParams + kIn, feat,
@@ -1749,7 +1756,27 @@ bmlp_status bmlp_rms(bmlp_handle h, const uint64_t* R1, uint64_t* Rstar, int64_t
     if (o.check_padding) check_padding(h, R1, n, n, ld, s, "R1");
     StatsRec sr(stats, h, s, &o);
     if (stats) stats->arm = product_arm(o, n, n, n);
-    if (n > 0) rms_core(h, R1, ld, Rstar, ld, n, o, s, sr);
+    if (n > 0) {
+      // The closure by squaring (BMLP-RMS), or -- forced, or where the learned model predicts it cheaper --
+      // by the selection from every source (Eq. 5 with V = I): the same bits.
+      const bool sel_ok = o.rms_variant == 0 && n <= smp_rows_max_n();
+      bool by_sel = sel_ok && o.dispatch == BMLP_DISPATCH_FORCED && o.smp_arm == BMLP_ARM_SMP_CLOSURE_SELECT;
+      GraphInfo gi;
+      if (sel_ok && o.dispatch == BMLP_DISPATCH_LEARNED && h->model) {
+        // outputs 2 (the closure by squaring, then its rows read) and 3 (the one-launch selection of the n
+        // identity rows), as for a session's closure
+        double delta0 = (double)n;
+        by_sel = call_stats_decide(h, R1, ld, n, nullptr, 0, 0, n, 0.f, 0, 0x4u | 0x8u, s, &gi, &delta0) == 3;
+      }
+      if (by_sel) {
+        if (gi.n != n) gi = graph_info(h, R1, ld, n, s);
+        if (stats) stats->arm = BMLP_ARM_SMP_CLOSURE_SELECT;
+        if (h->trace) h->trace->call_arm = BMLP_ARM_SMP_CLOSURE_SELECT;
+        closure_by_selection(h, R1, ld, n, Rstar, ld, gi, Csr{}, o, s, sr);
+      } else {
+        rms_core(h, R1, ld, Rstar, ld, n, o, s, sr);
+      }
+    }
     sr.finish();
   });
 }

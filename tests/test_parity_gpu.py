@@ -343,6 +343,25 @@ def test_smp_random(ctx, n, arm, reflexive, parm):
         assert st["arm"] == arm
 
 
+@pytest.mark.parametrize("n", [1, 2, 64, 65, 1000, 5000])
+def test_rms_closure_by_selection(ctx, n):
+    """bmlp_rms forced to the closure by selection, and under the learned schedule (which may pick either
+    route): the oracle's closure, padding words zeroed."""
+    rng = np.random.default_rng(777 + n)
+    for p in (1.2 / max(n, 1), 4.0 / max(n, 1)):
+        A, s, d = rand_graph(rng, n, min(p, 1.0))
+        ld = (n + 63) // 64 + 3
+        R = gpu_pack(ctx, n, s, d, ld)
+        want = oracle.closure_rows(n, s, d, ld=ld)
+        st = {}
+        out = torch.full_like(R, -1)
+        got = host(ctx.rms(R, n, out=out, opts=forced(smp_arm=B.ARM_SMP_CLOSURE_SELECT), stats=st))
+        assert np.array_equal(got, want), (n, p)
+        assert st["arm"] == B.ARM_SMP_CLOSURE_SELECT
+        out.fill_(-1)
+        assert np.array_equal(host(ctx.rms(R, n, out=out, opts=B.make_opts(dispatch=B.DISPATCH_LEARNED))), want)
+
+
 @pytest.mark.parametrize("n", [1, 64, 65, 1000, 5000])
 def test_closure_by_selection_is_the_closure(ctx, n):
     """The selection from every source (V = I) under the closure-by-selection arm returns R1+ itself,
