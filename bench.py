@@ -46,7 +46,7 @@ GEMM_TRAFFIC = {"k_gemm_mfma": {"sources": ["paper_2408_10369_amd/csrc/k_gemm.hi
                                             "paper_2408_10369_amd/csrc/mfma_tile.h",
                                             "paper_2408_10369_amd/csrc/mfma_tile2.h"],
                                 "sha256": "18a0dc75cc339d4fd23e6d9d4b68eaecc7d96cd31f3c750135ceb5ce19406606",
-                                "bytes_per_launch": 586.6e6}}
+                                "bytes_per_launch": 409.7e6}}
 
 
 def measured_traffic(kernel):
