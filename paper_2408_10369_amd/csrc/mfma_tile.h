@@ -61,6 +61,7 @@ struct MfmaLds {
   u64 bal[8][2][16];
   u32 zmask[2][8];  // per stage and staging wave (A: 0..3, B^T: 4..7): bit q = some row has a nonzero word q
   u32 satf[2][8];   // per vote (alternating) and wave: every output of the wave's 128 x 64 block is set
+  u64 cnt[8][3];    // per wave: new bits, words of k multiplied, changed (tile_counters)
 };
 
 struct MfmaTile {
@@ -76,6 +77,42 @@ struct MfmaTile {
   u32* changed2;  // optional second flag set with *changed
 };
 
+// Adds a tile's counts to the launch's counters (new bits, matrix-core work issued, the changed flags) with
+// one device atomic per counter and workgroup: the eight waves' sums meet in LDS first.  Same-address device
+// atomics are serialised; one per wave and counter (32,768 waves for a 16,384-node squaring) cost about a
+// quarter of a millisecond on a launch whose tiles saturate early and otherwise take 0.2 ms.  Every thread of
+// the workgroup calls it; pop is the lane's count, words and ch are wave-uniform.  The slots are read back
+// before any thread can reach the next tile's epilogue (the K loop has a barrier).
+__device__ __forceinline__ void tile_counters(u64 (&cnt)[8][3], const MfmaTile& g, u32 pop, u32 words, int ch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  u64 s = pop;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const u64 any = __ballot(ch);
+  if (lane == 0) {
+    cnt[wave][0] = s;
+    cnt[wave][1] = words;
+    cnt[wave][2] = any != 0ull ? 1ull : 0ull;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 p = 0, w = 0, c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      p += cnt[i][0];
+      w += cnt[i][1];
+      c |= cnt[i][2];
+    }
+    if (g.newbits && p) atomicAdd(g.newbits, (unsigned long long)p);
+    // matrix-core work actually issued: 8 blocks of 32 x 32 x 64 MACs (2 ops each) per word and wave
+    if (g.executed && w) atomicAdd(g.executed, (unsigned long long)w * 8ull * 131072ull);
+    if (g.changed && c) {
+      atomicOr(g.changed, 1u);
+      if (g.changed2) atomicOr(g.changed2, 1u);
+    }
+  }
+}
+
 // Output tile (tr, tc) of C = Cold | A.B (256 x 256) by one workgroup of 512 threads.  Every thread of
 // the workgroup must call it with the same tile.
 __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr, i64 tc) {
@@ -90,9 +127,6 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
   u64* __restrict__ D = g.D;
   const i64 ldd = g.ldd;
   const i64 M = g.M, K = g.K, N = g.N;
-  u32* __restrict__ changed = g.changed;
-  unsigned long long* __restrict__ newbits = g.newbits;
-  unsigned long long* __restrict__ executed = g.executed;
   auto& Ax = L.Ax;
   auto& Bx = L.Bx;
   auto& bal = L.bal;
@@ -304,16 +338,7 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
     }
     __builtin_amdgcn_wave_barrier();
   }
-  wave_count(pop, newbits);
-  // matrix-core work actually issued: 8 blocks of 32 x 32 x 64 MACs (2 ops each) per word
-  if (executed && lane == 0 && done_words) atomicAdd(executed, (unsigned long long)done_words * 8ull * 131072ull);
-  if (changed) {
-    const u64 any = __ballot(ch);
-    if (any && lane == 0) {
-      atomicOr(changed, 1u);
-      if (g.changed2) atomicOr(g.changed2, 1u);
-    }
-  }
+  tile_counters(L.cnt, g, pop, done_words, ch);
 }
 
 }  // namespace bmlp

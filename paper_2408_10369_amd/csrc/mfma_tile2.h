@@ -39,6 +39,7 @@ struct Mfma2Lds {
   u64 bal[8][2][16];
   u32 zmask[2][8];  // per stage and staging wave: bit q = word q of the chunk is nonzero in the wave's rows
   u32 satf[2][8];
+  u64 cnt[8][3];  // per wave: new bits, words of k multiplied, changed (tile_counters)
 };
 
 // physical 16-byte unit of logical unit u (u = half * KC / 8 + word / 4) in row r
@@ -298,15 +299,7 @@ __device__ __forceinline__ void mfma_tile2(Mfma2Lds<KC>& L, const MfmaTile& g, i
     }
     __builtin_amdgcn_wave_barrier();
   }
-  wave_count(pop, g.newbits);
-  if (g.executed && lane == 0 && done_words) atomicAdd(g.executed, (unsigned long long)done_words * 8ull * 131072ull);
-  if (g.changed) {
-    const u64 any = __ballot(ch);
-    if (any && lane == 0) {
-      atomicOr(g.changed, 1u);
-      if (g.changed2) atomicOr(g.changed2, 1u);
-    }
-  }
+  tile_counters(L.cnt, g, pop, done_words, ch);
 }
 
 }  // namespace bmlp
