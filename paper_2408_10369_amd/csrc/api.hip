@@ -2229,6 +2229,7 @@ bmlp_status bmlp_batched(bmlp_handle h, const bmlp_graph_desc* graphs, int32_t c
       const bool mfma = d.n >= batch_mfma_min_n();
       buf_words += (size_t)((mfma ? 3 : 2) * d.n * words_for(d.n));
       if (mfma) sizes.total_mblocks += (d.n + 255) / 256;
+      sizes.total_sgroups += (std::max<int64_t>(d.n, d.k) + 63) / 64;
     }
     sizes.rounds = plan.rounds;
     const size_t table_bytes = ((size_t)count * sizeof(BatchGraph) + 255) & ~(size_t)255;

@@ -105,82 +105,139 @@ __global__ void k_batch_modes(const BatchGraph* __restrict__ gs, int count, int 
 }
 
 // Statistics of each graph for the dispatcher's features: set bits of R1, its largest row count, its
-// nonempty rows, and the set bits of its query rows.  One wave per group of 64 rows of a graph (max(n, k)
-// rows, groups numbered batch-wide from sgroup_begin), eight rows at a time with all their loads in flight
-// (lanes over the words of a row); four atomics per wave into gst (4 u64 per graph, zeroed by the setup
-// kernel), so a large graph's rows spread over many waves.
+// nonempty rows, and the set bits of its query rows.  Two passes and no atomics (same-address device atomics
+// serialise): k_batch_stats takes a wave per group of 64 rows of a graph (max(n, k) rows, groups numbered
+// batch-wide from sgroup_begin) and writes the group's four partial values; k_batch_features combines a
+// graph's groups with one wave.  A group is read eight rows at a time with all their loads in flight (lanes
+// over the words of a row).  The wave's graph is found by a search over the wave-uniform group index, so its
+// loads are scalar.
 constexpr int kStatsRows = 8;
 __global__ void __launch_bounds__(256)
-k_batch_stats(const BatchGraph* __restrict__ gs, int count, i64 total_groups, unsigned long long* __restrict__ gst) {
+k_batch_stats(const BatchGraph* __restrict__ gs, int count, i64 total_groups, unsigned long long* __restrict__ part) {
   const int lane = threadIdx.x & 63;
-  const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
+  const i64 wave0 = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6));
   const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
-  for (i64 grp = wave; grp < total_groups; grp += nwaves) {
-    int lo = 0, hi = count - 1;
+  int lo = 0;
+  for (i64 grp = wave0; grp < total_groups; grp += nwaves) {
+    // groups only grow along the loop, so the search starts from the last graph found
+    int hi = count - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (gs[mid].sgroup_begin <= grp) lo = mid; else hi = mid - 1;
     }
-    const BatchGraph& G = gs[lo];
-    const u64 lm = (G.n & 63) ? ((1ull << (G.n & 63)) - 1ull) : ~0ull;
-    const i64 rows = G.n > G.k ? G.n : G.k;
-    const i64 first = (grp - G.sgroup_begin) * 64;
+    // the fields this pass reads, loaded once
+    const i64 gn = gs[lo].n, gk = gs[lo].k, gnw = gs[lo].nw, gld = gs[lo].ld, gldv = gs[lo].ldv;
+    const u64* __restrict__ R1 = gs[lo].R1;
+    const u64* __restrict__ V = gs[lo].V;
+    const u64 lm = (gn & 63) ? ((1ull << (gn & 63)) - 1ull) : ~0ull;
+    const i64 rows = gn > gk ? gn : gk;
+    const i64 first = (grp - gs[lo].sgroup_begin) * 64;
     const i64 last = first + 64 < rows ? first + 64 : rows;
-    unsigned long long bits = 0, mx = 0, nonempty = 0, vbits = 0;  // wave-uniform after the reductions
+    // a row of a graph with n < 65,536 has fewer set bits than 2^16: four rows' lane counts then share one
+    // 64-bit word of 16-bit fields through the cross-lane sums (no field overflows at any partial sum)
+    const bool packed = gn < 65536;
+    unsigned long long bits = 0, mx = 0, nonempty = 0;  // wave-uniform after the reductions
+    u32 vl = 0;                                         // this lane's set bits of the query rows
     for (i64 row0 = first; row0 < last; row0 += kStatsRows) {
-      u32 pr[kStatsRows], pv[kStatsRows];
+      u32 pr[kStatsRows];
 #pragma unroll
-      for (int r = 0; r < kStatsRows; ++r) pr[r] = pv[r] = 0u;
-      for (i64 w = lane; w < G.nw; w += 64) {
-        const u64 m = w == G.nw - 1 ? lm : ~0ull;
+      for (int r = 0; r < kStatsRows; ++r) pr[r] = 0u;
+      for (i64 w = lane; w < gnw; w += 64) {
+        const u64 m = w == gnw - 1 ? lm : ~0ull;
         u64 xr[kStatsRows], xv[kStatsRows];
 #pragma unroll
         for (int r = 0; r < kStatsRows; ++r) {
           const i64 row = row0 + r;
-          xr[r] = row < last && row < G.n ? G.R1[row * G.ld + w] : 0ull;
-          xv[r] = row < last && row < G.k ? G.V[row * G.ldv + w] : 0ull;
+          xr[r] = row < last && row < gn ? R1[row * gld + w] : 0ull;
+          xv[r] = row < last && row < gk ? V[row * gldv + w] : 0ull;
         }
 #pragma unroll
         for (int r = 0; r < kStatsRows; ++r) {
           pr[r] += (u32)__popcll(xr[r] & m);
-          pv[r] += (u32)__popcll(xv[r] & m);
+          vl += (u32)__popcll(xv[r] & m);
+        }
+      }
+      u32 tot[kStatsRows];
+      if (packed) {
+        unsigned long long a = (unsigned long long)pr[0] | ((unsigned long long)pr[1] << 16) |
+                               ((unsigned long long)pr[2] << 32) | ((unsigned long long)pr[3] << 48);
+        unsigned long long b = (unsigned long long)pr[4] | ((unsigned long long)pr[5] << 16) |
+                               ((unsigned long long)pr[6] << 32) | ((unsigned long long)pr[7] << 48);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off, 64);
+          b += __shfl_xor(b, off, 64);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          tot[r] = (u32)((a >> (16 * r)) & 0xFFFFull);
+          tot[4 + r] = (u32)((b >> (16 * r)) & 0xFFFFull);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < kStatsRows; ++r) {
+          u32 v = pr[r];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+          tot[r] = v;
         }
       }
 #pragma unroll
       for (int r = 0; r < kStatsRows; ++r) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          pr[r] += __shfl_xor(pr[r], off, 64);
-          pv[r] += __shfl_xor(pv[r], off, 64);
-        }
-        bits += pr[r];
-        mx = pr[r] > mx ? pr[r] : mx;
-        nonempty += pr[r] ? 1u : 0u;
-        vbits += pv[r];
+        bits += tot[r];
+        mx = tot[r] > mx ? tot[r] : mx;
+        nonempty += tot[r] ? 1u : 0u;
       }
     }
+    unsigned long long vbits = vl;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) vbits += __shfl_xor(vbits, off, 64);
     if (lane == 0) {
-      unsigned long long* st = gst + 4 * (i64)lo;
-      if (bits) {
-        atomicAdd(&st[0], bits);
-        atomicMax(&st[1], mx);
-        atomicAdd(&st[2], nonempty);
-      }
-      if (vbits) atomicAdd(&st[3], vbits);
+      unsigned long long* p = part + 4 * grp;
+      p[0] = bits;
+      p[1] = mx;
+      p[2] = nonempty;
+      p[3] = vbits;
     }
   }
 }
 
-// The call-level features of each graph's queries (as the library computes them for a selection call),
-// with feature 7 = 0.5 where the closure is computed anyway (an output of the batch), 0 where it is not.
-__global__ void k_batch_features(const BatchGraph* __restrict__ gs, int count, const unsigned long long* __restrict__ gst,
-                                 float* __restrict__ X) {
-  const i64 g = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+// Per graph: its statistics from its groups' partial values (one wave per graph), kept in gst, and the
+// dispatcher's input features.
+__global__ void __launch_bounds__(256)
+k_batch_features(const BatchGraph* __restrict__ gs, int count, const unsigned long long* __restrict__ part,
+                 unsigned long long* __restrict__ gst, float* __restrict__ X) {
+  const int lane = threadIdx.x & 63;
+  const i64 g = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6));
   if (g >= count) return;
   const BatchGraph& G = gs[g];
-  const unsigned long long* s = gst + 4 * g;
-  make_features(X + kIn * g, (double)G.n, (double)s[0], (double)s[1], (double)s[2], (double)G.k,
-                G.closure_req ? 0.5f : 0.f, 1, 0, (double)s[3], (double)s[3], 0.0, 0);
+  const i64 rows = G.n > G.k ? G.n : G.k;
+  const i64 groups = (rows + 63) / 64;
+  unsigned long long b = 0, mx = 0, ne = 0, vb = 0;
+  for (i64 i = lane; i < groups; i += 64) {
+    const unsigned long long* p = part + 4 * (G.sgroup_begin + i);
+    b += p[0];
+    mx = p[1] > mx ? p[1] : mx;
+    ne += p[2];
+    vb += p[3];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    b += __shfl_xor(b, off, 64);
+    const unsigned long long m2 = __shfl_xor(mx, off, 64);
+    mx = m2 > mx ? m2 : mx;
+    ne += __shfl_xor(ne, off, 64);
+    vb += __shfl_xor(vb, off, 64);
+  }
+  if (lane == 0) {
+    unsigned long long* s = gst + 4 * g;
+    s[0] = b;
+    s[1] = mx;
+    s[2] = ne;
+    s[3] = vb;
+    make_features(X + kIn * g, (double)G.n, (double)b, (double)mx, (double)ne, (double)G.k,
+                  G.closure_req ? 0.5f : 0.f, 1, 0, (double)vb, (double)vb, 0.0, 0);
+  }
 }
 
 // The model's choice per graph between reading its answers off the closure (output 2) and per-row
@@ -679,9 +736,10 @@ i64 batch_qsel_offset(int count, const BatchPlan& p) {
   return (w + 1) & ~(i64)1;  // 8-byte aligned for the statistics that follow
 }
 
-// per graph after qsel: need (1), statistics (4 u64), features (16 float), model outputs (4 float)
+// per graph after qsel: need (1), statistics (4 u64), features (16 float), model outputs (4 float); then
+// (aligned) the statistics pass's partial values, 4 u64 per 64-row group
 i64 batch_flag_words(int count, const BatchPlan& p) {
-  return batch_qsel_offset(count, p) + (i64)count * (1 + 1 + 8 + kIn + kOut) + 2;
+  return batch_qsel_offset(count, p) + (i64)count * (1 + 1 + 8 + kIn + kOut) + 2 + 8 * p.total_sgroups + 2;
 }
 
 i64 batch_select_tiles(i64 k, i64 n) {
@@ -693,7 +751,7 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
                               hipStream_t s) {
   // flags layout: changed[count * rounds] | any_active[rounds] | counters[rounds + 2] |
   //               gdense[count * rounds] | bdense[total_mblocks] | (aligned) qsel[count] | need[count] |
-  //               (aligned) stats[count][4 u64] | X[count][16] | Y[count][4]
+  //               (aligned) stats[count][4 u64] | X[count][16] | Y[count][4] | (aligned) part[total_sgroups][4 u64]
   u32* changed = flags;
   u32* any_active = flags + (i64)count * p.rounds;
   u32* counters = any_active + p.rounds;
@@ -704,6 +762,8 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
   unsigned long long* gst = (unsigned long long*)(flags + ((batch_qsel_offset(count, p) + 2 * (i64)count + 1) & ~(i64)1));
   float* X = (float*)(gst + 4 * (i64)count);
   float* Y = X + (i64)kIn * count;
+  unsigned long long* part =
+      (unsigned long long*)(flags + ((((u32*)(Y + (i64)kOut * count)) - flags + 1) & ~(i64)1));
   const i64 nflags = batch_flag_words(count, p);
   hipLaunchKernelGGL(k_batch_setup, dim3(grid_cap((p.total_rows / 8 * 64 + 255) / 256, 8192)), dim3(256), 0, s, d_graphs,
                      count, p.total_rows, flags, nflags);
@@ -716,10 +776,10 @@ hipError_t launch_batch_chain(BatchGraph* d_graphs, int count, const BatchPlan& 
   if (p.qmode == 2 && model) {
     // the dispatcher's choice per graph, on the device: statistics, features, the network, the argmin
     hipLaunchKernelGGL(k_batch_stats, dim3(grid_cap((p.total_sgroups * 64 + 255) / 256, 8192)), dim3(256), 0, s,
-                       (const BatchGraph*)d_graphs, count, p.total_sgroups, gst);
+                       (const BatchGraph*)d_graphs, count, p.total_sgroups, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_features, dim3(ggrid), dim3(256), 0, s, (const BatchGraph*)d_graphs, count,
-                       (const unsigned long long*)gst, X);
+    hipLaunchKernelGGL(k_batch_features, dim3((unsigned)((count * 64ll + 255) / 256)), dim3(256), 0, s,
+                       (const BatchGraph*)d_graphs, count, (const unsigned long long*)part, gst, X);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_mlp_forward(model, model + kParams, model + kParams + kIn, X, count, nullptr, nullptr, Y, s)) !=
         hipSuccess)

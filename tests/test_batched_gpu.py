@@ -202,3 +202,80 @@ def test_batched_selection_chunks_and_sizes(ctx, mode):
     opts = None if mode == "plain" else B.make_opts(dispatch=B.DISPATCH_FORCED, smp_arm=B.ARM_SMP_SPARSE)
     ctx.batched(graphs, opts=opts)
     check(graphs, refs)
+
+
+def _host_batch_features(specs):
+    """The dispatcher's features of each graph of a queries-only batch, from counts taken on the host (the
+    same formula as the library's: edges, largest row, nonempty rows, query bits; context 0, call level,
+    round 0, delta = previous = query bits, nothing visited)."""
+    F = np.zeros((len(specs), 16), np.float64)
+    for i, (n, s, d, srcs) in enumerate(specs):
+        A = np.zeros((n, n), bool)
+        A[s, d] = True
+        rowdeg = A.sum(axis=1)
+        m = float(A.sum())
+        k = float(len(srcs))
+        vb = float(len(set(int(x) for x in srcs)))
+        nn = max(float(n), 1.0)
+        deg = m / nn
+        F[i, 0] = np.log2(1 + nn) / 16
+        F[i, 1] = np.log2(1 + m) / 24
+        F[i, 2] = np.log2(1 + deg) / 8
+        F[i, 3] = np.log2(1 + rowdeg.max() / (1 + deg)) / 8
+        F[i, 4] = (rowdeg > 0).sum() / nn
+        F[i, 5] = np.log2(1 + k) / 16
+        F[i, 6] = min(k / nn, 4.0)
+        F[i, 8] = 1.0
+        F[i, 10] = vb / (max(k, 1.0) * nn)
+        F[i, 12] = np.log2(1 + vb) / 32
+        F[i, 13] = min(vb / max(vb, 1.0), 16.0) / 16
+        F[i, 14] = np.log2(1 + vb * deg) / 40
+    return F.astype(np.float32)
+
+
+def test_batched_learned_choice_from_exact_statistics():
+    """The learned batch decides per graph on the device from statistics that a two-pass reduction takes
+    over 64-row groups of every graph (set bits, largest row, nonempty rows, query bits).  With a model
+    whose choice flips across the batch, every graph's decision must be the one the same model makes from
+    the host's counts: alone (one graph per batch) and, as a count, in one batch of all the graphs."""
+    c = B.Context(0)
+    try:
+        rng = np.random.default_rng(31)
+        specs = []
+        for _ in range(40):
+            n = int(np.exp(rng.uniform(np.log(64), np.log(4096))))
+            m = int(rng.uniform(0.3, 10.0) * n)
+            s = rng.integers(0, n, m)
+            d = rng.integers(0, n, m)
+            if rng.random() < 0.3:  # a hub row: the largest row count differs from the mean
+                hub = rng.integers(0, n, n // 2)
+                s = np.concatenate([s, np.zeros(len(hub), np.int64)])
+                d = np.concatenate([d, hub])
+            k = int(rng.integers(1, 65))
+            specs.append((n, s, d, rng.choice(n, min(k, n), replace=False)))
+        F = _host_batch_features(specs)
+        # a network fitted to random targets around these graphs' features: its choices are arbitrary
+        # functions of every statistic
+        X = np.repeat(F, 20, axis=0) + rng.normal(0, 0.02, (len(F) * 20, 16)).astype(np.float32)
+        T = rng.normal(0, 1, (len(X), 4)).astype(np.float32)
+        c.dispatcher_train(X, T, np.ones_like(T), epochs=300, lr=1e-2, seed=4)
+        Y = c.dispatcher_forward(F)
+        want = Y[:, 3] < Y[:, 2]
+        sure = np.abs(Y[:, 3] - Y[:, 2]) > 1e-5
+        assert want[sure].any() and (~want[sure]).any(), "the model's choices do not vary"
+        learned = B.make_opts(dispatch=B.DISPATCH_LEARNED)
+        for i, spec in enumerate(specs):
+            graphs, refs = make_batch(c, [spec], with_closure=False)
+            st = {}
+            c.batched(graphs, opts=learned, stats=st)
+            check(graphs, refs)
+            if sure[i]:
+                assert st["arm_trace"][1] == int(want[i]), (i, spec[0], Y[i])
+        graphs, refs = make_batch(c, specs, with_closure=False)
+        st = {}
+        c.batched(graphs, opts=learned, stats=st)
+        check(graphs, refs)
+        lo = int((want & sure).sum())
+        assert lo <= st["arm_trace"][1] <= lo + int((~sure).sum())
+    finally:
+        c.close()
