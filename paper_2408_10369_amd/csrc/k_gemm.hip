@@ -89,11 +89,8 @@ k_gemm_valu(const u64* __restrict__ A, i64 lda, const u64* __restrict__ B, i64 l
       }
     }
   }
-  wave_count(pop, newbits);
-  if (changed) {
-    const u64 bal = __ballot(ch);
-    if (bal && lane == 0) atomicOr(changed, 1u);
-  }
+  __shared__ unsigned long long cslot[4][2];
+  block_counts<4>(pop, ch, newbits, changed, cslot);
 }
 
 template <int RPW>

@@ -311,15 +311,8 @@ k_smp_round(const u64* __restrict__ fr, u64* __restrict__ fr_out, i64 ldf, u64* 
     }
     __syncthreads();
   }
-  // per-wave totals
-  u64 s = cnt;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  const u64 bal = __ballot(any);
-  if ((t & 63) == 0) {
-    if (s && newbits) atomicAdd(newbits, (unsigned long long)s);
-    if (bal && changed) atomicOr(changed, 1u);
-  }
+  __shared__ unsigned long long cslot[kSmpThreads / 64][2];
+  block_counts<kSmpThreads / 64>(cnt, any, newbits, changed, cslot);
 }
 
 // Selection read off a closure: out[r] = OR of C[u, :] over the set bits u of V[r] (V[r] R1+ when C
@@ -420,7 +413,8 @@ k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__
     for (i64 w = nw + t; w < ldo; w += 256) out[orow * ldo + w] = 0ull;
     __syncthreads();
   }
-  wave_count(added, newbits);
+  __shared__ unsigned long long cslot[4][2];
+  block_counts<4>(added, 0, newbits, nullptr, cslot);
 }
 
 // The same gather with one wave per row, for n <= 16,384 (lane l owns words l + 64 j, j < WPL): no
@@ -539,7 +533,8 @@ k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict
     }
     for (i64 ww = nw + lane; ww < ldo; ww += 64) out[orow * ldo + ww] = 0ull;
   }
-  wave_count(added, newbits);
+  __shared__ unsigned long long cslot[4][2];
+  block_counts<4>(added, 0, newbits, nullptr, cslot);
 }
 
 // The queued pieces of the heavy rows: piece (row, j) walks the set bits numbered [p j, p j + p) of
@@ -643,7 +638,8 @@ k_gather_rows_q(const u64* __restrict__ V, i64 ldv, const u64* __restrict__ Cl, 
       }
     }
   }
-  wave_count(added, newbits);
+  __shared__ unsigned long long cslot[4][2];
+  block_counts<4>(added, 0, newbits, nullptr, cslot);
 }
 
 }  // namespace

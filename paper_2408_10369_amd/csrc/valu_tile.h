@@ -152,4 +152,34 @@ __device__ __forceinline__ void wave_count(u32 v, unsigned long long* counter) {
   if ((threadIdx.x & 63) == 0 && s) atomicAdd(counter, (unsigned long long)s);
 }
 
+// The workgroup's sum of `v` into *counter and, when some thread passes any != 0, *changed |= 1: one device
+// atomic per workgroup and target, the waves' parts meeting in `slot` (LDS) first.  Same-address device
+// atomics are serialised, so a launch of many short waves that each add to one counter (16,384 waves for a
+// squaring of 16,384 rows by gathers) waits for them.  Every thread of the workgroup calls it, after its
+// last use of `slot`; counter and changed may be null.
+template <int Waves>
+__device__ __forceinline__ void block_counts(u32 v, int any, unsigned long long* counter, u32* changed,
+                                             unsigned long long (&slot)[Waves][2]) {
+  if (!counter && !changed) return;  // the same in every thread
+  u64 s = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  const u64 bal = __ballot(any);
+  if ((threadIdx.x & 63) == 0) {
+    slot[threadIdx.x >> 6][0] = s;
+    slot[threadIdx.x >> 6][1] = bal != 0ull ? 1ull : 0ull;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 t = 0, c = 0;
+#pragma unroll
+    for (int i = 0; i < Waves; ++i) {
+      t += slot[i][0];
+      c |= slot[i][1];
+    }
+    if (counter && t) atomicAdd(counter, (unsigned long long)t);
+    if (changed && c) atomicOr(changed, 1u);
+  }
+}
+
 }  // namespace bmlp
