@@ -721,7 +721,10 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
       const u32* route = recs + (i64)it * kRmsRecWords + 4;
       unsigned long long* nb2 = rec_nb(it);
       if (may_gather) {
-        const GatherQueue q = sized(gq, bits, n);
+        // the pieces are sized on the device from R_it's bit count, which the decision kernel has just
+        // written into record it (the host's count is R_{it-1}'s)
+        GatherQueue q = sized(gq, bits, n);
+        q.bits = (const unsigned long long*)(recs + (i64)it * kRmsRecWords) + 1;
         ahead_gather = sr.gather_begin();
         hip_check(launch_gather_rows(nxt, ldi, n, nxt, ldi, n, 1, cur, ldi, s, nullptr, nb2, &q, route, RR_GATHER),
                   "gather_rows");

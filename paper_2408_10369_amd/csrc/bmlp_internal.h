@@ -136,6 +136,9 @@ struct GatherQueue {
   unsigned long long* n;
   i64 cap;
   int piece;
+  // optional: the set bits of V counted on the device; the kernels then size the pieces from it (twice
+  // the mean row, at least 64) instead of from `piece`, for gathers queued before that count reaches the host
+  const unsigned long long* bits = nullptr;
 };
 i64 gather_queue_capacity(i64 k, i64 n);
 // out[map(r)] = init | OR of Cl[u, :] over the set bits u of V[r], with init = 0 (0), V[r] (1) or the

@@ -427,13 +427,26 @@ k_gather_rows(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__
 // k_gather_rows_q, launched after this kernel, to OR into the row with 64-bit atomics.
 constexpr int kMinPiece = 64;
 
+// The piece size: the host's, or -- with a device count of V's set bits -- twice the mean row of V's `rows`
+// rows, at least kMinPiece, at most 2^24, a multiple of 8 (the host's rule, sized()).
+__device__ __forceinline__ int gather_piece(int piece, const unsigned long long* __restrict__ bits, i64 rows) {
+  if (!bits) return piece;
+  const unsigned long long mean = *bits / (unsigned long long)(rows > 0 ? rows : 1);
+  unsigned long long p = 2ull * mean;
+  if (p < (unsigned long long)kMinPiece) p = kMinPiece;
+  if (p > (1ull << 24)) p = 1ull << 24;
+  return (int)((p + 7ull) / 8ull * 8ull);
+}
+
 template <int WPL>
 __global__ void __launch_bounds__(256)
 k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__ Cl, i64 ldc, i64 n, int init,
                 u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map,
                 unsigned long long* __restrict__ newbits, int2* __restrict__ qe, unsigned long long* __restrict__ qn,
-                i64 qcap, int piece, const u32* __restrict__ pred, u32 pred_val) {
+                i64 qcap, int piece_arg, const unsigned long long* __restrict__ vbits, const u32* __restrict__ pred,
+                u32 pred_val) {
   if (pred && *pred != pred_val) return;  // another kernel serves this squaring
+  const int piece = gather_piece(piece_arg, vbits, k);
   const int lane = threadIdx.x & 63;
   const i64 wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const i64 nwaves = (i64)gridDim.x * 4;
@@ -543,11 +556,13 @@ k_gather_rows_w(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict
 // starting value and first piece (k_gather_rows_w, launched before).
 template <int WPL>
 __global__ void __launch_bounds__(256)
-k_gather_rows_q(const u64* __restrict__ V, i64 ldv, const u64* __restrict__ Cl, i64 ldc, i64 n,
+k_gather_rows_q(const u64* __restrict__ V, i64 ldv, i64 k, const u64* __restrict__ Cl, i64 ldc, i64 n,
                 u64* __restrict__ out, i64 ldo, const int32_t* __restrict__ row_map, const int2* __restrict__ qe,
-                const unsigned long long* __restrict__ qn, i64 qcap, int piece, unsigned long long* __restrict__ newbits,
+                const unsigned long long* __restrict__ qn, i64 qcap, int piece_arg,
+                const unsigned long long* __restrict__ vbits, unsigned long long* __restrict__ newbits,
                 const u32* __restrict__ pred, u32 pred_val) {
   if (pred && *pred != pred_val) return;
+  const int piece = gather_piece(piece_arg, vbits, k);  // the same as k_gather_rows_w's
   const int lane = threadIdx.x & 63;
   const i64 wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const i64 nwaves = (i64)gridDim.x * 4;
@@ -662,6 +677,7 @@ hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 l
     unsigned long long* qn = queued ? q->n : nullptr;
     const i64 qcap = queued ? q->cap : 0;
     const int piece = queued ? (std::max(q->piece, kMinPiece) + 7) / 8 * 8 : kMinPiece;
+    const unsigned long long* vbits = queued ? q->bits : nullptr;
     if (queued) {
       const hipError_t e = launch_fill_zero((u64*)qn, 1, s);
       if (e != hipSuccess) return e;
@@ -670,26 +686,26 @@ hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 l
     const unsigned grid = (unsigned)(blocks < 16384 ? blocks : 16384);
     if (nw <= 64)
       hipLaunchKernelGGL(k_gather_rows_w<1>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits, qe, qn, qcap, piece, pred, pred_val);
+                         row_map, newbits, qe, qn, qcap, piece, vbits, pred, pred_val);
     else if (nw <= 128)
       hipLaunchKernelGGL(k_gather_rows_w<2>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits, qe, qn, qcap, piece, pred, pred_val);
+                         row_map, newbits, qe, qn, qcap, piece, vbits, pred, pred_val);
     else
       hipLaunchKernelGGL(k_gather_rows_w<4>, dim3(grid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, init, out, ldo,
-                         row_map, newbits, qe, qn, qcap, piece, pred, pred_val);
+                         row_map, newbits, qe, qn, qcap, piece, vbits, pred, pred_val);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !queued) return e;
     // the pieces: their number is known on the device only, so a fixed grid strides over them
     const unsigned qgrid = grid < 2048 ? grid : 2048;
     if (nw <= 64)
-      hipLaunchKernelGGL(k_gather_rows_q<1>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
-                         qn, qcap, piece, newbits, pred, pred_val);
+      hipLaunchKernelGGL(k_gather_rows_q<1>, dim3(qgrid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, out, ldo, row_map,
+                         qe, qn, qcap, piece, vbits, newbits, pred, pred_val);
     else if (nw <= 128)
-      hipLaunchKernelGGL(k_gather_rows_q<2>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
-                         qn, qcap, piece, newbits, pred, pred_val);
+      hipLaunchKernelGGL(k_gather_rows_q<2>, dim3(qgrid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, out, ldo, row_map,
+                         qe, qn, qcap, piece, vbits, newbits, pred, pred_val);
     else
-      hipLaunchKernelGGL(k_gather_rows_q<4>, dim3(qgrid), dim3(256), 0, s, V, ldv, Cl, ldc, n, out, ldo, row_map, qe,
-                         qn, qcap, piece, newbits, pred, pred_val);
+      hipLaunchKernelGGL(k_gather_rows_q<4>, dim3(qgrid), dim3(256), 0, s, V, ldv, k, Cl, ldc, n, out, ldo, row_map,
+                         qe, qn, qcap, piece, vbits, newbits, pred, pred_val);
     return hipGetLastError();
   }
   const unsigned grid = (unsigned)(k < 65535 ? k : 65535);
