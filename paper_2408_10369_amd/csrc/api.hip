@@ -56,6 +56,8 @@ struct bmlp_ctx {
   u32* d_flags = nullptr;  // device flags / counters
   unsigned char* scratch = nullptr;  // this device's address of the file-scope scratch array (bmlp_smp_noalloc)
   u32* h_flags = nullptr;  // pinned host mirror
+  void* h_pin = nullptr;   // pinned host staging for larger readbacks (the relabelling's counts), grown on demand
+  size_t h_pin_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evp0 = nullptr, evp1 = nullptr;
   // timed products awaiting their readback (statistics): event pairs and matrix-core work counters
   static constexpr int kPend = 64;
@@ -519,6 +521,23 @@ GraphInfo graph_info(bmlp_ctx* c, const u64* R, i64 ld, i64 n, hipStream_t s) {
   return g;
 }
 
+// Pinned host staging of at least `bytes` (pageable copies of a few hundred KB cost the relabelling about
+// 0.4 ms of staging).  Its contents last until the next call that asks for it.
+void* pinned(bmlp_ctx* c, size_t bytes) {
+  if (c->h_pin_bytes < bytes) {
+    if (c->h_pin) {
+      hip_check(hipDeviceSynchronize(), "sync");  // no copy may still use the old buffer
+      hip_check(hipHostFree(c->h_pin), "hipHostFree");
+      c->h_pin = nullptr;
+      c->h_pin_bytes = 0;
+    }
+    const size_t nb = std::max<size_t>(bytes, (size_t)1 << 20);
+    hip_check(hipHostMalloc(&c->h_pin, nb, hipHostMallocDefault), "hipHostMalloc");
+    c->h_pin_bytes = nb;
+  }
+  return c->h_pin;
+}
+
 // Relabelling before the dense squarings.  Where a relation's closure is one big block -- the rows that
 // reach a giant strongly connected part times the columns it reaches, the sparse random digraphs just
 // above the percolation threshold -- the block is spread over every 256 x 256 output tile in the given
@@ -526,9 +545,16 @@ GraphInfo graph_info(bmlp_ctx* c, const u64* R, i64 ld, i64 n, hipStream_t s) {
 // nodes ordered by class (heavy row and light column, heavy both, light row and heavy column, light
 // both; heavy = at least a quarter of the largest popcount) the block becomes a few contiguous
 // rectangles.  The squarings are the same up to the relabelling, (P R P^T)^2 = P R^2 P^T, and the
-// closure is mapped back at the end.  Returns false (nothing to gain) unless the rows or the columns
-// split into the two classes with at least 2% heavy and 10% light.
-bool rms_relabel(bmlp_ctx* c, const u64* cur, i64 ld, i64 n, const bmlp_opts& o, hipStream_t s, int32_t** perm_out,
+// closure is mapped back at the end.  Relabels when the rows or the columns split into the two classes
+// with at least 2% heavy and 10% light.
+//
+// Failing that, the few dead nodes of a denser relation (a row or a column with almost no bits: out- or
+// in-degree 0 in a random digraph of mean degree 8 -- a handful of nodes) are moved to the end.  A 256 x
+// 256 output tile with such a row or column never saturates, so it runs the whole K loop, and a few dead
+// nodes scattered over the order touch a tenth of all tiles; gathered at the end they touch the last
+// tile row and column only.  This is done when at most 2% of the nodes are dead and it frees at least
+// 5% of the tiles.  Returns 1 for the classes, 2 for the dead nodes, 0 (nothing to gain) otherwise.
+int rms_relabel(bmlp_ctx* c, const u64* cur, i64 ld, i64 n, const bmlp_opts& o, hipStream_t s, int32_t** perm_out,
                  int32_t** inv_out) {
   const i64 nw = words_for(n);
   int32_t* rowpop = (int32_t*)ws(c, S_DEG, (size_t)n * sizeof(int32_t), o);
@@ -537,35 +563,63 @@ bool rms_relabel(bmlp_ctx* c, const u64* cur, i64 ld, i64 n, const bmlp_opts& o,
   hip_check(launch_row_popcount(cur, n, n, ld, rowpop, nullptr, s), "row_popcount");
   hip_check(launch_transpose(cur, n, n, ld, ct, nw, s), "transpose");
   hip_check(launch_row_popcount(ct, n, n, nw, colpop, nullptr, s), "row_popcount");
-  std::vector<int32_t> rp((size_t)n), cp((size_t)n);
-  hip_check(hipMemcpyAsync(rp.data(), rowpop, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
-  hip_check(hipMemcpyAsync(cp.data(), colpop, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
+  // pinned: the row counts, the column counts, then the permutation and its inverse (4 n words)
+  int32_t* const rp = (int32_t*)pinned(c, (size_t)(4 * n) * sizeof(int32_t));
+  int32_t* const cp = rp + n;
+  hip_check(hipMemcpyAsync(rp, rowpop, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
+  hip_check(hipMemcpyAsync(cp, colpop, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
   hip_check(hipStreamSynchronize(s), "sync");
-  const int32_t rmax = *std::max_element(rp.begin(), rp.end());
-  const int32_t cmax = *std::max_element(cp.begin(), cp.end());
-  if (rmax <= 0 || cmax <= 0) return false;
-  std::vector<int> cls((size_t)n);
+  const int32_t rmax = *std::max_element(rp, rp + n);
+  const int32_t cmax = *std::max_element(cp, cp + n);
+  if (rmax <= 0 || cmax <= 0) return 0;
+  // class 0 heavy row and light column, 1 heavy both, 2 light row and heavy column, 3 light both (written
+  // without branches: the classes of neighbouring nodes are unrelated)
+  std::vector<uint8_t> cls((size_t)n);
   i64 hin = 0, hout = 0;
   for (i64 v = 0; v < n; ++v) {
-    const bool in = 4 * (i64)rp[v] >= rmax, out = 4 * (i64)cp[v] >= cmax;
+    const int in = 4 * (i64)rp[v] >= rmax, out = 4 * (i64)cp[v] >= cmax;
     hin += in;
     hout += out;
-    cls[v] = in ? (out ? 1 : 0) : (out ? 2 : 3);
+    cls[v] = (uint8_t)(2 * (1 - in) + (in == out));
   }
   auto splits = [&](i64 h) { return h * 50 >= n && h * 10 <= 9 * n; };  // a light class of at least 10%
-  if (!splits(hin) && !splits(hout)) return false;
-  std::vector<int32_t> perm((size_t)(2 * n));
+  int mode = 1;
+  if (!splits(hin) && !splits(hout)) {
+    mode = 2;
+    // dead nodes: a row or a column with fewer than 1/64 of the largest count's bits
+    const i64 tiles = (n + 255) / 256;
+    std::vector<char> rt((size_t)tiles, 0), ct((size_t)tiles, 0);
+    i64 dead = 0;
+    for (i64 v = 0; v < n; ++v) {
+      const bool dr = 64 * (i64)rp[v] < rmax, dc = 64 * (i64)cp[v] < cmax;
+      cls[v] = (uint8_t)((dr || dc) ? 1 : 0);
+      dead += cls[v];
+      if (dr) rt[(size_t)(v / 256)] = 1;
+      if (dc) ct[(size_t)(v / 256)] = 1;
+    }
+    const i64 drt = std::count(rt.begin(), rt.end(), (char)1), dct = std::count(ct.begin(), ct.end(), (char)1);
+    const i64 dirty = drt * tiles + dct * tiles - drt * dct;  // tiles with a dead row or column now
+    const i64 last = (n - 1) / 256 - (n - dead) / 256 + 1;     // tile rows the dead nodes take at the end
+    const i64 after = 2 * last * tiles - last * last;
+    if (dead == 0 || dead * 50 > n || (dirty - after) * 20 < tiles * tiles) return 0;
+    for (i64 v = 0; v < n; ++v) cls[v] = (uint8_t)(1 + 2 * cls[v]);
+  }
+  // the nodes by class, in their order within a class: one branch-free pass per class (a write past the
+  // last placed node lands in perm[n], which the inverse overwrites)
+  int32_t* const perm = rp + 2 * n;
   i64 at = 0;
   for (int k = 0; k < 4; ++k)
-    for (i64 v = 0; v < n; ++v)
-      if (cls[v] == k) perm[at++] = (int32_t)v;
+    for (i64 v = 0; v < n; ++v) {
+      perm[at] = (int32_t)v;
+      at += cls[v] == k;
+    }
   for (i64 i = 0; i < n; ++i) perm[n + perm[i]] = (int32_t)i;
   int32_t* d = (int32_t*)ws(c, S_PERM, (size_t)(2 * n) * sizeof(int32_t), o);
-  hip_check(hipMemcpyAsync(d, perm.data(), (size_t)(2 * n) * sizeof(int32_t), hipMemcpyHostToDevice, s), "memcpy");
-  hip_check(hipStreamSynchronize(s), "sync");  // the host vector goes out of scope
+  hip_check(hipMemcpyAsync(d, perm, (size_t)(2 * n) * sizeof(int32_t), hipMemcpyHostToDevice, s), "memcpy");
+  hip_check(hipStreamSynchronize(s), "sync");  // the staging is reused by the next call
   *perm_out = d;
   *inv_out = d + n;
-  return true;
+  return mode;
 }
 
 // R1+ into `out` (n x ldo) -- the RMS fixpoint driver shared by rms, the closure arm of smp and the RMS
@@ -593,9 +647,12 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
   // relabel (once) before the first dense squaring on the matrix cores, when a tenth or more of the rows
   // are empty (a light class is certain) and the squarings are large enough to repay the passes over the
   // matrix (at n = 8,192 they do not); inv maps the closure back
+  // relabel before the first dense squaring where R1 has empty rows: many (the block of a closure just above
+  // the percolation threshold) or a few dead nodes (rms_relabel)
   bool may_relabel = may_gather && o.rms_variant == 0 && arm == BMLP_ARM_PRODUCT_MFMA && n >= 16384 &&
-                     (n - g0.nonempty) * 10 >= n;
+                     g0.nonempty < n;
   const int32_t* inv = nullptr;
+  int relabel_mode = 0;  // rms_relabel: 1 block classes (the products are block-structured), 2 dead nodes
   const int cap = ceil_log2(std::max<i64>(n, 2)) + 2;
   // Squaring t records its new-bit count (and the device's running bit count and route) in record t of the
   // chain.  While the host reads squaring t's count back, squaring t + 1 is already queued: a one-thread
@@ -697,7 +754,8 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
           may_relabel = false;
           int32_t* perm;
           int32_t* pinv;
-          if (rms_relabel(c, cur, ldi, n, o, s, &perm, &pinv)) {
+          relabel_mode = rms_relabel(c, cur, ldi, n, o, s, &perm, &pinv);
+          if (relabel_mode) {
             // R_{t-1} in nxt is not needed by a dense squaring; the next one finds both in the new labels
             hip_check(launch_permute(cur, ldi, perm, n, nxt, ldi, s), "permute");
             std::swap(cur, nxt);
@@ -706,7 +764,7 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
         }
         product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb,
                 g0.n == n ? (double)bits / ((double)n * (double)n) : -1.0,  // the bit count is kept once counted
-                inv != nullptr);
+                relabel_mode == 1);
       }
     }
     sr.trace(it, tarm);
@@ -733,7 +791,7 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
       // the bit count of R_it is not known on the host yet: a squaring that falls to the dense product
       // counts as dense for the tuned tile code (sparser ones go to the gathers)
       product(c, nxt, ldi, nxt, ldi, nxt, ldi, cur, ldi, nullptr, 0, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb2, -1.0,
-              inv != nullptr, route, RR_DENSE);
+              relabel_mode == 1, route, RR_DENSE);
     }
     // read back this squaring's count and, when the next one was enqueued, its route (one contiguous copy)
     const size_t words = ahead ? (size_t)kRmsRecWords + 5 : 2;
@@ -1248,6 +1306,7 @@ bmlp_status bmlp_destroy(bmlp_handle h) {
         if (h->slot[i]) (void)hipFree(h->slot[i]);
       if (h->d_flags) (void)hipFree(h->d_flags);
       if (h->h_flags) (void)hipHostFree(h->h_flags);
+      if (h->h_pin) (void)hipHostFree(h->h_pin);
       if (h->ev0) (void)hipEventDestroy(h->ev0);
       if (h->ev1) (void)hipEventDestroy(h->ev1);
       if (h->evp0) (void)hipEventDestroy(h->evp0);
@@ -1396,7 +1455,7 @@ bmlp_status bmlp_autotune(bmlp_handle h, int32_t kernel_mask, int32_t reps, cons
       }
       int32_t* perm;
       int32_t* pinv;
-      if (rms_relabel(h, R, nw, n, o, s, &perm, &pinv)) {
+      if (rms_relabel(h, R, nw, n, o, s, &perm, &pinv) == 1) {
         hip_check(launch_permute(R, nw, perm, n, P, nw, s), "permute");
         std::swap(R, P);
         for (int step = 0; step < 3; ++step) {

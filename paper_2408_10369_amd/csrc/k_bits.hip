@@ -156,16 +156,31 @@ __global__ void k_rows_from_rp(const i64* __restrict__ rp, i64 rows, int32_t* __
     for (i64 e = rp[r] + lane; e < rp[r + 1]; e += 64) out[e] = (int32_t)r;
 }
 
-// list of the rows of a with a set bit (order unspecified), *count = their number; one wave per row
+// list of the rows of a with a set bit (order unspecified), *count = their number.  A wave takes eight rows
+// with all their loads in flight and claims their slots in the list with one atomic (one same-address
+// atomic per row, each waited for, took 55 us for 16,384 rows).
 __global__ void k_nonempty_rows(const u64* __restrict__ a, i64 rows, i64 nw, i64 ld, int32_t* __restrict__ list,
                                 u32* __restrict__ count) {
   const int lane = threadIdx.x & 63;
   const i64 wave = (blockIdx.x * (i64)blockDim.x + threadIdx.x) >> 6;
   const i64 nwaves = ((i64)gridDim.x * blockDim.x) >> 6;
-  for (i64 r = wave; r < rows; r += nwaves) {
-    u64 any = 0;
-    for (i64 w = lane; w < nw; w += 64) any |= a[r * ld + w];
-    if (__ballot(any != 0ull) && lane == 0) list[atomicAdd(count, 1u)] = (int32_t)r;
+  for (i64 r0 = wave * 8; r0 < rows; r0 += nwaves * 8) {
+    u64 any[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) any[q] = 0ull;
+    for (i64 w = lane; w < nw; w += 64) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (r0 + q < rows) any[q] |= a[(r0 + q) * ld + w];
+    }
+    u32 mask = 0;  // wave-uniform: bit q = row r0 + q has a set bit
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (__ballot(any[q] != 0ull)) mask |= 1u << q;
+    u32 base = 0;
+    if (lane == 0 && mask) base = atomicAdd(count, (u32)__popc(mask));
+    base = __shfl(base, 0, 64);
+    if (lane < 8 && ((mask >> lane) & 1u)) list[base + (u32)__popc(mask & ((1u << lane) - 1u))] = (int32_t)(r0 + lane);
   }
 }
 
@@ -763,7 +778,7 @@ hipError_t launch_rows_from_rp(const i64* rp, i64 rows, int32_t* out, hipStream_
 
 hipError_t launch_nonempty_rows(const u64* a, i64 rows, i64 n, i64 ld, int32_t* list, u32* count, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_nonempty_rows, dim3(grid_for(rows * 64, kBlock, 16384)), dim3(kBlock), 0, s, a, rows,
+  hipLaunchKernelGGL(k_nonempty_rows, dim3(grid_for(rows * 8, kBlock, 16384)), dim3(kBlock), 0, s, a, rows,
                      words_for(n), ld, list, count);
   return hipGetLastError();
 }
