@@ -756,8 +756,13 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
           int32_t* pinv;
           relabel_mode = rms_relabel(c, cur, ldi, n, o, s, &perm, &pinv);
           if (relabel_mode) {
-            // R_{t-1} in nxt is not needed by a dense squaring; the next one finds both in the new labels
-            hip_check(launch_permute(cur, ldi, perm, n, nxt, ldi, s), "permute");
+            // P R P^T, from the R^T that rms_relabel left in S_BT: its rows gathered in the new order (P R^T),
+            // transposed (R P^T), the rows gathered again -- two row gathers and a transpose cost half the
+            // bit-level permutation.  R_{t-1} in nxt is not needed by a dense squaring.
+            u64* ct = ws_bits(c, S_BT, n, ldi, o);
+            hip_check(launch_copy_rows(ct, ldi, perm, n, n, nxt, ldi, s), "copy_rows");
+            hip_check(launch_transpose(nxt, n, n, ldi, ct, ldi, s), "transpose");
+            hip_check(launch_copy_rows(ct, ldi, perm, n, n, nxt, ldi, s), "copy_rows");
             std::swap(cur, nxt);
             inv = pinv;
           }
@@ -828,7 +833,12 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
     // Algorithm 1, last line: R2* = R2* R1
     product(c, cur, ldi, R1, ld1, nullptr, 0, out, ldo, nullptr, 0, n, n, n, nullptr, arm, s, sr);
   } else if (inv) {
-    hip_check(launch_permute(cur, ldi, inv, n, out, ldo, s), "permute");
+    // back to the given labels, P^T C P: rows gathered by the inverse, transposed, gathered, transposed
+    u64* t2 = ws_bits(c, S_BT, n, ldi, o);
+    hip_check(launch_copy_rows(cur, ldi, inv, n, n, nxt, ldi, s), "copy_rows");
+    hip_check(launch_transpose(nxt, n, n, ldi, t2, ldi, s), "transpose");
+    hip_check(launch_copy_rows(t2, ldi, inv, n, n, nxt, ldi, s), "copy_rows");
+    hip_check(launch_transpose(nxt, n, n, ldi, out, ldo, s), "transpose");
   } else {
     hip_check(launch_ewise(4, cur, ldi, nullptr, 0, out, ldo, n, n, s), "copy");
   }
