@@ -160,5 +160,7 @@ hipError_t launch_rms_decide(u32* recs, int t, i64 n, int mfma, int may_gather, 
 // out[0] += set bits, out[1] = max(out[1], largest row count), out[2] += rows with a set bit
 // (out must be zeroed)
 hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* out, hipStream_t s);
+// out[0..2] = (sum, max, nonzero entries) of deg[0..n), one workgroup, plain stores
+hipError_t launch_deg_stats(const int32_t* deg, i64 n, unsigned long long* out, hipStream_t s);
 
 }  // namespace bmlp

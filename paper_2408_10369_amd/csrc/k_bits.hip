@@ -847,6 +847,53 @@ hipError_t launch_popcount_total(const u64* a, i64 rows, i64 n, i64 ld, unsigned
   return hipGetLastError();
 }
 
+// (set bits, largest row count, nonempty rows) from per-row counts, by one workgroup with plain stores into
+// out[0..2] (no atomics, nothing to clear first)
+__global__ void __launch_bounds__(1024) k_deg_stats(const int32_t* __restrict__ deg, i64 n,
+                                                    unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[16][3];
+  unsigned long long sum = 0, mx = 0, ne = 0;
+#pragma unroll 8
+  for (i64 i = threadIdx.x; i < n; i += 1024) {
+    const unsigned long long d = (unsigned long long)deg[i];
+    sum += d;
+    mx = d > mx ? d : mx;
+    ne += d != 0ull ? 1ull : 0ull;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sum += __shfl_xor(sum, off, 64);
+    const unsigned long long m2 = __shfl_xor(mx, off, 64);
+    mx = m2 > mx ? m2 : mx;
+    ne += __shfl_xor(ne, off, 64);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[wv][0] = sum;
+    part[wv][1] = mx;
+    part[wv][2] = ne;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      s0 += part[w][0];
+      s1 = part[w][1] > s1 ? part[w][1] : s1;
+      s2 += part[w][2];
+    }
+    out[0] = s0;
+    out[1] = s1;
+    out[2] = s2;
+  }
+}
+
+hipError_t launch_deg_stats(const int32_t* deg, i64 n, unsigned long long* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_deg_stats, dim3(1), dim3(1024), 0, s, deg, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* out, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_graph_stats, dim3(grid_for(rows * 64, kBlock, kStatBlocks)), dim3(kBlock), 0, s, a, rows,
