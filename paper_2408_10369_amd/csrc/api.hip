@@ -1186,12 +1186,21 @@ int smp_choose_arm(bmlp_ctx* c, const bmlp_opts& o, const GraphInfo& gi, i64 k, 
 // them), the 16 features (features.h) and, with allowed != 0, the model's decision among the allowed
 // outputs.  Returns the decision, or -1 when the model is not asked.
 int call_stats_decide(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const u64* Q, i64 qrows, i64 ldq, i64 k,
-                      float context, int reflexive, u32 allowed, hipStream_t s, GraphInfo* gi, double* delta0) {
+                      float context, int reflexive, u32 allowed, const bmlp_opts& o, hipStream_t s, GraphInfo* gi,
+                      double* delta0) {
   unsigned long long* gst = (unsigned long long*)(c->d_flags + F_GSTATS);
   unsigned long long* cnt = (unsigned long long*)(c->d_flags + F_CNT);
   float* feat = (float*)(c->d_flags + F_FEAT);
-  hip_check(hipMemsetAsync(gst, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
-  hip_check(launch_graph_stats(R, n, n, ld, gst, s), "graph_stats");
+  const int32_t* deg = nullptr;
+  if (n <= kDegStatsMaxN) {  // as graph_info: the statistics from the per-row counts, which stay in S_DEG
+    int32_t* d = (int32_t*)ws(c, S_DEG, (size_t)n * sizeof(int32_t), o);
+    hip_check(launch_row_popcount(R, n, n, ld, d, nullptr, s), "row_popcount");
+    hip_check(launch_deg_stats(d, n, gst, s), "deg_stats");
+    deg = d;
+  } else {
+    hip_check(hipMemsetAsync(gst, 0, 3 * sizeof(unsigned long long), s), "hipMemsetAsync");
+    hip_check(launch_graph_stats(R, n, n, ld, gst, s), "graph_stats");
+  }
   if (Q) {
     hip_check(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
     hip_check(launch_popcount_total(Q, qrows, n, ldq, cnt, s), "popcount_total");
@@ -1218,6 +1227,7 @@ int call_stats_decide(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const u64* Q, i6
   gi->m = (i64)v[0];
   gi->maxdeg = (i64)v[1];
   gi->nonempty = (i64)v[2];
+  gi->deg = deg;
   *delta0 = (double)d0;
   if (c->trace) std::memcpy(c->trace->call_features, c->h_flags + F_FEAT, kIn * sizeof(float));
   if (!allowed) return -1;
@@ -1855,13 +1865,15 @@ bmlp_status bmlp_rms(bmlp_handle h, const uint64_t* R1, uint64_t* Rstar, int64_t
         // outputs 2 (the closure by squaring, then its rows read) and 3 (the one-launch selection of the n
         // identity rows), as for a session's closure
         double delta0 = (double)n;
-        by_sel = call_stats_decide(h, R1, ld, n, nullptr, 0, 0, n, 0.f, 0, 0x4u | 0x8u, s, &gi, &delta0) == 3;
+        by_sel = call_stats_decide(h, R1, ld, n, nullptr, 0, 0, n, 0.f, 0, 0x4u | 0x8u, o, s, &gi, &delta0) == 3;
       }
       if (by_sel) {
         if (gi.n != n) gi = graph_info(h, R1, ld, n, o, s);
         if (stats) stats->arm = BMLP_ARM_SMP_CLOSURE_SELECT;
         if (h->trace) h->trace->call_arm = BMLP_ARM_SMP_CLOSURE_SELECT;
-        closure_by_selection(h, R1, ld, n, Rstar, ld, gi, Csr{}, o, s, sr);
+        Csr pre;
+        pre.deg = gi.deg;  // R1's row counts, just left in S_DEG by the statistics pass
+        closure_by_selection(h, R1, ld, n, Rstar, ld, gi, pre, o, s, sr);
       } else {
         rms_core(h, R1, ld, Rstar, ld, n, o, s, sr);
       }
@@ -1908,7 +1920,7 @@ bmlp_status bmlp_smp(bmlp_handle h, const uint64_t* R1, int64_t n, int64_t ld, c
           u32 allowed = 0x5u;  // rounds, closure
           if (n <= smp_rows_max_n()) allowed |= 0x8u;  // one-launch sparse
           double delta0 = 0.0;
-          const int d = call_stats_decide(h, R1, ld, n, V, k, ldv, k, 0.f, refl, model_call ? allowed : 0u, s, &gi,
+          const int d = call_stats_decide(h, R1, ld, n, V, k, ldv, k, 0.f, refl, model_call ? allowed : 0u, o, s, &gi,
                                           &delta0);
           if (forced) arm = o.smp_arm;
           else if (model_call) arm = d == 2 ? BMLP_ARM_SMP_CLOSURE : d == 3 ? BMLP_ARM_SMP_SPARSE : BMLP_ARM_SMP_ADAPTIVE;
@@ -2196,7 +2208,7 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
         if (rowwise_ok) allowed |= 0x2u;
         if (n <= smp_rows_max_n()) allowed |= 0x8u;
         double delta0 = 0.0;
-        const int d = call_stats_decide(h, Rstep, ld, n, Rbase, n, ld, n, 1.f, 1, learned ? allowed : 0u, s, &gs,
+        const int d = call_stats_decide(h, Rstep, ld, n, Rbase, n, ld, n, 1.f, 1, learned ? allowed : 0u, o, s, &gs,
                                         &delta0);
         if (learned) {
           arm = d == 1 ? BMLP_ARM_COMPOSE_ROWWISE : d == 2 ? BMLP_ARM_COMPOSE_RMS : BMLP_ARM_COMPOSE_SEMINAIVE;
