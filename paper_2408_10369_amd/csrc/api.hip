@@ -129,6 +129,7 @@ enum FlagSlot {
   F_ROUNDS_OUT = 48,  // host side only: a one-launch selection's round count, read at the end of the call
   F_TOT0 = 50,        // host side only: the first running bit count of an RMS chain, uploaded from here
   F_DEFER = 54,       // an out-of-range fact given to bmlp_pack_coo_async (latched until bmlp_deferred_error)
+  F_VBITS = 56,       // 64-bit count of a gather's query-row bits, from which the device sizes its pieces
   F_CHAIN = 128,      // BMLP-RMS: one record of kRmsRecWords words per squaring (rms_core)
   F_WORDS = 512
 };
@@ -2250,7 +2251,16 @@ bmlp_status bmlp_compose_linear(bmlp_handle h, const uint64_t* Rbase, const uint
           hip_check(launch_set_onehot(v1, nw, drows, kr, n, nullptr, s), "set_onehot");
           if (sarm == BMLP_ARM_AUTO || sarm == BMLP_ARM_SMP_ADAPTIVE) sarm = smp_plain_arm(n, kr, gs.m);
           smp_core(h, Rstep, ld, n, v1, sel, kr, nw, 0, sarm, gs, 1, Csr{rp, ci}, o, s, sr);
-          const GatherQueue gq = gather_queue(h, kr, n, o);
+          // the selected rows hold as many bits as Rstep's closure rows (thousands where it is large): the
+          // pieces are sized on the device from their count, twice the mean row, instead of the default 64,
+          // which split such rows into many pieces merged with atomics
+          GatherQueue gq = gather_queue(h, kr, n, o);
+          if (gq.e) {
+            unsigned long long* vb = (unsigned long long*)(h->d_flags + F_VBITS);
+            hip_check(launch_fill_zero((u64*)vb, 1, s), "fill_zero");
+            hip_check(launch_popcount_total(sel, kr, n, nw, vb, s), "popcount_total");
+            gq.bits = vb;
+          }
           hip_check(launch_gather_rows(sel, nw, kr, Rbase, ld, n, 2, P, ld, s, drows, nullptr, &gq), "gather_rows");
           // the host list is read by the upload above; wait before it goes out of scope
           hip_check(hipStreamSynchronize(s), "sync");
