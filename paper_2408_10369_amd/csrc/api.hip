@@ -56,8 +56,6 @@ struct bmlp_ctx {
   u32* d_flags = nullptr;  // device flags / counters
   unsigned char* scratch = nullptr;  // this device's address of the file-scope scratch array (bmlp_smp_noalloc)
   u32* h_flags = nullptr;  // pinned host mirror
-  void* h_pin = nullptr;   // pinned host staging for larger readbacks (the relabelling's counts), grown on demand
-  size_t h_pin_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evp0 = nullptr, evp1 = nullptr;
   // timed products awaiting their readback (statistics): event pairs and matrix-core work counters
   static constexpr int kPend = 64;
@@ -130,6 +128,7 @@ enum FlagSlot {
   F_TOT0 = 50,        // host side only: the first running bit count of an RMS chain, uploaded from here
   F_DEFER = 54,       // an out-of-range fact given to bmlp_pack_coo_async (latched until bmlp_deferred_error)
   F_VBITS = 56,       // 64-bit count of a gather's query-row bits, from which the device sizes its pieces
+  F_RELABEL = 58,     // 9 x 64-bit: the relabelling's class counts (k_relabel_classes)
   F_CHAIN = 128,      // BMLP-RMS: one record of kRmsRecWords words per squaring (rms_core)
   F_WORDS = 512
 };
@@ -537,23 +536,6 @@ GraphInfo graph_info(bmlp_ctx* c, const u64* R, i64 ld, i64 n, const bmlp_opts& 
   return g;
 }
 
-// Pinned host staging of at least `bytes` (pageable copies of a few hundred KB cost the relabelling about
-// 0.4 ms of staging).  Its contents last until the next call that asks for it.
-void* pinned(bmlp_ctx* c, size_t bytes) {
-  if (c->h_pin_bytes < bytes) {
-    if (c->h_pin) {
-      hip_check(hipDeviceSynchronize(), "sync");  // no copy may still use the old buffer
-      hip_check(hipHostFree(c->h_pin), "hipHostFree");
-      c->h_pin = nullptr;
-      c->h_pin_bytes = 0;
-    }
-    const size_t nb = std::max<size_t>(bytes, (size_t)1 << 20);
-    hip_check(hipHostMalloc(&c->h_pin, nb, hipHostMallocDefault), "hipHostMalloc");
-    c->h_pin_bytes = nb;
-  }
-  return c->h_pin;
-}
-
 // Relabelling before the dense squarings.  Where a relation's closure is one big block -- the rows that
 // reach a giant strongly connected part times the columns it reaches, the sparse random digraphs just
 // above the percolation threshold -- the block is spread over every 256 x 256 output tile in the given
@@ -579,60 +561,30 @@ int rms_relabel(bmlp_ctx* c, const u64* cur, i64 ld, i64 n, const bmlp_opts& o, 
   hip_check(launch_row_popcount(cur, n, n, ld, rowpop, nullptr, s), "row_popcount");
   hip_check(launch_transpose(cur, n, n, ld, ct, nw, s), "transpose");
   hip_check(launch_row_popcount(ct, n, n, nw, colpop, nullptr, s), "row_popcount");
-  // pinned: the row counts, the column counts, then the permutation and its inverse (4 n words)
-  int32_t* const rp = (int32_t*)pinned(c, (size_t)(4 * n) * sizeof(int32_t));
-  int32_t* const cp = rp + n;
-  hip_check(hipMemcpyAsync(rp, rowpop, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
-  hip_check(hipMemcpyAsync(cp, colpop, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "memcpy");
+  // the classes are counted and the permutation formed on the device; the host reads the counts alone
+  unsigned long long* sum = (unsigned long long*)(c->d_flags + F_RELABEL);
+  hip_check(launch_relabel_classes(rowpop, colpop, n, sum, s), "relabel_classes");
+  hip_check(hipMemcpyAsync(c->h_flags + F_RELABEL, sum, 7 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+            "memcpy");
   hip_check(hipStreamSynchronize(s), "sync");
-  const int32_t rmax = *std::max_element(rp, rp + n);
-  const int32_t cmax = *std::max_element(cp, cp + n);
+  unsigned long long v[7];
+  std::memcpy(v, c->h_flags + F_RELABEL, sizeof v);
+  const i64 rmax = (i64)v[0], cmax = (i64)v[1], hin = (i64)v[2], hout = (i64)v[3], dead = (i64)v[4];
+  const i64 drt = (i64)v[5], dct = (i64)v[6];
   if (rmax <= 0 || cmax <= 0) return 0;
-  // class 0 heavy row and light column, 1 heavy both, 2 light row and heavy column, 3 light both (written
-  // without branches: the classes of neighbouring nodes are unrelated)
-  std::vector<uint8_t> cls((size_t)n);
-  i64 hin = 0, hout = 0;
-  for (i64 v = 0; v < n; ++v) {
-    const int in = 4 * (i64)rp[v] >= rmax, out = 4 * (i64)cp[v] >= cmax;
-    hin += in;
-    hout += out;
-    cls[v] = (uint8_t)(2 * (1 - in) + (in == out));
-  }
   auto splits = [&](i64 h) { return h * 50 >= n && h * 10 <= 9 * n; };  // a light class of at least 10%
   int mode = 1;
   if (!splits(hin) && !splits(hout)) {
-    mode = 2;
     // dead nodes: a row or a column with fewer than 1/64 of the largest count's bits
     const i64 tiles = (n + 255) / 256;
-    std::vector<char> rt((size_t)tiles, 0), ct((size_t)tiles, 0);
-    i64 dead = 0;
-    for (i64 v = 0; v < n; ++v) {
-      const bool dr = 64 * (i64)rp[v] < rmax, dc = 64 * (i64)cp[v] < cmax;
-      cls[v] = (uint8_t)((dr || dc) ? 1 : 0);
-      dead += cls[v];
-      if (dr) rt[(size_t)(v / 256)] = 1;
-      if (dc) ct[(size_t)(v / 256)] = 1;
-    }
-    const i64 drt = std::count(rt.begin(), rt.end(), (char)1), dct = std::count(ct.begin(), ct.end(), (char)1);
     const i64 dirty = drt * tiles + dct * tiles - drt * dct;  // tiles with a dead row or column now
     const i64 last = (n - 1) / 256 - (n - dead) / 256 + 1;     // tile rows the dead nodes take at the end
     const i64 after = 2 * last * tiles - last * last;
     if (dead == 0 || dead * 50 > n || (dirty - after) * 20 < tiles * tiles) return 0;
-    for (i64 v = 0; v < n; ++v) cls[v] = (uint8_t)(1 + 2 * cls[v]);
+    mode = 2;
   }
-  // the nodes by class, in their order within a class: one branch-free pass per class (a write past the
-  // last placed node lands in perm[n], which the inverse overwrites)
-  int32_t* const perm = rp + 2 * n;
-  i64 at = 0;
-  for (int k = 0; k < 4; ++k)
-    for (i64 v = 0; v < n; ++v) {
-      perm[at] = (int32_t)v;
-      at += cls[v] == k;
-    }
-  for (i64 i = 0; i < n; ++i) perm[n + perm[i]] = (int32_t)i;
   int32_t* d = (int32_t*)ws(c, S_PERM, (size_t)(2 * n) * sizeof(int32_t), o);
-  hip_check(hipMemcpyAsync(d, perm, (size_t)(2 * n) * sizeof(int32_t), hipMemcpyHostToDevice, s), "memcpy");
-  hip_check(hipStreamSynchronize(s), "sync");  // the staging is reused by the next call
+  hip_check(launch_relabel_perm(rowpop, colpop, n, mode, sum, d, d + n, s), "relabel_perm");
   *perm_out = d;
   *inv_out = d + n;
   return mode;
@@ -1344,7 +1296,6 @@ bmlp_status bmlp_destroy(bmlp_handle h) {
         if (h->slot[i]) (void)hipFree(h->slot[i]);
       if (h->d_flags) (void)hipFree(h->d_flags);
       if (h->h_flags) (void)hipHostFree(h->h_flags);
-      if (h->h_pin) (void)hipHostFree(h->h_pin);
       if (h->ev0) (void)hipEventDestroy(h->ev0);
       if (h->ev1) (void)hipEventDestroy(h->ev1);
       if (h->evp0) (void)hipEventDestroy(h->evp0);

@@ -162,5 +162,11 @@ hipError_t launch_rms_decide(u32* recs, int t, i64 n, int mfma, int may_gather, 
 hipError_t launch_graph_stats(const u64* a, i64 rows, i64 n, i64 ld, unsigned long long* out, hipStream_t s);
 // out[0..2] = (sum, max, nonzero entries) of deg[0..n), one workgroup, plain stores
 hipError_t launch_deg_stats(const int32_t* deg, i64 n, unsigned long long* out, hipStream_t s);
+// The relabelling of rms_core from row and column counts (n <= 262,144): out (9 u64) = rmax, cmax, heavy
+// rows, heavy columns, dead nodes, tiles with a dead row, tiles with a dead column; then perm / inv for
+// mode 1 (heavy/light classes) or 2 (dead nodes last), maxes = that out.
+hipError_t launch_relabel_classes(const int32_t* rp, const int32_t* cp, i64 n, unsigned long long* out, hipStream_t s);
+hipError_t launch_relabel_perm(const int32_t* rp, const int32_t* cp, i64 n, int mode, const unsigned long long* maxes,
+                               int32_t* perm, int32_t* inv, hipStream_t s);
 
 }  // namespace bmlp

@@ -888,6 +888,166 @@ __global__ void __launch_bounds__(1024) k_deg_stats(const int32_t* __restrict__ 
   }
 }
 
+// The relabelling's classes, from a relation's row and column counts rp, cp (n each), by one workgroup.
+// With the largest counts rmax, cmax: a node is heavy as a row when 4 rp >= rmax, as a column when
+// 4 cp >= cmax, dead as a row when 64 rp < rmax, as a column when 64 cp < cmax.  out (9 u64): rmax, cmax,
+// heavy rows, heavy columns, dead nodes (dead row or column), 256-node tiles holding a dead row, tiles
+// holding a dead column, and two zero words.  Tiles are flagged in LDS: n <= 256 * kRelabelTiles.
+constexpr int kRelabelTiles = 1024;
+__device__ __forceinline__ unsigned long long block_sum_1024(unsigned long long v, unsigned long long* part) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();  // part may still be read by a previous call
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) t += part[w];
+  return t;
+}
+__device__ __forceinline__ unsigned long long block_max_1024(unsigned long long v, unsigned long long* part) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) t = part[w] > t ? part[w] : t;
+  return t;
+}
+
+__global__ void __launch_bounds__(1024) k_relabel_classes(const int32_t* __restrict__ rp, const int32_t* __restrict__ cp,
+                                                          i64 n, unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[16];
+  __shared__ u32 rt[kRelabelTiles], ct[kRelabelTiles];
+  const int t = threadIdx.x;
+  const i64 tiles = (n + 255) / 256;
+  for (i64 i = t; i < tiles; i += 1024) rt[i] = ct[i] = 0u;
+  unsigned long long mr = 0, mc = 0;
+  for (i64 v = t; v < n; v += 1024) {
+    const unsigned long long a = (unsigned long long)rp[v], b = (unsigned long long)cp[v];
+    mr = a > mr ? a : mr;
+    mc = b > mc ? b : mc;
+  }
+  const unsigned long long rmax = block_max_1024(mr, part);
+  const unsigned long long cmax = block_max_1024(mc, part);
+  unsigned long long hin = 0, hout = 0, dead = 0;
+  for (i64 v = t; v < n; v += 1024) {
+    const unsigned long long a = (unsigned long long)rp[v], b = (unsigned long long)cp[v];
+    hin += 4 * a >= rmax ? 1u : 0u;
+    hout += 4 * b >= cmax ? 1u : 0u;
+    const bool dr = 64 * a < rmax, dc = 64 * b < cmax;
+    dead += (dr || dc) ? 1u : 0u;
+    if (dr) rt[v / 256] = 1u;  // benign races: every writer stores 1
+    if (dc) ct[v / 256] = 1u;
+  }
+  hin = block_sum_1024(hin, part);
+  hout = block_sum_1024(hout, part);
+  dead = block_sum_1024(dead, part);  // its barriers also order the tile flags before they are read
+  unsigned long long drt = 0, dct = 0;
+  for (i64 i = t; i < tiles; i += 1024) {
+    drt += rt[i];
+    dct += ct[i];
+  }
+  drt = block_sum_1024(drt, part);
+  dct = block_sum_1024(dct, part);
+  if (t == 0) {
+    out[0] = rmax;
+    out[1] = cmax;
+    out[2] = hin;
+    out[3] = hout;
+    out[4] = dead;
+    out[5] = drt;
+    out[6] = dct;
+    out[7] = 0ull;
+    out[8] = 0ull;
+  }
+}
+
+// The relabelling itself: the nodes ordered by class, in their given order within a class, as perm[new] =
+// old and inv[old] = new, by one workgroup (a stable counting sort: thread t takes the nodes of one
+// contiguous chunk, a workgroup scan gives each thread its place in every class).  mode 1: the four
+// heavy/light classes (0 heavy row and light column, 1 heavy both, 2 light row and heavy column, 3 light
+// both); mode 2: the dead nodes after all others.  rmax, cmax are k_relabel_classes' out[0], out[1].
+__global__ void __launch_bounds__(1024) k_relabel_perm(const int32_t* __restrict__ rp, const int32_t* __restrict__ cp,
+                                                       i64 n, int mode, const unsigned long long* __restrict__ maxes,
+                                                       int32_t* __restrict__ perm, int32_t* __restrict__ inv) {
+  __shared__ unsigned long long wsum[2][16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const unsigned long long rmax = maxes[0], cmax = maxes[1];
+  auto cls_of = [&](i64 v) -> int {
+    const unsigned long long a = (unsigned long long)rp[v], b = (unsigned long long)cp[v];
+    if (mode == 1) {
+      const int in = 4 * a >= rmax, out = 4 * b >= cmax;
+      return 2 * (1 - in) + (in == out);
+    }
+    return (64 * a < rmax || 64 * b < cmax) ? 3 : 1;
+  };
+  const i64 chunk = (n + 1023) / 1024;
+  const i64 v0 = (i64)t * chunk, v1 = v0 + chunk < n ? v0 + chunk : n;
+  // this thread's count per class, two classes per 64-bit word (32-bit fields: n < 2^31)
+  unsigned long long c01 = 0, c23 = 0;
+  for (i64 v = v0; v < v1; ++v) {
+    const int k = cls_of(v);
+    c01 += k == 0 ? 1ull : k == 1 ? (1ull << 32) : 0ull;
+    c23 += k == 2 ? 1ull : k == 3 ? (1ull << 32) : 0ull;
+  }
+  // exclusive scan over the threads: within the wave by shuffles, then over the 16 waves' totals
+  unsigned long long s01 = c01, s23 = c23;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long a = __shfl_up(s01, off, 64), b = __shfl_up(s23, off, 64);
+    if (lane >= off) {
+      s01 += a;
+      s23 += b;
+    }
+  }
+  if (lane == 63) {
+    wsum[0][wv] = s01;
+    wsum[1][wv] = s23;
+  }
+  __syncthreads();
+  unsigned long long b01 = 0, b23 = 0, t01 = 0, t23 = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    if (w < wv) {
+      b01 += wsum[0][w];
+      b23 += wsum[1][w];
+    }
+    t01 += wsum[0][w];
+    t23 += wsum[1][w];
+  }
+  s01 += b01 - c01;  // exclusive prefix of this thread
+  s23 += b23 - c23;
+  // the first position of each class, then of this thread within it
+  const i64 tot0 = (i64)(t01 & 0xFFFFFFFFull), tot1 = (i64)(t01 >> 32), tot2 = (i64)(t23 & 0xFFFFFFFFull);
+  i64 pos[4] = {(i64)(s01 & 0xFFFFFFFFull), tot0 + (i64)(s01 >> 32), tot0 + tot1 + (i64)(s23 & 0xFFFFFFFFull),
+                tot0 + tot1 + tot2 + (i64)(s23 >> 32)};
+  for (i64 v = v0; v < v1; ++v) {
+    const int k = cls_of(v);
+    const i64 p = pos[k]++;
+    perm[p] = (int32_t)v;
+    inv[v] = (int32_t)p;
+  }
+}
+
+hipError_t launch_relabel_classes(const int32_t* rp, const int32_t* cp, i64 n, unsigned long long* out, hipStream_t s) {
+  if (n <= 0 || (n + 255) / 256 > kRelabelTiles) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_relabel_classes, dim3(1), dim3(1024), 0, s, rp, cp, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_relabel_perm(const int32_t* rp, const int32_t* cp, i64 n, int mode, const unsigned long long* maxes,
+                               int32_t* perm, int32_t* inv, hipStream_t s) {
+  if (n <= 0 || (mode != 1 && mode != 2)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_relabel_perm, dim3(1), dim3(1024), 0, s, rp, cp, n, mode, maxes, perm, inv);
+  return hipGetLastError();
+}
+
 hipError_t launch_deg_stats(const int32_t* deg, i64 n, unsigned long long* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_deg_stats, dim3(1), dim3(1024), 0, s, deg, n, out);
