@@ -766,7 +766,10 @@ i64 batch_bfs_max_n() { return (i64)kBfsWords * 64; }
 
 i64 batch_ms_max_n() { return (i64)kMsWords * 64; }
 
-i64 batch_mfma_min_n() { return 1024; }
+// A graph of at least one whole 256 x 256 tile squares its dense blocks on the matrix cores: on the
+// 512-graph batch (n from 64 to 4,096) the threshold at 256 ran 12.5 ms, at 512 12.8 ms, at 1,024 13.7 ms,
+// at 2,048 15.9 ms (plain schedule).
+i64 batch_mfma_min_n() { return 256; }
 
 i64 batch_qsel_offset(int count, const BatchPlan& p) {
   const i64 w = 2 * (i64)count * p.rounds + 2 * (i64)p.rounds + 2 + p.total_mblocks;
