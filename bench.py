@@ -45,8 +45,8 @@ KERNELS = {0: ("k_gemm_valu", "bit-packed Boolean product on the VALU", "alu", V
 GEMM_TRAFFIC = {"k_gemm_mfma": {"sources": ["paper_2408_10369_amd/csrc/k_gemm.hip",
                                             "paper_2408_10369_amd/csrc/mfma_tile.h",
                                             "paper_2408_10369_amd/csrc/mfma_tile2.h"],
-                                "sha256": "b6e0794351520e594964619341a7293cf896ea9cdd9fb340474879ca430f41bd",
-                                "bytes_per_launch": 373.1e6}}
+                                "sha256": "e3bf4d7813161745c720ae85670a1647477f30706baec45eec3aa736865133a5",
+                                "bytes_per_launch": 451.2e6}}
 
 
 def measured_traffic(kernel):

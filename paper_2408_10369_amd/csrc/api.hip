@@ -443,14 +443,19 @@ int tuned_variant(const bmlp_ctx* c, int kernel, i64 M, i64 K, i64 N, double den
 // One Boolean product C = Cold | A.B (D, changed optional) with the chosen arm.  The MFMA arm reads B
 // transposed: pass BT when the caller has it, else B is transposed into workspace first.
 // `density`: the fraction of set bits of A when the caller knows it (else -1); with `structured` (A is a
-// relabelled, block-structured relation) it picks the tuned tile code.
+// relabelled, block-structured relation) it picks the tuned tile code.  `early` (or a nonzero *early_flag
+// on the device): A.B likely saturates within the first chunk of k (a squaring of a dense relation,
+// rms_early_votes), so the matrix-core tiles vote before loading ahead.
 void product(bmlp_ctx* c, const u64* A, i64 lda, const u64* B, i64 ldb, const u64* Cold, i64 ldco, u64* C, i64 ldc,
              u64* D, i64 ldd, i64 M, i64 K, i64 N, u32* changed, int arm, hipStream_t s, StatsRec& sr,
              const u64* BT = nullptr, i64 ldbt = 0, unsigned long long* newbits = nullptr, double density = -1.0,
-             bool structured = false, const u32* pred = nullptr, u32 pred_val = 0) {
+             bool structured = false, const u32* pred = nullptr, u32 pred_val = 0, const u32* early_flag = nullptr,
+             bool early = false) {
   GemmArgs g{A, lda, B, ldb, Cold, ldco, C, ldc, D, ldd, M, K, N, changed};
   g.executed = sr.exec_counter();
   g.newbits = newbits;
+  g.early_flag = early_flag;
+  g.early = early;
   g.pred = pred;  // with pred, the product (and the transpose it needs) runs only when *pred == pred_val
   g.pred_val = pred_val;
   if (arm == BMLP_ARM_PRODUCT_MFMA) {
@@ -735,9 +740,9 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
             inv = pinv;
           }
         }
+        const double dens = g0.n == n ? (double)bits / ((double)n * (double)n) : -1.0;  // kept once counted
         product(c, cur, ldi, cur, ldi, cur, ldi, nxt, ldi, nullptr, 0, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb,
-                g0.n == n ? (double)bits / ((double)n * (double)n) : -1.0,  // the bit count is kept once counted
-                relabel_mode == 1);
+                dens, relabel_mode == 1, nullptr, 0, nullptr, g0.n == n && rms_early_votes(n, bits));
       }
     }
     sr.trace(it, tarm);
@@ -763,8 +768,9 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
       }
       // the bit count of R_it is not known on the host yet: a squaring that falls to the dense product
       // counts as dense for the tuned tile code (sparser ones go to the gathers)
+      // (the decision kernel also flags a dense R, whose tiles vote after their first chunk: rms_early_votes)
       product(c, nxt, ldi, nxt, ldi, nxt, ldi, cur, ldi, nullptr, 0, n, n, n, nullptr, arm, s, sr, nullptr, 0, nb2, -1.0,
-              relabel_mode == 1, route, RR_DENSE);
+              relabel_mode == 1, route, RR_DENSE, recs + (i64)it * kRmsRecWords + kRmsRecEarly);
     }
     // read back this squaring's count and, when the next one was enqueued, its route (one contiguous copy)
     const size_t words = ahead ? (size_t)kRmsRecWords + 5 : 2;
@@ -782,6 +788,8 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
     dbits = (i64)added;
     have_prev = true;
     const bool changed = added != 0;
+    // an all-ones R is its own square (the count is exact once R1's bits were counted)
+    const bool full = g0.n == n && bits >= n * n;
     std::swap(cur, nxt);
     queued = ahead ? c->h_flags[F_CHAIN + (i64)it * kRmsRecWords + 4] : (u32)RR_HOST;
     if (ahead && queued != RR_DENSE) sr.cancel_last();  // the product enqueued ahead did not run
@@ -791,7 +799,7 @@ void rms_core(bmlp_ctx* c, const u64* R1, i64 ld1, u64* out, i64 ldo, i64 n, con
       else sr.cancel(ahead_gather);
       ahead_gather = -1;
     }
-    if (!changed) break;
+    if (!changed || full) break;
     need(queued != RR_STOP, BMLP_EDEVICE, "RMS: the device saw no new bits");
     if (ahead && queued != RR_GATHER) may_gather = false;  // the device found that gathers no longer pay
     need(it < cap, BMLP_EITER, "RMS exceeded %d products (n=%lld)", cap, (long long)n);

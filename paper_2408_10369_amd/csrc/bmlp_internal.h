@@ -94,6 +94,10 @@ struct GemmArgs {
   const u32* pred = nullptr;              // when given, the kernel runs only if *pred == pred_val
   u32 pred_val = 0;
   unsigned long long* executed = nullptr;  // += matrix-core ops actually issued (MFMA arm, optional)
+  // A likely saturates early (MFMA arm, second tile code): with early set, or early_flag given and nonzero,
+  // a whole tile votes on saturation after its first chunk of k, before it loads further chunks
+  const u32* early_flag = nullptr;
+  bool early = false;
 };
 enum ProductKernel { PK_VALU = 0, PK_MFMA = 1 };
 // variant (autotuner candidates, identical bits): rows per wave of the tile for M > 64: 0 -> 16, 1 -> 8,
@@ -152,9 +156,9 @@ hipError_t launch_gather_rows(const u64* V, i64 ldv, i64 k, const u64* Cl, i64 l
                               const u32* pred = nullptr, u32 pred_val = 0);
 i64 gather_rows_max_n();
 // The route of BMLP-RMS squaring t, decided on the device from the bits squaring t - 1 added: recs holds
-// kRmsRecWords-word records {new bits u64, running count u64, route u32} per squaring; reads record t - 1,
-// writes record t's running count and route (stop / row gathers / dense product / back to the host for
-// the semi-naive form or the relabelling).  One thread.
+// kRmsRecWords-word records {new bits u64, running count u64, route u32, early flag u32} per squaring; reads
+// record t - 1, writes record t's running count, route (stop / row gathers / dense product / back to the
+// host for the semi-naive form or the relabelling) and early flag (rms_early_votes).  One thread.
 hipError_t launch_rms_decide(u32* recs, int t, i64 n, int mfma, int may_gather, int may_semi, int dense_ok,
                              i64 gather_max_n, hipStream_t s);
 // out[0] += set bits, out[1] = max(out[1], largest row count), out[2] += rows with a set bit

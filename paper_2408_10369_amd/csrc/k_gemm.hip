@@ -201,7 +201,8 @@ k_gemm_mfma2(MfmaTile g, const u32* __restrict__ pred, u32 pred_val) {
 }
 
 // The device-side choice of the next RMS squaring's route (see launch_rms_decide), the same rules the host
-// driver applies: stop when the last squaring added nothing; row gathers while they pay; the semi-naive
+// driver applies: stop when the last squaring added nothing or R is all ones (its own square; the running
+// count never exceeds R's bits, so it reaches n^2 only then); row gathers while they pay; the semi-naive
 // form (driven by the host) when it may pay; else the dense product, unless the relabelling is still due.
 __global__ void k_rms_decide(u32* __restrict__ recs, int t, i64 n, int mfma, int may_gather, int may_semi,
                              int dense_ok, i64 gather_max_n) {
@@ -212,11 +213,12 @@ __global__ void k_rms_decide(u32* __restrict__ recs, int t, i64 n, int mfma, int
   const unsigned long long bits = prev[1] + added;
   cur[1] = bits;
   u32 route;
-  if (added == 0) route = RR_STOP;
+  if (added == 0 || bits >= (unsigned long long)n * (unsigned long long)n) route = RR_STOP;
   else if (may_gather && rms_gather_pays(n, (i64)bits, mfma != 0, gather_max_n)) route = RR_GATHER;
   else if (may_semi && rms_semi_may_pay(n, (i64)added, mfma != 0)) route = RR_HOST;
   else route = dense_ok ? RR_DENSE : RR_HOST;
   recs[(i64)t * kRmsRecWords + 4] = route;
+  recs[(i64)t * kRmsRecWords + kRmsRecEarly] = rms_early_votes(n, (i64)bits) ? 1u : 0u;
 }
 
 }  // namespace
@@ -244,8 +246,10 @@ hipError_t launch_gemm_mfma(const GemmArgs& g, const u64* BT, i64 ldbt, hipStrea
   if (words_for(g.K) > kMaxKWords) return hipErrorInvalidValue;
   if (!gemm_mfma_variant_ok(variant, g, BT, ldbt)) variant = 0;
   const i64 tiles = ((g.M + kMT - 1) / kMT) * ((g.N + kMT - 1) / kMT);
-  const MfmaTile t{g.A, g.lda, BT, ldbt, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N,
-                    g.changed, g.newbits, g.executed, nullptr};
+  MfmaTile t{g.A, g.lda, BT, ldbt, g.Cold, g.ldco, g.C, g.ldc, g.D, g.ldd, g.M, g.K, g.N,
+              g.changed, g.newbits, g.executed, nullptr};
+  t.early_flag = g.early_flag;
+  t.early = g.early ? 1u : 0u;
   const dim3 grid((unsigned)tiles), block(512);
   switch (variant) {
     case 6: hipLaunchKernelGGL((k_gemm_mfma<3>), grid, block, 0, s, t, g.pred, g.pred_val); break;

@@ -54,11 +54,12 @@ constexpr i64 kMaxKWords = 65536;  // sums <= 4 K <= 2^24 stay exact in fp32
 
 __device__ __forceinline__ u32 rotr2(u32 x) { return __builtin_amdgcn_alignbit(x, x, 2); }
 
-// LDS of one tile (128 KiB + epilogue ballots), declared once per kernel that uses mfma_tile
+// LDS of one tile (128 KiB + the C_old tile and the epilogue's ballots), declared once per kernel that uses mfma_tile
 struct MfmaLds {
   uint4 Ax[2][2][kMT][kMChunk];  // per stage, lane half h, row and word slot: the dwords half h feeds in
   uint4 Bx[2][2][kMT][kMChunk];
-  u64 bal[8][2][16];
+  u64 bal[8][2][16];  // per wave: the ballots of a block row (tile_epilogue)
+  u64 cold[kMT][4];  // the tile's C_old words (row, word of the tile), kept by tile_cold_full
   u32 zmask[2][8];  // per stage and staging wave (A: 0..3, B^T: 4..7): bit q = some row has a nonzero word q
   u32 satf[2][8];   // per vote (alternating) and wave: every output of the wave's 128 x 64 block is set
   u64 cnt[8][3];    // per wave: new bits, words of k multiplied, changed (tile_counters)
@@ -75,6 +76,10 @@ struct MfmaTile {
   unsigned long long* newbits;
   unsigned long long* executed;
   u32* changed2;  // optional second flag set with *changed
+  // the second tile code: a whole tile votes after its first chunk, before loading ahead, when early is
+  // nonzero or *early_flag is (A is dense, so the tiles likely saturate there)
+  const u32* early_flag = nullptr;
+  u32 early = 0;
 };
 
 // Adds a tile's counts to the launch's counters (new bits, matrix-core work issued, the changed flags) with
@@ -113,6 +118,92 @@ __device__ __forceinline__ void tile_counters(u64 (&cnt)[8][3], const MfmaTile& 
   }
 }
 
+// Reads the C_old words of output tile (row0, col0), 256 rows of 4 words: thread t takes words t and
+// t + 512 (row e / 4, word e % 4) and keeps them in `cold` for the epilogue.  Returns, the same in every
+// thread, whether every bit of the tile is set; such a tile is final (C = C_old whatever A.B adds), and it
+// is copied to C (and D cleared) here.  Every thread of the 512 must call it; it ends with a barrier.
+__device__ __forceinline__ bool tile_cold_full(u64 (&cold)[kMT][4], const MfmaTile& g, i64 row0, i64 col0) {
+  static_assert(kMT * 4 == 2 * 512, "two C_old words per thread");
+  const int t = threadIdx.x;
+  const i64 nw = (g.N + 63) >> 6;
+  const u64 last_mask = (g.N & 63) ? ((1ull << (g.N & 63)) - 1ull) : ~0ull;
+  u64 v[2];
+  bool in[2];
+  int full = 1;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = t + 512 * k;
+    const i64 row = row0 + (e >> 2), w = (col0 >> 6) + (e & 3);
+    in[k] = row < g.M && w < nw;
+    v[k] = in[k] ? g.Cold[row * g.ldco + w] : 0ull;
+    if (in[k]) full &= v[k] == (w == nw - 1 ? last_mask : ~0ull);
+    cold[e >> 2][e & 3] = v[k];
+  }
+  if (!__syncthreads_and(full)) return false;
+  const bool copy = g.C != g.Cold || g.ldc != g.ldco;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = t + 512 * k;
+    const i64 row = row0 + (e >> 2), w = (col0 >> 6) + (e & 3);
+    if (in[k]) {
+      if (copy) g.C[row * g.ldc + w] = v[k];
+      if (g.D) g.D[row * g.ldd + w] = 0ull;
+    }
+  }
+  return true;
+}
+
+// s_waitcnt lgkmcnt(0), with vmcnt and expcnt at their maxima (gfx9 encoding): waits for LDS, not for memory
+constexpr int kWaitLdsOnly = 0xC07F;
+
+// The tile's epilogue: C = C_old | (sum > 0), D = C & ~C_old, then the counters.  A 32 x 32 fp32 block sits
+// in lane l as column l % 32, register r holding row 8 (r / 4) + 4 (l / 32) + r % 4, so a ballot of "> 0" on
+// register r holds columns 0..31 of two rows: 8 (r / 4) + r % 4 in its low half and the row 4 below in its
+// high half.  Lane 0 keeps the ballots of a block row in LDS (bal, per wave); lane rho < 32 then assembles
+// row rho's word of C from the two blocks side by side (columns 0..31 and 32..63).  Only LDS is waited
+// for: the stores of C are never waited on, and C_old comes from LDS (tile_cold_full's copy).  cold: that
+// copy, or null for C_old = 0.  Every thread of the 512 must call it.
+__device__ __forceinline__ void tile_epilogue(const v16f_t (&acc)[4][2], u64 (&bal)[8][2][16], const u64 (*cold)[4],
+                                              const MfmaTile& g, i64 row0, i64 col0, u32 done_words,
+                                              u64 (&cnt)[8][3]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int rho = lane & 31;
+  const int hh = (rho >> 2) & 1, r = ((rho >> 3) << 2) | (rho & 3);  // rho = 8 (r / 4) + 4 hh + r % 4
+  const i64 nw = (g.N + 63) >> 6;
+  const i64 w = (col0 >> 6) + wc;
+  int ch = 0;
+  u32 pop = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const u64 b = __ballot(acc[i][j][q] > 0.f);
+        if (lane == 0) bal[wave][j][q] = b;
+      }
+    }
+    // the lanes below read what lane 0 of the same wave wrote (LDS keeps a wave's order)
+    __builtin_amdgcn_s_waitcnt(kWaitLdsOnly);
+    __builtin_amdgcn_wave_barrier();
+    const int trow = wr * 128 + i * 32 + rho;
+    const i64 row = row0 + trow;
+    if (lane < 32 && row < g.M && w < nw) {
+      const u64 word = ((bal[wave][0][r] >> (32 * hh)) & 0xFFFFFFFFull) |
+                       (((bal[wave][1][r] >> (32 * hh)) & 0xFFFFFFFFull) << 32);
+      const u64 old = cold ? cold[trow][wc] : 0ull;
+      const u64 nv = word | old;
+      g.C[row * g.ldc + w] = nv;
+      if (g.D) g.D[row * g.ldd + w] = nv & ~old;
+      ch |= (nv != old);
+      pop += (u32)__popcll(nv & ~old);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  tile_counters(cnt, g, pop, done_words, ch);
+}
+
 // Output tile (tr, tc) of C = Cold | A.B (256 x 256) by one workgroup of 512 threads.  Every thread of
 // the workgroup must call it with the same tile.
 __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr, i64 tc) {
@@ -121,15 +212,9 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
   const u64* __restrict__ BT = g.BT;
   const i64 ldbt = g.ldbt;
   const u64* __restrict__ Cold = g.Cold;
-  const i64 ldco = g.ldco;
-  u64* __restrict__ C = g.C;
-  const i64 ldc = g.ldc;
-  u64* __restrict__ D = g.D;
-  const i64 ldd = g.ldd;
   const i64 M = g.M, K = g.K, N = g.N;
   auto& Ax = L.Ax;
   auto& Bx = L.Bx;
-  auto& bal = L.bal;
   auto& zmask = L.zmask;
   auto& satf = L.satf;
   const int t = threadIdx.x;
@@ -139,28 +224,6 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
   const int h = lane >> 5, l32 = lane & 31;
   const i64 row0 = tr * kMT, col0 = tc * kMT;
   const i64 kwords = (K + 63) >> 6;
-  const i64 nw = (N + 63) >> 6;
-
-  // A tile whose C_old bits are all set is final (C = C_old whatever A.B adds): copy it and stop.
-  if (Cold) {
-    const u64 last_mask = (N & 63) ? ((1ull << (N & 63)) - 1ull) : ~0ull;
-    int full = 1;
-    for (int e = t; e < kMT * 4; e += 512) {
-      const i64 row = row0 + (e >> 2), w = (col0 >> 6) + (e & 3);
-      if (row < M && w < nw) full &= Cold[row * ldco + w] == (w == nw - 1 ? last_mask : ~0ull);
-    }
-    if (__syncthreads_and(full)) {
-      const bool copy = C != Cold || ldc != ldco;
-      for (int e = t; e < kMT * 4; e += 512) {
-        const i64 row = row0 + (e >> 2), w = (col0 >> 6) + (e & 3);
-        if (row < M && w < nw) {
-          if (copy) C[row * ldc + w] = Cold[row * ldco + w];
-          if (D) D[row * ldd + w] = 0ull;
-        }
-      }
-      return;
-    }
-  }
 
   v16f_t acc[4][2];
 #pragma unroll
@@ -277,6 +340,8 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
   };
   load(s0, 0);
   load(s1, 1);
+  // the first loads are in flight while the C_old check waits for its words
+  if (Cold && tile_cold_full(L.cold, g, row0, col0)) return;
   stage(s0, 0);
   if (2 < nchunks) load(s0, 2);
   int pending = -1;  // vote slot to read after the next barrier
@@ -304,41 +369,7 @@ __device__ __forceinline__ void mfma_tile(MfmaLds& L, const MfmaTile& g, i64 tr,
     }
   }
 
-  // epilogue: a 32 x 32 fp32 block sits in lane l as column l % 32, register r holding row
-  // 8 (r / 4) + 4 (l / 32) + r % 4; ballot "> 0" per register, assemble 32 rows x 1 word per block row
-  int ch = 0;
-  u32 pop = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const u64 b = __ballot(acc[i][j][r] > 0.f);
-        if (lane == 0) bal[wave][j][r] = b;
-      }
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    if (lane < 32) {
-      const int rho = lane;  // row within the block: rho = 8 (r / 4) + 4 hh + r % 4
-      const int hh = (rho >> 2) & 1, r = ((rho >> 3) << 2) | (rho & 3);
-      const u64 word = ((bal[wave][0][r] >> (32 * hh)) & 0xFFFFFFFFull) |
-                       (((bal[wave][1][r] >> (32 * hh)) & 0xFFFFFFFFull) << 32);
-      const i64 row = row0 + wr * 128 + i * 32 + rho;
-      const i64 w = (col0 + wc * 64) / 64;
-      if (row < M && w < nw) {
-        const u64 old = Cold ? Cold[row * ldco + w] : 0ull;
-        const u64 nv = word | old;
-        C[row * ldc + w] = nv;
-        if (D) D[row * ldd + w] = nv & ~old;
-        ch |= (nv != old);
-        pop += (u32)__popcll(nv & ~old);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  tile_counters(L.cnt, g, pop, done_words, ch);
+  tile_epilogue(acc, L.bal, Cold ? L.cold : nullptr, g, row0, col0, done_words, L.cnt);
 }
 
 }  // namespace bmlp

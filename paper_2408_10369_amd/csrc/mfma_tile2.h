@@ -31,12 +31,14 @@ namespace bmlp {
 //    of its B^T rows.
 //  * The kernel needs 16-byte aligned rows of A and B^T (even leading dimensions, aligned bases).
 //  * Tiles whose C_old is all ones are copied; waves vote on saturation and the workgroup stops early
-//    (as in mfma_tile); the epilogue is the same.
+//    (as in mfma_tile); the epilogue is the same.  When A is known to be dense (MfmaTile::early),
+//    a whole tile votes right after its first chunk, before loading the next.
 template <int KC>
 struct Mfma2Lds {
   static_assert(KC == 8 || KC == 16, "KC is 8 or 16 words");  // 16 needs more registers than two waves per SIMD have
   u32 X[2][2][kMT][2 * KC];  // stage, operand (0: A, 1: B^T), row, swizzled half-planar dwords
   u64 bal[8][2][16];
+  u64 cold[kMT][4];  // the tile's C_old words, kept by tile_cold_full
   u32 zmask[2][8];  // per stage and staging wave: bit q = word q of the chunk is nonzero in the wave's rows
   u32 satf[2][8];
   u64 cnt[8][3];  // per wave: new bits, words of k multiplied, changed (tile_counters)
@@ -72,11 +74,6 @@ __device__ __forceinline__ void mfma_tile2(Mfma2Lds<KC>& L, const MfmaTile& g, i
   const u64* __restrict__ A = g.A;
   const u64* __restrict__ BT = g.BT;
   const u64* __restrict__ Cold = g.Cold;
-  const i64 ldco = g.ldco;
-  u64* __restrict__ C = g.C;
-  const i64 ldc = g.ldc;
-  u64* __restrict__ D = g.D;
-  const i64 ldd = g.ldd;
   const i64 M = g.M, K = g.K, N = g.N;
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -85,28 +82,6 @@ __device__ __forceinline__ void mfma_tile2(Mfma2Lds<KC>& L, const MfmaTile& g, i
   const int h = lane >> 5, l32 = lane & 31;
   const i64 row0 = tr * kMT, col0 = tc * kMT;
   const i64 kwords = (K + 63) >> 6;
-  const i64 nw = (N + 63) >> 6;
-
-  // A tile whose C_old bits are all set is final (C = C_old whatever A.B adds): copy it and stop.
-  if (Cold) {
-    const u64 last_mask = (N & 63) ? ((1ull << (N & 63)) - 1ull) : ~0ull;
-    int full = 1;
-    for (int e = t; e < kMT * 4; e += 512) {
-      const i64 row = row0 + (e >> 2), w = (col0 >> 6) + (e & 3);
-      if (row < M && w < nw) full &= Cold[row * ldco + w] == (w == nw - 1 ? last_mask : ~0ull);
-    }
-    if (__syncthreads_and(full)) {
-      const bool copy = C != Cold || ldc != ldco;
-      for (int e = t; e < kMT * 4; e += 512) {
-        const i64 row = row0 + (e >> 2), w = (col0 >> 6) + (e & 3);
-        if (row < M && w < nw) {
-          if (copy) C[row * ldc + w] = Cold[row * ldco + w];
-          if (D) D[row * ldd + w] = 0ull;
-        }
-      }
-      return;
-    }
-  }
 
   v16f_t acc[4][2];
 #pragma unroll
@@ -225,12 +200,56 @@ __device__ __forceinline__ void mfma_tile2(Mfma2Lds<KC>& L, const MfmaTile& g, i
   };
   const bool whole = row0 + kMT <= M && col0 + kMT <= N;
   bool wsat = false;  // wave-uniform
+  // words of chunk buf to multiply (wave-uniform): none once the wave is saturated
+  auto chunk_mask = [&](int buf) -> u32 {
+    return wsat ? 0u
+                : __builtin_amdgcn_readfirstlane((L.zmask[buf][2 * wr] | L.zmask[buf][2 * wr + 1]) &
+                                                 L.zmask[buf][4 + wc]);
+  };
+  // the wave is saturated once every one of its sums is positive
+  auto update_wsat = [&]() {
+    if (wsat) return;
+    float mn = acc[0][0][0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) mn = fminf(mn, acc[i][j][e]);
+    wsat = __ballot(!(mn > 0.f)) == 0ull;
+  };
   load(0);
+  // the first loads are in flight while the C_old check waits for its words
+  if (Cold && tile_cold_full(L.cold, g, row0, col0)) return;
   stage(0);
-  if (1 < nchunks) load(1);
   int pending = -1;
   int votes = 0;
-  for (i64 c = 0; c < nchunks; ++c) {
+  i64 c0 = 0;
+  if (whole && nchunks > 1 && (g.early || (g.early_flag && *g.early_flag != 0u))) {
+    // A is dense: the first chunk alone likely saturates the tile, so it is consumed and voted on
+    // before any further chunk is loaded (a chunk loaded ahead would hold the workgroup until it arrived).
+    // A tile that is not saturated then starts the pipeline at chunk 1.
+    __syncthreads();
+    compute(0, chunk_mask(0));
+    update_wsat();
+    if (lane == 0) L.satf[0][wave] = wsat ? 1u : 0u;
+    __syncthreads();
+    u32 all = 1u;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) all &= L.satf[0][w];
+    if (all) {
+      c0 = nchunks;
+    } else {
+      load(1);
+      stage(1);
+      if (2 < nchunks) load(2);
+      c0 = 1;
+      votes = 1;
+    }
+  } else if (1 < nchunks) {
+    load(1);
+  }
+  for (i64 c = c0; c < nchunks; ++c) {
     __syncthreads();
     if (pending >= 0) {
       u32 all = 1u;
@@ -244,62 +263,17 @@ __device__ __forceinline__ void mfma_tile2(Mfma2Lds<KC>& L, const MfmaTile& g, i
       stage(buf ^ 1);
       if (c + 2 < nchunks) load(c + 2);
     }
-    const u32 mask = wsat ? 0u
-                          : __builtin_amdgcn_readfirstlane((L.zmask[buf][2 * wr] | L.zmask[buf][2 * wr + 1]) &
-                                                           L.zmask[buf][4 + wc]);
-    compute(buf, mask);
+    compute(buf, chunk_mask(buf));
     // votes after 1, 2, 4, 8, ... chunks
     if (whole && ((c + 1) & c) == 0) {
-      if (!wsat) {
-        float mn = acc[0][0][0];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) mn = fminf(mn, acc[i][j][e]);
-        wsat = __ballot(!(mn > 0.f)) == 0ull;
-      }
+      update_wsat();
       pending = votes & 1;
       if (lane == 0) L.satf[pending][wave] = wsat ? 1u : 0u;
       ++votes;
     }
   }
 
-  // epilogue (the layout of a 32 x 32 fp32 block is that of mfma_tile)
-  int ch = 0;
-  u32 pop = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const u64 b = __ballot(acc[i][j][r] > 0.f);
-        if (lane == 0) L.bal[wave][j][r] = b;
-      }
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    if (lane < 32) {
-      const int rho = lane;
-      const int hh = (rho >> 2) & 1, r = ((rho >> 3) << 2) | (rho & 3);
-      const u64 word = ((L.bal[wave][0][r] >> (32 * hh)) & 0xFFFFFFFFull) |
-                       (((L.bal[wave][1][r] >> (32 * hh)) & 0xFFFFFFFFull) << 32);
-      const i64 row = row0 + wr * 128 + i * 32 + rho;
-      const i64 w = (col0 + wc * 64) / 64;
-      if (row < M && w < nw) {
-        const u64 old = Cold ? Cold[row * ldco + w] : 0ull;
-        const u64 nv = word | old;
-        C[row * ldc + w] = nv;
-        if (D) D[row * ldd + w] = nv & ~old;
-        ch |= (nv != old);
-        pop += (u32)__popcll(nv & ~old);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  tile_counters(L.cnt, g, pop, done_words, ch);
+  tile_epilogue(acc, L.bal, Cold ? L.cold : nullptr, g, row0, col0, done_words, L.cnt);
 }
 
 }  // namespace bmlp

@@ -62,7 +62,15 @@ __host__ __device__ inline bool rms_semi_may_pay(i64 n, i64 dbits, bool mfma) {
 
 // Routes of a squaring chosen on the device (k_rms_decide)
 enum RmsRoute : u32 { RR_STOP = 0, RR_GATHER = 1, RR_DENSE = 2, RR_HOST = 3 };
-// Per-squaring record on the device, 8 words: new bits (u64), running bit count (u64), route (u32)
+// Per-squaring record on the device, 8 words: new bits (u64), running bit count (u64), route (u32), and a
+// flag (rms_early_votes) under which the dense product's tiles vote on saturation after their first chunk
+// of k, before loading ahead
 constexpr int kRmsRecWords = 8;
+constexpr int kRmsRecEarly = 5;
+
+// A squaring of an R with at least a quarter of its bits set likely saturates each output tile within its
+// first chunk of 512 values of k: with set bits spread at density rho, an output stays unset there with
+// probability about (1 - rho^2)^512, below e^-32 from rho = 1/4.
+__host__ __device__ inline bool rms_early_votes(i64 n, i64 bits) { return 4.0 * (double)bits >= (double)n * (double)n; }
 
 }  // namespace bmlp

@@ -225,6 +225,41 @@ def test_rms_mfma_arm(ctx, n):
         assert np.array_equal(got, oracle.closure_rows(n, s, d)), (n, p)
 
 
+def test_rms_dense_relation_early_votes(ctx):
+    """A dense relation (a quarter or more of its bits set): its matrix-core squarings vote on saturation
+    right after the first chunk of k.  Tiles saturated there stop; rows empty over the first 640 columns get
+    nothing from that chunk and go on through the pipeline (saturated at the next vote); columns with no
+    edge into them never saturate and run the whole of k.  The closure is compared with Warshall's
+    algorithm."""
+    n = 2048
+    rng = np.random.default_rng(5)
+    A = (rng.random((n, n)) < 0.9).astype(np.uint8)
+    A[:, :256] = 0
+    A[1024:, :640] = 0
+    s, d = np.nonzero(A)
+    R = gpu_pack(ctx, n, s.astype(np.int32), d.astype(np.int32))
+    st = {}
+    got = host(ctx.rms(R, n, stats=st))
+    assert np.array_equal(got, oracle.warshall(boolops.to_bits(A), n))
+    assert st["iterations"] == 2
+
+
+def test_rms_stops_at_all_ones(ctx):
+    """An all-ones relation is its own square: once a squaring leaves R full, the fixpoint is reached
+    without the squaring that would only confirm it."""
+    n = 2048
+    rng = np.random.default_rng(6)
+    A = (rng.random((n, n)) < 0.5).astype(np.uint8)
+    s, d = np.nonzero(A)
+    R = gpu_pack(ctx, n, s.astype(np.int32), d.astype(np.int32))
+    st = {}
+    got = host(ctx.rms(R, n, stats=st))
+    want = oracle.warshall(boolops.to_bits(A), n)
+    assert np.array_equal(got, want)
+    assert np.array_equal(boolops.from_bits(want, n), np.ones((n, n), np.uint8))
+    assert st["iterations"] == 1
+
+
 @pytest.mark.parametrize("n", [2, 3, 5, 9, 17, 100, 1000, 1025])
 def test_rms_path_graph_loop_counts(ctx, n):
     s, d = gen.path_graph(n)
