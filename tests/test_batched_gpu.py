@@ -77,6 +77,25 @@ def test_batched_mixed_sizes(ctx, mode):
     assert st["iterations"] >= 1 and st["bool_ops"] > 0
 
 
+@pytest.mark.parametrize("mode", ["plain", "closure"])
+def test_batched_dense_blocks(ctx, mode):
+    """Dense graphs (30% of the pairs) square on the matrix cores.  No edge enters the first 128 columns,
+    so those outputs never saturate and their tiles run the whole of k; rows of the lower half are empty
+    over the first 384 columns, so the first chunks of k add nothing to them; a 700-node graph has partial
+    tiles, which never vote on saturation."""
+    rng = np.random.default_rng(21)
+    specs = []
+    for n in (1024, 1536, 1024, 700):
+        A = (rng.random((n, n)) < 0.3).astype(np.uint8)
+        A[:, :128] = 0
+        A[n // 2:, :384] = 0
+        s, d = np.nonzero(A)
+        specs.append((n, s, d, rng.choice(n, 40, replace=False)))
+    graphs, refs = make_batch(ctx, specs)
+    ctx.batched(graphs, opts=mode_opts(mode))
+    check(graphs, refs)
+
+
 @pytest.mark.parametrize("mode", ["plain", "learned"])
 def test_batched_matrix_core_graphs(ctx, mode):
     # graphs at and above the matrix-core size: dense from the first round, ragged (n not a multiple
