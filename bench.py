@@ -45,7 +45,7 @@ KERNELS = {0: ("k_gemm_valu", "bit-packed Boolean product on the VALU", "alu", V
 GEMM_TRAFFIC = {"k_gemm_mfma": {"sources": ["paper_2408_10369_amd/csrc/k_gemm.hip",
                                             "paper_2408_10369_amd/csrc/mfma_tile.h",
                                             "paper_2408_10369_amd/csrc/mfma_tile2.h"],
-                                "sha256": "e3bf4d7813161745c720ae85670a1647477f30706baec45eec3aa736865133a5",
+                                "sha256": "048b481c700004740b8aec997fcf49a28e2108e75bea6ae05bc17f17331ab897",
                                 "bytes_per_launch": 451.2e6}}
 
 

@@ -141,9 +141,9 @@ hipError_t launch_rpw(const GemmArgs& g, hipStream_t s, i64 target_blocks) {
 //      while a block-structured product (its work in one corner) still spreads over all XCDs.  It needs
 //      an even number of row tiles and a multiple of 4 column tiles, else order 1 is used;
 //   3  column strips: XCD x gets the column tiles [x c/8, (x + 1) c/8) (c = ctiles) and walks them in
-//      sub-strips of 8 columns, row by row, so the workgroups an XCD holds at once (8 rows of 8 columns
-//      at two per CU) share 8 panels of A and 8 of B^T, and the 8 B^T panels of a sub-strip stay in its
-//      L2 while the rows go by.  It needs multiples of 8 row tiles and of 64 column tiles, else order 1.
+//      sub-strips of 8 columns, row by row, so the workgroups an XCD holds at once (one per CU, 32: four
+//      rows of 8 columns) share 4 panels of A and 8 of B^T, and the 8 B^T panels of a sub-strip stay in
+//      its L2 while the rows go by.  It needs multiples of 8 row tiles and of 64 column tiles, else order 1.
 __device__ __forceinline__ void grouped(i64 li, i64 rows, i64 cols, i64 gmax, i64* i, i64* j) {
   const i64 gsz = rows < gmax ? rows : gmax;
   const i64 group = li / (gsz * cols), first = group * gsz;
