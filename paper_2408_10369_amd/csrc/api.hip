@@ -434,6 +434,8 @@ int tune_bucket(i64 M, i64 K, i64 N, double density, bool structured = false) {
 }
 // Candidates the autotuner chooses among, and the built-in defaults (measured on MI355X at n = 16,384)
 constexpr int kTuneCandidates[bmlp_ctx::kTuneKernels] = {kMfmaVariants, kValuVariants};
+static_assert(kMfmaVariants <= BMLP_TUNE_MAX_CANDIDATES && kValuVariants <= BMLP_TUNE_MAX_CANDIDATES,
+              "the tuning report holds BMLP_TUNE_MAX_CANDIDATES candidates per bucket");
 constexpr int kTuneDefault[bmlp_ctx::kTuneKernels] = {0, 0};
 int tuned_variant(const bmlp_ctx* c, int kernel, i64 M, i64 K, i64 N, double density, bool structured = false) {
   const int v = c->tune[kernel][tune_bucket(M, K, N, density, structured)];
